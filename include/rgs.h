@@ -1,0 +1,288 @@
+/*
+ * rgs.h -- C ABI of librgs.so, the MI355X (gfx950) partitioned 3D Gaussian
+ * splatting rasterizer of RetinaGS (arXiv 2406.11836).
+ *
+ * The method (Sec. 3.2-3.4 of the paper): the scene is cut into K = 2^L
+ * convex cells by a KD tree over the Gaussian centres (Sec. 3.3); for every
+ * pixel ray, each cell k blends, front to back, the Gaussians whose ray
+ * crossing point lies inside it (Eq. 3, Eq. 4 with the indicator of Eq. 6)
+ * into a partial colour C_k and transmittance T_k; the partials are merged in
+ * the order the ray visits the cells (Eq. 5), which reproduces the
+ * single-worker render (Eq. 2) exactly.  Here all K cells live on one GPU and
+ * the merge is an on-device pass; the backward sends the loss gradient
+ * through the merge to every cell (Sec. 3.4).
+ *
+ * Conventions (all entry points):
+ *   - Pointers are device memory unless marked [host].  The caller owns every
+ *     buffer, including workspaces sized by the *_workspace() queries; the
+ *     library never allocates and keeps no state between calls, so calls on
+ *     different streams with disjoint buffers may run concurrently.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and
+ *     the call returns without waiting, except rgs_bin_sort, which copies one
+ *     counter to the host (the instance count) and therefore waits once.
+ *   - Argument errors are reported synchronously (RGS_E_ARG) and enqueue
+ *     nothing.  A failed kernel launch returns RGS_E_HIP and records the HIP
+ *     error code (rgs_last_hip_error, per thread).  Faults inside kernels
+ *     surface at the caller's next synchronisation.
+ *   - Degenerate data is not an error: Gaussians behind z_near, with a zero
+ *     quaternion, opacity below 1/255 or an empty footprint are culled (no
+ *     instances, zero gradient); N = 0 renders the background with T = 1.
+ *   - Gradient outputs are overwritten, never accumulated.
+ *
+ * Layouts (float32, structure of arrays):
+ *   means [3][N], log_scales [3][N], quats [4][N] (w, x, y, z),
+ *   opacity [N] (logit; alpha = sigmoid), sh [3 (D+1)^2][N] with row
+ *   3 j + channel for the real SH index j = l^2 + l + m, D = sh_degree <= 3.
+ *   A view's image is [3][H][W]; several views are concatenated in order.
+ *   "src" numbers a (view, Gaussian) pair: src = view * N + gid.
+ */
+#ifndef RGS_H
+#define RGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RGS_ABI_VERSION 1
+#define RGS_TILE 16       /* screen tiles are 16 x 16 pixels */
+#define RGS_MAX_L 6       /* K = 2^L <= 64 cells */
+#define RGS_MAX_VIEWS 16  /* views per call */
+#define RGS_REC_FLOATS 12 /* floats per projected render record */
+
+typedef int32_t rgs_status;
+enum {
+    RGS_OK = 0,
+    RGS_E_ARG = -1,         /* invalid argument; nothing enqueued */
+    RGS_E_CAPACITY = -2,    /* caller buffers too small; see *n_required */
+    RGS_E_HIP = -3,         /* a HIP call failed; see rgs_last_hip_error() */
+    RGS_E_UNSUPPORTED = -4  /* size outside what this build supports */
+};
+
+typedef void *rgs_stream; /* hipStream_t */
+
+int32_t rgs_abi_version(void);
+const char *rgs_status_string(rgs_status status);
+int32_t rgs_last_hip_error(void);
+
+/* Gaussian parameters (Sec. 3.1: centre mu, covariance from scale and
+ * rotation, opacity alpha, SH colour). */
+typedef struct {
+    int64_t n;
+    int32_t sh_degree;
+    const float *means;
+    const float *log_scales;
+    const float *quats;
+    const float *opacity;
+    const float *sh;
+} rgs_gaussians;
+
+/* Gradients w.r.t. the parameters, same layouts (written, not accumulated). */
+typedef struct {
+    float *means;
+    float *log_scales;
+    float *quats;
+    float *opacity;
+    float *sh;
+} rgs_gaussians_grad;
+
+/* [host] Pinhole camera, OpenCV axes (x right, y down, z forward):
+ * p_cam = R p_world + t, R row-major; campos is the camera centre o of the
+ * paper's rays l(t) = o + t d (Sec. 3.2).  Pixel (x, y) samples image point
+ * (x + 0.5, y + 0.5).  bg is added once, after the merge. */
+typedef struct {
+    float R[9];
+    float t[3];
+    float campos[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float z_near;
+    float bg[3];
+} rgs_camera;
+
+/* KD tree of depth L over the Gaussian centres (Sec. 3.3). */
+typedef struct {
+    int32_t L;
+    float *split;          /* [max(K-1,1)] split values, heap order; axis of a node = depth mod 3 */
+    float *box_lo;         /* [3][K] leaf boxes, half-open [lo, hi), +-inf outer faces */
+    float *box_hi;         /* [3][K] */
+    int32_t *center_cell;  /* [N] leaf containing each centre (output of rgs_kd_partition) */
+    int32_t *counts;       /* [K] centres per leaf */
+    uint32_t *own_mask;    /* [N][ceil(K/32)] the paper's subsets N_k, or NULL to skip */
+} rgs_kdtree;
+
+/* Per-(view, Gaussian) projection output. */
+typedef struct {
+    float *rec;         /* [V*N][12]: mx, my, ca, cb, cc, alpha, tau, z, r, g, b, flags */
+    int16_t *rect;      /* [V*N][4]: sample-pixel rectangle x_lo, x_hi, y_lo, y_hi */
+    uint64_t *cellmask; /* [V*N]: cells the footprint can reach (bit k = cell k) */
+    uint32_t *count;    /* [V*N]: instances = |cellmask| * tiles in rect; 0 = culled */
+} rgs_projected;
+
+/* Tile/cell instance lists and slots (one slot per non-empty (tile, cell)). */
+typedef struct {
+    int64_t capacity;       /* instance capacity of keys and vals */
+    int64_t slot_capacity;  /* slot capacity: >= min(instances, total_tiles * K) */
+    uint32_t *keys;         /* [capacity] sorted keys (global_tile << L) | rank of cell in view order */
+    uint64_t *vals;         /* [capacity] sorted (src << 32) | position in emission order */
+    uint32_t *pair_src;     /* [V*N] visible pairs in (view, depth, gid) order */
+    uint32_t *pair_off;     /* [V*N+1] first instance of each ordered pair */
+    int32_t *pair_rank;     /* [V*N] position of src in pair_src (valid where count > 0) */
+    uint32_t *slot_key;     /* [slot_capacity] key of each slot */
+    uint32_t *slot_range;   /* [slot_capacity][2] begin, end into keys/vals */
+    uint32_t *tile_slot;    /* [total_tiles+1] first slot of each global tile (slots of a tile are in view order) */
+    uint32_t *counters;     /* [4]: pairs, instances, slots, 0 */
+    int64_t n_instances;    /* [out, host] */
+} rgs_bins;
+
+/* Per-slot partial maps (Eq. 3, Eq. 4): 256 pixels of the slot's tile. */
+typedef struct {
+    float *C;        /* [slot_capacity][3][256] partial colour C_k */
+    float *T;        /* [slot_capacity][256]    partial transmittance T_k */
+    uint32_t *last;  /* [slot_capacity][256]    1 + index in the slot of the last processed instance */
+} rgs_partials;
+
+typedef struct {
+    float *dC;       /* [slot_capacity][3][256] dL/dC_k */
+    float *dT;       /* [slot_capacity][256]    dL/dT_k */
+} rgs_partials_grad;
+
+/* ------------------------------------------------------------------ */
+/* Views                                                               */
+/* ------------------------------------------------------------------ */
+/* Size of the device view table. */
+size_t rgs_views_bytes(void);
+/* Writes the device view table for n_views cameras (<= RGS_MAX_VIEWS) and the
+ * per-view cell order ([host] rank_of[v][K]: rank of cell k in view v's merge
+ * order, from rgs_cell_order).  Copies from host memory on `stream`; the
+ * host arrays may be reused when the call returns.  Global tiles of view v
+ * follow those of views 0..v-1 (16 x 16 tiles, row-major). */
+rgs_status rgs_views_upload(const rgs_camera *cams, int32_t n_views, int32_t L,
+                            const int32_t *rank_of, void *views_dev, rgs_stream stream);
+/* [host] total 16x16 tiles over the views. */
+int64_t rgs_total_tiles(const rgs_camera *cams, int32_t n_views);
+
+/* ------------------------------------------------------------------ */
+/* KD partition (Sec. 3.3)                                             */
+/* ------------------------------------------------------------------ */
+/* Depth-L tree: at depth l the axis is l mod 3 (X, Y, Z in turn) and the
+ * split is the floor(n/2)-th smallest coordinate (0-based, IEEE total order)
+ * of the node's centres; centres below the split go left, the rest right; an
+ * empty node splits at the midpoint of its finite bounds (one finite bound:
+ * that bound; none: 0).  Leaves are numbered by their path bits (left 0,
+ * right 1), first level most significant.  own_mask, if not NULL, marks
+ * N_k = { i : centre in the leaf box inflated by D_i on every face },
+ * D_i = d_factor * max_a exp(log_scale_a) (the paper uses three times the
+ * major axis).  Writes split, box_lo/hi, center_cell, counts, own_mask. */
+size_t rgs_kd_partition_workspace(int64_t n, int32_t L);
+rgs_status rgs_kd_partition(const rgs_gaussians *g, int32_t L, float d_factor, const rgs_kdtree *kd,
+                            void *ws, size_t ws_bytes, rgs_stream stream);
+
+/* [host] The order in which any ray from campos visits the cells (Eq. 5's
+ * permutation o_l): in-order traversal, near child first, near = left iff
+ * campos[axis] < split.  order[r] = cell at rank r; rank_of[k] = rank of k. */
+rgs_status rgs_cell_order(int32_t L, const float *split_host, const float campos[3], int32_t *order,
+                          int32_t *rank_of);
+
+/* ------------------------------------------------------------------ */
+/* Projection and SH colour (Sec. 3.1)                                  */
+/* ------------------------------------------------------------------ */
+/* Per (view, Gaussian): activations, EWA screen covariance with a 0.3 px^2
+ * low-pass and the Jacobian at the guarded camera-space centre, its inverse
+ * (conic), screen mean, cut threshold tau = min(9, 2 ln(255 alpha))
+ * (contribution iff d^2 <= tau), SH colour 0.5 + sum f Y clamped at 0,
+ * sample-pixel rectangle, the cell set (KD leaves met by the padded box of
+ * the footprint's ray crossing points) and the instance count.
+ * rec[11] holds flag bits (bit 0: the footprint lies in one cell). */
+rgs_status rgs_project_sh(const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
+                          const void *views_dev, const rgs_kdtree *kd, const rgs_projected *out,
+                          rgs_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Binning and sorting                                                  */
+/* ------------------------------------------------------------------ */
+/* Orders the visible (view, Gaussian) pairs by (view, depth z, gid), emits one
+ * instance per (pair, cell in its cell set, tile in its rectangle), sorts the
+ * instances stably by (global tile, rank of the cell in the view's order) with
+ * an LSD radix sort, and builds the slot table.  Copies the instance count to
+ * host (*n_required, bins->n_instances); if it exceeds bins->capacity, or the
+ * slot bound exceeds bins->slot_capacity, returns RGS_E_CAPACITY having
+ * written only the pair arrays; the caller grows the buffers and calls again. */
+size_t rgs_bin_sort_workspace(int64_t n, int32_t n_views, int64_t total_tiles, int32_t L, int64_t capacity);
+rgs_status rgs_bin_sort(const rgs_projected *proj, int64_t n, const rgs_camera *cams, int32_t n_views,
+                        const void *views_dev, int32_t L, rgs_bins *bins, int64_t *n_required,
+                        void *ws, size_t ws_bytes, rgs_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Partial render (Eq. 3, Eq. 4, Eq. 6)                                 */
+/* ------------------------------------------------------------------ */
+/* For every slot (tile t, cell k) and pixel p of t, front to back over the
+ * slot's instances: the instance contributes iff d^2 <= tau and its crossing
+ * point x = campos + z D(p) lies in cell k's box; sigma = min(0.99,
+ * alpha exp(-d^2/2)); C_k += T_k sigma c; T_k *= 1 - sigma; a pixel stops
+ * after the contribution that takes T_k below eps_T (eps_T = 0: never). */
+rgs_status rgs_render_partial(const rgs_projected *proj, int64_t n, const rgs_bins *bins,
+                              const rgs_camera *cams, int32_t n_views, const void *views_dev,
+                              const rgs_kdtree *kd, float eps_T, const rgs_partials *out,
+                              rgs_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Merge (Eq. 5)                                                        */
+/* ------------------------------------------------------------------ */
+/* Per pixel: fold (C, T) <- (C + T C_k, T T_k) over the tile's slots in the
+ * view's cell order starting from (0, 1); image = C + T bg, T_final = T.
+ * image: concatenated [3][H][W] per view; T_final: concatenated [H][W]. */
+rgs_status rgs_merge_partials(const rgs_partials *parts, const rgs_bins *bins, const rgs_camera *cams,
+                              int32_t n_views, const void *views_dev, float *image, float *T_final,
+                              rgs_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Loss (L1 + w (1 - SSIM))                                             */
+/* ------------------------------------------------------------------ */
+/* One view, [3][H][W] in [0,1]: L1 = mean |x - y|; SSIM with an 11x11
+ * Gaussian window (std 1.5), zero padding, C1 = 1e-4, C2 = 9e-4, mean over
+ * 3HW.  Writes the scalar loss (device) and d loss / d image. */
+size_t rgs_loss_workspace(int32_t H, int32_t W);
+rgs_status rgs_loss_l1_ssim(const float *image, const float *target, int32_t H, int32_t W,
+                            float ssim_weight, float *loss, float *d_image, void *ws, size_t ws_bytes,
+                            rgs_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Backward                                                             */
+/* ------------------------------------------------------------------ */
+/* Merge backward (the manager's gradient to every sub-model, Sec. 3.4):
+ * dC_k = P_k g, dT_k = P_k (<g, R_k> + gT Q_k) with P_k the transmittance
+ * before k, R_k the merged colour (with background) after k and Q_k the
+ * transmittance after k.  d_T_final may be NULL (zero). */
+rgs_status rgs_merge_partials_bwd(const float *d_image, const float *d_T_final, const rgs_partials *parts,
+                                  const rgs_bins *bins, const rgs_camera *cams, int32_t n_views,
+                                  const void *views_dev, const rgs_partials_grad *out, rgs_stream stream);
+
+/* Partial-render backward plus the per-pair reduction: back to front from
+ * each pixel's `last`, recovering the transmittance before each contribution
+ * by division, giving per-instance gradients of (screen mean, conic, alpha,
+ * colour) summed over the tile's pixels, then summed over each pair's
+ * instances in a fixed order (no atomics).  d_proj: [9][V*N] rows
+ * d mx, d my, d ca, d cb, d cc, d alpha, d r, d g, d b (zero for culled
+ * pairs; cb is the off-diagonal conic entry). */
+size_t rgs_render_bwd_workspace(int64_t capacity);
+rgs_status rgs_render_partial_bwd(const rgs_partials_grad *dparts, const rgs_partials *parts,
+                                  const rgs_bins *bins, const rgs_projected *proj, int64_t n,
+                                  const rgs_camera *cams, int32_t n_views, const void *views_dev,
+                                  const rgs_kdtree *kd, float *d_proj, void *ws, size_t ws_bytes,
+                                  rgs_stream stream);
+
+/* Projection backward: chain rule from d_proj to the parameters, summed over
+ * the views.  Exact derivative: zero through the colour clamp, the clamp of
+ * the projected x/z, y/z (where the clamped value is proportional to z) and
+ * for culled pairs. */
+rgs_status rgs_project_sh_bwd(const float *d_proj, const rgs_gaussians *g, const rgs_projected *proj,
+                              const rgs_camera *cams, int32_t n_views, const void *views_dev,
+                              const rgs_gaussians_grad *out, rgs_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RGS_H */

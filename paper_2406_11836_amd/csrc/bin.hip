@@ -1,0 +1,240 @@
+// bin.hip -- tile/cell instance lists, depth order and slot table.
+//
+// 1. The visible (view, Gaussian) pairs are compacted in (view, gid) order
+//    and sorted stably by the fp32 bits of their camera depth (positive
+//    floats order like their bits), then by view: (view, z, gid) order.
+// 2. Each pair emits, contiguously and in that order, one instance per
+//    (cell of its cell set, tile of its rectangle), keyed
+//    (global tile << L) | rank of the cell in the view's merge order.
+// 3. A stable LSD radix sort on the key alone keeps every (tile, cell)
+//    group in depth order, so the sort never looks at the depth bits.
+// 4. Slot boundaries are found on a dense (tile, rank) table, compacted by a
+//    scan; the slots of a tile come out contiguous and in merge order.
+#include "common.hpp"
+
+namespace rgs {
+
+static constexpr int BN_THREADS = 256;
+
+__global__ __launch_bounds__(BN_THREADS) void k_vis_flags(const uint32_t* __restrict__ count, int64_t m,
+                                                          uint32_t* __restrict__ flag) {
+    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (i < m) flag[i] = count[i] > 0u ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(BN_THREADS) void k_vis_compact(const uint32_t* __restrict__ count,
+                                                            const uint32_t* __restrict__ pos, const float* __restrict__ rec,
+                                                            int64_t m, uint32_t* __restrict__ zkey,
+                                                            uint32_t* __restrict__ src_out) {
+    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (i >= m || count[i] == 0u) return;
+    const uint32_t p = pos[i];
+    zkey[p] = __float_as_uint(rec[i * RGS_REC_FLOATS + 7]);
+    src_out[p] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(BN_THREADS) void k_view_keys(const uint32_t* __restrict__ src, const uint32_t* __restrict__ n_dev,
+                                                          int64_t n_gauss, uint32_t* __restrict__ vkey) {
+    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (i < (int64_t)*n_dev) vkey[i] = (uint32_t)(src[i] / (uint64_t)n_gauss);
+}
+
+// Per ordered pair: its rank, and its instance count (for the offsets scan).
+__global__ __launch_bounds__(BN_THREADS) void k_pair_counts(const uint32_t* __restrict__ pair_src,
+                                                            const uint32_t* __restrict__ n_dev, int64_t m_max,
+                                                            const uint32_t* __restrict__ count,
+                                                            int32_t* __restrict__ pair_rank, uint32_t* __restrict__ cnt) {
+    int64_t r = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (r >= m_max) return;
+    if (r < (int64_t)*n_dev) {
+        const uint32_t s = pair_src[r];
+        pair_rank[s] = (int32_t)r;
+        cnt[r] = count[s];
+    } else {
+        cnt[r] = 0u;
+    }
+}
+
+// One thread per ordered pair writes its instances (cells ascending, tiles row-major).
+__global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict__ pair_src, const uint32_t* __restrict__ n_dev,
+                                                     const uint32_t* __restrict__ pair_off, const int16_t* __restrict__ rect,
+                                                     const uint64_t* __restrict__ cellmask, int64_t n_gauss,
+                                                     const ViewTable* __restrict__ vt, uint32_t* __restrict__ keys,
+                                                     uint64_t* __restrict__ vals) {
+    const int64_t r = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (r >= (int64_t)*n_dev) return;
+    const uint32_t src = pair_src[r];
+    const int v = (int)(src / (uint64_t)n_gauss);
+    const ViewParams& V = vt->v[v];
+    const int L = vt->L;
+    const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
+    const int x0 = (int)(int16_t)(rr.x & 0xffffu) >> 4, x1 = (int)(int16_t)(rr.x >> 16) >> 4;
+    const int y0 = (int)(int16_t)(rr.y & 0xffffu) >> 4, y1 = (int)(int16_t)(rr.y >> 16) >> 4;
+    uint64_t mask = cellmask[src];
+    uint32_t j = pair_off[r];
+    const uint64_t hi = (uint64_t)src << 32;
+    while (mask) {
+        const int cell = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const uint32_t rank = V.rank_of_cell[cell];
+        for (int ty = y0; ty <= y1; ++ty) {
+            const uint32_t rowbase = V.tile_offset + (uint32_t)ty * (uint32_t)V.tiles_x;
+            for (int tx = x0; tx <= x1; ++tx) {
+                keys[j] = ((rowbase + (uint32_t)tx) << L) | rank;
+                vals[j] = hi | j;
+                ++j;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(BN_THREADS) void k_fill_u32(uint32_t* __restrict__ p, int64_t m, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (i < m) p[i] = v;
+}
+
+// Slot boundaries on the dense (tile, rank) table.
+__global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __restrict__ keys, int64_t n_inst,
+                                                            uint32_t* __restrict__ dstart, uint32_t* __restrict__ dend) {
+    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (i >= n_inst) return;
+    const uint32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) dstart[k] = (uint32_t)i;
+    if (i == n_inst - 1 || keys[i + 1] != k) dend[k] = (uint32_t)(i + 1);
+}
+
+__global__ __launch_bounds__(BN_THREADS) void k_slot_flags(const uint32_t* __restrict__ dstart, int64_t m,
+                                                           uint32_t* __restrict__ flag) {
+    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (i < m) flag[i] = dstart[i] != 0xffffffffu ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(BN_THREADS) void k_slot_compact(const uint32_t* __restrict__ dstart,
+                                                             const uint32_t* __restrict__ dend,
+                                                             const uint32_t* __restrict__ sidx, int64_t m,
+                                                             uint32_t* __restrict__ slot_key,
+                                                             uint32_t* __restrict__ slot_range) {
+    int64_t e = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (e >= m) return;
+    const uint32_t b = dstart[e];
+    if (b == 0xffffffffu) return;
+    const uint32_t s = sidx[e];
+    slot_key[s] = (uint32_t)e;
+    slot_range[2 * s] = b;
+    slot_range[2 * s + 1] = dend[e];
+}
+
+__global__ __launch_bounds__(BN_THREADS) void k_tile_slots(const uint32_t* __restrict__ sidx, int64_t total_tiles, int K,
+                                                           const uint32_t* __restrict__ n_slots,
+                                                           uint32_t* __restrict__ tile_slot) {
+    int64_t t = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (t < total_tiles) tile_slot[t] = sidx[t * K];
+    if (t == total_tiles) tile_slot[t] = *n_slots;
+}
+
+size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t capacity) {
+    const int64_t m = (int64_t)n_views * n;
+    const int64_t dense = total_tiles << L;
+    WsCarver c{nullptr, 0, 0};
+    c.take<uint32_t>(m + 1);          // flags / counts
+    c.take<uint32_t>(m + 1);          // positions
+    c.take<uint32_t>(m + 1);          // z keys
+    c.take<uint32_t>(m + 1);          // z keys alt
+    c.take<uint32_t>(m + 1);          // src alt
+    c.take<uint32_t>(capacity + 1);   // instance keys alt
+    c.take<uint64_t>(capacity + 1);   // instance vals alt
+    c.take<uint32_t>(dense + 1);      // dense start
+    c.take<uint32_t>(dense + 1);      // dense end
+    c.take<uint32_t>(dense + 1);      // dense flags
+    c.take<uint32_t>(dense + 1);      // slot index
+    const int64_t big = m > capacity ? m : capacity;
+    const int64_t big2 = big > dense ? big : dense;
+    c.take<char>(radix_ws_bytes(big2 + 1));
+    c.take<char>(scan_ws_bytes(big2 + 1));
+    return c.used + 256;
+}
+
+static inline int bits_for(uint64_t v) {  // bits needed to represent values < v
+    int b = 0;
+    while (b < 63 && (1ull << b) < v) ++b;
+    return b;
+}
+
+rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt_dev, int L,
+                    int64_t total_tiles, rgs_bins* bins, int64_t* n_required, void* ws, size_t ws_bytes,
+                    hipStream_t s) {
+    const int64_t m = (int64_t)n_views * n;
+    const int64_t dense = total_tiles << L;
+    WsCarver c{reinterpret_cast<char*>(ws), 0, ws_bytes};
+    uint32_t* flag = c.take<uint32_t>(m + 1);
+    uint32_t* pos = c.take<uint32_t>(m + 1);
+    uint32_t* zkey = c.take<uint32_t>(m + 1);
+    uint32_t* zkey_alt = c.take<uint32_t>(m + 1);
+    uint32_t* src_alt = c.take<uint32_t>(m + 1);
+    uint32_t* keys_alt = c.take<uint32_t>(bins->capacity + 1);
+    uint64_t* vals_alt = c.take<uint64_t>(bins->capacity + 1);
+    uint32_t* dstart = c.take<uint32_t>(dense + 1);
+    uint32_t* dend = c.take<uint32_t>(dense + 1);
+    uint32_t* dflag = c.take<uint32_t>(dense + 1);
+    uint32_t* sidx = c.take<uint32_t>(dense + 1);
+    const int64_t big = m > bins->capacity ? m : bins->capacity;
+    const int64_t big2 = big > dense ? big : dense;
+    void* rws = c.take<char>(radix_ws_bytes(big2 + 1));
+    void* sws = c.take<char>(scan_ws_bytes(big2 + 1));
+    if (!c.ok()) return RGS_E_ARG;
+    uint32_t* cnt = bins->counters;  // [0] pairs [1] instances [2] slots
+    rgs_status st;
+    auto grid = [](int64_t k) { return dim3((unsigned)((k + BN_THREADS - 1) / BN_THREADS > 0 ? (k + BN_THREADS - 1) / BN_THREADS : 1)); };
+
+    // 1. visible pairs in (view, gid) order, then stable sorts by depth and by view
+    if (m > 0) hipLaunchKernelGGL(k_vis_flags, grid(m), dim3(BN_THREADS), 0, s, proj->count, m, flag);
+    if ((st = exclusive_scan_u32(flag, pos, m, &cnt[0], sws, s)) != RGS_OK) return st;
+    if (m > 0)
+        hipLaunchKernelGGL(k_vis_compact, grid(m), dim3(BN_THREADS), 0, s, proj->count, pos, proj->rec, m, zkey,
+                           bins->pair_src);
+    RGS_LAUNCH_CHECK();
+    if ((st = radix_sort_u32_u32_dev(zkey, bins->pair_src, zkey_alt, src_alt, &cnt[0], m, 32, rws, s)) != RGS_OK)
+        return st;
+    if (n_views > 1) {
+        hipLaunchKernelGGL(k_view_keys, grid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], n, zkey);
+        if ((st = radix_sort_u32_u32_dev(zkey, bins->pair_src, zkey_alt, src_alt, &cnt[0], m, bits_for(n_views), rws, s)) !=
+            RGS_OK)
+            return st;
+    }
+    // 2. instance offsets per ordered pair; the instance count goes to the host
+    if (m > 0) hipLaunchKernelGGL(k_pair_counts, grid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], m, proj->count,
+                                  bins->pair_rank, flag);
+    if ((st = exclusive_scan_u32(flag, bins->pair_off, m, &cnt[1], sws, s)) != RGS_OK) return st;
+    RGS_HIP_CHECK(hipMemcpyAsync(bins->pair_off + m, &cnt[1], sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    uint32_t h_cnt[2] = {0u, 0u};
+    RGS_HIP_CHECK(hipMemcpyAsync(h_cnt, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    RGS_HIP_CHECK(hipStreamSynchronize(s));
+    const int64_t n_inst = h_cnt[1];
+    bins->n_instances = n_inst;
+    if (n_required) *n_required = n_inst;
+    const int64_t slot_bound = n_inst < dense ? n_inst : dense;
+    if (n_inst > bins->capacity || slot_bound > bins->slot_capacity) return RGS_E_CAPACITY;
+
+    // 3. emit and sort instances by (tile, rank)
+    if (m > 0)
+        hipLaunchKernelGGL(k_emit, grid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], bins->pair_off, proj->rect,
+                           proj->cellmask, n, vt_dev, bins->keys, bins->vals);
+    RGS_LAUNCH_CHECK();
+    const int key_bits = L + bits_for((uint64_t)total_tiles);
+    if (key_bits > 32) return RGS_E_UNSUPPORTED;
+    if ((st = radix_sort_u32_u64(bins->keys, bins->vals, keys_alt, vals_alt, n_inst, key_bits, rws, s)) != RGS_OK)
+        return st;
+
+    // 4. slots
+    hipLaunchKernelGGL(k_fill_u32, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, 0xffffffffu);
+    if (n_inst > 0) hipLaunchKernelGGL(k_slot_bounds, grid(n_inst), dim3(BN_THREADS), 0, s, bins->keys, n_inst, dstart, dend);
+    hipLaunchKernelGGL(k_slot_flags, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, dflag);
+    if ((st = exclusive_scan_u32(dflag, sidx, dense, &cnt[2], sws, s)) != RGS_OK) return st;
+    hipLaunchKernelGGL(k_slot_compact, grid(dense), dim3(BN_THREADS), 0, s, dstart, dend, sidx, dense, bins->slot_key,
+                       bins->slot_range);
+    hipLaunchKernelGGL(k_tile_slots, grid(total_tiles + 1), dim3(BN_THREADS), 0, s, sidx, total_tiles, 1 << L, &cnt[2],
+                       bins->tile_slot);
+    return launch_check();
+}
+
+}  // namespace rgs

@@ -1,0 +1,141 @@
+// common.hpp -- shared device definitions of librgs (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rgs.h"
+
+#define RGS_MAXK 64
+
+// Per-view constants used by every kernel, uploaded once per call batch.
+struct ViewParams {
+    float R[9];          // world -> camera rotation, row-major
+    float t[3];
+    float o[3];          // camera centre
+    float fx, fy, cx, cy;
+    float gx, gy;        // guard of the EWA Jacobian: |x/z| <= gx, |y/z| <= gy
+    float znear;
+    float bg[3];
+    int32_t W, H, tiles_x, tiles_y;
+    uint32_t tile_offset;   // first global tile of this view
+    uint32_t pix_offset;    // first pixel of this view in concatenated [H][W] maps
+    uint8_t cell_of_rank[RGS_MAXK];
+    uint8_t rank_of_cell[RGS_MAXK];
+};
+
+struct ViewTable {
+    int32_t n_views;
+    int32_t L;
+    uint32_t total_tiles;
+    uint32_t pad;
+    ViewParams v[RGS_MAX_VIEWS];
+};
+
+// Which view owns global tile gt (views are few; linear scan, uniform per wave).
+__device__ __forceinline__ int view_of_tile(const ViewTable* __restrict__ vt, uint32_t gt) {
+    int v = 0;
+    for (int k = 1; k < vt->n_views; ++k)
+        if (gt >= vt->v[k].tile_offset) v = k;
+    return v;
+}
+
+// IEEE total-order key of a non-NaN float (larger key <=> larger value, -0 < +0).
+__device__ __forceinline__ uint32_t f2key(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key2f(uint32_t k) {
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Wave64 sum reduction with DPP row operations; the total lands in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xb1, 0xf, 0xf, false)); // quad_perm [1,0,3,2]
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4e, 0xf, 0xf, false)); // quad_perm [2,3,0,1]
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x124, 0xf, 0xf, false)); // row_ror:4
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128, 0xf, 0xf, false)); // row_ror:8
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xa, 0xf, false)); // row_bcast:15
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xc, 0xf, false)); // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    v = wave_sum_to_lane63(v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// Inclusive wave64 scan of u32 (shuffle based).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint32_t u = __shfl_xor(v, d, 64);
+        v = v > u ? v : u;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------ host side
+namespace rgs {
+void set_hip_error(hipError_t e);
+rgs_status launch_check();
+}  // namespace rgs
+
+#define RGS_LAUNCH_CHECK()                        \
+    do {                                          \
+        rgs_status _s = rgs::launch_check();      \
+        if (_s != RGS_OK) return _s;              \
+    } while (0)
+
+#define RGS_HIP_CHECK(expr)                       \
+    do {                                          \
+        hipError_t _e = (expr);                   \
+        if (_e != hipSuccess) {                   \
+            rgs::set_hip_error(_e);               \
+            return RGS_E_HIP;                     \
+        }                                         \
+    } while (0)
+
+// Workspace carving: 256-byte aligned sub-buffers.
+struct WsCarver {
+    char* base;
+    size_t used;
+    size_t cap;
+    template <typename T>
+    T* take(size_t count) {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + count * sizeof(T);
+        return base ? reinterpret_cast<T*>(base + off) : nullptr;
+    }
+    bool ok() const { return used <= cap; }
+};
+
+// Device-wide primitives (sort.hip).
+namespace rgs {
+size_t scan_ws_bytes(int64_t n);
+// out[i] = sum_{j<i} in[j]; if total != nullptr, *total (device) = sum of all.
+rgs_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* ws,
+                              hipStream_t s);
+size_t radix_ws_bytes(int64_t n);
+// Stable LSD sort of (key, value) by key bits [0, bits); the result ends in
+// keys/vals (the alt buffers are scratch of the same size).
+rgs_status radix_sort_u32_u64(uint32_t* keys, uint64_t* vals, uint32_t* keys_alt, uint64_t* vals_alt,
+                              int64_t n, int bits, void* ws, hipStream_t s);
+rgs_status radix_sort_u32_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                              int64_t n, int bits, void* ws, hipStream_t s);
+// The same, with n read on the device (upper bound n_max for the grid).
+rgs_status radix_sort_u32_u32_dev(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                                  const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s);
+}  // namespace rgs

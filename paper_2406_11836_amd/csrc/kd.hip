@@ -1,0 +1,211 @@
+// kd.hip -- KD-tree partition of the Gaussian centres (RetinaGS Sec. 3.3).
+//
+// Level by level, every node's split is the floor(n/2)-th smallest centre
+// coordinate (IEEE total order) on axis depth mod 3, found exactly by a radix
+// select over the 32 key bits, 8 bits per pass: each pass histograms the
+// digit of the members still matching the selected prefix, per node, and one
+// thread per node picks the digit holding the target rank.  Members are then
+// moved to the child (coordinate < split: left).  Leaf boxes are the
+// intersections of the half-spaces along each root-to-leaf path.
+#include "common.hpp"
+
+namespace rgs {
+
+static constexpr int KD_THREADS = 256;
+
+struct KdState {        // per node of the current level
+    uint32_t prefix;    // selected high bits of the split key
+    uint32_t mask;      // which bits are selected
+    uint32_t k;         // rank still to find among members matching prefix
+    uint32_t n;         // members of the node
+};
+
+__global__ __launch_bounds__(KD_THREADS) void k_kd_init(int32_t* __restrict__ node, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * KD_THREADS + threadIdx.x;
+    if (i < n) node[i] = 0;
+}
+
+// hist[(node - first) * 256 + digit] over members whose key matches the node's prefix.
+__global__ __launch_bounds__(KD_THREADS) void k_kd_hist(const float* __restrict__ coord, const int32_t* __restrict__ node,
+                                                        int64_t n, int first, int cnt, const KdState* __restrict__ st,
+                                                        int shift, uint32_t* __restrict__ hist) {
+    extern __shared__ uint32_t s_h[];  // [cnt][256]
+    for (int k = threadIdx.x; k < cnt * 256; k += KD_THREADS) s_h[k] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * KD_THREADS;
+    for (int64_t i = (int64_t)blockIdx.x * KD_THREADS + threadIdx.x; i < n; i += stride) {
+        const int nd = node[i] - first;
+        const uint32_t key = f2key(coord[i]);
+        const KdState s = st[nd];
+        if ((key & s.mask) == s.prefix) atomicAdd(&s_h[nd * 256 + ((key >> shift) & 0xffu)], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < cnt * 256; k += KD_THREADS)
+        if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
+}
+
+__global__ void k_kd_state_init(KdState* __restrict__ st, int cnt) {
+    int t = threadIdx.x;
+    if (t < cnt) st[t] = KdState{0u, 0u, 0u, 0u};
+}
+
+__global__ void k_kd_zero(uint32_t* __restrict__ p, int m) {
+    for (int k = threadIdx.x + blockIdx.x * blockDim.x; k < m; k += blockDim.x * gridDim.x) p[k] = 0;
+}
+
+// One thread per node: pick the digit containing rank k.
+__global__ void k_kd_select(KdState* __restrict__ st, const uint32_t* __restrict__ hist, int cnt, int shift, int pass) {
+    int t = threadIdx.x;
+    if (t >= cnt) return;
+    KdState s = st[t];
+    const uint32_t* h = hist + t * 256;
+    if (pass == 0) {
+        uint32_t tot = 0;
+        for (int d = 0; d < 256; ++d) tot += h[d];
+        s.n = tot;
+        s.k = tot / 2;
+    }
+    if (s.n == 0) { st[t] = s; return; }
+    uint32_t cum = 0;
+    int dsel = 255;
+    for (int d = 0; d < 256; ++d) {
+        if (cum + h[d] > s.k) { dsel = d; break; }
+        cum += h[d];
+    }
+    s.k -= cum;
+    s.prefix |= (uint32_t)dsel << shift;
+    s.mask |= 0xffu << shift;
+    st[t] = s;
+}
+
+// Node bounds along the path (for empty nodes) and the split value.
+__global__ void k_kd_finish_level(const KdState* __restrict__ st, float* __restrict__ split, int first, int cnt,
+                                  int level) {
+    int t = threadIdx.x;
+    if (t >= cnt) return;
+    const int nd = first + t;
+    const int a = level % 3;
+    float s;
+    if (st[t].n > 0) {
+        s = key2f(st[t].prefix);
+    } else {
+        float lo = -INFINITY, hi = INFINITY;
+        int c = nd, d = level;
+        while (c > 0) {
+            int p = (c - 1) >> 1;
+            --d;
+            if (d % 3 == a) {
+                if (c == 2 * p + 1) { if (split[p] < hi) hi = split[p]; }
+                else { if (split[p] > lo) lo = split[p]; }
+            }
+            c = p;
+        }
+        if (isfinite(lo) && isfinite(hi)) s = 0.5f * (lo + hi);
+        else if (isfinite(lo)) s = lo;
+        else if (isfinite(hi)) s = hi;
+        else s = 0.0f;
+    }
+    split[nd] = s;
+}
+
+__global__ __launch_bounds__(KD_THREADS) void k_kd_assign(const float* __restrict__ coord, int32_t* __restrict__ node,
+                                                          int64_t n, const float* __restrict__ split) {
+    int64_t i = (int64_t)blockIdx.x * KD_THREADS + threadIdx.x;
+    if (i >= n) return;
+    const int nd = node[i];
+    node[i] = (coord[i] < split[nd]) ? 2 * nd + 1 : 2 * nd + 2;
+}
+
+__global__ void k_kd_boxes(const float* __restrict__ split, int L, float* __restrict__ lo, float* __restrict__ hi,
+                           int32_t* __restrict__ counts) {
+    const int K = 1 << L;
+    int k = threadIdx.x;
+    if (k >= K) return;
+    float l[3] = {-INFINITY, -INFINITY, -INFINITY}, h[3] = {INFINITY, INFINITY, INFINITY};
+    int nd = 0;
+    for (int d = 0; d < L; ++d) {
+        const int a = d % 3;
+        const int right = (k >> (L - 1 - d)) & 1;
+        if (right) { l[a] = split[nd]; nd = 2 * nd + 2; }
+        else { h[a] = split[nd]; nd = 2 * nd + 1; }
+    }
+    for (int a = 0; a < 3; ++a) {
+        lo[a * K + k] = l[a];
+        hi[a * K + k] = h[a];
+    }
+    counts[k] = 0;
+}
+
+__global__ __launch_bounds__(KD_THREADS) void k_kd_leaves(const int32_t* __restrict__ node, int64_t n, int L,
+                                                          const float* __restrict__ means,
+                                                          const float* __restrict__ log_scales, float d_factor,
+                                                          const float* __restrict__ lo, const float* __restrict__ hi,
+                                                          int32_t* __restrict__ center_cell, int32_t* __restrict__ counts,
+                                                          uint32_t* __restrict__ own_mask) {
+    int64_t i = (int64_t)blockIdx.x * KD_THREADS + threadIdx.x;
+    if (i >= n) return;
+    const int K = 1 << L;
+    const int leaf = node[i] - (K - 1);
+    center_cell[i] = leaf;
+    atomicAdd(&counts[leaf], 1);
+    if (!own_mask) return;
+    // D_i = d_factor * max scale; transcendental in fp64, rounded once
+    const float s0 = (float)exp((double)log_scales[i]);
+    const float s1 = (float)exp((double)log_scales[n + i]);
+    const float s2 = (float)exp((double)log_scales[2 * n + i]);
+    const float Di = d_factor * fmaxf(fmaxf(s0, s1), s2);
+    const int Wm = (K + 31) / 32;
+    uint32_t m[2] = {0u, 0u};
+    const float u[3] = {means[i], means[n + i], means[2 * n + i]};
+    for (int k = 0; k < K; ++k) {
+        bool in = true;
+        for (int a = 0; a < 3; ++a) {
+            if (!((lo[a * K + k] - u[a]) <= Di)) in = false;
+            if (!((u[a] - hi[a * K + k]) <= Di)) in = false;
+        }
+        if (in) m[k >> 5] |= 1u << (k & 31);
+    }
+    for (int w = 0; w < Wm; ++w) own_mask[i * Wm + w] = m[w];
+}
+
+size_t kd_ws_bytes(int64_t n, int L) {
+    const int K = 1 << L;
+    return (size_t)n * sizeof(int32_t) + 256 + (size_t)K * 256 * sizeof(uint32_t) + 256 + (size_t)K * sizeof(KdState) + 256;
+}
+
+rgs_status kd_partition(const rgs_gaussians* g, int L, float d_factor, const rgs_kdtree* kd, void* ws, hipStream_t s) {
+    const int64_t n = g->n;
+    const int K = 1 << L;
+    WsCarver c{reinterpret_cast<char*>(ws), 0, (size_t)-1};
+    int32_t* node = c.take<int32_t>(n > 0 ? n : 1);
+    uint32_t* hist = c.take<uint32_t>((size_t)K * 256);
+    KdState* st = c.take<KdState>(K);
+    const unsigned gridN = (unsigned)((n + KD_THREADS - 1) / KD_THREADS);
+    if (n > 0) hipLaunchKernelGGL(k_kd_init, dim3(gridN), dim3(KD_THREADS), 0, s, node, n);
+    int hist_blocks = (int)((n + KD_THREADS * 16 - 1) / (KD_THREADS * 16));
+    if (hist_blocks < 1) hist_blocks = 1;
+    if (hist_blocks > 4096) hist_blocks = 4096;
+    for (int l = 0; l < L; ++l) {
+        const int first = (1 << l) - 1, cnt = 1 << l;
+        const float* coord = g->means + (int64_t)(l % 3) * n;
+        hipLaunchKernelGGL(k_kd_state_init, dim3(1), dim3(64), 0, s, st, cnt);
+        for (int p = 0; p < 4; ++p) {
+            const int shift = 24 - 8 * p;
+            hipLaunchKernelGGL(k_kd_zero, dim3(16), dim3(256), 0, s, hist, cnt * 256);
+            if (n > 0)
+                hipLaunchKernelGGL(k_kd_hist, dim3(hist_blocks), dim3(KD_THREADS), cnt * 256 * sizeof(uint32_t), s, coord,
+                                   node, n, first, cnt, st, shift, hist);
+            hipLaunchKernelGGL(k_kd_select, dim3(1), dim3(64), 0, s, st, hist, cnt, shift, p);
+        }
+        hipLaunchKernelGGL(k_kd_finish_level, dim3(1), dim3(64), 0, s, st, kd->split, first, cnt, l);
+        if (n > 0) hipLaunchKernelGGL(k_kd_assign, dim3(gridN), dim3(KD_THREADS), 0, s, coord, node, n, kd->split);
+        RGS_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_kd_boxes, dim3(1), dim3(64), 0, s, kd->split, L, kd->box_lo, kd->box_hi, kd->counts);
+    if (n > 0)
+        hipLaunchKernelGGL(k_kd_leaves, dim3(gridN), dim3(KD_THREADS), 0, s, node, n, L, g->means, g->log_scales, d_factor,
+                           kd->box_lo, kd->box_hi, kd->center_cell, kd->counts, kd->own_mask);
+    return launch_check();
+}
+
+}  // namespace rgs

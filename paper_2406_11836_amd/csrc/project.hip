@@ -1,0 +1,448 @@
+// project.hip -- per-(view, Gaussian) projection, SH colour and cell sets
+// (RetinaGS Sec. 3.1, with the cell sets that Eq. 6 needs), and its backward.
+//
+// One thread per Gaussian loops over the views, so the parameters (up to
+// 59 floats) are read from HBM once per batch of views; loads and the
+// structure-of-arrays stores are coalesced.  The decision path (activations,
+// covariance, EWA, conic, screen mean, tau, rectangle, cell set) is written
+// as single IEEE binary32 operations in a fixed order with no contraction;
+// its transcendentals are computed in fp64 and rounded once, so the integer
+// outputs (rectangle, cell set, count) are reproducible on any IEEE machine.
+#include "common.hpp"
+
+namespace rgs {
+
+static constexpr int PJ_THREADS = 256;
+
+// Real SH basis (degree <= 3) in polynomial form on the unit sphere, with the
+// Condon-Shortley phase; index j = l^2 + l + m.
+__device__ __forceinline__ void sh_eval(int D, float x, float y, float z, float* Y) {
+    Y[0] = 0.28209479177387814f;
+    if (D < 1) return;
+    Y[1] = -0.4886025119029199f * y;
+    Y[2] = 0.4886025119029199f * z;
+    Y[3] = -0.4886025119029199f * x;
+    if (D < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, yz = y * z, xz = x * z;
+    Y[4] = 1.0925484305920792f * xy;
+    Y[5] = -1.0925484305920792f * yz;
+    Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+    Y[7] = -1.0925484305920792f * xz;
+    Y[8] = 0.5462742152960396f * (xx - yy);
+    if (D < 3) return;
+    Y[9] = -0.5900435899266435f * y * (3.0f * xx - yy);
+    Y[10] = 2.890611442640554f * xy * z;
+    Y[11] = -0.4570457994644658f * y * (4.0f * zz - xx - yy);
+    Y[12] = 0.3731763325901154f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -0.4570457994644658f * x * (4.0f * zz - xx - yy);
+    Y[14] = 1.445305721320277f * z * (xx - yy);
+    Y[15] = -0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+// Gradient of the polynomial forms above w.r.t. (x, y, z).
+__device__ __forceinline__ void sh_grad(int D, float x, float y, float z, float (*G)[3]) {
+    G[0][0] = G[0][1] = G[0][2] = 0.f;
+    if (D < 1) return;
+    const float c1 = 0.4886025119029199f;
+    G[1][0] = 0.f; G[1][1] = -c1; G[1][2] = 0.f;
+    G[2][0] = 0.f; G[2][1] = 0.f; G[2][2] = c1;
+    G[3][0] = -c1; G[3][1] = 0.f; G[3][2] = 0.f;
+    if (D < 2) return;
+    const float a = 1.0925484305920792f, b = 0.31539156525252005f, c = 0.5462742152960396f;
+    G[4][0] = a * y; G[4][1] = a * x; G[4][2] = 0.f;
+    G[5][0] = 0.f; G[5][1] = -a * z; G[5][2] = -a * y;
+    G[6][0] = -2.f * b * x; G[6][1] = -2.f * b * y; G[6][2] = 4.f * b * z;
+    G[7][0] = -a * z; G[7][1] = 0.f; G[7][2] = -a * x;
+    G[8][0] = 2.f * c * x; G[8][1] = -2.f * c * y; G[8][2] = 0.f;
+    if (D < 3) return;
+    const float k0 = -0.5900435899266435f, k1 = 2.890611442640554f, k2 = -0.4570457994644658f,
+                k3 = 0.3731763325901154f, k5 = 1.445305721320277f;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    // y (3x^2 - y^2)
+    G[9][0] = k0 * 6.f * x * y; G[9][1] = k0 * (3.f * xx - 3.f * yy); G[9][2] = 0.f;
+    // x y z
+    G[10][0] = k1 * y * z; G[10][1] = k1 * x * z; G[10][2] = k1 * x * y;
+    // y (4z^2 - x^2 - y^2)
+    G[11][0] = k2 * (-2.f * x * y); G[11][1] = k2 * (4.f * zz - xx - 3.f * yy); G[11][2] = k2 * 8.f * y * z;
+    // z (2z^2 - 3x^2 - 3y^2)
+    G[12][0] = k3 * (-6.f * x * z); G[12][1] = k3 * (-6.f * y * z); G[12][2] = k3 * (6.f * zz - 3.f * xx - 3.f * yy);
+    // x (4z^2 - x^2 - y^2)
+    G[13][0] = k2 * (4.f * zz - 3.f * xx - yy); G[13][1] = k2 * (-2.f * x * y); G[13][2] = k2 * 8.f * x * z;
+    // z (x^2 - y^2)
+    G[14][0] = k5 * 2.f * x * z; G[14][1] = k5 * (-2.f * y * z); G[14][2] = k5 * (xx - yy);
+    // x (x^2 - 3y^2)
+    G[15][0] = k0 * (3.f * xx - 3.f * yy); G[15][1] = k0 * (-6.f * x * y); G[15][2] = 0.f;
+}
+
+struct Proj32 {
+    float mx, my, ca, cb, cc, tau, z, alpha, s00, s11;
+    bool vis;
+};
+
+// The fixed-order fp32 decision path (see the file comment).
+__device__ __forceinline__ void proj32(float mu0, float mu1, float mu2, float ls0, float ls1, float ls2, float qw,
+                                       float qx, float qy, float qz, float logit, const ViewParams& V, Proj32& p) {
+    p.vis = false;
+    const float s0 = (float)exp((double)ls0), s1 = (float)exp((double)ls1), s2 = (float)exp((double)ls2);
+    const float alpha = (float)(1.0 / (1.0 + exp(-(double)logit)));
+    const float qq = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    if (!(qq > 0.0f)) return;
+    const float qn = sqrtf(qq);
+    const float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+    float r[3][3];
+    r[0][0] = 1.0f - 2.0f * (y * y + z * z);
+    r[0][1] = 2.0f * (x * y - w * z);
+    r[0][2] = 2.0f * (x * z + w * y);
+    r[1][0] = 2.0f * (x * y + w * z);
+    r[1][1] = 1.0f - 2.0f * (x * x + z * z);
+    r[1][2] = 2.0f * (y * z - w * x);
+    r[2][0] = 2.0f * (x * z - w * y);
+    r[2][1] = 2.0f * (y * z + w * x);
+    r[2][2] = 1.0f - 2.0f * (x * x + y * y);
+    const float sc[3] = {s0, s1, s2};
+    float M[3][3], S[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) M[a][b] = r[a][b] * sc[b];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) S[a][b] = (M[a][0] * M[b][0] + M[a][1] * M[b][1]) + M[a][2] * M[b][2];
+    float tc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) tc[a] = ((V.R[3 * a] * mu0 + V.R[3 * a + 1] * mu1) + V.R[3 * a + 2] * mu2) + V.t[a];
+    const float zc = tc[2];
+    if (!(zc > V.znear)) return;
+    const float xz = tc[0] / zc, yz = tc[1] / zc;
+    const float xg = fminf(fmaxf(xz, -V.gx), V.gx) * zc;
+    const float yg = fminf(fmaxf(yz, -V.gy), V.gy) * zc;
+    const float zz = zc * zc;
+    const float J00 = V.fx / zc, J02 = -(V.fx * xg) / zz, J11 = V.fy / zc, J12 = -(V.fy * yg) / zz;
+    float T[2][3], U[2][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        T[0][b] = J00 * V.R[b] + J02 * V.R[6 + b];
+        T[1][b] = J11 * V.R[3 + b] + J12 * V.R[6 + b];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) U[a][b] = (T[a][0] * S[0][b] + T[a][1] * S[1][b]) + T[a][2] * S[2][b];
+    const float s00 = ((U[0][0] * T[0][0] + U[0][1] * T[0][1]) + U[0][2] * T[0][2]) + 0.3f;
+    const float s01 = (U[0][0] * T[1][0] + U[0][1] * T[1][1]) + U[0][2] * T[1][2];
+    const float s11 = ((U[1][0] * T[1][0] + U[1][1] * T[1][1]) + U[1][2] * T[1][2]) + 0.3f;
+    const float det = s00 * s11 - s01 * s01;
+    if (!(det > 0.0f)) return;
+    p.ca = s11 / det;
+    p.cb = -s01 / det;
+    p.cc = s00 / det;
+    p.mx = V.fx * xz + V.cx;
+    p.my = V.fy * yz + V.cy;
+    p.z = zc;
+    p.alpha = alpha;
+    p.s00 = s00;
+    p.s11 = s11;
+    const float tau = fminf(9.0f, (float)(2.0 * log(255.0 * (double)alpha)));
+    p.tau = tau;
+    if (!(tau >= 0.0f)) return;
+    if (!(isfinite(p.mx) && isfinite(p.my))) return;
+    p.vis = true;
+}
+
+// Sample-pixel rectangle of the footprint d^2 <= tau (padded against rounding).
+__device__ __forceinline__ bool rect32(const Proj32& p, const ViewParams& V, int r[4]) {
+    const float ex = sqrtf(p.tau * p.s00) * 1.00001f + 1e-3f;
+    const float ey = sqrtf(p.tau * p.s11) * 1.00001f + 1e-3f;
+    const float xlo = fmaxf(ceilf((p.mx - ex) - 0.5f), 0.0f);
+    const float xhi = fminf(floorf((p.mx + ex) - 0.5f), (float)(V.W - 1));
+    const float ylo = fmaxf(ceilf((p.my - ey) - 0.5f), 0.0f);
+    const float yhi = fminf(floorf((p.my + ey) - 0.5f), (float)(V.H - 1));
+    if (!(xlo <= xhi) || !(ylo <= yhi)) return false;
+    r[0] = (int)xlo; r[1] = (int)xhi; r[2] = (int)ylo; r[3] = (int)yhi;
+    return true;
+}
+
+// KD leaves met by the padded box of the crossing points x(p) = o + z D(p)
+// over the rectangle's four corner samples (x(p) is affine in the pixel).
+__device__ __forceinline__ uint64_t cellset32(const Proj32& p, const int r[4], const ViewParams& V, int L,
+                                              const float* __restrict__ split) {
+    if (L == 0) return 1ull;
+    const float u0 = (float)r[0] + 0.5f, u1 = (float)r[1] + 0.5f;
+    const float v0 = (float)r[2] + 0.5f, v1 = (float)r[3] + 0.5f;
+    const float dx[2] = {(u0 - V.cx) / V.fx, (u1 - V.cx) / V.fx};
+    const float dy[2] = {(v0 - V.cy) / V.fy, (v1 - V.cy) / V.fy};
+    float lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float oa = V.o[a];
+        float mn = INFINITY, mxv = -INFINITY;
+#pragma unroll
+        for (int jy = 0; jy < 2; ++jy)
+#pragma unroll
+            for (int jx = 0; jx < 2; ++jx) {
+                const float Da = (V.R[a] * dx[jx] + V.R[3 + a] * dy[jy]) + V.R[6 + a];
+                const float xa = fmaf(p.z, Da, oa);
+                mn = fminf(mn, xa);
+                mxv = fmaxf(mxv, xa);
+            }
+        const float mdx = fmaxf(fabsf(dx[0]), fabsf(dx[1])), mdy = fmaxf(fabsf(dy[0]), fabsf(dy[1]));
+        const float pad = 0x1p-16f * (fabsf(oa) + p.z * ((fabsf(V.R[a]) * mdx + fabsf(V.R[3 + a]) * mdy) + fabsf(V.R[6 + a])));
+        lo[a] = mn - pad;
+        hi[a] = mxv + pad;
+    }
+    // iterative traversal of the heap-ordered tree
+    uint64_t mask = 0;
+    int stack[RGS_MAX_L + 2];
+    int sp = 0;
+    stack[sp++] = 0;
+    const int K = 1 << L;
+    while (sp > 0) {
+        const int nd = stack[--sp];
+        if (nd >= K - 1) { mask |= 1ull << (nd - (K - 1)); continue; }
+        int depth = 31 - __clz(nd + 1);
+        const int a = depth % 3;
+        const float s = split[nd];
+        // push right first so that left is visited first (order is irrelevant for the mask)
+        if (hi[a] >= s) stack[sp++] = 2 * nd + 2;
+        if (lo[a] < s) stack[sp++] = 2 * nd + 1;
+    }
+    return mask;
+}
+
+__global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const ViewTable* __restrict__ vt,
+                                                        const float* __restrict__ split, rgs_projected out) {
+    const int64_t n = g.n;
+    const int64_t i = (int64_t)blockIdx.x * PJ_THREADS + threadIdx.x;
+    if (i >= n) return;
+    const int D = g.sh_degree;
+    const int nc = (D + 1) * (D + 1);
+    const float mu0 = g.means[i], mu1 = g.means[n + i], mu2 = g.means[2 * n + i];
+    const float ls0 = g.log_scales[i], ls1 = g.log_scales[n + i], ls2 = g.log_scales[2 * n + i];
+    const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
+    const float logit = g.opacity[i];
+    float f[48];
+    for (int k = 0; k < 3 * nc; ++k) f[k] = g.sh[(int64_t)k * n + i];
+    const int L = vt->L;
+    for (int v = 0; v < vt->n_views; ++v) {
+        const ViewParams& V = vt->v[v];
+        const int64_t src = (int64_t)v * n + i;
+        Proj32 p;
+        proj32(mu0, mu1, mu2, ls0, ls1, ls2, qw, qx, qy, qz, logit, V, p);
+        int r[4] = {0, 0, 0, 0};
+        bool ok = p.vis && rect32(p, V, r);
+        float4* rec = reinterpret_cast<float4*>(out.rec + src * RGS_REC_FLOATS);
+        if (!ok) {
+            out.count[src] = 0u;
+            out.cellmask[src] = 0ull;
+            reinterpret_cast<uint2*>(out.rect)[src] = make_uint2(0u, 0u);
+            rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            continue;
+        }
+        const uint64_t mask = cellset32(p, r, V, L, split);
+        const uint32_t ntx = (uint32_t)((r[1] >> 4) - (r[0] >> 4) + 1);
+        const uint32_t nty = (uint32_t)((r[3] >> 4) - (r[2] >> 4) + 1);
+        out.count[src] = (uint32_t)__popcll(mask) * ntx * nty;
+        out.cellmask[src] = mask;
+        const uint32_t rx = ((uint32_t)(uint16_t)r[0]) | ((uint32_t)(uint16_t)r[1] << 16);
+        const uint32_t ry = ((uint32_t)(uint16_t)r[2]) | ((uint32_t)(uint16_t)r[3] << 16);
+        reinterpret_cast<uint2*>(out.rect)[src] = make_uint2(rx, ry);
+        // colour from the view direction (value path)
+        float dx = mu0 - V.o[0], dy = mu1 - V.o[1], dz = mu2 - V.o[2];
+        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= inv; dy *= inv; dz *= inv;
+        float Y[16];
+        sh_eval(D, dx, dy, dz, Y);
+        float col[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.5f;
+            for (int j = 0; j < nc; ++j) acc = fmaf(f[3 * j + ch], Y[j], acc);
+            col[ch] = fmaxf(acc, 0.0f);
+        }
+        const uint32_t flags = (__popcll(mask) == 1) ? 1u : 0u;
+        rec[0] = make_float4(p.mx, p.my, p.ca, p.cb);
+        rec[1] = make_float4(p.cc, p.alpha, p.tau, p.z);
+        rec[2] = make_float4(col[0], col[1], col[2], __uint_as_float(flags));
+    }
+}
+
+rgs_status project_launch(const rgs_gaussians* g, const ViewTable* vt, const float* split,
+                          const rgs_projected* out, hipStream_t s) {
+    if (g->n <= 0) return RGS_OK;
+    const unsigned grid = (unsigned)((g->n + PJ_THREADS - 1) / PJ_THREADS);
+    hipLaunchKernelGGL(k_project, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, *out);
+    return launch_check();
+}
+
+// ------------------------------------------------------------------ backward
+// Recomputes the forward in fp32 and applies the chain rule; gradients of
+// the views are summed in registers and written once per parameter.
+__global__ __launch_bounds__(PJ_THREADS) void k_project_bwd(const float* __restrict__ dproj, rgs_gaussians g,
+                                                            const uint32_t* __restrict__ count,
+                                                            const ViewTable* __restrict__ vt, rgs_gaussians_grad out) {
+    const int64_t n = g.n;
+    const int64_t i = (int64_t)blockIdx.x * PJ_THREADS + threadIdx.x;
+    if (i >= n) return;
+    const int D = g.sh_degree;
+    const int nc = (D + 1) * (D + 1);
+    const int64_t VN = (int64_t)vt->n_views * n;
+    const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
+    const float ls[3] = {g.log_scales[i], g.log_scales[n + i], g.log_scales[2 * n + i]};
+    const float q4[4] = {g.quats[i], g.quats[n + i], g.quats[2 * n + i], g.quats[3 * n + i]};
+    const float logit = g.opacity[i];
+    float gmu[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, gop = 0.f;
+    float gsh[48];
+    for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+
+    // view-independent quantities
+    const float s[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
+    const float alpha = 1.0f / (1.0f + expf(-logit));
+    const float qn = sqrtf(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
+    const float w = q4[0] / qn, x = q4[1] / qn, y = q4[2] / qn, z = q4[3] / qn;
+    const float Rq[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
+                            {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
+                            {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+    float M[3][3], S[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[a][b] = Rq[a][b] * s[b];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) S[a][b] = M[a][0] * M[b][0] + M[a][1] * M[b][1] + M[a][2] * M[b][2];
+    float GS[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    bool any = false;
+
+    for (int v = 0; v < vt->n_views; ++v) {
+        const int64_t src = (int64_t)v * n + i;
+        if (count[src] == 0u) continue;
+        any = true;
+        const ViewParams& V = vt->v[v];
+        float gd[9];
+        for (int c = 0; c < 9; ++c) gd[c] = dproj[c * VN + src];
+        float t[3];
+        for (int a = 0; a < 3; ++a) t[a] = V.R[3 * a] * mu[0] + V.R[3 * a + 1] * mu[1] + V.R[3 * a + 2] * mu[2] + V.t[a];
+        const float zc = t[2];
+        const float xz = t[0] / zc, yz = t[1] / zc;
+        const int clx = (xz < -V.gx) ? -1 : (xz > V.gx ? 1 : 0);
+        const int cly = (yz < -V.gy) ? -1 : (yz > V.gy ? 1 : 0);
+        const float xg = clx ? (float)clx * V.gx * zc : t[0];
+        const float yg = cly ? (float)cly * V.gy * zc : t[1];
+        const float iz = 1.0f / zc, iz2 = iz * iz;
+        const float J00 = V.fx * iz, J02 = -V.fx * xg * iz2, J11 = V.fy * iz, J12 = -V.fy * yg * iz2;
+        float T[2][3];
+        for (int b = 0; b < 3; ++b) {
+            T[0][b] = J00 * V.R[b] + J02 * V.R[6 + b];
+            T[1][b] = J11 * V.R[3 + b] + J12 * V.R[6 + b];
+        }
+        float TS[2][3];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b) TS[a][b] = T[a][0] * S[0][b] + T[a][1] * S[1][b] + T[a][2] * S[2][b];
+        const float a00 = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + 0.3f;
+        const float a01 = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
+        const float a11 = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + 0.3f;
+        const float det = a00 * a11 - a01 * a01;
+        const float idet = 1.0f / det;
+        const float Cn[2][2] = {{a11 * idet, -a01 * idet}, {-a01 * idet, a00 * idet}};
+        // conic -> screen covariance: G_S2 = -Cn G_C Cn, G_C = [[ga, gb/2], [gb/2, gc]]
+        const float GC[2][2] = {{gd[2], 0.5f * gd[3]}, {0.5f * gd[3], gd[4]}};
+        float tmp[2][2], GS2[2][2];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) tmp[a][b] = Cn[a][0] * GC[0][b] + Cn[a][1] * GC[1][b];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) GS2[a][b] = -(tmp[a][0] * Cn[0][b] + tmp[a][1] * Cn[1][b]);
+        // S2 = T S T^T: G_T = 2 G_S2 T S ; G_S += T^T G_S2 T
+        float GT[2][3];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 3; ++b) GT[a][b] = 2.f * (GS2[a][0] * TS[0][b] + GS2[a][1] * TS[1][b]);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                GS[a][b] += T[0][a] * (GS2[0][0] * T[0][b] + GS2[0][1] * T[1][b]) +
+                            T[1][a] * (GS2[1][0] * T[0][b] + GS2[1][1] * T[1][b]);
+        // T = J R: G_J = G_T R^T (only the four non-zero entries of J vary)
+        float GJ00 = 0.f, GJ02 = 0.f, GJ11 = 0.f, GJ12 = 0.f;
+        for (int b = 0; b < 3; ++b) {
+            GJ00 += GT[0][b] * V.R[b];
+            GJ02 += GT[0][b] * V.R[6 + b];
+            GJ11 += GT[1][b] * V.R[3 + b];
+            GJ12 += GT[1][b] * V.R[6 + b];
+        }
+        float gt[3] = {0.f, 0.f, 0.f};
+        const float iz3 = iz2 * iz;
+        gt[2] += -GJ00 * V.fx * iz2 - GJ11 * V.fy * iz2;
+        gt[2] += GJ02 * 2.f * V.fx * xg * iz3 + GJ12 * 2.f * V.fy * yg * iz3;
+        const float gxg = -GJ02 * V.fx * iz2, gyg = -GJ12 * V.fy * iz2;
+        if (clx) gt[2] += gxg * (float)clx * V.gx; else gt[0] += gxg;
+        if (cly) gt[2] += gyg * (float)cly * V.gy; else gt[1] += gyg;
+        // screen mean mx = fx t.x / z + cx
+        gt[0] += gd[0] * V.fx * iz;
+        gt[2] += -gd[0] * V.fx * t[0] * iz2;
+        gt[1] += gd[1] * V.fy * iz;
+        gt[2] += -gd[1] * V.fy * t[1] * iz2;
+        for (int a = 0; a < 3; ++a) gmu[a] += V.R[a] * gt[0] + V.R[3 + a] * gt[1] + V.R[6 + a] * gt[2];
+        // colour
+        float d[3] = {mu[0] - V.o[0], mu[1] - V.o[1], mu[2] - V.o[2]};
+        const float dn = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const float idn = 1.0f / dn;
+        const float dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
+        float Y[16], GY[16][3];
+        sh_eval(D, dir[0], dir[1], dir[2], Y);
+        sh_grad(D, dir[0], dir[1], dir[2], GY);
+        float gdir[3] = {0.f, 0.f, 0.f};
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.5f;
+            for (int j = 0; j < nc; ++j) acc = fmaf(g.sh[(int64_t)(3 * j + ch) * n + i], Y[j], acc);
+            if (!(acc > 0.f)) continue;
+            const float gc = gd[6 + ch];
+            for (int j = 0; j < nc; ++j) {
+                gsh[3 * j + ch] += Y[j] * gc;
+                const float fj = g.sh[(int64_t)(3 * j + ch) * n + i];
+                gdir[0] += fj * GY[j][0] * gc;
+                gdir[1] += fj * GY[j][1] * gc;
+                gdir[2] += fj * GY[j][2] * gc;
+            }
+        }
+        const float dg = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
+        for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - dir[a] * dg) * idn;
+        gop += gd[5] * alpha * (1.f - alpha);
+    }
+    if (any) {
+        // S = M M^T: G_M = 2 G_S M; M = Rq diag(s)
+        float GM[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) GM[a][b] = 2.f * (GS[a][0] * M[0][b] + GS[a][1] * M[1][b] + GS[a][2] * M[2][b]);
+        float GR[3][3];
+        for (int b = 0; b < 3; ++b) {
+            float gs = 0.f;
+            for (int a = 0; a < 3; ++a) { gs += GM[a][b] * Rq[a][b]; GR[a][b] = GM[a][b] * s[b]; }
+            gls[b] = gs * s[b];
+        }
+        float gw = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        gy += GR[0][0] * (-4.f * y); gz += GR[0][0] * (-4.f * z);
+        gw += GR[0][1] * (-2.f * z); gx += GR[0][1] * (2.f * y); gy += GR[0][1] * (2.f * x); gz += GR[0][1] * (-2.f * w);
+        gw += GR[0][2] * (2.f * y); gx += GR[0][2] * (2.f * z); gy += GR[0][2] * (2.f * w); gz += GR[0][2] * (2.f * x);
+        gw += GR[1][0] * (2.f * z); gx += GR[1][0] * (2.f * y); gy += GR[1][0] * (2.f * x); gz += GR[1][0] * (2.f * w);
+        gx += GR[1][1] * (-4.f * x); gz += GR[1][1] * (-4.f * z);
+        gw += GR[1][2] * (-2.f * x); gx += GR[1][2] * (-2.f * w); gy += GR[1][2] * (2.f * z); gz += GR[1][2] * (2.f * y);
+        gw += GR[2][0] * (-2.f * y); gx += GR[2][0] * (2.f * z); gy += GR[2][0] * (-2.f * w); gz += GR[2][0] * (2.f * x);
+        gw += GR[2][1] * (2.f * x); gx += GR[2][1] * (2.f * w); gy += GR[2][1] * (2.f * z); gz += GR[2][1] * (2.f * y);
+        gx += GR[2][2] * (-4.f * x); gy += GR[2][2] * (-4.f * y);
+        const float qh[4] = {w, x, y, z}, gqh[4] = {gw, gx, gy, gz};
+        const float dot = qh[0] * gqh[0] + qh[1] * gqh[1] + qh[2] * gqh[2] + qh[3] * gqh[3];
+        for (int a = 0; a < 4; ++a) gq[a] = (gqh[a] - qh[a] * dot) / qn;
+    }
+    for (int a = 0; a < 3; ++a) { out.means[a * n + i] = gmu[a]; out.log_scales[a * n + i] = gls[a]; }
+    for (int a = 0; a < 4; ++a) out.quats[a * n + i] = gq[a];
+    out.opacity[i] = gop;
+    for (int k = 0; k < 3 * nc; ++k) out.sh[(int64_t)k * n + i] = gsh[k];
+}
+
+rgs_status project_bwd_launch(const float* dproj, const rgs_gaussians* g, const uint32_t* count, const ViewTable* vt,
+                              const rgs_gaussians_grad* out, hipStream_t s) {
+    if (g->n <= 0) return RGS_OK;
+    const unsigned grid = (unsigned)((g->n + PJ_THREADS - 1) / PJ_THREADS);
+    hipLaunchKernelGGL(k_project_bwd, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out);
+    return launch_check();
+}
+
+}  // namespace rgs

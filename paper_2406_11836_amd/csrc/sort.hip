@@ -1,0 +1,283 @@
+// sort.hip -- device-wide exclusive scan and stable LSD radix sort (gfx950).
+//
+// Scan: reduce per 4096-element tile, scan the tile sums in one block, then
+// scan each tile with its offset.  Tiles are staged through LDS so that
+// global loads and stores stay coalesced.
+//
+// Radix sort: 8-bit digits, least significant first.  Per pass a histogram
+// kernel counts digits per 2048-key tile (LDS atomics on integers), the
+// digit-major table [256][tiles] is scanned, and a scatter kernel ranks each
+// key stably inside its tile: every wave walks its strip in order, finds the
+// lanes sharing its digit with eight ballots, and keeps a running count per
+// digit in LDS; keys are then reordered in LDS by digit so that the global
+// writes come out as contiguous runs.
+#include "common.hpp"
+
+namespace rgs {
+
+// ------------------------------------------------------------------ scan
+static constexpr int SCAN_THREADS = 256;
+static constexpr int SCAN_ITEMS = 16;
+static constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+__device__ __forceinline__ int skew(int i) { return i + (i >> 5); }
+
+// Block-wide exclusive scan of one value per thread; returns the block total.
+__device__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* s_wave /*[4]*/, uint32_t* excl) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int k = 0; k < 4; ++k) {
+        uint32_t t = s_wave[k];
+        if (k < w) base += t;
+        tot += t;
+    }
+    *excl = base + inc - v;
+    __syncthreads();
+    return tot;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                              uint32_t* __restrict__ partial) {
+    __shared__ uint32_t s_wave[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t acc = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int64_t i = base + k * SCAN_THREADS + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    uint32_t ex;
+    uint32_t tot = block_excl_scan_256(acc, s_wave, &ex);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the tile sums, in place; total to *total if non-null.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(uint32_t* __restrict__ partial, int64_t m,
+                                                                uint32_t* __restrict__ total) {
+    __shared__ uint32_t s_wave[4];
+    uint32_t carry = 0;
+    for (int64_t b = 0; b < m; b += SCAN_THREADS) {
+        int64_t i = b + threadIdx.x;
+        uint32_t v = i < m ? partial[i] : 0u;
+        uint32_t ex;
+        uint32_t tot = block_excl_scan_256(v, s_wave, &ex);
+        if (i < m) partial[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __restrict__ in, int64_t n,
+                                                             const uint32_t* __restrict__ partial,
+                                                             uint32_t* __restrict__ out) {
+    __shared__ uint32_t s[SCAN_TILE + SCAN_TILE / 32];
+    __shared__ uint32_t s_wave[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int li = k * SCAN_THREADS + threadIdx.x;
+        int64_t i = base + li;
+        s[skew(li)] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[SCAN_ITEMS], acc = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = s[skew(threadIdx.x * SCAN_ITEMS + k)];
+        acc += v[k];
+    }
+    uint32_t ex;
+    block_excl_scan_256(acc, s_wave, &ex);
+    uint32_t run = partial[blockIdx.x] + ex;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        s[skew(threadIdx.x * SCAN_ITEMS + k)] = run;
+        run += v[k];
+    }
+    __syncthreads();
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        int li = k * SCAN_THREADS + threadIdx.x;
+        int64_t i = base + li;
+        if (i < n) out[i] = s[skew(li)];
+    }
+}
+
+size_t scan_ws_bytes(int64_t n) {
+    int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    return (size_t)(tiles + 1) * sizeof(uint32_t) + 256;
+}
+
+rgs_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* ws,
+                              hipStream_t s) {
+    int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    uint32_t* partial = reinterpret_cast<uint32_t*>(ws);
+    if (n <= 0) {
+        if (total) hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, (int64_t)0, total);
+        return launch_check();
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, n, partial);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, tiles, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, n, partial, out);
+    return launch_check();
+}
+
+// ------------------------------------------------------------------ radix sort
+static constexpr int RS_THREADS = 256;
+static constexpr int RS_ITEMS = 8;
+static constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // 2048 keys per block
+static constexpr int RS_WAVE_ITEMS = 64 * RS_ITEMS;    // a wave's strip
+
+__device__ __forceinline__ int64_t rs_n(int64_t n, const uint32_t* n_dev) {
+    return n_dev ? (int64_t)*n_dev : n;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n_host,
+                                                        const uint32_t* __restrict__ n_dev, int shift,
+                                                        uint32_t* __restrict__ hist, int ntiles) {
+    __shared__ uint32_t s_h[256];
+    const int64_t n = rs_n(n_host, n_dev);
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        int64_t i = base + k * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & 0xffu], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = s_h[threadIdx.x];
+}
+
+template <typename V>
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ keys_in,
+                                                           const V* __restrict__ vals_in, int64_t n_host,
+                                                           const uint32_t* __restrict__ n_dev, int shift,
+                                                           const uint32_t* __restrict__ offsets, int ntiles,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           V* __restrict__ vals_out) {
+    __shared__ uint32_t s_cnt[4][256];  // per-wave running digit counts, then wave prefixes
+    __shared__ uint32_t s_dstart[256];  // tile-local start of each digit
+    __shared__ uint32_t s_goff[256];    // global start of each digit for this tile
+    __shared__ uint32_t s_wave[4];
+    __shared__ uint32_t s_keys[RS_TILE];
+    __shared__ V s_vals[RS_TILE];
+
+    const int64_t n = rs_n(n_host, n_dev);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int k = threadIdx.x; k < 4 * 256; k += RS_THREADS) (&s_cnt[0][0])[k] = 0;
+    __syncthreads();
+
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t tile_n = (n - base) < RS_TILE ? (n - base) : RS_TILE;
+    uint32_t key[RS_ITEMS];
+    V val[RS_ITEMS];
+    uint32_t rank[RS_ITEMS];
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        const int64_t i = base + (int64_t)w * RS_WAVE_ITEMS + k * 64 + lane;
+        const bool valid = i < n;
+        key[k] = valid ? keys_in[i] : 0u;
+        val[k] = valid ? vals_in[i] : V(0);
+        const uint32_t d = (key[k] >> shift) & 0xffu;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        uint32_t prior = 0;
+        if (valid) prior = s_cnt[w][d];
+        rank[k] = prior + (uint32_t)__popcll(m & lt_mask);
+        // the highest lane of each digit group publishes the new count
+        if (valid && (m >> lane) == 1ull) s_cnt[w][d] = prior + (uint32_t)__popcll(m);
+        if (!valid) rank[k] = 0xffffffffu;
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        const uint32_t c0 = s_cnt[0][d], c1 = s_cnt[1][d], c2 = s_cnt[2][d], c3 = s_cnt[3][d];
+        s_cnt[0][d] = 0;
+        s_cnt[1][d] = c0;
+        s_cnt[2][d] = c0 + c1;
+        s_cnt[3][d] = c0 + c1 + c2;
+        const uint32_t tot = c0 + c1 + c2 + c3;
+        s_goff[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
+        uint32_t ex;
+        block_excl_scan_256(tot, s_wave, &ex);
+        s_dstart[d] = ex;
+    }
+    __syncthreads();
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        if (rank[k] == 0xffffffffu) continue;
+        const uint32_t d = (key[k] >> shift) & 0xffu;
+        const uint32_t p = s_dstart[d] + s_cnt[w][d] + rank[k];
+        s_keys[p] = key[k];
+        s_vals[p] = val[k];
+    }
+    __syncthreads();
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        const int p = k * RS_THREADS + threadIdx.x;
+        if (p < tile_n) {
+            const uint32_t kk = s_keys[p];
+            const uint32_t d = (kk >> shift) & 0xffu;
+            const uint32_t o = s_goff[d] + ((uint32_t)p - s_dstart[d]);
+            keys_out[o] = kk;
+            vals_out[o] = s_vals[p];
+        }
+    }
+}
+
+size_t radix_ws_bytes(int64_t n) {
+    int64_t tiles = (n + RS_TILE - 1) / RS_TILE;
+    if (tiles < 1) tiles = 1;
+    size_t h = (size_t)256 * tiles * sizeof(uint32_t);
+    return 2 * ((h + 255) & ~size_t(255)) + scan_ws_bytes(256 * tiles) + 512;
+}
+
+template <typename V>
+static rgs_status radix_sort_impl(uint32_t* keys, V* vals, uint32_t* keys_alt, V* vals_alt, int64_t n,
+                                  const uint32_t* n_dev, int bits, void* ws, hipStream_t s) {
+    if (n <= 0 || bits <= 0) return RGS_OK;
+    int64_t tiles = (n + RS_TILE - 1) / RS_TILE;
+    size_t h = (size_t)256 * tiles * sizeof(uint32_t);
+    size_t hpad = (h + 255) & ~size_t(255);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(ws);
+    uint32_t* offs = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + hpad);
+    void* scan_ws = reinterpret_cast<char*>(ws) + 2 * hpad;
+    int passes = (bits + 7) / 8;
+    uint32_t *ki = keys, *ko = keys_alt;
+    V *vi = vals, *vo = vals_alt;
+    for (int p = 0; p < passes; ++p) {
+        int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(RS_THREADS), 0, s, ki, n, n_dev, shift, hist,
+                           (int)tiles);
+        rgs_status st = exclusive_scan_u32(hist, offs, 256 * tiles, nullptr, scan_ws, s);
+        if (st != RGS_OK) return st;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<V>), dim3((unsigned)tiles), dim3(RS_THREADS), 0, s, ki, vi,
+                           n, n_dev, shift, offs, (int)tiles, ko, vo);
+        RGS_LAUNCH_CHECK();
+        uint32_t* tk = ki; ki = ko; ko = tk;
+        V* tv = vi; vi = vo; vo = tv;
+    }
+    if (ki != keys) {
+        // odd number of passes: copy back
+        int64_t cnt = n;
+        RGS_HIP_CHECK(hipMemcpyAsync(keys, ki, cnt * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        RGS_HIP_CHECK(hipMemcpyAsync(vals, vi, cnt * sizeof(V), hipMemcpyDeviceToDevice, s));
+    }
+    return RGS_OK;
+}
+
+rgs_status radix_sort_u32_u64(uint32_t* keys, uint64_t* vals, uint32_t* keys_alt, uint64_t* vals_alt, int64_t n,
+                              int bits, void* ws, hipStream_t s) {
+    return radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, nullptr, bits, ws, s);
+}
+rgs_status radix_sort_u32_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                              int bits, void* ws, hipStream_t s) {
+    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, nullptr, bits, ws, s);
+}
+rgs_status radix_sort_u32_u32_dev(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                                  const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s) {
+    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n_max, n_dev, bits, ws, s);
+}
+
+}  // namespace rgs

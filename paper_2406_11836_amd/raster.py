@@ -1,0 +1,289 @@
+"""One forward/backward pass of the partitioned rasterizer, driven through librgs.
+
+``Rasterizer`` allocates device buffers with torch (memory and streams only)
+and calls the C ABI in order:
+
+  forward:  rgs_views_upload -> rgs_project_sh -> rgs_bin_sort
+            -> rgs_render_partial -> rgs_merge_partials
+  backward: rgs_merge_partials_bwd -> rgs_render_partial_bwd
+            -> rgs_project_sh_bwd
+
+``RetinaRasterize`` wraps the pair in a ``torch.autograd.Function``.  Every
+arithmetic step runs in the HIP library; this module only marshals
+arguments and owns buffers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PARAM_KEYS = ("means", "log_scales", "quats", "opacity", "sh")
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_device(params, device="cuda"):
+    """numpy/torch parameter dict -> contiguous float32 device tensors."""
+    out = {}
+    for k in PARAM_KEYS:
+        v = params[k]
+        t = v if isinstance(v, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(v, np.float32))
+        out[k] = t.to(device=device, dtype=torch.float32).contiguous()
+    out["sh_degree"] = int(params["sh_degree"])
+    return out
+
+
+def gaussians_struct(params) -> L.Gaussians:
+    g = L.Gaussians()
+    g.n = int(params["means"].shape[1])
+    g.sh_degree = int(params["sh_degree"])
+    for k in PARAM_KEYS:
+        setattr(g, k, params[k].data_ptr())
+    return g
+
+
+@dataclass
+class KD:
+    L: int
+    split: torch.Tensor
+    box_lo: torch.Tensor
+    box_hi: torch.Tensor
+    center_cell: torch.Tensor
+    counts: torch.Tensor
+    own_mask: torch.Tensor | None
+    split_host: np.ndarray
+
+    def struct(self) -> L.KdTree:
+        k = L.KdTree()
+        k.L = self.L
+        k.split, k.box_lo, k.box_hi = self.split.data_ptr(), self.box_lo.data_ptr(), self.box_hi.data_ptr()
+        k.center_cell, k.counts = self.center_cell.data_ptr(), self.counts.data_ptr()
+        k.own_mask = self.own_mask.data_ptr() if self.own_mask is not None else None
+        return k
+
+
+@dataclass
+class FwdState:
+    """Device buffers of one forward pass, kept for the backward."""
+    n: int
+    cams: list
+    cam_arr: object
+    kd: KD
+    views: torch.Tensor
+    proj: dict
+    bins: dict
+    bins_struct: L.Bins
+    parts: dict
+    image: torch.Tensor
+    T_final: torch.Tensor
+    eps_T: float
+    total_tiles: int
+    slot_capacity: int
+    keep: list = field(default_factory=list)
+
+    def proj_struct(self) -> L.Projected:
+        s = L.Projected()
+        s.rec, s.rect = self.proj["rec"].data_ptr(), self.proj["rect"].data_ptr()
+        s.cellmask, s.count = self.proj["cellmask"].data_ptr(), self.proj["count"].data_ptr()
+        return s
+
+    def parts_struct(self) -> L.Partials:
+        s = L.Partials()
+        s.C, s.T, s.last = self.parts["C"].data_ptr(), self.parts["T"].data_ptr(), self.parts["last"].data_ptr()
+        return s
+
+    def images(self):
+        """Per-view (image [3,H,W], T_final [H,W]) views of the concatenated outputs."""
+        out = []
+        po = 0
+        for c in self.cams:
+            H, W = int(c["H"]), int(c["W"])
+            out.append((self.image[3 * po: 3 * po + 3 * H * W].view(3, H, W), self.T_final[po: po + H * W].view(H, W)))
+            po += H * W
+        return out
+
+
+class Rasterizer:
+    def __init__(self, device: str = "cuda"):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        self.capacity_hint = 0
+
+    def _empty(self, n, dtype):
+        return torch.empty(int(max(n, 1)), dtype=dtype, device=self.device)
+
+    # ------------------------------------------------------------ KD tree
+    def kd_partition(self, params, Ldepth: int, d_factor: float = 3.0, own_mask: bool = True) -> KD:
+        n = int(params["means"].shape[1])
+        K = 1 << Ldepth
+        kd = KD(L=Ldepth, split=self._empty(max(K - 1, 1), torch.float32),
+                box_lo=self._empty(3 * K, torch.float32), box_hi=self._empty(3 * K, torch.float32),
+                center_cell=self._empty(n, torch.int32), counts=self._empty(K, torch.int32),
+                own_mask=self._empty(n * ((K + 31) // 32), torch.int32) if own_mask else None,
+                split_host=np.zeros(max(K - 1, 1), np.float32))
+        ws_bytes = self.lib.rgs_kd_partition_workspace(n, Ldepth)
+        ws = self._empty(ws_bytes, torch.uint8)
+        g = gaussians_struct(params)
+        ks = kd.struct()
+        L.check("rgs_kd_partition", self.lib.rgs_kd_partition(C.byref(g), Ldepth, d_factor, C.byref(ks), _p(ws), ws_bytes,
+                                                               _stream()))
+        kd.split_host = kd.split.cpu().numpy().copy()
+        return kd
+
+    def cell_ranks(self, kd: KD, cams) -> np.ndarray:
+        K = 1 << kd.L
+        ranks = np.zeros((len(cams), K), np.int32)
+        order = np.zeros(K, np.int32)
+        for v, c in enumerate(cams):
+            o = np.asarray(c["o"], np.float32)
+            rk = np.zeros(K, np.int32)
+            L.check("rgs_cell_order", self.lib.rgs_cell_order(kd.L, kd.split_host.ctypes.data_as(C.c_void_p),
+                                                               o.ctypes.data_as(C.c_void_p),
+                                                               order.ctypes.data_as(C.c_void_p),
+                                                               rk.ctypes.data_as(C.c_void_p)))
+            ranks[v] = rk
+        return ranks
+
+    # ------------------------------------------------------------ forward
+    def forward(self, params, kd: KD, cams, eps_T: float = 5e-5) -> FwdState:
+        lib = self.lib
+        V = len(cams)
+        if V < 1 or V > L.RGS_MAX_VIEWS:
+            raise ValueError("1..%d views per call" % L.RGS_MAX_VIEWS)
+        n = int(params["means"].shape[1])
+        cam_arr = L.camera_array(cams)
+        stream = _stream()
+        ranks = self.cell_ranks(kd, cams)
+        views = self._empty(lib.rgs_views_bytes(), torch.uint8)
+        L.check("rgs_views_upload", lib.rgs_views_upload(cam_arr, V, kd.L, ranks.ctypes.data_as(C.c_void_p), _p(views),
+                                                         stream))
+        g = gaussians_struct(params)
+        ks = kd.struct()
+        m = V * n
+        proj = dict(rec=self._empty(m * L.REC_FLOATS, torch.float32), rect=self._empty(m * 4, torch.int16),
+                    cellmask=self._empty(m, torch.int64), count=self._empty(m, torch.int32))
+        ps = L.Projected(proj["rec"].data_ptr(), proj["rect"].data_ptr(), proj["cellmask"].data_ptr(),
+                         proj["count"].data_ptr())
+        L.check("rgs_project_sh", lib.rgs_project_sh(C.byref(g), cam_arr, V, _p(views), C.byref(ks), C.byref(ps), stream))
+        T = int(lib.rgs_total_tiles(cam_arr, V))
+        K = 1 << kd.L
+        bins = dict(pair_src=self._empty(m, torch.int32), pair_off=self._empty(m + 1, torch.int32),
+                    pair_rank=self._empty(m, torch.int32), tile_slot=self._empty(T + 1, torch.int32),
+                    counters=torch.zeros(4, dtype=torch.int32, device=self.device))
+        cap = max(self.capacity_hint, 1)
+        while True:
+            slot_cap = min(cap, T * K)
+            bins["keys"] = self._empty(cap, torch.int32)
+            bins["vals"] = self._empty(cap, torch.int64)
+            bins["slot_key"] = self._empty(slot_cap, torch.int32)
+            bins["slot_range"] = self._empty(2 * slot_cap, torch.int32)
+            bs = L.Bins()
+            bs.capacity, bs.slot_capacity = cap, slot_cap
+            for k in ("keys", "vals", "pair_src", "pair_off", "pair_rank", "slot_key", "slot_range", "tile_slot",
+                      "counters"):
+                setattr(bs, k, bins[k].data_ptr())
+            ws_bytes = lib.rgs_bin_sort_workspace(n, V, T, kd.L, cap)
+            ws = self._empty(ws_bytes, torch.uint8)
+            need = C.c_int64(0)
+            st = lib.rgs_bin_sort(C.byref(ps), n, cam_arr, V, _p(views), kd.L, C.byref(bs), C.byref(need), _p(ws),
+                                  ws_bytes, stream)
+            if st == L.RGS_E_CAPACITY:
+                cap = int(need.value * 1.15) + 1024
+                self.capacity_hint = cap
+                continue
+            L.check("rgs_bin_sort", st)
+            break
+        n_inst = int(bs.n_instances)
+        slot_cap = int(bs.slot_capacity)
+        parts = dict(C=self._empty(slot_cap * 768, torch.float32), T=self._empty(slot_cap * 256, torch.float32),
+                     last=self._empty(slot_cap * 256, torch.int32))
+        pt = L.Partials(parts["C"].data_ptr(), parts["T"].data_ptr(), parts["last"].data_ptr())
+        L.check("rgs_render_partial", lib.rgs_render_partial(C.byref(ps), n, C.byref(bs), cam_arr, V, _p(views),
+                                                             C.byref(ks), float(eps_T), C.byref(pt), stream))
+        npix = sum(int(c["W"]) * int(c["H"]) for c in cams)
+        image = self._empty(3 * npix, torch.float32)
+        T_final = self._empty(npix, torch.float32)
+        L.check("rgs_merge_partials", lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam_arr, V, _p(views), _p(image),
+                                                             _p(T_final), stream))
+        return FwdState(n=n, cams=list(cams), cam_arr=cam_arr, kd=kd, views=views, proj=proj, bins=bins,
+                        bins_struct=bs, parts=parts, image=image, T_final=T_final, eps_T=eps_T, total_tiles=T,
+                        slot_capacity=slot_cap, keep=[ws, n_inst])
+
+    # ------------------------------------------------------------ backward
+    def backward(self, st: FwdState, params, d_image: torch.Tensor, d_T_final: torch.Tensor | None = None):
+        lib = self.lib
+        V = len(st.cams)
+        stream = _stream()
+        d_image = d_image.contiguous()
+        if d_T_final is not None:
+            d_T_final = d_T_final.contiguous()
+        pg = dict(dC=self._empty(st.slot_capacity * 768, torch.float32), dT=self._empty(st.slot_capacity * 256, torch.float32))
+        pgs = L.PartialsGrad(pg["dC"].data_ptr(), pg["dT"].data_ptr())
+        pt = st.parts_struct()
+        bs = st.bins_struct
+        L.check("rgs_merge_partials_bwd", lib.rgs_merge_partials_bwd(_p(d_image), _p(d_T_final), C.byref(pt), C.byref(bs),
+                                                                     st.cam_arr, V, _p(st.views), C.byref(pgs), stream))
+        ps = st.proj_struct()
+        ks = st.kd.struct()
+        m = V * st.n
+        dproj = self._empty(9 * m, torch.float32)
+        ws_bytes = lib.rgs_render_bwd_workspace(bs.capacity)
+        ws = self._empty(ws_bytes, torch.uint8)
+        L.check("rgs_render_partial_bwd", lib.rgs_render_partial_bwd(C.byref(pgs), C.byref(pt), C.byref(bs), C.byref(ps),
+                                                                     st.n, st.cam_arr, V, _p(st.views), C.byref(ks),
+                                                                     _p(dproj), _p(ws), ws_bytes, stream))
+        grads = {k: torch.empty_like(params[k]) for k in PARAM_KEYS}
+        gg = L.GaussiansGrad(*[grads[k].data_ptr() for k in PARAM_KEYS])
+        g = gaussians_struct(params)
+        L.check("rgs_project_sh_bwd", lib.rgs_project_sh_bwd(_p(dproj), C.byref(g), C.byref(ps), st.cam_arr, V,
+                                                             _p(st.views), C.byref(gg), stream))
+        grads["_dproj"] = dproj
+        grads["_dparts"] = pg
+        return grads
+
+    # ------------------------------------------------------------ loss
+    def loss(self, image: torch.Tensor, target: torch.Tensor, ssim_weight: float = 0.0):
+        """L1 + w (1 - SSIM) of one [3,H,W] view: (loss scalar tensor, d loss / d image)."""
+        _, H, W = image.shape
+        lossv = torch.empty(1, dtype=torch.float32, device=self.device)
+        d = torch.empty_like(image)
+        ws_bytes = self.lib.rgs_loss_workspace(H, W)
+        ws = self._empty(ws_bytes, torch.uint8)
+        L.check("rgs_loss_l1_ssim", self.lib.rgs_loss_l1_ssim(_p(image.contiguous()), _p(target.contiguous()), H, W,
+                                                              float(ssim_weight), _p(lossv), _p(d), _p(ws), ws_bytes,
+                                                              _stream()))
+        return lossv, d
+
+
+class RetinaRasterize(torch.autograd.Function):
+    """(means, log_scales, quats, opacity, sh) -> (image, T_final) for the
+    views in ``cams``, merged over the KD cells of ``kd``."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity, sh, cams, kd, rast, sh_degree, eps_T):
+        params = dict(means=means.contiguous(), log_scales=log_scales.contiguous(), quats=quats.contiguous(),
+                      opacity=opacity.contiguous(), sh=sh.contiguous(), sh_degree=sh_degree)
+        st = rast.forward(params, kd, cams, eps_T)
+        ctx.st, ctx.rast, ctx.params = st, rast, params
+        return st.image, st.T_final
+
+    @staticmethod
+    def backward(ctx, d_image, d_T_final):
+        g = ctx.rast.backward(ctx.st, ctx.params, d_image, d_T_final)
+        return g["means"], g["log_scales"], g["quats"], g["opacity"], g["sh"], None, None, None, None, None
+
+
+def rasterize(params, cams, kd: KD, rast: Rasterizer, eps_T: float = 5e-5):
+    return RetinaRasterize.apply(params["means"], params["log_scales"], params["quats"], params["opacity"],
+                                 params["sh"], cams, kd, rast, int(params["sh_degree"]), eps_T)

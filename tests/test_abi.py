@@ -1,0 +1,106 @@
+"""The C ABI on the CPU: the library loads and exports every symbol the
+header declares; host-only entry points agree with the oracle; argument
+errors are reported without touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "rgs.h")).read()
+    return sorted(set(re.findall(r"\b(rgs_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2406_11836_amd import _lib
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_2406_11836_amd import _lib
+    syms = header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(_lib.EXPORTED)
+
+
+def test_abi_version_and_status(lib):
+    assert lib.rgs_abi_version() == 1
+    assert lib.rgs_status_string(0) == b"ok"
+    assert lib.rgs_status_string(-2) == b"buffer capacity too small"
+
+
+def test_cell_order_matches_oracle(lib, orc):
+    rng = np.random.default_rng(3)
+    for L in range(0, 7):
+        means = rng.normal(size=(3, 500)).astype(np.float32)
+        kd = orc.kd_partition(means, np.full((3, 500), -3.0, np.float32), L)
+        K = 1 << L
+        for _ in range(10):
+            o = rng.normal(size=3).astype(np.float32)
+            order = np.zeros(K, np.int32)
+            rank = np.zeros(K, np.int32)
+            sp = np.ascontiguousarray(kd["split"] if K > 1 else np.zeros(1, np.float32))
+            st = lib.rgs_cell_order(L, sp.ctypes.data_as(C.c_void_p), o.ctypes.data_as(C.c_void_p),
+                                    order.ctypes.data_as(C.c_void_p), rank.ctypes.data_as(C.c_void_p))
+            assert st == 0
+            oo, rr = orc.cell_order(L, kd["split"], o.astype(np.float64))
+            assert np.array_equal(order, oo) and np.array_equal(rank, rr)
+
+
+def test_total_tiles_and_workspaces(lib):
+    from paper_2406_11836_amd import _lib, scenes
+    cams = [scenes.orbit_camera(4, 0.1, 0.3, 1600, 1060), scenes.orbit_camera(4, 0.1, 0.3, 33, 17)]
+    arr = _lib.camera_array(cams)
+    assert lib.rgs_total_tiles(arr, 1) == 100 * 67
+    assert lib.rgs_total_tiles(arr, 2) == 100 * 67 + 3 * 2
+    assert lib.rgs_loss_workspace(0, 5) == 0
+    assert lib.rgs_loss_workspace(10, 10) >= 11 * 300 * 4
+    assert lib.rgs_bin_sort_workspace(1000, 1, 100, 3, 5000) > 0
+    assert lib.rgs_bin_sort_workspace(1000, 0, 100, 3, 5000) == 0
+    assert lib.rgs_kd_partition_workspace(1000, 7) == 0
+    assert lib.rgs_render_bwd_workspace(100) >= 900 * 4
+
+
+def test_argument_errors_enqueue_nothing(lib):
+    """Every entry point rejects invalid arguments synchronously (no device needed)."""
+    from paper_2406_11836_amd import _lib as L
+    E = L.RGS_E_ARG
+    g = L.Gaussians()
+    g.n, g.sh_degree = 10, 4          # bad degree
+    cam = L.camera_array([dict(R=np.eye(3), t=[0, 0, 0], o=[0, 0, 0], fx=100, fy=100, cx=8, cy=8, W=16, H=16,
+                               z_near=0.1)])
+    kd = L.KdTree()
+    ps = L.Projected()
+    bs = L.Bins()
+    pt = L.Partials()
+    pg = L.PartialsGrad()
+    gg = L.GaussiansGrad()
+    assert lib.rgs_kd_partition(C.byref(g), 2, 3.0, C.byref(kd), None, 0, None) == E
+    assert lib.rgs_project_sh(C.byref(g), cam, 1, None, C.byref(kd), C.byref(ps), None) == E
+    assert lib.rgs_project_sh(None, cam, 1, None, C.byref(kd), C.byref(ps), None) == E
+    need = C.c_int64(0)
+    assert lib.rgs_bin_sort(C.byref(ps), 10, cam, 1, None, 2, C.byref(bs), C.byref(need), None, 0, None) == E
+    assert lib.rgs_render_partial(C.byref(ps), 10, C.byref(bs), cam, 1, None, C.byref(kd), 5e-5, C.byref(pt), None) == E
+    assert lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam, 1, None, None, None, None) == E
+    assert lib.rgs_merge_partials_bwd(None, None, C.byref(pt), C.byref(bs), cam, 1, None, C.byref(pg), None) == E
+    assert lib.rgs_render_partial_bwd(C.byref(pg), C.byref(pt), C.byref(bs), C.byref(ps), 10, cam, 1, None,
+                                      C.byref(kd), None, None, 0, None) == E
+    assert lib.rgs_project_sh_bwd(None, C.byref(g), C.byref(ps), cam, 1, None, C.byref(gg), None) == E
+    assert lib.rgs_loss_l1_ssim(None, None, 4, 4, 0.2, None, None, None, 0, None) == E
+    rk = np.zeros(4, np.int32)
+    assert lib.rgs_views_upload(cam, 0, 2, rk.ctypes.data_as(C.c_void_p), None, None) == E
+    assert lib.rgs_views_upload(cam, 1, 7, rk.ctypes.data_as(C.c_void_p), None, None) == E
+    # bad camera: z_near <= 0
+    bad = L.camera_array([dict(R=np.eye(3), t=[0, 0, 0], o=[0, 0, 0], fx=100, fy=100, cx=8, cy=8, W=16, H=16,
+                               z_near=0.0)])
+    assert lib.rgs_views_upload(bad, 1, 2, rk.ctypes.data_as(C.c_void_p), None, None) == E
+    o = np.zeros(3, np.float32)
+    assert lib.rgs_cell_order(7, None, o.ctypes.data_as(C.c_void_p), None, None) == E
