@@ -27,7 +27,7 @@ size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t 
 rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt_dev, int L, int64_t total_tiles,
                     rgs_bins* bins, int64_t* n_required, void* ws, size_t ws_bytes, hipStream_t s);
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
-                             float eps_T, const rgs_partials* out, int64_t slot_bound, hipStream_t s);
+                             float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s);
 size_t render_bwd_ws_bytes(int64_t capacity);
 rgs_status render_bwd_launch(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
                              const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt,
@@ -213,11 +213,11 @@ static int64_t slot_bound_of(const rgs_bins* bins, const rgs_camera* cams, int32
 
 rgs_status rgs_render_partial(const rgs_projected* proj, int64_t n, const rgs_bins* bins, const rgs_camera* cams,
                               int32_t n_views, const void* views_dev, const rgs_kdtree* kd, float eps_T,
-                              const rgs_partials* out, rgs_stream stream) {
+                              const rgs_partials* out, uint64_t* stats, rgs_stream stream) {
     if (!proj_ok(proj) || n < 0 || !bins_ok(bins) || !cams_ok(cams, n_views) || !views_dev || !kd || !kd->box_lo ||
         !kd->box_hi || !out || !out->C || !out->T || !out->last || !(eps_T >= 0.f) || eps_T >= 1.f)
         return RGS_E_ARG;
-    return render_fwd_launch(proj, bins, reinterpret_cast<const ViewTable*>(views_dev), kd, eps_T, out,
+    return render_fwd_launch(proj, bins, reinterpret_cast<const ViewTable*>(views_dev), kd, eps_T, out, stats,
                              slot_bound_of(bins, cams, n_views, kd->L), S(stream));
 }
 

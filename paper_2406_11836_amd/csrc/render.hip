@@ -52,7 +52,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
                                                    const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
                                                    const float* __restrict__ box_hi, float eps_T,
                                                    float* __restrict__ outC, float* __restrict__ outT,
-                                                   uint32_t* __restrict__ outLast) {
+                                                   uint32_t* __restrict__ outLast,
+                                                   unsigned long long* __restrict__ stats) {
     __shared__ float4 sA[RD_BATCH], sB[RD_BATCH], sCl[RD_BATCH];
     const uint32_t slot = blockIdx.x;
     if (slot >= counters[2]) return;
@@ -89,6 +90,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
         last[r] = 0u;
     }
     const float o0 = V.o[0], o1 = V.o[1], o2 = V.o[2];
+    uint32_t n_eval = 0, n_con = 0;
 
     for (uint32_t base = begin; base < end; base += RD_BATCH) {
         const bool alive = !(done[0] && done[1] && done[2] && done[3]);
@@ -120,6 +122,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
                 d2[r] = fmaf(dy, fmaf(b.x, dy, B), A);
                 hit[r] = !done[r] && (d2[r] <= b.z);
                 any |= hit[r];
+                if (stats) n_eval += done[r] ? 0u : 1u;
             }
             if (!any) continue;
             const float4 cl = sCl[t];
@@ -135,6 +138,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
                                     (blo[2] <= x2) && (x2 < bhi[2]);
                     if (!in) continue;
                 }
+                if (stats) ++n_con;
                 const float G = __expf(-0.5f * d2[r]);
                 const float sg_ = fminf(0.99f, b.y * G);
                 const float wgt = sg_ * T[r];
@@ -147,6 +151,18 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
             }
         }
         __syncthreads();
+    }
+    if (stats) {
+        unsigned long long e = n_eval, c = n_con;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            e += __shfl_xor(e, d, 64);
+            c += __shfl_xor(c, d, 64);
+        }
+        if (lane == 0) {
+            atomicAdd(&stats[0], e);
+            atomicAdd(&stats[1], c);
+        }
     }
     float* oc = outC + (size_t)slot * 768;
     float* ot = outT + (size_t)slot * 256;
@@ -163,10 +179,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
 }
 
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
-                             float eps_T, const rgs_partials* out, int64_t slot_bound, hipStream_t s) {
+                             float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s) {
     if (slot_bound <= 0) return RGS_OK;
     hipLaunchKernelGGL(k_render_fwd, dim3((unsigned)slot_bound), dim3(64), 0, s, proj->rec, bins->vals, bins->slot_key,
-                       bins->slot_range, bins->counters, vt, kd->box_lo, kd->box_hi, eps_T, out->C, out->T, out->last);
+                       bins->slot_range, bins->counters, vt, kd->box_lo, kd->box_hi, eps_T, out->C, out->T, out->last,
+                       reinterpret_cast<unsigned long long*>(stats));
     return launch_check();
 }
 

@@ -33,6 +33,14 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _mark(marks, name):
+    """Record a timing event on the launch stream (measurement only)."""
+    if marks is not None:
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        marks.append((name, e))
+
+
 def to_device(params, device="cuda"):
     """numpy/torch parameter dict -> contiguous float32 device tensors."""
     out = {}
@@ -156,8 +164,12 @@ class Rasterizer:
         return ranks
 
     # ------------------------------------------------------------ forward
-    def forward(self, params, kd: KD, cams, eps_T: float = 5e-5) -> FwdState:
+    def forward(self, params, kd: KD, cams, eps_T: float = 5e-5, stats: torch.Tensor | None = None,
+                marks: list | None = None) -> FwdState:
+        """stats: optional int64 device tensor [2] (evaluated, contributing pairs), incremented.
+        marks: optional list receiving (stage, event) pairs at stage ends."""
         lib = self.lib
+        _mark(marks, "start")
         V = len(cams)
         if V < 1 or V > L.RGS_MAX_VIEWS:
             raise ValueError("1..%d views per call" % L.RGS_MAX_VIEWS)
@@ -168,6 +180,7 @@ class Rasterizer:
         views = self._empty(lib.rgs_views_bytes(), torch.uint8)
         L.check("rgs_views_upload", lib.rgs_views_upload(cam_arr, V, kd.L, ranks.ctypes.data_as(C.c_void_p), _p(views),
                                                          stream))
+        _mark(marks, "views")
         g = gaussians_struct(params)
         ks = kd.struct()
         m = V * n
@@ -176,6 +189,7 @@ class Rasterizer:
         ps = L.Projected(proj["rec"].data_ptr(), proj["rect"].data_ptr(), proj["cellmask"].data_ptr(),
                          proj["count"].data_ptr())
         L.check("rgs_project_sh", lib.rgs_project_sh(C.byref(g), cam_arr, V, _p(views), C.byref(ks), C.byref(ps), stream))
+        _mark(marks, "project")
         T = int(lib.rgs_total_tiles(cam_arr, V))
         K = 1 << kd.L
         bins = dict(pair_src=self._empty(m, torch.int32), pair_off=self._empty(m + 1, torch.int32),
@@ -204,25 +218,30 @@ class Rasterizer:
                 continue
             L.check("rgs_bin_sort", st)
             break
+        _mark(marks, "bin_sort")
         n_inst = int(bs.n_instances)
         slot_cap = int(bs.slot_capacity)
         parts = dict(C=self._empty(slot_cap * 768, torch.float32), T=self._empty(slot_cap * 256, torch.float32),
                      last=self._empty(slot_cap * 256, torch.int32))
         pt = L.Partials(parts["C"].data_ptr(), parts["T"].data_ptr(), parts["last"].data_ptr())
         L.check("rgs_render_partial", lib.rgs_render_partial(C.byref(ps), n, C.byref(bs), cam_arr, V, _p(views),
-                                                             C.byref(ks), float(eps_T), C.byref(pt), stream))
+                                                             C.byref(ks), float(eps_T), C.byref(pt), _p(stats), stream))
+        _mark(marks, "render_fwd")
         npix = sum(int(c["W"]) * int(c["H"]) for c in cams)
         image = self._empty(3 * npix, torch.float32)
         T_final = self._empty(npix, torch.float32)
         L.check("rgs_merge_partials", lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam_arr, V, _p(views), _p(image),
                                                              _p(T_final), stream))
+        _mark(marks, "merge")
         return FwdState(n=n, cams=list(cams), cam_arr=cam_arr, kd=kd, views=views, proj=proj, bins=bins,
                         bins_struct=bs, parts=parts, image=image, T_final=T_final, eps_T=eps_T, total_tiles=T,
                         slot_capacity=slot_cap, keep=[ws, n_inst])
 
     # ------------------------------------------------------------ backward
-    def backward(self, st: FwdState, params, d_image: torch.Tensor, d_T_final: torch.Tensor | None = None):
+    def backward(self, st: FwdState, params, d_image: torch.Tensor, d_T_final: torch.Tensor | None = None,
+                 marks: list | None = None):
         lib = self.lib
+        _mark(marks, "bwd_start")
         V = len(st.cams)
         stream = _stream()
         d_image = d_image.contiguous()
@@ -234,6 +253,7 @@ class Rasterizer:
         bs = st.bins_struct
         L.check("rgs_merge_partials_bwd", lib.rgs_merge_partials_bwd(_p(d_image), _p(d_T_final), C.byref(pt), C.byref(bs),
                                                                      st.cam_arr, V, _p(st.views), C.byref(pgs), stream))
+        _mark(marks, "merge_bwd")
         ps = st.proj_struct()
         ks = st.kd.struct()
         m = V * st.n
@@ -243,11 +263,13 @@ class Rasterizer:
         L.check("rgs_render_partial_bwd", lib.rgs_render_partial_bwd(C.byref(pgs), C.byref(pt), C.byref(bs), C.byref(ps),
                                                                      st.n, st.cam_arr, V, _p(st.views), C.byref(ks),
                                                                      _p(dproj), _p(ws), ws_bytes, stream))
+        _mark(marks, "render_bwd")
         grads = {k: torch.empty_like(params[k]) for k in PARAM_KEYS}
         gg = L.GaussiansGrad(*[grads[k].data_ptr() for k in PARAM_KEYS])
         g = gaussians_struct(params)
         L.check("rgs_project_sh_bwd", lib.rgs_project_sh_bwd(_p(dproj), C.byref(g), C.byref(ps), st.cam_arr, V,
                                                              _p(st.views), C.byref(gg), stream))
+        _mark(marks, "project_bwd")
         grads["_dproj"] = dproj
         grads["_dparts"] = pg
         return grads

@@ -88,7 +88,7 @@ def test_argument_errors_enqueue_nothing(lib):
     assert lib.rgs_project_sh(None, cam, 1, None, C.byref(kd), C.byref(ps), None) == E
     need = C.c_int64(0)
     assert lib.rgs_bin_sort(C.byref(ps), 10, cam, 1, None, 2, C.byref(bs), C.byref(need), None, 0, None) == E
-    assert lib.rgs_render_partial(C.byref(ps), 10, C.byref(bs), cam, 1, None, C.byref(kd), 5e-5, C.byref(pt), None) == E
+    assert lib.rgs_render_partial(C.byref(ps), 10, C.byref(bs), cam, 1, None, C.byref(kd), 5e-5, C.byref(pt), None, None) == E
     assert lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam, 1, None, None, None, None) == E
     assert lib.rgs_merge_partials_bwd(None, None, C.byref(pt), C.byref(bs), cam, 1, None, C.byref(pg), None) == E
     assert lib.rgs_render_partial_bwd(C.byref(pg), C.byref(pt), C.byref(bs), C.byref(ps), 10, cam, 1, None,
