@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the cross-GPU merge would be an "
@@ -86,6 +88,12 @@ def main():
     from paper_2406_11836_amd import raster, scenes
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     p, cam, tgt, L = scenes.config2(n=args.n)
     W, H = cam["W"], cam["H"]
     rast = raster.Rasterizer("cuda:0")

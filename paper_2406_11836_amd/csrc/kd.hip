@@ -142,12 +142,17 @@ __global__ __launch_bounds__(KD_THREADS) void k_kd_leaves(const int32_t* __restr
                                                           const float* __restrict__ lo, const float* __restrict__ hi,
                                                           int32_t* __restrict__ center_cell, int32_t* __restrict__ counts,
                                                           uint32_t* __restrict__ own_mask) {
-    int64_t i = (int64_t)blockIdx.x * KD_THREADS + threadIdx.x;
-    if (i >= n) return;
+    __shared__ int32_t s_cnt[RGS_MAXK];
     const int K = 1 << L;
-    const int leaf = node[i] - (K - 1);
+    if (threadIdx.x < K) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * KD_THREADS + threadIdx.x;
+    const int leaf = i < n ? node[i] - (K - 1) : 0;
+    if (i < n) atomicAdd(&s_cnt[leaf], 1);
+    __syncthreads();
+    if (threadIdx.x < K && s_cnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], s_cnt[threadIdx.x]);
+    if (i >= n) return;
     center_cell[i] = leaf;
-    atomicAdd(&counts[leaf], 1);
     if (!own_mask) return;
     // D_i = d_factor * max scale; transcendental in fp64, rounded once
     const float s0 = (float)exp((double)log_scales[i]);

@@ -3,7 +3,7 @@
 // SSIM uses an 11x11 Gaussian window (std 1.5, normalised), zero padding and
 // C1 = 0.01^2, C2 = 0.03^2; the window is separable, so the five local
 // moments (mu_x, mu_y, E[x^2], E[y^2], E[xy]) take a horizontal and a
-// vertical 11-tap pass.  The backward needs d SSIM / d (mu_x, E[x^2], E[xy])
+// vertical 11-tap pass, both run from LDS on 32x32 tiles with a 5-pixel halo.  The backward needs d SSIM / d (mu_x, E[x^2], E[xy])
 // per pixel, convolved again with the (symmetric) window.  Block partial sums
 // are combined by one block in a fixed order, so the scalar is reproducible.
 #include "common.hpp"
@@ -33,52 +33,64 @@ __global__ __launch_bounds__(LS_THREADS) void k_l1_only(const float* __restrict_
     }
 }
 
-// Horizontal pass of the five moment images.
-__global__ __launch_bounds__(LS_THREADS) void k_ssim_h(const float* __restrict__ x, const float* __restrict__ y, int H, int W,
-                                                       int64_t m, Win11 win, float* __restrict__ h5) {
-    const int64_t i = (int64_t)blockIdx.x * LS_THREADS + threadIdx.x;
-    if (i >= m) return;
-    const int c = (int)(i % W);
-    const int64_t rowbase = i - c;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
-#pragma unroll
-    for (int k = 0; k < 11; ++k) {
-        const int cc = c + k - 5;
-        if (cc < 0 || cc >= W) continue;
-        const float xv = x[rowbase + cc], yv = y[rowbase + cc], w = win.w[k];
-        a0 = fmaf(w, xv, a0);
-        a1 = fmaf(w, yv, a1);
-        a2 = fmaf(w, xv * xv, a2);
-        a3 = fmaf(w, yv * yv, a3);
-        a4 = fmaf(w, xv * yv, a4);
-    }
-    h5[i] = a0; h5[m + i] = a1; h5[2 * m + i] = a2; h5[3 * m + i] = a3; h5[4 * m + i] = a4;
-}
+// Tiled SSIM: one 256-thread block per 32x32 output tile of one channel,
+// with the 5-pixel halo staged in LDS; both separable passes run from LDS.
+static constexpr int TS = 32, HALO = 5, TW = TS + 2 * HALO;  // 42
 
-// Vertical pass, SSIM map, its partial derivatives, and block sums.
-__global__ __launch_bounds__(LS_THREADS) void k_ssim_v(const float* __restrict__ x, const float* __restrict__ y,
-                                                       const float* __restrict__ h5, int H, int W, int64_t m, Win11 win,
-                                                       float* __restrict__ d3, float* __restrict__ part) {
+// Forward: SSIM map terms and d SSIM / d (mu_x, E[x^2], E[xy]) per pixel,
+// plus block sums of the SSIM map and of |x - y|.
+__global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __restrict__ x, const float* __restrict__ y,
+                                                               int H, int W, Win11 win, float* __restrict__ d3,
+                                                               float* __restrict__ part) {
+    __shared__ float sx[TW * TW], sy[TW * TW];
+    __shared__ float hm[5][TW * TS];
     __shared__ float s_w[2][4];
-    const int64_t i = (int64_t)blockIdx.x * LS_THREADS + threadIdx.x;
+    const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TS - 1) / TS;
+    const int b = blockIdx.x;
+    const int ch = b / (tiles_x * tiles_y);
+    const int tt = b % (tiles_x * tiles_y);
+    const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TS;
+    const int64_t HW = (int64_t)H * W;
+    const float* xc = x + ch * HW;
+    const float* yc = y + ch * HW;
+    for (int k = threadIdx.x; k < TW * TW; k += LS_THREADS) {
+        const int r = k / TW, c = k % TW;
+        const int gy = y0 + r - HALO, gx = x0 + c - HALO;
+        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        sx[k] = in ? xc[(int64_t)gy * W + gx] : 0.f;
+        sy[k] = in ? yc[(int64_t)gy * W + gx] : 0.f;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < TW * TS; k += LS_THREADS) {
+        const int r = k / TS, c = k % TS;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+#pragma unroll
+        for (int t = 0; t < 11; ++t) {
+            const float xv = sx[r * TW + c + t], yv = sy[r * TW + c + t], w = win.w[t];
+            a0 = fmaf(w, xv, a0);
+            a1 = fmaf(w, yv, a1);
+            a2 = fmaf(w, xv * xv, a2);
+            a3 = fmaf(w, yv * yv, a3);
+            a4 = fmaf(w, xv * yv, a4);
+        }
+        hm[0][k] = a0; hm[1][k] = a1; hm[2][k] = a2; hm[3][k] = a3; hm[4][k] = a4;
+    }
+    __syncthreads();
     float l1 = 0.f, ss = 0.f;
-    if (i < m) {
-        const int64_t HW = (int64_t)H * W;
-        const int64_t plane = i / HW;
-        const int64_t within = i - plane * HW;
-        const int r = (int)(within / W), c = (int)(within % W);
+    for (int k = threadIdx.x; k < TS * TS; k += LS_THREADS) {
+        const int r = k / TS, c = k % TS;
+        const int gy = y0 + r, gx = x0 + c;
+        if (gy >= H || gx >= W) continue;
         float mu_x = 0.f, mu_y = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
 #pragma unroll
-        for (int k = 0; k < 11; ++k) {
-            const int rr = r + k - 5;
-            if (rr < 0 || rr >= H) continue;
-            const int64_t j = plane * HW + (int64_t)rr * W + c;
-            const float w = win.w[k];
-            mu_x = fmaf(w, h5[j], mu_x);
-            mu_y = fmaf(w, h5[m + j], mu_y);
-            exx = fmaf(w, h5[2 * m + j], exx);
-            eyy = fmaf(w, h5[3 * m + j], eyy);
-            exy = fmaf(w, h5[4 * m + j], exy);
+        for (int t = 0; t < 11; ++t) {
+            const int q = (r + t) * TS + c;
+            const float w = win.w[t];
+            mu_x = fmaf(w, hm[0][q], mu_x);
+            mu_y = fmaf(w, hm[1][q], mu_y);
+            exx = fmaf(w, hm[2][q], exx);
+            eyy = fmaf(w, hm[3][q], eyy);
+            exy = fmaf(w, hm[4][q], exy);
         }
         const float C1 = 1e-4f, C2 = 9e-4f;
         const float A1 = 2.f * mu_x * mu_y + C1;
@@ -87,13 +99,15 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_v(const float* __restrict__
         const float B2 = (exx - mu_x * mu_x) + (eyy - mu_y * mu_y) + C2;
         const float Nn = A1 * A2, Dd = B1 * B2;
         const float iD = 1.f / Dd;
-        ss = Nn * iD;
+        ss += Nn * iD;
         const float dN = 2.f * mu_y * A2 - 2.f * mu_y * A1;
         const float dD = 2.f * mu_x * B2 - 2.f * mu_x * B1;
+        const int64_t i = ch * HW + (int64_t)gy * W + gx;
+        const int64_t m = 3 * HW;
         d3[i] = (dN * Dd - Nn * dD) * iD * iD;
         d3[m + i] = -Nn * B1 * iD * iD;
         d3[2 * m + i] = 2.f * A1 * iD;
-        l1 = fabsf(x[i] - y[i]);
+        l1 += fabsf(sx[(r + HALO) * TW + c + HALO] - sy[(r + HALO) * TW + c + HALO]);
     }
     l1 = wave_sum(l1);
     ss = wave_sum(ss);
@@ -105,49 +119,63 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_v(const float* __restrict__
     }
 }
 
-__global__ __launch_bounds__(LS_THREADS) void k_conv_h3(const float* __restrict__ d3, int W, int64_t m, Win11 win,
-                                                        float* __restrict__ e3) {
-    const int64_t i = (int64_t)blockIdx.x * LS_THREADS + threadIdx.x;
-    if (i >= m) return;
-    const int c = (int)(i % W);
-    const int64_t rowbase = i - c;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll
-    for (int k = 0; k < 11; ++k) {
-        const int cc = c + k - 5;
-        if (cc < 0 || cc >= W) continue;
-        const float w = win.w[k];
-        a0 = fmaf(w, d3[rowbase + cc], a0);
-        a1 = fmaf(w, d3[m + rowbase + cc], a1);
-        a2 = fmaf(w, d3[2 * m + rowbase + cc], a2);
-    }
-    e3[i] = a0; e3[m + i] = a1; e3[2 * m + i] = a2;
-}
-
-__global__ __launch_bounds__(LS_THREADS) void k_ssim_grad(const float* __restrict__ x, const float* __restrict__ y,
-                                                          const float* __restrict__ e3, int H, int W, int64_t m, Win11 win,
-                                                          float invN, float sc, float* __restrict__ dx) {
-    const int64_t i = (int64_t)blockIdx.x * LS_THREADS + threadIdx.x;
-    if (i >= m) return;
+// Backward: convolve the three derivative maps with the (symmetric) window
+// and combine: dL/dx = sign(x - y)/N + sc (w*g_mu + 2 x w*g_xx + y w*g_xy).
+__global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __restrict__ x, const float* __restrict__ y,
+                                                               const float* __restrict__ d3, int H, int W, Win11 win,
+                                                               float invN, float sc, float* __restrict__ dx) {
+    __shared__ float sd[3][TW * TW];
+    __shared__ float hm[3][TW * TS];
+    const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TS - 1) / TS;
+    const int b = blockIdx.x;
+    const int ch = b / (tiles_x * tiles_y);
+    const int tt = b % (tiles_x * tiles_y);
+    const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TS;
     const int64_t HW = (int64_t)H * W;
-    const int64_t plane = i / HW;
-    const int64_t within = i - plane * HW;
-    const int r = (int)(within / W), c = (int)(within % W);
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-#pragma unroll
-    for (int k = 0; k < 11; ++k) {
-        const int rr = r + k - 5;
-        if (rr < 0 || rr >= H) continue;
-        const int64_t j = plane * HW + (int64_t)rr * W + c;
-        const float w = win.w[k];
-        g0 = fmaf(w, e3[j], g0);
-        g1 = fmaf(w, e3[m + j], g1);
-        g2 = fmaf(w, e3[2 * m + j], g2);
+    const int64_t m = 3 * HW;
+    for (int k = threadIdx.x; k < TW * TW; k += LS_THREADS) {
+        const int r = k / TW, c = k % TW;
+        const int gy = y0 + r - HALO, gx = x0 + c - HALO;
+        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        const int64_t i = ch * HW + (int64_t)gy * W + gx;
+        sd[0][k] = in ? d3[i] : 0.f;
+        sd[1][k] = in ? d3[m + i] : 0.f;
+        sd[2][k] = in ? d3[2 * m + i] : 0.f;
     }
-    const float xv = x[i], yv = y[i];
-    const float d = xv - yv;
-    const float l1g = (float)((d > 0.f) - (d < 0.f)) * invN;
-    dx[i] = l1g + sc * (g0 + 2.f * xv * g1 + yv * g2);
+    __syncthreads();
+    for (int k = threadIdx.x; k < TW * TS; k += LS_THREADS) {
+        const int r = k / TS, c = k % TS;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+        for (int t = 0; t < 11; ++t) {
+            const int q = r * TW + c + t;
+            const float w = win.w[t];
+            a0 = fmaf(w, sd[0][q], a0);
+            a1 = fmaf(w, sd[1][q], a1);
+            a2 = fmaf(w, sd[2][q], a2);
+        }
+        hm[0][k] = a0; hm[1][k] = a1; hm[2][k] = a2;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < TS * TS; k += LS_THREADS) {
+        const int r = k / TS, c = k % TS;
+        const int gy = y0 + r, gx = x0 + c;
+        if (gy >= H || gx >= W) continue;
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+#pragma unroll
+        for (int t = 0; t < 11; ++t) {
+            const int q = (r + t) * TS + c;
+            const float w = win.w[t];
+            g0 = fmaf(w, hm[0][q], g0);
+            g1 = fmaf(w, hm[1][q], g1);
+            g2 = fmaf(w, hm[2][q], g2);
+        }
+        const int64_t i = ch * HW + (int64_t)gy * W + gx;
+        const float xv = x[i], yv = y[i];
+        const float d = xv - yv;
+        const float l1g = (float)((d > 0.f) - (d < 0.f)) * invN;
+        dx[i] = l1g + sc * (g0 + 2.f * xv * g1 + yv * g2);
+    }
 }
 
 __global__ __launch_bounds__(LS_THREADS) void k_loss_final(const float* __restrict__ part, int nb, float invN, float w,
@@ -172,34 +200,35 @@ __global__ __launch_bounds__(LS_THREADS) void k_loss_final(const float* __restri
 size_t loss_ws_bytes(int H, int W) {
     const int64_t m = 3 * (int64_t)H * W;
     const int64_t nb = (m + LS_THREADS - 1) / LS_THREADS;
-    return (size_t)(5 + 3 + 3) * m * sizeof(float) + (size_t)2 * nb * sizeof(float) + 1024;
+    const int64_t nt = 3 * (int64_t)((W + TS - 1) / TS) * ((H + TS - 1) / TS);
+    const int64_t np = nb > nt ? nb : nt;
+    return (size_t)3 * m * sizeof(float) + (size_t)2 * np * sizeof(float) + 1024;
 }
 
 rgs_status loss_launch(const float* image, const float* target, int H, int W, float ssim_w, float* loss, float* dimg,
                        void* ws, hipStream_t s) {
     const int64_t m = 3 * (int64_t)H * W;
     const int64_t nb = (m + LS_THREADS - 1) / LS_THREADS;
+    const int64_t nt = 3 * (int64_t)((W + TS - 1) / TS) * ((H + TS - 1) / TS);
     WsCarver c{reinterpret_cast<char*>(ws), 0, (size_t)-1};
-    float* h5 = c.take<float>(5 * m);
     float* d3 = c.take<float>(3 * m);
-    float* e3 = c.take<float>(3 * m);
-    float* part = c.take<float>(2 * nb);
+    float* part = c.take<float>(2 * (nb > nt ? nb : nt));
     const float invN = (float)(1.0 / (double)m);
     Win11 win;
     double g[11], gs = 0.0;
     for (int k = 0; k < 11; ++k) { g[k] = exp(-((k - 5) * (k - 5)) / (2.0 * 1.5 * 1.5)); gs += g[k]; }
     for (int k = 0; k < 11; ++k) win.w[k] = (float)(g[k] / gs);
-    const dim3 grid((unsigned)nb);
+    int parts;
     if (ssim_w == 0.f) {
-        hipLaunchKernelGGL(k_l1_only, grid, dim3(LS_THREADS), 0, s, image, target, m, invN, dimg, part);
+        hipLaunchKernelGGL(k_l1_only, dim3((unsigned)nb), dim3(LS_THREADS), 0, s, image, target, m, invN, dimg, part);
+        parts = (int)nb;
     } else {
-        hipLaunchKernelGGL(k_ssim_h, grid, dim3(LS_THREADS), 0, s, image, target, H, W, m, win, h5);
-        hipLaunchKernelGGL(k_ssim_v, grid, dim3(LS_THREADS), 0, s, image, target, h5, H, W, m, win, d3, part);
-        hipLaunchKernelGGL(k_conv_h3, grid, dim3(LS_THREADS), 0, s, d3, W, m, win, e3);
-        hipLaunchKernelGGL(k_ssim_grad, grid, dim3(LS_THREADS), 0, s, image, target, e3, H, W, m, win, invN,
-                           -ssim_w * invN, dimg);
+        hipLaunchKernelGGL(k_ssim_fwd_tiled, dim3((unsigned)nt), dim3(LS_THREADS), 0, s, image, target, H, W, win, d3, part);
+        hipLaunchKernelGGL(k_ssim_bwd_tiled, dim3((unsigned)nt), dim3(LS_THREADS), 0, s, image, target, d3, H, W, win,
+                           invN, -ssim_w * invN, dimg);
+        parts = (int)nt;
     }
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LS_THREADS), 0, s, part, (int)nb, invN, ssim_w, loss);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LS_THREADS), 0, s, part, parts, invN, ssim_w, loss);
     return launch_check();
 }
 

@@ -210,18 +210,19 @@ __device__ __forceinline__ uint64_t cellset32(const Proj32& p, const int r[4], c
     return mask;
 }
 
+template <int D>
 __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const ViewTable* __restrict__ vt,
                                                         const float* __restrict__ split, rgs_projected out) {
     const int64_t n = g.n;
     const int64_t i = (int64_t)blockIdx.x * PJ_THREADS + threadIdx.x;
     if (i >= n) return;
-    const int D = g.sh_degree;
-    const int nc = (D + 1) * (D + 1);
+    constexpr int nc = (D + 1) * (D + 1);
     const float mu0 = g.means[i], mu1 = g.means[n + i], mu2 = g.means[2 * n + i];
     const float ls0 = g.log_scales[i], ls1 = g.log_scales[n + i], ls2 = g.log_scales[2 * n + i];
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
     const float logit = g.opacity[i];
-    float f[48];
+    float f[3 * nc];
+#pragma unroll
     for (int k = 0; k < 3 * nc; ++k) f[k] = g.sh[(int64_t)k * n + i];
     const int L = vt->L;
     for (int v = 0; v < vt->n_views; ++v) {
@@ -259,6 +260,7 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float acc = 0.5f;
+#pragma unroll
             for (int j = 0; j < nc; ++j) acc = fmaf(f[3 * j + ch], Y[j], acc);
             col[ch] = fmaxf(acc, 0.0f);
         }
@@ -273,29 +275,38 @@ rgs_status project_launch(const rgs_gaussians* g, const ViewTable* vt, const flo
                           const rgs_projected* out, hipStream_t s) {
     if (g->n <= 0) return RGS_OK;
     const unsigned grid = (unsigned)((g->n + PJ_THREADS - 1) / PJ_THREADS);
-    hipLaunchKernelGGL(k_project, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, *out);
+    switch (g->sh_degree) {
+        case 0: hipLaunchKernelGGL(k_project<0>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, *out); break;
+        case 1: hipLaunchKernelGGL(k_project<1>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, *out); break;
+        case 2: hipLaunchKernelGGL(k_project<2>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, *out); break;
+        default: hipLaunchKernelGGL(k_project<3>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, *out); break;
+    }
     return launch_check();
 }
 
 // ------------------------------------------------------------------ backward
 // Recomputes the forward in fp32 and applies the chain rule; gradients of
 // the views are summed in registers and written once per parameter.
+template <int D>
 __global__ __launch_bounds__(PJ_THREADS) void k_project_bwd(const float* __restrict__ dproj, rgs_gaussians g,
                                                             const uint32_t* __restrict__ count,
                                                             const ViewTable* __restrict__ vt, rgs_gaussians_grad out) {
     const int64_t n = g.n;
     const int64_t i = (int64_t)blockIdx.x * PJ_THREADS + threadIdx.x;
     if (i >= n) return;
-    const int D = g.sh_degree;
-    const int nc = (D + 1) * (D + 1);
+    constexpr int nc = (D + 1) * (D + 1);
     const int64_t VN = (int64_t)vt->n_views * n;
     const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
     const float ls[3] = {g.log_scales[i], g.log_scales[n + i], g.log_scales[2 * n + i]};
     const float q4[4] = {g.quats[i], g.quats[n + i], g.quats[2 * n + i], g.quats[3 * n + i]};
     const float logit = g.opacity[i];
     float gmu[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, gop = 0.f;
-    float gsh[48];
-    for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+    float gsh[3 * nc], fsh[3 * nc];
+#pragma unroll
+    for (int k = 0; k < 3 * nc; ++k) {
+        gsh[k] = 0.f;
+        fsh[k] = g.sh[(int64_t)k * n + i];
+    }
 
     // view-independent quantities
     const float s[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
@@ -389,17 +400,19 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project_bwd(const float* __restr
         sh_eval(D, dir[0], dir[1], dir[2], Y);
         sh_grad(D, dir[0], dir[1], dir[2], GY);
         float gdir[3] = {0.f, 0.f, 0.f};
+#pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float acc = 0.5f;
-            for (int j = 0; j < nc; ++j) acc = fmaf(g.sh[(int64_t)(3 * j + ch) * n + i], Y[j], acc);
-            if (!(acc > 0.f)) continue;
-            const float gc = gd[6 + ch];
+#pragma unroll
+            for (int j = 0; j < nc; ++j) acc = fmaf(fsh[3 * j + ch], Y[j], acc);
+            const float gc = (acc > 0.f) ? gd[6 + ch] : 0.f;
+#pragma unroll
             for (int j = 0; j < nc; ++j) {
                 gsh[3 * j + ch] += Y[j] * gc;
-                const float fj = g.sh[(int64_t)(3 * j + ch) * n + i];
-                gdir[0] += fj * GY[j][0] * gc;
-                gdir[1] += fj * GY[j][1] * gc;
-                gdir[2] += fj * GY[j][2] * gc;
+                const float fj = fsh[3 * j + ch] * gc;
+                gdir[0] += fj * GY[j][0];
+                gdir[1] += fj * GY[j][1];
+                gdir[2] += fj * GY[j][2];
             }
         }
         const float dg = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
@@ -434,6 +447,7 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project_bwd(const float* __restr
     for (int a = 0; a < 3; ++a) { out.means[a * n + i] = gmu[a]; out.log_scales[a * n + i] = gls[a]; }
     for (int a = 0; a < 4; ++a) out.quats[a * n + i] = gq[a];
     out.opacity[i] = gop;
+#pragma unroll
     for (int k = 0; k < 3 * nc; ++k) out.sh[(int64_t)k * n + i] = gsh[k];
 }
 
@@ -441,7 +455,12 @@ rgs_status project_bwd_launch(const float* dproj, const rgs_gaussians* g, const 
                               const rgs_gaussians_grad* out, hipStream_t s) {
     if (g->n <= 0) return RGS_OK;
     const unsigned grid = (unsigned)((g->n + PJ_THREADS - 1) / PJ_THREADS);
-    hipLaunchKernelGGL(k_project_bwd, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out);
+    switch (g->sh_degree) {
+        case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
+        default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
+    }
     return launch_check();
 }
 

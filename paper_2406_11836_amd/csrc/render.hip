@@ -74,7 +74,6 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
     const float dxp = (fxp - V.cx) / V.fx;
     float Dp[4][3];
     float fyp[4];
-    bool done[4];
     float T[4], C[4][3];
     uint32_t last[4];
 #pragma unroll
@@ -84,7 +83,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
         const float dyp = (fyp[r] - V.cy) / V.fy;
 #pragma unroll
         for (int a = 0; a < 3; ++a) Dp[r][a] = (V.R[a] * dxp + V.R[3 + a] * dyp) + V.R[6 + a];
-        done[r] = !(sg.px < V.W && py < V.H);
+        // a stopped (or off-image) pixel samples row +inf: d^2 = inf fails every test
+        if (!(sg.px < V.W && py < V.H)) fyp[r] = INFINITY;
         T[r] = 1.0f;
         C[r][0] = C[r][1] = C[r][2] = 0.0f;
         last[r] = 0u;
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
     uint32_t n_eval = 0, n_con = 0;
 
     for (uint32_t base = begin; base < end; base += RD_BATCH) {
-        const bool alive = !(done[0] && done[1] && done[2] && done[3]);
+        const bool alive = (fyp[0] != INFINITY) | (fyp[1] != INFINITY) | (fyp[2] != INFINITY) | (fyp[3] != INFINITY);
         if (__ballot(alive) == 0ull) break;
         const uint32_t idx = base + lane;
         if (idx < end) {
@@ -120,9 +120,9 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
             for (int r = 0; r < 4; ++r) {
                 const float dy = fyp[r] - a.y;
                 d2[r] = fmaf(dy, fmaf(b.x, dy, B), A);
-                hit[r] = !done[r] && (d2[r] <= b.z);
+                hit[r] = d2[r] <= b.z;
                 any |= hit[r];
-                if (stats) n_eval += done[r] ? 0u : 1u;
+                if (stats) n_eval += (fyp[r] != INFINITY) ? 1u : 0u;
             }
             if (!any) continue;
             const float4 cl = sCl[t];
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
                     if (!in) continue;
                 }
                 if (stats) ++n_con;
-                const float G = __expf(-0.5f * d2[r]);
+                const float G = __builtin_amdgcn_exp2f(d2[r] * -0.72134752044448170368f);  // exp(-d^2/2)
                 const float sg_ = fminf(0.99f, b.y * G);
                 const float wgt = sg_ * T[r];
                 C[r][0] = fmaf(wgt, cl.x, C[r][0]);
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
                 C[r][2] = fmaf(wgt, cl.z, C[r][2]);
                 T[r] = T[r] * (1.0f - sg_);
                 last[r] = base - begin + (uint32_t)t + 1u;
-                if (T[r] < eps_T) done[r] = true;
+                if (T[r] < eps_T) fyp[r] = INFINITY;
             }
         }
         __syncthreads();
@@ -294,13 +294,14 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float* __restrict__ rec
                     if (!in) continue;
                 }
                 contrib = true;
-                const float G = __expf(-0.5f * d2);
+                const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
                 const float aG = b.y * G;
                 const float sgm = fminf(0.99f, aG);
                 const float om = 1.0f - sgm;
-                const float Tb = Tcur[r] / om;  // transmittance before this contribution
+                const float rom = __builtin_amdgcn_rcpf(om);
+                const float Tb = Tcur[r] * rom;  // transmittance before this contribution
                 const float dot = gC[r][0] * (cl.x - Bc[r][0]) + gC[r][1] * (cl.y - Bc[r][1]) + gC[r][2] * (cl.z - Bc[r][2]);
-                const float dsg = Tb * dot - gTf[r] / om;
+                const float dsg = Tb * dot - gTf[r] * rom;
                 const float wc = Tb * sgm;
                 g[6] = fmaf(wc, gC[r][0], g[6]);
                 g[7] = fmaf(wc, gC[r][1], g[7]);
@@ -324,14 +325,31 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float* __restrict__ rec
                 if (lane < 9) rp[lane] = 0.f;
                 continue;
             }
-            float out = 0.f;
+            // values 0..7: reduce-scatter over lane bits 5, 4, 3 (exchanging the
+            // half a lane does not keep), then a full sum over bits 2, 1, 0;
+            // lane 8v ends with the total of value v.  Value 8: full sum.
+            const float s8 = wave_sum_to_lane63(g[8]);
+            const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
+            float q4[4];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) {
-                const float sum = wave_sum_to_lane63(g[c]);
-                const float v = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sum), 63));
-                if (lane == c) out = v;
+            for (int k = 0; k < 4; ++k) {
+                const float keep = h5 ? g[4 + k] : g[k];
+                const float give = h5 ? g[k] : g[4 + k];
+                q4[k] = keep + __shfl_xor(give, 32, 64);
             }
-            if (lane < 9) rp[lane] = out;
+            float q2[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const float keep = h4 ? q4[2 + k] : q4[k];
+                const float give = h4 ? q4[k] : q4[2 + k];
+                q2[k] = keep + __shfl_xor(give, 16, 64);
+            }
+            float q1 = (h3 ? q2[1] : q2[0]) + __shfl_xor(h3 ? q2[0] : q2[1], 8, 64);
+            q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0xb1, 0xf, 0xf, false));  // xor 1
+            q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0x4e, 0xf, 0xf, false));  // xor 2
+            q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0x141, 0xf, 0xf, false)); // half-row mirror
+            if ((lane & 7) == 0) rp[lane >> 3] = q1;
+            if (lane == 63) rp[8] = s8;
         }
         __syncthreads();
     }
