@@ -150,7 +150,7 @@ def main():
     achieved = flops / t_rf / 1e12
     roof = {"kernel": "k_render_fwd", "bound": "alu", "achieved": round(achieved, 3),
             "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": None, "algorithmic_flop": flops, "pairs_evaluated": n_eval, "pairs_contributing": n_con,
+            "traffic": None, "algorithmic_flop": flops, "pairs_in_rect": n_eval, "pairs_contributing": n_con,
             "avg_ms": round(stages["render_fwd"], 4)}
 
     cpu = None

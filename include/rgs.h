@@ -224,8 +224,9 @@ rgs_status rgs_bin_sort(const rgs_projected *proj, int64_t n, const rgs_camera *
  * alpha exp(-d^2/2)); C_k += T_k sigma c; T_k *= 1 - sigma; a pixel stops
  * after the contribution that takes T_k below eps_T (eps_T = 0: never). */
 /* stats, if not NULL, must point to two device uint64 counters that are
- * incremented by the number of (pixel, instance) pairs whose contribute test
- * was evaluated (pixel not yet stopped) and of pairs that contributed. */
+ * incremented by the number of (pixel, instance) pairs the method must test
+ * (pixel inside the Gaussian's rectangle and not yet stopped) and of pairs
+ * that contributed. */
 rgs_status rgs_render_partial(const rgs_projected *proj, int64_t n, const rgs_bins *bins,
                               const rgs_camera *cams, int32_t n_views, const void *views_dev,
                               const rgs_kdtree *kd, float eps_T, const rgs_partials *out,

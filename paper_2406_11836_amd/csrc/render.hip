@@ -1,23 +1,25 @@
 // render.hip -- per-cell partial blending (RetinaGS Eq. 3, Eq. 4 with the
 // indicator of Eq. 6), its backward, and the per-pair gradient reduction.
 //
-// One wave64 per slot (tile t, cell k).  Lane l owns the four pixels of
-// column l mod 16 in rows l/16, l/16 + 4, l/16 + 8, l/16 + 12, so the
-// x-only terms of d^2 are computed once per Gaussian and lane:
+// One 256-thread block per slot (tile t, cell k); wave w owns the 8x8
+// quadrant (w & 1, w >> 1) of the 16x16 tile, one pixel per lane.  The
+// contribute decision d^2 <= tau uses the exact fp32 operation sequence the
+// CPU oracle mirrors:
 //   dx = (x + 0.5) - mx, A = (ca dx) dx, B = (2 cb) dx,
-//   d^2 = fma(dy, fma(cc, dy, B), A),          dy = (y + 0.5) - my,
-// the exact fp32 operation sequence the CPU oracle mirrors for the contribute
-// decision d^2 <= tau.  Gaussians are staged 64 at a time through LDS (one
-// coalesced 48-byte record per lane) and read back as wave-uniform
-// broadcasts.  A pixel stops after the contribution that takes its T_k below
-// eps_T; the wave leaves as soon as all 256 pixels have stopped.
+//   d^2 = fma(dy, fma(cc, dy, B), A),          dy = (y + 0.5) - my.
+// Gaussian records are staged through LDS (one coalesced 48-byte record per
+// thread) with a 4-bit mask of the quadrants their rectangle meets, and read
+// back as wave-uniform broadcasts; a wave skips Gaussians outside its
+// quadrant with a scalar branch.  A pixel stops after the contribution that
+// takes its T_k below eps_T; the block leaves once all 256 pixels stopped.
 //
 // Backward walks each slot back to front from the largest per-pixel `last`,
-// recovers the transmittance before every contribution by division, sums
-// each instance's gradient over the lane's four pixels, then over the wave
-// with DPP row operations (no atomics), and stores one 9-float record at
-// the instance's emission position; a second kernel sums each pair's
-// records (contiguous by construction) in a fixed order.
+// recovers the transmittance before every contribution from a reciprocal,
+// sums each instance's gradient over every wave's 64 pixels with a
+// reduce-scatter butterfly (no atomics), adds the four quadrant sums in a
+// fixed order and stores one 9-float record at the instance's emission
+// position; a second kernel sums each pair's records (contiguous by
+// construction) in a fixed order.
 #include "common.hpp"
 
 namespace rgs {
@@ -45,109 +47,123 @@ __device__ __forceinline__ SlotGeom slot_geom(const ViewTable* __restrict__ vt, 
     return g;
 }
 
-__global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec, const uint64_t* __restrict__ vals,
-                                                   const uint32_t* __restrict__ slot_key,
-                                                   const uint32_t* __restrict__ slot_range,
-                                                   const uint32_t* __restrict__ counters,
-                                                   const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
-                                                   const float* __restrict__ box_hi, float eps_T,
-                                                   float* __restrict__ outC, float* __restrict__ outT,
-                                                   uint32_t* __restrict__ outLast,
-                                                   unsigned long long* __restrict__ stats) {
-    __shared__ float4 sA[RD_BATCH], sB[RD_BATCH], sCl[RD_BATCH];
+// Quadrant mask of a Gaussian's rectangle within tile (tx, ty): bit q set iff
+// the rectangle meets 8x8 quadrant q = 2 qy + qx of the 16x16 tile.
+__device__ __forceinline__ uint32_t quad_mask(uint2 rr, int tx, int ty) {
+    const int x0 = (int)(int16_t)(rr.x & 0xffffu) - tx * 16, x1 = (int)(int16_t)(rr.x >> 16) - tx * 16;
+    const int y0 = (int)(int16_t)(rr.y & 0xffffu) - ty * 16, y1 = (int)(int16_t)(rr.y >> 16) - ty * 16;
+    const uint32_t mx = ((x0 <= 7 && x1 >= 0) ? 1u : 0u) | ((x0 <= 15 && x1 >= 8) ? 2u : 0u);
+    const uint32_t my = ((y0 <= 7 && y1 >= 0) ? 1u : 0u) | ((y0 <= 15 && y1 >= 8) ? 2u : 0u);
+    uint32_t m = 0;
+    if (my & 1u) m |= mx;
+    if (my & 2u) m |= mx << 2;
+    return m;
+}
+
+// Forward: one 256-thread block per slot; wave w owns the 8x8 quadrant
+// (w & 1, w >> 1) of the tile, one pixel per lane.  Records are staged 256 at
+// a time in LDS, each with the quadrant mask of its rectangle so that a wave
+// skips Gaussians that cannot touch its quadrant with a scalar branch.
+__global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ rec, const int16_t* __restrict__ rect,
+                                                    const uint64_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ slot_key,
+                                                    const uint32_t* __restrict__ slot_range,
+                                                    const uint32_t* __restrict__ counters,
+                                                    const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
+                                                    const float* __restrict__ box_hi, float eps_T,
+                                                    float* __restrict__ outC, float* __restrict__ outT,
+                                                    uint32_t* __restrict__ outLast,
+                                                    unsigned long long* __restrict__ stats) {
+    constexpr int NB = 256;
+    __shared__ float4 sA[NB], sB[NB], sCl[NB];
+    __shared__ uint32_t sM[NB];
+    __shared__ uint2 sR[NB];
+    __shared__ uint32_t s_alive[4];
     const uint32_t slot = blockIdx.x;
     if (slot >= counters[2]) return;
     const int L = vt->L, K = 1 << L;
-    const int lane = lane_id();
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t key = slot_key[slot];
-    const SlotGeom sg = slot_geom(vt, key, L);
-    const ViewParams& V = vt->v[sg.v];
+    const uint32_t gt = key >> L;
+    const int v = view_of_tile(vt, gt);
+    const ViewParams& V = vt->v[v];
+    const uint32_t lt = gt - V.tile_offset;
+    const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
+    const int cell = V.cell_of_rank[key & ((1u << L) - 1u)];
     const uint32_t begin = slot_range[2 * slot], end = slot_range[2 * slot + 1];
-    float blo[3], bhi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        blo[a] = box_lo[a * K + sg.cell];
-        bhi[a] = box_hi[a * K + sg.cell];
-    }
-    // per-pixel ray direction D(p) (fixed fp32 order, mirrored by the oracle)
-    const float fxp = (float)sg.px + 0.5f;
-    const float dxp = (fxp - V.cx) / V.fx;
-    float Dp[4][3];
-    float fyp[4];
-    float T[4], C[4][3];
-    uint32_t last[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int py = sg.py0 + 4 * r;
-        fyp[r] = (float)py + 0.5f;
-        const float dyp = (fyp[r] - V.cy) / V.fy;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) Dp[r][a] = (V.R[a] * dxp + V.R[3 + a] * dyp) + V.R[6 + a];
-        // a stopped (or off-image) pixel samples row +inf: d^2 = inf fails every test
-        if (!(sg.px < V.W && py < V.H)) fyp[r] = INFINITY;
-        T[r] = 1.0f;
-        C[r][0] = C[r][1] = C[r][2] = 0.0f;
-        last[r] = 0u;
-    }
+    const float blo0 = box_lo[cell], blo1 = box_lo[K + cell], blo2 = box_lo[2 * K + cell];
+    const float bhi0 = box_hi[cell], bhi1 = box_hi[K + cell], bhi2 = box_hi[2 * K + cell];
+    const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
+    const int px = tx * 16 + lx, py = ty * 16 + ly;
+    const float fxp = (float)px + 0.5f;
+    float fyp = (float)py + 0.5f;
+    const float dxp = (fxp - V.cx) / V.fx, dyp = (fyp - V.cy) / V.fy;
+    const float D0 = (V.R[0] * dxp + V.R[3] * dyp) + V.R[6];
+    const float D1 = (V.R[1] * dxp + V.R[4] * dyp) + V.R[7];
+    const float D2 = (V.R[2] * dxp + V.R[5] * dyp) + V.R[8];
     const float o0 = V.o[0], o1 = V.o[1], o2 = V.o[2];
-    uint32_t n_eval = 0, n_con = 0;
+    // a stopped (or off-image) pixel samples row +inf: d^2 = inf fails every test
+    if (!(px < V.W && py < V.H)) fyp = INFINITY;
+    float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    uint32_t last = 0u, n_eval = 0u, n_con = 0u;
+    const uint32_t qbit = 1u << (w + 1);
 
-    for (uint32_t base = begin; base < end; base += RD_BATCH) {
-        const bool alive = (fyp[0] != INFINITY) | (fyp[1] != INFINITY) | (fyp[2] != INFINITY) | (fyp[3] != INFINITY);
-        if (__ballot(alive) == 0ull) break;
-        const uint32_t idx = base + lane;
+    for (uint32_t base = begin; base < end; base += NB) {
+        const uint64_t alive = __ballot(fyp != INFINITY);
+        if (lane == 0) s_alive[w] = alive != 0ull ? 1u : 0u;
+        const uint32_t idx = base + tid;
         if (idx < end) {
             const uint32_t src = (uint32_t)(vals[idx] >> 32);
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
-            float4 a = rp[0], b = rp[1], cl = rp[2];
+            float4 a = rp[0];
+            const float4 b = rp[1], cl = rp[2];
             a.w = 2.0f * a.w;  // 2 cb (exact)
-            sA[lane] = a;
-            sB[lane] = b;
-            sCl[lane] = cl;
+            sA[tid] = a;
+            sB[tid] = b;
+            sCl[tid] = cl;
+            const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
+            sM[tid] = (quad_mask(rr, tx, ty) << 1) | (__float_as_uint(cl.w) & 1u);
+            if (stats) sR[tid] = rr;
         }
         __syncthreads();
-        const int nb = (int)((end - base) < (uint32_t)RD_BATCH ? (end - base) : (uint32_t)RD_BATCH);
-        for (int t = 0; t < nb; ++t) {
-            const float4 a = sA[t];
-            const float4 b = sB[t];
-            const float dx = fxp - a.x;
-            const float A = (a.z * dx) * dx;
-            const float B = a.w * dx;
-            float d2[4];
-            bool hit[4];
-            bool any = false;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float dy = fyp[r] - a.y;
-                d2[r] = fmaf(dy, fmaf(b.x, dy, B), A);
-                hit[r] = d2[r] <= b.z;
-                any |= hit[r];
-                if (stats) n_eval += (fyp[r] != INFINITY) ? 1u : 0u;
-            }
-            if (!any) continue;
-            const float4 cl = sCl[t];
-            const bool interior = (__float_as_uint(cl.w) & 1u) != 0u;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (!hit[r]) continue;
-                if (!interior) {
-                    const float x0 = fmaf(b.w, Dp[r][0], o0);
-                    const float x1 = fmaf(b.w, Dp[r][1], o1);
-                    const float x2 = fmaf(b.w, Dp[r][2], o2);
-                    const bool in = (blo[0] <= x0) && (x0 < bhi[0]) && (blo[1] <= x1) && (x1 < bhi[1]) &&
-                                    (blo[2] <= x2) && (x2 < bhi[2]);
+        if ((s_alive[0] | s_alive[1] | s_alive[2] | s_alive[3]) == 0u) break;
+        const int nb = (int)((end - base) < (uint32_t)NB ? (end - base) : (uint32_t)NB);
+        if (alive != 0ull) {
+            for (int t = 0; t < nb; ++t) {
+                const uint32_t m = __builtin_amdgcn_readfirstlane(sM[t]);
+                if (!(m & qbit)) continue;
+                const float4 a = sA[t];
+                const float4 b = sB[t];
+                const float dx = fxp - a.x;
+                const float A = (a.z * dx) * dx;
+                const float B = a.w * dx;
+                const float dy = fyp - a.y;
+                const float d2 = fmaf(dy, fmaf(b.x, dy, B), A);
+                if (stats && fyp != INFINITY) {
+                    // pairs the method must test: pixel inside the Gaussian's rectangle
+                    const uint2 rr = sR[t];
+                    const bool inr = px >= (int)(int16_t)(rr.x & 0xffffu) && px <= (int)(int16_t)(rr.x >> 16) &&
+                                     py >= (int)(int16_t)(rr.y & 0xffffu) && py <= (int)(int16_t)(rr.y >> 16);
+                    n_eval += inr ? 1u : 0u;
+                }
+                if (!(d2 <= b.z)) continue;
+                if (!(m & 1u)) {
+                    const float x0 = fmaf(b.w, D0, o0), x1 = fmaf(b.w, D1, o1), x2 = fmaf(b.w, D2, o2);
+                    const bool in = (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
+                                    (x2 < bhi2);
                     if (!in) continue;
                 }
                 if (stats) ++n_con;
-                const float G = __builtin_amdgcn_exp2f(d2[r] * -0.72134752044448170368f);  // exp(-d^2/2)
-                const float sg_ = fminf(0.99f, b.y * G);
-                const float wgt = sg_ * T[r];
-                C[r][0] = fmaf(wgt, cl.x, C[r][0]);
-                C[r][1] = fmaf(wgt, cl.y, C[r][1]);
-                C[r][2] = fmaf(wgt, cl.z, C[r][2]);
-                T[r] = T[r] * (1.0f - sg_);
-                last[r] = base - begin + (uint32_t)t + 1u;
-                if (T[r] < eps_T) fyp[r] = INFINITY;
+                const float4 cl = sCl[t];
+                const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
+                const float sg = fminf(0.99f, b.y * G);
+                const float wgt = sg * T;
+                C0 = fmaf(wgt, cl.x, C0);
+                C1 = fmaf(wgt, cl.y, C1);
+                C2 = fmaf(wgt, cl.z, C2);
+                T = T * (1.0f - sg);
+                last = base - begin + (uint32_t)t + 1u;
+                if (T < eps_T) fyp = INFINITY;
             }
         }
         __syncthreads();
@@ -164,192 +180,190 @@ __global__ __launch_bounds__(64) void k_render_fwd(const float* __restrict__ rec
             atomicAdd(&stats[1], c);
         }
     }
+    const int p = ly * 16 + lx;
     float* oc = outC + (size_t)slot * 768;
-    float* ot = outT + (size_t)slot * 256;
-    uint32_t* ol = outLast + (size_t)slot * 256;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int p = ((lane >> 4) + 4 * r) * 16 + (lane & 15);
-        oc[p] = C[r][0];
-        oc[256 + p] = C[r][1];
-        oc[512 + p] = C[r][2];
-        ot[p] = T[r];
-        ol[p] = last[r];
-    }
+    oc[p] = C0;
+    oc[256 + p] = C1;
+    oc[512 + p] = C2;
+    outT[(size_t)slot * 256 + p] = T;
+    outLast[(size_t)slot * 256 + p] = last;
 }
 
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
                              float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s) {
     if (slot_bound <= 0) return RGS_OK;
-    hipLaunchKernelGGL(k_render_fwd, dim3((unsigned)slot_bound), dim3(64), 0, s, proj->rec, bins->vals, bins->slot_key,
-                       bins->slot_range, bins->counters, vt, kd->box_lo, kd->box_hi, eps_T, out->C, out->T, out->last,
-                       reinterpret_cast<unsigned long long*>(stats));
+    hipLaunchKernelGGL(k_render_fwd, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect, bins->vals,
+                       bins->slot_key, bins->slot_range, bins->counters, vt, kd->box_lo, kd->box_hi, eps_T, out->C, out->T,
+                       out->last, reinterpret_cast<unsigned long long*>(stats));
     return launch_check();
 }
 
 // ------------------------------------------------------------------ backward
-__global__ __launch_bounds__(64) void k_render_bwd(const float* __restrict__ rec, const uint64_t* __restrict__ vals,
-                                                   const uint32_t* __restrict__ slot_key,
-                                                   const uint32_t* __restrict__ slot_range,
-                                                   const uint32_t* __restrict__ counters,
-                                                   const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
-                                                   const float* __restrict__ box_hi, const float* __restrict__ partT,
-                                                   const uint32_t* __restrict__ partLast, const float* __restrict__ dC,
-                                                   const float* __restrict__ dT, float* __restrict__ records) {
-    __shared__ float4 sA[RD_BATCH], sB[RD_BATCH], sCl[RD_BATCH];
-    __shared__ uint32_t sJ[RD_BATCH];
+// Sum of g[0..8] over the wave: values 0..7 by reduce-scatter over lane bits
+// 5, 4, 3 (each lane exchanges the half it does not keep) and a full sum over
+// bits 2, 1, 0, so lane 8v ends with value v; value 8 ends in lane 63.
+__device__ __forceinline__ void wave_sum9(const float* g, int lane, float* out_v, float* out_8) {
+    *out_8 = wave_sum_to_lane63(g[8]);
+    const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
+    float q4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float keep = h5 ? g[4 + k] : g[k];
+        const float give = h5 ? g[k] : g[4 + k];
+        q4[k] = keep + __shfl_xor(give, 32, 64);
+    }
+    float q2[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float keep = h4 ? q4[2 + k] : q4[k];
+        const float give = h4 ? q4[k] : q4[2 + k];
+        q2[k] = keep + __shfl_xor(give, 16, 64);
+    }
+    float q1 = (h3 ? q2[1] : q2[0]) + __shfl_xor(h3 ? q2[0] : q2[1], 8, 64);
+    q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0xb1, 0xf, 0xf, false));  // xor 1
+    q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0x4e, 0xf, 0xf, false));  // xor 2
+    q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0x141, 0xf, 0xf, false)); // half-row mirror
+    *out_v = q1;
+}
+
+// Backward: same block layout as the forward (wave w = quadrant w, one pixel
+// per lane).  Batches of 64 instances are walked back to front from the
+// block's largest `last`; every wave sums each instance's gradient over its
+// 64 pixels (zero when culled or not contributing) into LDS, and the four
+// quadrant sums are added in a fixed order into the instance's record.
+__global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ rec, const int16_t* __restrict__ rect,
+                                                    const uint64_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ slot_key,
+                                                    const uint32_t* __restrict__ slot_range,
+                                                    const uint32_t* __restrict__ counters,
+                                                    const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
+                                                    const float* __restrict__ box_hi, const float* __restrict__ partT,
+                                                    const uint32_t* __restrict__ partLast, const float* __restrict__ dC,
+                                                    const float* __restrict__ dT, float* __restrict__ records) {
+    constexpr int NB = 64;
+    __shared__ float4 sA[NB], sB[NB], sCl[NB];
+    __shared__ uint32_t sM[NB], sJ[NB];
+    __shared__ float sG[4][NB][9];
+    __shared__ uint32_t s_max[4];
     const uint32_t slot = blockIdx.x;
     if (slot >= counters[2]) return;
     const int L = vt->L, K = 1 << L;
-    const int lane = lane_id();
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t key = slot_key[slot];
-    const SlotGeom sg = slot_geom(vt, key, L);
-    const ViewParams& V = vt->v[sg.v];
+    const uint32_t gt = key >> L;
+    const int v = view_of_tile(vt, gt);
+    const ViewParams& V = vt->v[v];
+    const uint32_t lt = gt - V.tile_offset;
+    const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
+    const int cell = V.cell_of_rank[key & ((1u << L) - 1u)];
     const uint32_t begin = slot_range[2 * slot], end = slot_range[2 * slot + 1];
-    float blo[3], bhi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        blo[a] = box_lo[a * K + sg.cell];
-        bhi[a] = box_hi[a * K + sg.cell];
-    }
-    const float fxp = (float)sg.px + 0.5f;
-    const float dxp = (fxp - V.cx) / V.fx;
-    float Dp[4][3], fyp[4];
-    float Tcur[4], gTf[4], gC[4][3], Bc[4][3];
-    uint32_t last[4];
-    uint32_t maxlast = 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int py = sg.py0 + 4 * r;
-        fyp[r] = (float)py + 0.5f;
-        const float dyp = (fyp[r] - V.cy) / V.fy;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) Dp[r][a] = (V.R[a] * dxp + V.R[3 + a] * dyp) + V.R[6 + a];
-        const int p = ((lane >> 4) + 4 * r) * 16 + (lane & 15);
-        const bool valid = sg.px < V.W && py < V.H;
-        const float Tf = partT[(size_t)slot * 256 + p];
-        last[r] = valid ? partLast[(size_t)slot * 256 + p] : 0u;
-        Tcur[r] = Tf;
-        gTf[r] = valid ? dT[(size_t)slot * 256 + p] * Tf : 0.f;
-        for (int ch = 0; ch < 3; ++ch) {
-            gC[r][ch] = valid ? dC[(size_t)slot * 768 + ch * 256 + p] : 0.f;
-            Bc[r][ch] = 0.f;
-        }
-        maxlast = last[r] > maxlast ? last[r] : maxlast;
-    }
-    maxlast = wave_max_u32(maxlast);
+    const float blo0 = box_lo[cell], blo1 = box_lo[K + cell], blo2 = box_lo[2 * K + cell];
+    const float bhi0 = box_hi[cell], bhi1 = box_hi[K + cell], bhi2 = box_hi[2 * K + cell];
+    const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
+    const int px = tx * 16 + lx, py = ty * 16 + ly;
+    const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
+    const float dxp = (fxp - V.cx) / V.fx, dyp = (fyp - V.cy) / V.fy;
+    const float D0 = (V.R[0] * dxp + V.R[3] * dyp) + V.R[6];
+    const float D1 = (V.R[1] * dxp + V.R[4] * dyp) + V.R[7];
+    const float D2 = (V.R[2] * dxp + V.R[5] * dyp) + V.R[8];
     const float o0 = V.o[0], o1 = V.o[1], o2 = V.o[2];
+    const int p = ly * 16 + lx;
+    const bool valid = px < V.W && py < V.H;
+    const float Tf = partT[(size_t)slot * 256 + p];
+    const uint32_t last = valid ? partLast[(size_t)slot * 256 + p] : 0u;
+    float Tcur = Tf;
+    const float gTf = valid ? dT[(size_t)slot * 256 + p] * Tf : 0.f;
+    const float gC0 = valid ? dC[(size_t)slot * 768 + p] : 0.f;
+    const float gC1 = valid ? dC[(size_t)slot * 768 + 256 + p] : 0.f;
+    const float gC2 = valid ? dC[(size_t)slot * 768 + 512 + p] : 0.f;
+    float B0 = 0.f, B1 = 0.f, B2 = 0.f;
+    const uint32_t wmax = wave_max_u32(last);
+    if (lane == 0) s_max[w] = wmax;
+    __syncthreads();
+    const uint32_t bmax = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
     const uint32_t len = end - begin;
-
     // instances never reached by any pixel get zero records
-    for (uint32_t k = maxlast + lane; k < len; k += 64) {
-        const uint32_t j = (uint32_t)vals[begin + k];
-        float* rp = records + (size_t)j * 9;
+    for (uint32_t k = bmax + tid; k < len; k += 256) {
+        float* rp = records + (size_t)(uint32_t)vals[begin + k] * 9;
         for (int c = 0; c < 9; ++c) rp[c] = 0.f;
     }
-    if (maxlast == 0) return;
-
-    int bstart = (int)(((maxlast - 1) / RD_BATCH) * RD_BATCH);
-    for (; bstart >= 0; bstart -= RD_BATCH) {
-        const uint32_t idx = begin + (uint32_t)bstart + lane;
-        if ((uint32_t)bstart + lane < maxlast) {
-            const uint64_t vv = vals[idx];
+    const uint32_t qbit = 1u << (w + 1);
+    for (int bstart = bmax == 0 ? -1 : (int)(((bmax - 1) / NB) * NB); bstart >= 0; bstart -= NB) {
+        if (tid < NB && (uint32_t)bstart + tid < bmax) {
+            const uint64_t vv = vals[begin + bstart + tid];
             const uint32_t src = (uint32_t)(vv >> 32);
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
-            float4 a = rp[0], b = rp[1], cl = rp[2];
-            sA[lane] = a;
-            sB[lane] = b;
-            sCl[lane] = cl;
-            sJ[lane] = (uint32_t)vv;
+            const float4 cl = rp[2];
+            sA[tid] = rp[0];
+            sB[tid] = rp[1];
+            sCl[tid] = cl;
+            const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
+            sM[tid] = (quad_mask(rr, tx, ty) << 1) | (__float_as_uint(cl.w) & 1u);
+            sJ[tid] = (uint32_t)vv;
         }
+        for (int k = tid; k < 4 * NB * 9; k += 256) (&sG[0][0][0])[k] = 0.f;
         __syncthreads();
-        int tmax = (int)maxlast - 1 - bstart;
-        if (tmax > RD_BATCH - 1) tmax = RD_BATCH - 1;
+        int tmax = (int)bmax - 1 - bstart;
+        if (tmax > NB - 1) tmax = NB - 1;
         for (int t = tmax; t >= 0; --t) {
             const uint32_t pos1 = (uint32_t)(bstart + t) + 1u;  // this instance's index + 1
+            if (pos1 > wmax) continue;
+            const uint32_t m = __builtin_amdgcn_readfirstlane(sM[t]);
+            if (!(m & qbit)) continue;
             const float4 a = sA[t];
             const float4 b = sB[t];
-            const float4 cl = sCl[t];
-            const bool interior = (__float_as_uint(cl.w) & 1u) != 0u;
-            const float cb2 = 2.0f * a.w;
-            const float dx = fxp - a.x;
-            const float A = (a.z * dx) * dx;
-            const float Bx = cb2 * dx;
             float g[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) g[c] = 0.f;
             bool contrib = false;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (pos1 > last[r]) continue;
-                const float dy = fyp[r] - a.y;
-                const float d2 = fmaf(dy, fmaf(b.x, dy, Bx), A);
-                if (!(d2 <= b.z)) continue;
-                if (!interior) {
-                    const float x0 = fmaf(b.w, Dp[r][0], o0);
-                    const float x1 = fmaf(b.w, Dp[r][1], o1);
-                    const float x2 = fmaf(b.w, Dp[r][2], o2);
-                    const bool in = (blo[0] <= x0) && (x0 < bhi[0]) && (blo[1] <= x1) && (x1 < bhi[1]) &&
-                                    (blo[2] <= x2) && (x2 < bhi[2]);
-                    if (!in) continue;
+            const float dx = fxp - a.x, dy = fyp - a.y;
+            const float d2 = fmaf(dy, fmaf(b.x, dy, (2.0f * a.w) * dx), (a.z * dx) * dx);
+            if (pos1 <= last && d2 <= b.z) {
+                bool in = true;
+                if (!(m & 1u)) {
+                    const float x0 = fmaf(b.w, D0, o0), x1 = fmaf(b.w, D1, o1), x2 = fmaf(b.w, D2, o2);
+                    in = (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) && (x2 < bhi2);
                 }
-                contrib = true;
-                const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
-                const float aG = b.y * G;
-                const float sgm = fminf(0.99f, aG);
-                const float om = 1.0f - sgm;
-                const float rom = __builtin_amdgcn_rcpf(om);
-                const float Tb = Tcur[r] * rom;  // transmittance before this contribution
-                const float dot = gC[r][0] * (cl.x - Bc[r][0]) + gC[r][1] * (cl.y - Bc[r][1]) + gC[r][2] * (cl.z - Bc[r][2]);
-                const float dsg = Tb * dot - gTf[r] * rom;
-                const float wc = Tb * sgm;
-                g[6] = fmaf(wc, gC[r][0], g[6]);
-                g[7] = fmaf(wc, gC[r][1], g[7]);
-                g[8] = fmaf(wc, gC[r][2], g[8]);
-                Bc[r][0] = fmaf(sgm, cl.x - Bc[r][0], Bc[r][0]);
-                Bc[r][1] = fmaf(sgm, cl.y - Bc[r][1], Bc[r][1]);
-                Bc[r][2] = fmaf(sgm, cl.z - Bc[r][2], Bc[r][2]);
-                Tcur[r] = Tb;
-                if (aG < 0.99f) {
-                    const float dd2 = -0.5f * aG * dsg;
-                    g[5] = fmaf(dsg, G, g[5]);
-                    g[0] -= dd2 * 2.0f * (a.z * dx + a.w * dy);
-                    g[1] -= dd2 * 2.0f * (a.w * dx + b.x * dy);
-                    g[2] = fmaf(dd2, dx * dx, g[2]);
-                    g[3] = fmaf(dd2, 2.0f * dx * dy, g[3]);
-                    g[4] = fmaf(dd2, dy * dy, g[4]);
+                if (in) {
+                    contrib = true;
+                    const float4 cl = sCl[t];
+                    const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
+                    const float aG = b.y * G;
+                    const float sgm = fminf(0.99f, aG);
+                    const float rom = __builtin_amdgcn_rcpf(1.0f - sgm);
+                    const float Tb = Tcur * rom;  // transmittance before this contribution
+                    const float dot = gC0 * (cl.x - B0) + gC1 * (cl.y - B1) + gC2 * (cl.z - B2);
+                    const float dsg = Tb * dot - gTf * rom;
+                    const float wc = Tb * sgm;
+                    g[6] = wc * gC0;
+                    g[7] = wc * gC1;
+                    g[8] = wc * gC2;
+                    B0 = fmaf(sgm, cl.x - B0, B0);
+                    B1 = fmaf(sgm, cl.y - B1, B1);
+                    B2 = fmaf(sgm, cl.z - B2, B2);
+                    Tcur = Tb;
+                    if (aG < 0.99f) {
+                        const float dd2 = -0.5f * aG * dsg;
+                        g[5] = dsg * G;
+                        g[0] = -dd2 * 2.0f * (a.z * dx + a.w * dy);
+                        g[1] = -dd2 * 2.0f * (a.w * dx + b.x * dy);
+                        g[2] = dd2 * dx * dx;
+                        g[3] = dd2 * 2.0f * dx * dy;
+                        g[4] = dd2 * dy * dy;
+                    }
                 }
             }
-            float* rp = records + (size_t)sJ[t] * 9;
-            if (__ballot(contrib) == 0ull) {
-                if (lane < 9) rp[lane] = 0.f;
-                continue;
-            }
-            // values 0..7: reduce-scatter over lane bits 5, 4, 3 (exchanging the
-            // half a lane does not keep), then a full sum over bits 2, 1, 0;
-            // lane 8v ends with the total of value v.  Value 8: full sum.
-            const float s8 = wave_sum_to_lane63(g[8]);
-            const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
-            float q4[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float keep = h5 ? g[4 + k] : g[k];
-                const float give = h5 ? g[k] : g[4 + k];
-                q4[k] = keep + __shfl_xor(give, 32, 64);
-            }
-            float q2[2];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const float keep = h4 ? q4[2 + k] : q4[k];
-                const float give = h4 ? q4[k] : q4[2 + k];
-                q2[k] = keep + __shfl_xor(give, 16, 64);
-            }
-            float q1 = (h3 ? q2[1] : q2[0]) + __shfl_xor(h3 ? q2[0] : q2[1], 8, 64);
-            q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0xb1, 0xf, 0xf, false));  // xor 1
-            q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0x4e, 0xf, 0xf, false));  // xor 2
-            q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0x141, 0xf, 0xf, false)); // half-row mirror
-            if ((lane & 7) == 0) rp[lane >> 3] = q1;
-            if (lane == 63) rp[8] = s8;
+            if (__ballot(contrib) == 0ull) continue;
+            float sv, s8;
+            wave_sum9(g, lane, &sv, &s8);
+            if ((lane & 7) == 0) sG[w][t][lane >> 3] = sv;
+            if (lane == 63) sG[w][t][8] = s8;
+        }
+        __syncthreads();
+        for (int k = tid; k < NB * 9; k += 256) {
+            const int t = k / 9, c = k % 9;
+            if ((uint32_t)bstart + t < bmax)
+                records[(size_t)sJ[t] * 9 + c] = (sG[0][t][c] + sG[1][t][c]) + (sG[2][t][c] + sG[3][t][c]);
         }
         __syncthreads();
     }
@@ -385,9 +399,9 @@ rgs_status render_bwd_launch(const rgs_partials_grad* dparts, const rgs_partials
                              const rgs_kdtree* kd, float* dproj, void* ws, int64_t slot_bound, hipStream_t s) {
     float* records = reinterpret_cast<float*>(ws);
     if (slot_bound > 0)
-        hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)slot_bound), dim3(64), 0, s, proj->rec, bins->vals, bins->slot_key,
-                           bins->slot_range, bins->counters, vt, kd->box_lo, kd->box_hi, parts->T, parts->last, dparts->dC,
-                           dparts->dT, records);
+        hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect, bins->vals,
+                           bins->slot_key, bins->slot_range, bins->counters, vt, kd->box_lo, kd->box_hi, parts->T,
+                           parts->last, dparts->dC, dparts->dT, records);
     RGS_LAUNCH_CHECK();
     const int64_t m = (int64_t)n_views * n;
     if (m > 0)
