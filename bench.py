@@ -65,6 +65,99 @@ def cpu_baseline(p, cam, L, target_s: float):
     return n / t / 1e6, n, t
 
 
+def serving(args):
+    """Continuous-batching server against the one-view-at-a-time plain (K = 1)
+    path on the same Poisson traces (first 100 requests of each are warm-up)."""
+    import torch
+
+    from paper_2406_11836_amd import raster, scenes, serve
+
+    t0 = time.perf_counter()
+    p = scenes.scene_city_device(args.serve_n, seed=50, D=3)
+    rast = raster.Rasterizer("cuda:0")
+    kd64 = rast.kd_partition(p, 6)
+    kd1 = rast.kd_partition(p, 0, own_mask=False)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    out = {"metric": "serve p50/p99 ms & frames/s @100M splats K=64 vs plain path", "unit": "ms",
+           "n_gpus": 1, "dtype": "f32", "data": "synthetic (device-generated aerial city)",
+           "config": {"workload": "%d Gaussians SH3 resident, K=64, Poisson requests, 40%% 1280x720 / 40%% "
+                                  "1920x1080 / 20%% 3840x2160" % args.serve_n, "requests_per_rate": args.serve_requests,
+                      "warmup_requests": 100},
+           "scene_prep_s": round(prep_s, 2), "rates": {}}
+    for rate in [float(x) for x in args.serve_rates.split(",")]:
+        res = {}
+        for name, kd, kw in (("batched", kd64, dict(max_batch=8, workers=2, cull=True)),
+                             ("plain", kd1, dict(max_batch=1, workers=1, cull=False))):
+            reqs = serve.serve_trace(rate, args.serve_requests, seed=int(30 + rate))
+            srv = serve.Server(p, kd, **kw)
+            srv.run(reqs)
+            res[name] = serve.latency_stats(reqs, 100, srv)
+            print("rate %g %s %s" % (rate, name, res[name]), file=sys.stderr, flush=True)
+        out["rates"][str(int(rate))] = res
+    return out
+
+
+def batched(args):
+    """16 views of uneven resolution in one fused pass (per-view L1, summed)
+    against 16 sequential single-view plain (K = 1) passes on the same views."""
+    import numpy as np
+    import torch
+
+    from paper_2406_11836_amd import raster, scenes
+
+    p = scenes.scene_clusters(4_000_000, seed=40, D=3)
+    cams = scenes.config4_cameras(16)
+    targets = [torch.from_numpy(scenes.target_image(42 + k, c["W"], c["H"])).cuda() for k, c in enumerate(cams)]
+    rast = raster.Rasterizer("cuda:0")
+    dp = raster.to_device(p)
+    kd16 = rast.kd_partition(dp, 4)
+    kd1 = rast.kd_partition(dp, 0)
+
+    def fused():
+        st = rast.forward(dp, kd16, cams, 5e-5)
+        d = torch.empty_like(st.image)
+        po = 0
+        for (img, _), tg, c in zip(st.images(), targets, cams):
+            _, dv = rast.loss(img, tg, 0.0)
+            n = 3 * c["W"] * c["H"]
+            d[po: po + n] = dv.view(-1)
+            po += n
+        return rast.backward(st, dp, d)
+
+    def sequential():
+        acc = None
+        for c, tg in zip(cams, targets):
+            st = rast.forward(dp, kd1, [c], 5e-5)
+            _, dv = rast.loss(st.image.view(3, c["H"], c["W"]), tg, 0.0)
+            g = rast.backward(st, dp, dv.view(-1))
+            acc = g if acc is None else {k: acc[k] + g[k] for k in raster.PARAM_KEYS}
+        return acc
+
+    def timeit(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    t_f = timeit(fused, args.steps, args.warmup)
+    t_s = timeit(sequential, max(2, args.steps // 2), 1)
+    pix = sum(c["W"] * c["H"] for c in cams)
+    return {"metric": "batched 16-view fwd+bwd ms & Mpix/s @4M splats K=16 vs 16 sequential plain passes",
+            "value": round(pix / (t_f * 1e-3) / 1e6, 3), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(t_f, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "4M Gaussians SH3, 16 views of {960x540,1600x1060,1920x1080,3840x2160}, K=16, L1",
+                       "total_pixels": pix, "resolutions": [[c["W"], c["H"]] for c in cams]},
+            "sequential_plain_ms": round(t_s, 3), "speedup_vs_sequential": round(t_s / t_f, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +166,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving: 100M-Gaussian city resident in HBM, Poisson traces, continuous batching vs plain path")
+    ap.add_argument("--serve-n", type=int, default=100_000_000)
+    ap.add_argument("--serve-requests", type=int, default=2100)
+    ap.add_argument("--serve-rates", type=str, default="50,200,800")
+    ap.add_argument("--batched", action="store_true",
+                    help="16-view batched step (4M Gaussians) against 16 sequential plain K=1 passes")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -88,6 +188,12 @@ def main():
     from paper_2406_11836_amd import raster, scenes
 
     torch.cuda.set_device(0)
+    if args.batched:
+        print(json.dumps(batched(args)))
+        return
+    if args.serve:
+        print(json.dumps(serving(args)))
+        return
     if args.calib_copy:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

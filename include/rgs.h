@@ -111,6 +111,8 @@ typedef struct {
     int32_t *center_cell;  /* [N] leaf containing each centre (output of rgs_kd_partition) */
     int32_t *counts;       /* [K] centres per leaf */
     uint32_t *own_mask;    /* [N][ceil(K/32)] the paper's subsets N_k, or NULL to skip */
+    float *cell_bounds;    /* [6][K] per cell: min x,y,z then max x,y,z of centre -/+ D_i over its
+                              Gaussians (empty cell: +inf / -inf), or NULL to skip */
 } rgs_kdtree;
 
 /* Per-(view, Gaussian) projection output. */
@@ -159,8 +161,15 @@ size_t rgs_views_bytes(void);
  * order, from rgs_cell_order).  Copies from host memory on `stream`; the
  * host arrays may be reused when the call returns.  Global tiles of view v
  * follow those of views 0..v-1 (16 x 16 tiles, row-major). */
+/* cell_visible ([host] n_views masks, or NULL = every cell): bit k clear
+ * promises that no Gaussian whose centre lies in cell k (kd->center_cell) can
+ * reach view v; rgs_project_sh then culls those Gaussians without reading
+ * their parameters.  A caller that clears bits must be conservative (e.g. the
+ * cell's centre bounds inflated by the largest 3-sigma extent, tested against
+ * a padded frustum); a wrong mask changes the image. */
 rgs_status rgs_views_upload(const rgs_camera *cams, int32_t n_views, int32_t L,
-                            const int32_t *rank_of, void *views_dev, rgs_stream stream);
+                            const int32_t *rank_of, const uint64_t *cell_visible, void *views_dev,
+                            rgs_stream stream);
 /* [host] total 16x16 tiles over the views. */
 int64_t rgs_total_tiles(const rgs_camera *cams, int32_t n_views);
 
@@ -175,7 +184,9 @@ int64_t rgs_total_tiles(const rgs_camera *cams, int32_t n_views);
  * right 1), first level most significant.  own_mask, if not NULL, marks
  * N_k = { i : centre in the leaf box inflated by D_i on every face },
  * D_i = d_factor * max_a exp(log_scale_a) (the paper uses three times the
- * major axis).  Writes split, box_lo/hi, center_cell, counts, own_mask. */
+ * major axis).  Writes split, box_lo/hi, center_cell, counts, own_mask and
+ * cell_bounds (the box of N_k's inflated centres: what a view must see for
+ * cell k to matter, used for cell culling). */
 size_t rgs_kd_partition_workspace(int64_t n, int32_t L);
 rgs_status rgs_kd_partition(const rgs_gaussians *g, int32_t L, float d_factor, const rgs_kdtree *kd,
                             void *ws, size_t ws_bytes, rgs_stream stream);
@@ -196,6 +207,7 @@ rgs_status rgs_cell_order(int32_t L, const float *split_host, const float campos
  * sample-pixel rectangle, the cell set (KD leaves met by the padded box of
  * the footprint's ray crossing points) and the instance count.
  * rec[11] holds flag bits (bit 0: the footprint lies in one cell). */
+/* If the views carry cell visibility masks, kd->center_cell must be set. */
 rgs_status rgs_project_sh(const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
                           const void *views_dev, const rgs_kdtree *kd, const rgs_projected *out,
                           rgs_stream stream);

@@ -37,7 +37,7 @@ class Camera(C.Structure):
 
 class KdTree(C.Structure):
     _fields_ = [("L", i32), ("split", vp), ("box_lo", vp), ("box_hi", vp), ("center_cell", vp), ("counts", vp),
-                ("own_mask", vp)]
+                ("own_mask", vp), ("cell_bounds", vp)]
 
 
 class Projected(C.Structure):
@@ -64,7 +64,7 @@ _SIGS = {
     "rgs_status_string": (C.c_char_p, [i32]),
     "rgs_last_hip_error": (i32, []),
     "rgs_views_bytes": (sz, []),
-    "rgs_views_upload": (i32, [P(Camera), i32, i32, vp, vp, vp]),
+    "rgs_views_upload": (i32, [P(Camera), i32, i32, vp, vp, vp, vp]),
     "rgs_total_tiles": (i64, [P(Camera), i32]),
     "rgs_kd_partition_workspace": (sz, [i64, i32]),
     "rgs_kd_partition": (i32, [P(Gaussians), i32, f32, P(KdTree), vp, sz, vp]),

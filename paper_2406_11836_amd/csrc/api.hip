@@ -19,8 +19,8 @@ rgs_status launch_check() {
 
 size_t kd_ws_bytes(int64_t n, int L);
 rgs_status kd_partition(const rgs_gaussians* g, int L, float d_factor, const rgs_kdtree* kd, void* ws, hipStream_t s);
-rgs_status project_launch(const rgs_gaussians* g, const ViewTable* vt, const float* split, const rgs_projected* out,
-                          hipStream_t s);
+rgs_status project_launch(const rgs_gaussians* g, const ViewTable* vt, const float* split, const int32_t* center_cell,
+                          const rgs_projected* out, hipStream_t s);
 rgs_status project_bwd_launch(const float* dproj, const rgs_gaussians* g, const uint32_t* count, const ViewTable* vt,
                               const rgs_gaussians_grad* out, hipStream_t s);
 size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t capacity);
@@ -93,8 +93,8 @@ int64_t rgs_total_tiles(const rgs_camera* cams, int32_t n_views) {
     return t;
 }
 
-rgs_status rgs_views_upload(const rgs_camera* cams, int32_t n_views, int32_t L, const int32_t* rank_of, void* views_dev,
-                            rgs_stream stream) {
+rgs_status rgs_views_upload(const rgs_camera* cams, int32_t n_views, int32_t L, const int32_t* rank_of,
+                            const uint64_t* cell_visible, void* views_dev, rgs_stream stream) {
     if (!cams_ok(cams, n_views) || L < 0 || L > RGS_MAX_L || !rank_of || !views_dev) return RGS_E_ARG;
     const int K = 1 << L;
     ViewTable vt;
@@ -127,6 +127,9 @@ rgs_status rgs_views_upload(const rgs_camera* cams, int32_t n_views, int32_t L, 
             p.rank_of_cell[k] = (uint8_t)r;
             p.cell_of_rank[r] = (uint8_t)k;
         }
+        const uint64_t full = (K == 64) ? ~0ull : ((1ull << K) - 1ull);
+        p.cell_visible = cell_visible ? (cell_visible[v] & full) : full;
+        if (p.cell_visible != full) vt.culled = 1u;
     }
     vt.total_tiles = tile_off;
     RGS_HIP_CHECK(hipMemcpyAsync(views_dev, &vt, sizeof(vt), hipMemcpyHostToDevice, S(stream)));
@@ -178,7 +181,7 @@ rgs_status rgs_project_sh(const rgs_gaussians* g, const rgs_camera* cams, int32_
     if (!gauss_ok(g) || !cams_ok(cams, n_views) || !views_dev || !kd || !proj_ok(out)) return RGS_E_ARG;
     if (kd->L < 0 || kd->L > RGS_MAX_L || (kd->L > 0 && !kd->split)) return RGS_E_ARG;
     if ((int64_t)n_views * g->n >= 0x7fffffffLL) return RGS_E_UNSUPPORTED;
-    return project_launch(g, reinterpret_cast<const ViewTable*>(views_dev), kd->split, out, S(stream));
+    return project_launch(g, reinterpret_cast<const ViewTable*>(views_dev), kd->split, kd->center_cell, out, S(stream));
 }
 
 size_t rgs_bin_sort_workspace(int64_t n, int32_t n_views, int64_t total_tiles, int32_t L, int64_t capacity) {

@@ -21,13 +21,14 @@ struct ViewParams {
     uint32_t pix_offset;    // first pixel of this view in concatenated [H][W] maps
     uint8_t cell_of_rank[RGS_MAXK];
     uint8_t rank_of_cell[RGS_MAXK];
+    uint64_t cell_visible;  // bit k: cell k may reach this view
 };
 
 struct ViewTable {
     int32_t n_views;
     int32_t L;
     uint32_t total_tiles;
-    uint32_t pad;
+    uint32_t culled;     // 1 if some view's cell_visible mask is not full
     ViewParams v[RGS_MAX_VIEWS];
 };
 

@@ -141,7 +141,7 @@ __global__ __launch_bounds__(KD_THREADS) void k_kd_leaves(const int32_t* __restr
                                                           const float* __restrict__ log_scales, float d_factor,
                                                           const float* __restrict__ lo, const float* __restrict__ hi,
                                                           int32_t* __restrict__ center_cell, int32_t* __restrict__ counts,
-                                                          uint32_t* __restrict__ own_mask) {
+                                                          uint32_t* __restrict__ own_mask, uint32_t* __restrict__ bounds_key) {
     __shared__ int32_t s_cnt[RGS_MAXK];
     const int K = 1 << L;
     if (threadIdx.x < K) s_cnt[threadIdx.x] = 0;
@@ -153,15 +153,23 @@ __global__ __launch_bounds__(KD_THREADS) void k_kd_leaves(const int32_t* __restr
     if (threadIdx.x < K && s_cnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], s_cnt[threadIdx.x]);
     if (i >= n) return;
     center_cell[i] = leaf;
-    if (!own_mask) return;
+    if (!own_mask && !bounds_key) return;
     // D_i = d_factor * max scale; transcendental in fp64, rounded once
     const float s0 = (float)exp((double)log_scales[i]);
     const float s1 = (float)exp((double)log_scales[n + i]);
     const float s2 = (float)exp((double)log_scales[2 * n + i]);
     const float Di = d_factor * fmaxf(fmaxf(s0, s1), s2);
+    const float u[3] = {means[i], means[n + i], means[2 * n + i]};
+    if (bounds_key) {
+        // order-preserving integer keys: min/max with integer atomics (deterministic)
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&bounds_key[a * K + leaf], f2key(u[a] - Di));
+            atomicMax(&bounds_key[(3 + a) * K + leaf], f2key(u[a] + Di));
+        }
+    }
+    if (!own_mask) return;
     const int Wm = (K + 31) / 32;
     uint32_t m[2] = {0u, 0u};
-    const float u[3] = {means[i], means[n + i], means[2 * n + i]};
     for (int k = 0; k < K; ++k) {
         bool in = true;
         for (int a = 0; a < 3; ++a) {
@@ -173,9 +181,23 @@ __global__ __launch_bounds__(KD_THREADS) void k_kd_leaves(const int32_t* __restr
     for (int w = 0; w < Wm; ++w) own_mask[i * Wm + w] = m[w];
 }
 
+__global__ void k_kd_bounds_init(uint32_t* __restrict__ bk, int K) {
+    int t = threadIdx.x;
+    if (t < 6 * K) bk[t] = (t < 3 * K) ? 0xffffffffu : 0u;
+}
+
+__global__ void k_kd_bounds_final(const uint32_t* __restrict__ bk, int K, float* __restrict__ bounds) {
+    int t = threadIdx.x;
+    if (t >= 6 * K) return;
+    const uint32_t k = bk[t];
+    if (t < 3 * K) bounds[t] = (k == 0xffffffffu) ? INFINITY : key2f(k);
+    else bounds[t] = (k == 0u) ? -INFINITY : key2f(k);
+}
+
 size_t kd_ws_bytes(int64_t n, int L) {
     const int K = 1 << L;
-    return (size_t)n * sizeof(int32_t) + 256 + (size_t)K * 256 * sizeof(uint32_t) + 256 + (size_t)K * sizeof(KdState) + 256;
+    return (size_t)n * sizeof(int32_t) + 256 + (size_t)K * 256 * sizeof(uint32_t) + 256 + (size_t)K * sizeof(KdState) + 256 +
+           (size_t)6 * K * sizeof(uint32_t) + 256;
 }
 
 rgs_status kd_partition(const rgs_gaussians* g, int L, float d_factor, const rgs_kdtree* kd, void* ws, hipStream_t s) {
@@ -185,6 +207,7 @@ rgs_status kd_partition(const rgs_gaussians* g, int L, float d_factor, const rgs
     int32_t* node = c.take<int32_t>(n > 0 ? n : 1);
     uint32_t* hist = c.take<uint32_t>((size_t)K * 256);
     KdState* st = c.take<KdState>(K);
+    uint32_t* bk = c.take<uint32_t>((size_t)6 * K);
     const unsigned gridN = (unsigned)((n + KD_THREADS - 1) / KD_THREADS);
     if (n > 0) hipLaunchKernelGGL(k_kd_init, dim3(gridN), dim3(KD_THREADS), 0, s, node, n);
     int hist_blocks = (int)((n + KD_THREADS * 16 - 1) / (KD_THREADS * 16));
@@ -207,9 +230,12 @@ rgs_status kd_partition(const rgs_gaussians* g, int L, float d_factor, const rgs
         RGS_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_kd_boxes, dim3(1), dim3(64), 0, s, kd->split, L, kd->box_lo, kd->box_hi, kd->counts);
+    if (kd->cell_bounds) hipLaunchKernelGGL(k_kd_bounds_init, dim3(1), dim3(384), 0, s, bk, K);
     if (n > 0)
         hipLaunchKernelGGL(k_kd_leaves, dim3(gridN), dim3(KD_THREADS), 0, s, node, n, L, g->means, g->log_scales, d_factor,
-                           kd->box_lo, kd->box_hi, kd->center_cell, kd->counts, kd->own_mask);
+                           kd->box_lo, kd->box_hi, kd->center_cell, kd->counts, kd->own_mask,
+                           kd->cell_bounds ? bk : nullptr);
+    if (kd->cell_bounds) hipLaunchKernelGGL(k_kd_bounds_final, dim3(1), dim3(384), 0, s, bk, K, kd->cell_bounds);
     return launch_check();
 }
 

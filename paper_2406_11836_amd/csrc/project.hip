@@ -212,11 +212,24 @@ __device__ __forceinline__ uint64_t cellset32(const Proj32& p, const int r[4], c
 
 template <int D>
 __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const ViewTable* __restrict__ vt,
-                                                        const float* __restrict__ split, rgs_projected out) {
+                                                        const float* __restrict__ split,
+                                                        const int32_t* __restrict__ center_cell, rgs_projected out) {
     const int64_t n = g.n;
     const int64_t i = (int64_t)blockIdx.x * PJ_THREADS + threadIdx.x;
     if (i >= n) return;
     constexpr int nc = (D + 1) * (D + 1);
+    // cell culling: views that cannot see this Gaussian's cell get count 0,
+    // and the parameters are not read unless some view needs them
+    uint32_t view_ok = (1u << vt->n_views) - 1u;
+    if (vt->culled) {
+        const int cell = center_cell[i];
+        view_ok = 0u;
+        for (int v = 0; v < vt->n_views; ++v)
+            if ((vt->v[v].cell_visible >> cell) & 1ull) view_ok |= 1u << v;
+        for (int v = 0; v < vt->n_views; ++v)
+            if (!((view_ok >> v) & 1u)) out.count[(int64_t)v * n + i] = 0u;
+        if (view_ok == 0u) return;
+    }
     const float mu0 = g.means[i], mu1 = g.means[n + i], mu2 = g.means[2 * n + i];
     const float ls0 = g.log_scales[i], ls1 = g.log_scales[n + i], ls2 = g.log_scales[2 * n + i];
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
@@ -226,6 +239,7 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
     for (int k = 0; k < 3 * nc; ++k) f[k] = g.sh[(int64_t)k * n + i];
     const int L = vt->L;
     for (int v = 0; v < vt->n_views; ++v) {
+        if (!((view_ok >> v) & 1u)) continue;
         const ViewParams& V = vt->v[v];
         const int64_t src = (int64_t)v * n + i;
         Proj32 p;
@@ -271,15 +285,15 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
     }
 }
 
-rgs_status project_launch(const rgs_gaussians* g, const ViewTable* vt, const float* split,
+rgs_status project_launch(const rgs_gaussians* g, const ViewTable* vt, const float* split, const int32_t* center_cell,
                           const rgs_projected* out, hipStream_t s) {
     if (g->n <= 0) return RGS_OK;
     const unsigned grid = (unsigned)((g->n + PJ_THREADS - 1) / PJ_THREADS);
     switch (g->sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project<0>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, *out); break;
-        case 1: hipLaunchKernelGGL(k_project<1>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, *out); break;
-        case 2: hipLaunchKernelGGL(k_project<2>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, *out); break;
-        default: hipLaunchKernelGGL(k_project<3>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, *out); break;
+        case 0: hipLaunchKernelGGL(k_project<0>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, *out); break;
+        case 1: hipLaunchKernelGGL(k_project<1>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, *out); break;
+        case 2: hipLaunchKernelGGL(k_project<2>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, *out); break;
+        default: hipLaunchKernelGGL(k_project<3>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, *out); break;
     }
     return launch_check();
 }

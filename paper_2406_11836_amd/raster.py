@@ -71,6 +71,8 @@ class KD:
     counts: torch.Tensor
     own_mask: torch.Tensor | None
     split_host: np.ndarray
+    cell_bounds: torch.Tensor | None = None
+    cell_bounds_host: np.ndarray | None = None
 
     def struct(self) -> L.KdTree:
         k = L.KdTree()
@@ -78,6 +80,7 @@ class KD:
         k.split, k.box_lo, k.box_hi = self.split.data_ptr(), self.box_lo.data_ptr(), self.box_hi.data_ptr()
         k.center_cell, k.counts = self.center_cell.data_ptr(), self.counts.data_ptr()
         k.own_mask = self.own_mask.data_ptr() if self.own_mask is not None else None
+        k.cell_bounds = self.cell_bounds.data_ptr() if self.cell_bounds is not None else None
         return k
 
 
@@ -139,7 +142,7 @@ class Rasterizer:
                 box_lo=self._empty(3 * K, torch.float32), box_hi=self._empty(3 * K, torch.float32),
                 center_cell=self._empty(n, torch.int32), counts=self._empty(K, torch.int32),
                 own_mask=self._empty(n * ((K + 31) // 32), torch.int32) if own_mask else None,
-                split_host=np.zeros(max(K - 1, 1), np.float32))
+                split_host=np.zeros(max(K - 1, 1), np.float32), cell_bounds=self._empty(6 * K, torch.float32))
         ws_bytes = self.lib.rgs_kd_partition_workspace(n, Ldepth)
         ws = self._empty(ws_bytes, torch.uint8)
         g = gaussians_struct(params)
@@ -147,6 +150,7 @@ class Rasterizer:
         L.check("rgs_kd_partition", self.lib.rgs_kd_partition(C.byref(g), Ldepth, d_factor, C.byref(ks), _p(ws), ws_bytes,
                                                                _stream()))
         kd.split_host = kd.split.cpu().numpy().copy()
+        kd.cell_bounds_host = kd.cell_bounds.cpu().numpy().reshape(6, K).copy()
         return kd
 
     def cell_ranks(self, kd: KD, cams) -> np.ndarray:
@@ -165,9 +169,10 @@ class Rasterizer:
 
     # ------------------------------------------------------------ forward
     def forward(self, params, kd: KD, cams, eps_T: float = 5e-5, stats: torch.Tensor | None = None,
-                marks: list | None = None) -> FwdState:
+                marks: list | None = None, cell_visible=None) -> FwdState:
         """stats: optional int64 device tensor [2] (evaluated, contributing pairs), incremented.
-        marks: optional list receiving (stage, event) pairs at stage ends."""
+        marks: optional list receiving (stage, event) pairs at stage ends.
+        cell_visible: optional per-view uint64 masks of the KD cells that may reach each view."""
         lib = self.lib
         _mark(marks, "start")
         V = len(cams)
@@ -178,8 +183,10 @@ class Rasterizer:
         stream = _stream()
         ranks = self.cell_ranks(kd, cams)
         views = self._empty(lib.rgs_views_bytes(), torch.uint8)
-        L.check("rgs_views_upload", lib.rgs_views_upload(cam_arr, V, kd.L, ranks.ctypes.data_as(C.c_void_p), _p(views),
-                                                         stream))
+        vis = None if cell_visible is None else np.ascontiguousarray(cell_visible, np.uint64)
+        L.check("rgs_views_upload", lib.rgs_views_upload(cam_arr, V, kd.L, ranks.ctypes.data_as(C.c_void_p),
+                                                         None if vis is None else vis.ctypes.data_as(C.c_void_p),
+                                                         _p(views), stream))
         _mark(marks, "views")
         g = gaussians_struct(params)
         ks = kd.struct()
@@ -221,6 +228,11 @@ class Rasterizer:
         _mark(marks, "bin_sort")
         n_inst = int(bs.n_instances)
         slot_cap = int(bs.slot_capacity)
+        if slot_cap > (1 << 18):
+            # large bound (many views / tiles): size the partial maps by the
+            # actual slot count instead (one small device-to-host read)
+            slot_cap = max(int(bins["counters"][2].item()), 1)
+            bs.slot_capacity = slot_cap
         parts = dict(C=self._empty(slot_cap * 768, torch.float32), T=self._empty(slot_cap * 256, torch.float32),
                      last=self._empty(slot_cap * 256, torch.int32))
         pt = L.Partials(parts["C"].data_ptr(), parts["T"].data_ptr(), parts["last"].data_ptr())

@@ -222,3 +222,70 @@ def with_kd_axis_aligned_camera(split_x: float, W: int, H: int, dist: float = 3.
     cam["o"] = np.array([np.float32(split_x), np.float32(-dist), np.float32(0.0)], np.float32)
     cam["t"] = (-(cam["R"].astype(np.float64) @ cam["o"].astype(np.float64))).astype(np.float32)
     return cam
+
+
+def scene_city_device(n: int, seed: int, D: int = 3, half: float = 1000.0, n_boxes: int = 4000, device="cuda"):
+    """The aerial-city layout of scene_city, drawn on the GPU with torch's
+    Philox generator (for scenes too large to draw on the host); returns
+    float32 device tensors in the same layout.  Not bit-identical to
+    scene_city (different generator)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f32 = torch.float32
+
+    def U(shape, a, b):
+        return torch.rand(shape, generator=g, device=device, dtype=f32) * (b - a) + a
+
+    def N(shape, m, s):
+        return torch.randn(shape, generator=g, device=device, dtype=f32) * s + m
+
+    n_ground = n // 2
+    n_box = n - n_ground
+    bx = U((n_boxes, 2), -0.95 * half, 0.95 * half)
+    side = U((n_boxes, 2), 10.0, 60.0)
+    height = U((n_boxes,), 10.0, 150.0)
+    yaw = U((n_boxes,), 0.0, math.pi / 2)
+    a_walls = 2 * (side[:, 0] + side[:, 1]) * height
+    a_roof = side[:, 0] * side[:, 1]
+    area = (a_walls + a_roof).double()
+    cnt = torch.floor(n_box * area / area.sum()).long()
+    cnt[: n_box - int(cnt.sum())] += 1
+    bid = torch.repeat_interleave(torch.arange(n_boxes, device=device), cnt)
+    u = torch.rand((n_box, 3), generator=g, device=device, dtype=f32)
+    sx, sy, h = side[bid, 0], side[bid, 1], height[bid]
+    per = 2 * (sx + sy)
+    roof = u[:, 0] < (a_roof[bid] / (a_walls + a_roof)[bid])
+    t = u[:, 1] * per
+    lx = torch.where(t < sx, t - sx / 2, torch.where(t < sx + sy, sx / 2,
+                     torch.where(t < 2 * sx + sy, sx / 2 - (t - sx - sy), -sx / 2)))
+    ly = torch.where(t < sx, -sy / 2, torch.where(t < sx + sy, -sy / 2 + (t - sx),
+                     torch.where(t < 2 * sx + sy, sy / 2, sy / 2 - (t - 2 * sx - sy))))
+    lz = u[:, 2] * h
+    lx = torch.where(roof, (u[:, 1] - 0.5) * sx, lx)
+    ly = torch.where(roof, (u[:, 2] - 0.5) * sy, ly)
+    lz = torch.where(roof, h, lz)
+    c, s_ = torch.cos(yaw[bid]), torch.sin(yaw[bid])
+    X = bx[bid, 0] + c * lx - s_ * ly
+    Y = bx[bid, 1] + s_ * lx + c * ly
+    means = torch.empty((3, n), device=device, dtype=f32)
+    means[0, :n_ground] = U((n_ground,), -half, half)
+    means[1, :n_ground] = U((n_ground,), -half, half)
+    means[2, :n_ground] = 0.0
+    means[0, n_ground:], means[1, n_ground:], means[2, n_ground:] = X, Y, lz
+    h_ground = math.sqrt((2 * half) ** 2 / max(n_ground, 1))
+    h_box = math.sqrt(float(area.sum()) / max(n_box, 1))
+    mu_s = torch.empty(n, device=device, dtype=f32)
+    mu_s[:n_ground] = math.log(0.5 * h_ground)
+    mu_s[n_ground:] = math.log(0.5 * h_box)
+    log_scales = mu_s[None, :] + N((3, n), 0.0, 0.5)
+    q = torch.randn((4, n), generator=g, device=device, dtype=f32)
+    q = q / q.norm(dim=0, keepdim=True)
+    opacity = N((n,), 0.0, 1.0)
+    nc = (D + 1) ** 2
+    sh = torch.empty((3 * nc, n), device=device, dtype=f32)
+    sh[0:3] = (U((3, n), 0.0, 1.0) - 0.5) / Y00
+    if nc > 1:
+        sh[3:] = N((3 * (nc - 1), n), 0.0, 0.2)
+    return dict(means=means.contiguous(), log_scales=log_scales.contiguous(), quats=q.contiguous(),
+                opacity=opacity.contiguous(), sh=sh.contiguous(), sh_degree=D)

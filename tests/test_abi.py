@@ -96,11 +96,38 @@ def test_argument_errors_enqueue_nothing(lib):
     assert lib.rgs_project_sh_bwd(None, C.byref(g), C.byref(ps), cam, 1, None, C.byref(gg), None) == E
     assert lib.rgs_loss_l1_ssim(None, None, 4, 4, 0.2, None, None, None, 0, None) == E
     rk = np.zeros(4, np.int32)
-    assert lib.rgs_views_upload(cam, 0, 2, rk.ctypes.data_as(C.c_void_p), None, None) == E
-    assert lib.rgs_views_upload(cam, 1, 7, rk.ctypes.data_as(C.c_void_p), None, None) == E
+    assert lib.rgs_views_upload(cam, 0, 2, rk.ctypes.data_as(C.c_void_p), None, None, None) == E
+    assert lib.rgs_views_upload(cam, 1, 7, rk.ctypes.data_as(C.c_void_p), None, None, None) == E
     # bad camera: z_near <= 0
     bad = L.camera_array([dict(R=np.eye(3), t=[0, 0, 0], o=[0, 0, 0], fx=100, fy=100, cx=8, cy=8, W=16, H=16,
                                z_near=0.0)])
-    assert lib.rgs_views_upload(bad, 1, 2, rk.ctypes.data_as(C.c_void_p), None, None) == E
+    assert lib.rgs_views_upload(bad, 1, 2, rk.ctypes.data_as(C.c_void_p), None, None, None) == E
     o = np.zeros(3, np.float32)
     assert lib.rgs_cell_order(7, None, o.ctypes.data_as(C.c_void_p), None, None) == E
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the ABI structs have the C layout (offsets and sizes)."""
+    import subprocess
+
+    from paper_2406_11836_amd import _lib as L
+    structs = {"rgs_gaussians": L.Gaussians, "rgs_gaussians_grad": L.GaussiansGrad, "rgs_camera": L.Camera,
+               "rgs_kdtree": L.KdTree, "rgs_projected": L.Projected, "rgs_bins": L.Bins, "rgs_partials": L.Partials,
+               "rgs_partials_grad": L.PartialsGrad}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rgs.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    expect = []
+    for cname, py in structs.items():
+        expect.append("%s %d" % (cname, C.sizeof(py)))
+        for f, _ in py._fields_:
+            expect.append("%s.%s %d" % (cname, f, getattr(py, f).offset))
+    assert [x for x in out if x] == expect
