@@ -55,36 +55,66 @@ __global__ __launch_bounds__(BN_THREADS) void k_pair_counts(const uint32_t* __re
     }
 }
 
-// One thread per ordered pair writes its instances (cells ascending, tiles row-major).
+// Position of the c-th set bit (0-based) of a 64-bit mask.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int c) {
+    const int lo = __popc((uint32_t)m);
+    int base = 0;
+    uint32_t w = (uint32_t)m;
+    if (c >= lo) { c -= lo; w = (uint32_t)(m >> 32); base = 32; }
+    for (int k = 0; k < c; ++k) w &= w - 1u;
+    return base + __ffs(w) - 1;
+}
+
+// Instance emission, balanced over instances: a block takes 256 consecutive
+// ordered pairs, prefix-sums their counts in LDS and walks the block's
+// instances in chunks of 256; each thread finds its pair by binary search and
+// decodes (cell, tile) from the index inside the pair (cells ascending, tiles
+// row-major), so writes are coalesced whatever the per-pair counts.
 __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict__ pair_src, const uint32_t* __restrict__ n_dev,
                                                      const uint32_t* __restrict__ pair_off, const int16_t* __restrict__ rect,
                                                      const uint64_t* __restrict__ cellmask, int64_t n_gauss,
                                                      const ViewTable* __restrict__ vt, uint32_t* __restrict__ keys,
                                                      uint64_t* __restrict__ vals) {
-    const int64_t r = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (r >= (int64_t)*n_dev) return;
-    const uint32_t src = pair_src[r];
-    const int v = (int)(src / (uint64_t)n_gauss);
-    const ViewParams& V = vt->v[v];
+    __shared__ uint32_t s_off[BN_THREADS + 1];
+    __shared__ uint32_t s_src[BN_THREADS];
+    __shared__ uint2 s_rect[BN_THREADS];
+    __shared__ uint64_t s_mask[BN_THREADS];
+    const int64_t npairs = (int64_t)*n_dev;
+    const int64_t r0 = (int64_t)blockIdx.x * BN_THREADS;
+    if (r0 >= npairs) return;
+    const int nb = (int)((npairs - r0) < BN_THREADS ? (npairs - r0) : BN_THREADS);
+    const int t = threadIdx.x;
+    if (t < nb) {
+        const uint32_t src = pair_src[r0 + t];
+        s_src[t] = src;
+        s_rect[t] = reinterpret_cast<const uint2*>(rect)[src];
+        s_mask[t] = cellmask[src];
+        s_off[t] = pair_off[r0 + t];
+    }
+    if (t == 0) s_off[nb] = pair_off[r0 + nb];
+    __syncthreads();
+    const uint32_t j0 = s_off[0], j1 = s_off[nb];
     const int L = vt->L;
-    const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
-    const int x0 = (int)(int16_t)(rr.x & 0xffffu) >> 4, x1 = (int)(int16_t)(rr.x >> 16) >> 4;
-    const int y0 = (int)(int16_t)(rr.y & 0xffffu) >> 4, y1 = (int)(int16_t)(rr.y >> 16) >> 4;
-    uint64_t mask = cellmask[src];
-    uint32_t j = pair_off[r];
-    const uint64_t hi = (uint64_t)src << 32;
-    while (mask) {
-        const int cell = __ffsll((unsigned long long)mask) - 1;
-        mask &= mask - 1;
-        const uint32_t rank = V.rank_of_cell[cell];
-        for (int ty = y0; ty <= y1; ++ty) {
-            const uint32_t rowbase = V.tile_offset + (uint32_t)ty * (uint32_t)V.tiles_x;
-            for (int tx = x0; tx <= x1; ++tx) {
-                keys[j] = ((rowbase + (uint32_t)tx) << L) | rank;
-                vals[j] = hi | j;
-                ++j;
-            }
+    for (uint32_t j = j0 + t; j < j1; j += BN_THREADS) {
+        // last pair with s_off[p] <= j
+        int lo = 0, hi = nb - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
         }
+        const uint32_t src = s_src[lo];
+        const uint2 rr = s_rect[lo];
+        const int x0 = (int)(int16_t)(rr.x & 0xffffu) >> 4, x1 = (int)(int16_t)(rr.x >> 16) >> 4;
+        const int y0 = (int)(int16_t)(rr.y & 0xffffu) >> 4, y1 = (int)(int16_t)(rr.y >> 16) >> 4;
+        const uint32_t ntx = (uint32_t)(x1 - x0 + 1), ntiles = ntx * (uint32_t)(y1 - y0 + 1);
+        const uint32_t q = j - s_off[lo];
+        const uint32_t c = q / ntiles, tt = q - c * ntiles;
+        const uint32_t ty = (uint32_t)y0 + tt / ntx, tx = (uint32_t)x0 + tt % ntx;
+        const int v = (int)(src / (uint64_t)n_gauss);
+        const ViewParams& V = vt->v[v];
+        const int cell = nth_set_bit(s_mask[lo], (int)c);
+        keys[j] = ((V.tile_offset + ty * (uint32_t)V.tiles_x + tx) << L) | (uint32_t)V.rank_of_cell[cell];
+        vals[j] = ((uint64_t)src << 32) | j;
     }
 }
 
@@ -132,6 +162,44 @@ __global__ __launch_bounds__(BN_THREADS) void k_tile_slots(const uint32_t* __res
     if (t == total_tiles) tile_slot[t] = *n_slots;
 }
 
+// Launch order of the slots: largest first (size classes by floor(log2 len)),
+// so that long slots do not start last and stretch the tail of the render.
+__global__ __launch_bounds__(BN_THREADS) void k_slot_class_count(const uint32_t* __restrict__ slot_range,
+                                                                 const uint32_t* __restrict__ n_slots,
+                                                                 uint32_t* __restrict__ cls_cnt) {
+    __shared__ uint32_t s_c[32];
+    if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t s = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (s < (int64_t)*n_slots) {
+        const uint32_t len = slot_range[2 * s + 1] - slot_range[2 * s];
+        atomicAdd(&s_c[31 - __clz(len | 1u)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && s_c[threadIdx.x]) atomicAdd(&cls_cnt[threadIdx.x], s_c[threadIdx.x]);
+}
+
+// cls_cnt[32] counts -> cls_off[32] start of each class, classes in decreasing order.
+__global__ void k_slot_class_offsets(const uint32_t* __restrict__ cls_cnt, uint32_t* __restrict__ cls_off) {
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int c = 31; c >= 0; --c) {
+        cls_off[c] = run;
+        run += cls_cnt[c];
+    }
+}
+
+__global__ __launch_bounds__(BN_THREADS) void k_slot_class_place(const uint32_t* __restrict__ slot_range,
+                                                                 const uint32_t* __restrict__ n_slots,
+                                                                 uint32_t* __restrict__ cls_off,
+                                                                 uint32_t* __restrict__ slot_order) {
+    const int64_t s = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (s >= (int64_t)*n_slots) return;
+    const uint32_t len = slot_range[2 * s + 1] - slot_range[2 * s];
+    const uint32_t p = atomicAdd(&cls_off[31 - __clz(len | 1u)], 1u);
+    slot_order[p] = (uint32_t)s;
+}
+
 size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t capacity) {
     const int64_t m = (int64_t)n_views * n;
     const int64_t dense = total_tiles << L;
@@ -147,6 +215,7 @@ size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t 
     c.take<uint32_t>(dense + 1);      // dense end
     c.take<uint32_t>(dense + 1);      // dense flags
     c.take<uint32_t>(dense + 1);      // slot index
+    c.take<uint32_t>(64);             // slot size classes
     const int64_t big = m > capacity ? m : capacity;
     const int64_t big2 = big > dense ? big : dense;
     c.take<char>(radix_ws_bytes(big2 + 1));
@@ -177,6 +246,7 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     uint32_t* dend = c.take<uint32_t>(dense + 1);
     uint32_t* dflag = c.take<uint32_t>(dense + 1);
     uint32_t* sidx = c.take<uint32_t>(dense + 1);
+    uint32_t* cls = c.take<uint32_t>(64);
     const int64_t big = m > bins->capacity ? m : bins->capacity;
     const int64_t big2 = big > dense ? big : dense;
     void* rws = c.take<char>(radix_ws_bytes(big2 + 1));
@@ -234,6 +304,12 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
                        bins->slot_range);
     hipLaunchKernelGGL(k_tile_slots, grid(total_tiles + 1), dim3(BN_THREADS), 0, s, sidx, total_tiles, 1 << L, &cnt[2],
                        bins->tile_slot);
+    // 5. launch order of the slots (largest size class first)
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(BN_THREADS), 0, s, cls, (int64_t)32, 0u);
+    hipLaunchKernelGGL(k_slot_class_count, grid(slot_bound), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], cls);
+    hipLaunchKernelGGL(k_slot_class_offsets, dim3(1), dim3(64), 0, s, cls, cls + 32);
+    hipLaunchKernelGGL(k_slot_class_place, grid(slot_bound), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], cls + 32,
+                       bins->slot_order);
     return launch_check();
 }
 

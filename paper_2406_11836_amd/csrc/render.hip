@@ -68,6 +68,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
                                                     const uint64_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
+                                                    const uint32_t* __restrict__ slot_order,
                                                     const uint32_t* __restrict__ counters,
                                                     const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
                                                     const float* __restrict__ box_hi, float eps_T,
@@ -79,8 +80,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
     __shared__ uint32_t sM[NB];
     __shared__ uint2 sR[NB];
     __shared__ uint32_t s_alive[4];
-    const uint32_t slot = blockIdx.x;
-    if (slot >= counters[2]) return;
+    if (blockIdx.x >= counters[2]) return;
+    const uint32_t slot = slot_order[blockIdx.x];
     const int L = vt->L, K = 1 << L;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t key = slot_key[slot];
@@ -193,8 +194,8 @@ rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, co
                              float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s) {
     if (slot_bound <= 0) return RGS_OK;
     hipLaunchKernelGGL(k_render_fwd, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect, bins->vals,
-                       bins->slot_key, bins->slot_range, bins->counters, vt, kd->box_lo, kd->box_hi, eps_T, out->C, out->T,
-                       out->last, reinterpret_cast<unsigned long long*>(stats));
+                       bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
+                       eps_T, out->C, out->T, out->last, reinterpret_cast<unsigned long long*>(stats));
     return launch_check();
 }
 
@@ -235,6 +236,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
                                                     const uint64_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
+                                                    const uint32_t* __restrict__ slot_order,
                                                     const uint32_t* __restrict__ counters,
                                                     const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
                                                     const float* __restrict__ box_hi, const float* __restrict__ partT,
@@ -245,8 +247,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
     __shared__ uint32_t sM[NB], sJ[NB];
     __shared__ float sG[4][NB][9];
     __shared__ uint32_t s_max[4];
-    const uint32_t slot = blockIdx.x;
-    if (slot >= counters[2]) return;
+    if (blockIdx.x >= counters[2]) return;
+    const uint32_t slot = slot_order[blockIdx.x];
     const int L = vt->L, K = 1 << L;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t key = slot_key[slot];
@@ -400,8 +402,8 @@ rgs_status render_bwd_launch(const rgs_partials_grad* dparts, const rgs_partials
     float* records = reinterpret_cast<float*>(ws);
     if (slot_bound > 0)
         hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect, bins->vals,
-                           bins->slot_key, bins->slot_range, bins->counters, vt, kd->box_lo, kd->box_hi, parts->T,
-                           parts->last, dparts->dC, dparts->dT, records);
+                           bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
+                           parts->T, parts->last, dparts->dC, dparts->dT, records);
     RGS_LAUNCH_CHECK();
     const int64_t m = (int64_t)n_views * n;
     if (m > 0)

@@ -209,10 +209,11 @@ class Rasterizer:
             bins["vals"] = self._empty(cap, torch.int64)
             bins["slot_key"] = self._empty(slot_cap, torch.int32)
             bins["slot_range"] = self._empty(2 * slot_cap, torch.int32)
+            bins["slot_order"] = self._empty(slot_cap, torch.int32)
             bs = L.Bins()
             bs.capacity, bs.slot_capacity = cap, slot_cap
             for k in ("keys", "vals", "pair_src", "pair_off", "pair_rank", "slot_key", "slot_range", "tile_slot",
-                      "counters"):
+                      "slot_order", "counters"):
                 setattr(bs, k, bins[k].data_ptr())
             ws_bytes = lib.rgs_bin_sort_workspace(n, V, T, kd.L, cap)
             ws = self._empty(ws_bytes, torch.uint8)
