@@ -130,41 +130,55 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
         if ((s_alive[0] | s_alive[1] | s_alive[2] | s_alive[3]) == 0u) break;
         const int nb = (int)((end - base) < (uint32_t)NB ? (end - base) : (uint32_t)NB);
         if (alive != 0ull) {
-            for (int t = 0; t < nb; ++t) {
-                const uint32_t m = __builtin_amdgcn_readfirstlane(sM[t]);
-                if (!(m & qbit)) continue;
-                const float4 a = sA[t];
-                const float4 b = sB[t];
-                const float dx = fxp - a.x;
-                const float A = (a.z * dx) * dx;
-                const float B = a.w * dx;
-                const float dy = fyp - a.y;
-                const float d2 = fmaf(dy, fmaf(b.x, dy, B), A);
-                if (stats && fyp != INFINITY) {
-                    // pairs the method must test: pixel inside the Gaussian's rectangle
-                    const uint2 rr = sR[t];
-                    const bool inr = px >= (int)(int16_t)(rr.x & 0xffffu) && px <= (int)(int16_t)(rr.x >> 16) &&
-                                     py >= (int)(int16_t)(rr.y & 0xffffu) && py <= (int)(int16_t)(rr.y >> 16);
-                    n_eval += inr ? 1u : 0u;
+            // Gaussians of this batch whose rectangle meets the wave's quadrant,
+            // walked in order with the next one's LDS loads issued early
+#pragma unroll
+            for (int k = 0; k < NB / 64; ++k) {
+                const int tl = k * 64 + lane;
+                uint64_t rel = __ballot(tl < nb && (sM[tl] & qbit) != 0u);
+                if (rel == 0ull) continue;
+                int t = k * 64 + (int)__builtin_ctzll(rel);
+                float4 a = sA[t], b = sB[t];
+                while (rel) {
+                    const int tc = t;
+                    const float4 ac = a, bc = b;
+                    rel &= rel - 1ull;
+                    if (rel) {
+                        t = k * 64 + (int)__builtin_ctzll(rel);
+                        a = sA[t];
+                        b = sB[t];
+                    }
+                    const float dx = fxp - ac.x;
+                    const float A = (ac.z * dx) * dx;
+                    const float B = ac.w * dx;
+                    const float dy = fyp - ac.y;
+                    const float d2 = fmaf(dy, fmaf(bc.x, dy, B), A);
+                    if (stats && fyp != INFINITY) {
+                        // pairs the method must test: pixel inside the Gaussian's rectangle
+                        const uint2 rr = sR[tc];
+                        const bool inr = px >= (int)(int16_t)(rr.x & 0xffffu) && px <= (int)(int16_t)(rr.x >> 16) &&
+                                         py >= (int)(int16_t)(rr.y & 0xffffu) && py <= (int)(int16_t)(rr.y >> 16);
+                        n_eval += inr ? 1u : 0u;
+                    }
+                    if (!(d2 <= bc.z)) continue;
+                    const float4 cl = sCl[tc];
+                    if (!(__float_as_uint(cl.w) & 1u)) {
+                        const float x0 = fmaf(bc.w, D0, o0), x1 = fmaf(bc.w, D1, o1), x2 = fmaf(bc.w, D2, o2);
+                        const bool in = (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
+                                        (x2 < bhi2);
+                        if (!in) continue;
+                    }
+                    if (stats) ++n_con;
+                    const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
+                    const float sg = fminf(0.99f, bc.y * G);
+                    const float wgt = sg * T;
+                    C0 = fmaf(wgt, cl.x, C0);
+                    C1 = fmaf(wgt, cl.y, C1);
+                    C2 = fmaf(wgt, cl.z, C2);
+                    T = T * (1.0f - sg);
+                    last = base - begin + (uint32_t)tc + 1u;
+                    if (T < eps_T) fyp = INFINITY;
                 }
-                if (!(d2 <= b.z)) continue;
-                if (!(m & 1u)) {
-                    const float x0 = fmaf(b.w, D0, o0), x1 = fmaf(b.w, D1, o1), x2 = fmaf(b.w, D2, o2);
-                    const bool in = (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
-                                    (x2 < bhi2);
-                    if (!in) continue;
-                }
-                if (stats) ++n_con;
-                const float4 cl = sCl[t];
-                const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
-                const float sg = fminf(0.99f, b.y * G);
-                const float wgt = sg * T;
-                C0 = fmaf(wgt, cl.x, C0);
-                C1 = fmaf(wgt, cl.y, C1);
-                C2 = fmaf(wgt, cl.z, C2);
-                T = T * (1.0f - sg);
-                last = base - begin + (uint32_t)t + 1u;
-                if (T < eps_T) fyp = INFINITY;
             }
         }
         __syncthreads();
@@ -305,13 +319,15 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
         }
         for (int k = tid; k < 4 * NB * 9; k += 256) (&sG[0][0][0])[k] = 0.f;
         __syncthreads();
-        int tmax = (int)bmax - 1 - bstart;
-        if (tmax > NB - 1) tmax = NB - 1;
-        for (int t = tmax; t >= 0; --t) {
+        // Gaussians of this batch below the wave's largest `last` whose
+        // rectangle meets the wave's quadrant, walked back to front
+        const int tl = lane;
+        uint64_t rel = __ballot((uint32_t)(bstart + tl) + 1u <= wmax && (uint32_t)(bstart + tl) < bmax &&
+                                (sM[tl] & qbit) != 0u);
+        while (rel) {
+            const int t = 63 - (int)__builtin_clzll(rel);
+            rel &= ~(1ull << t);
             const uint32_t pos1 = (uint32_t)(bstart + t) + 1u;  // this instance's index + 1
-            if (pos1 > wmax) continue;
-            const uint32_t m = __builtin_amdgcn_readfirstlane(sM[t]);
-            if (!(m & qbit)) continue;
             const float4 a = sA[t];
             const float4 b = sB[t];
             float g[9];
@@ -321,14 +337,14 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
             const float dx = fxp - a.x, dy = fyp - a.y;
             const float d2 = fmaf(dy, fmaf(b.x, dy, (2.0f * a.w) * dx), (a.z * dx) * dx);
             if (pos1 <= last && d2 <= b.z) {
+                const float4 cl = sCl[t];
                 bool in = true;
-                if (!(m & 1u)) {
+                if (!(__float_as_uint(cl.w) & 1u)) {
                     const float x0 = fmaf(b.w, D0, o0), x1 = fmaf(b.w, D1, o1), x2 = fmaf(b.w, D2, o2);
                     in = (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) && (x2 < bhi2);
                 }
                 if (in) {
                     contrib = true;
-                    const float4 cl = sCl[t];
                     const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
                     const float aG = b.y * G;
                     const float sgm = fminf(0.99f, aG);

@@ -94,9 +94,14 @@ class Server:
         return self.n * 104.0 + px * 320.0
 
     def _worker(self, wid, jobs: queue.Queue, done: queue.Queue):
-        torch.cuda.set_device(self.device)
-        stream = torch.cuda.Stream(device=self.device)  # default priority
-        rast = raster.Rasterizer(str(self.device))
+        try:
+            dev = self.device if self.device.index is not None else torch.device("cuda", torch.cuda.current_device())
+            torch.cuda.set_device(dev)
+            stream = torch.cuda.Stream(device=dev)  # default priority
+            rast = raster.Rasterizer(str(dev))
+        except BaseException as e:  # report set-up failures too
+            done.put((wid, [], 0.0, e))
+            return
         while True:
             batch = jobs.get()
             if batch is None:

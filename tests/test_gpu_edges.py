@@ -1,0 +1,172 @@
+"""Edge cases and full-size sampled parity on the GPU.
+
+Edge cases: no Gaussians; every Gaussian culled; one screen-filling Gaussian;
+many centres exactly on KD split planes.  Full size: the benchmark's own
+workload (1M Gaussians, 1600x1060, K = 8, SH 3) in the same launch
+configuration, checked against the oracle on a seeded sample of pixels
+(image, partial maps) and on a sample of Gaussians (gradients of a seeded
+linear objective, with the oracle run over every pixel of their rectangles);
+the loss at full resolution on seeded images.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import device_params, gpu_partials_dense, grad_close, log
+from paper_2406_11836_amd import raster, scenes
+
+pytestmark = pytest.mark.gpu
+EPS_T = 5e-5
+
+
+@pytest.fixture(scope="module")
+def rast():
+    return raster.Rasterizer()
+
+
+def test_no_gaussians(rast):
+    p = scenes.scene_uniform(0, seed=1, D=1)
+    dp = device_params(p)
+    kd = rast.kd_partition(dp, 2)
+    cam = scenes.orbit_camera(3.0, 0.2, 0.3, 70, 50, bg=(0.25, 0.5, 0.75))
+    st = rast.forward(dp, kd, [cam], EPS_T)
+    img = st.image.view(3, 50, 70).cpu().numpy()
+    assert np.all(img[0] == np.float32(0.25)) and np.all(img[1] == 0.5) and np.all(img[2] == 0.75)
+    assert torch.all(st.T_final == 1.0)
+    g = rast.backward(st, dp, torch.ones_like(st.image))
+    assert g["means"].numel() == 0
+
+
+def test_everything_culled(rast):
+    """Camera looking away from the scene: no instance, image = background, zero gradients."""
+    p = scenes.scene_uniform(5000, seed=2, D=2)
+    dp = device_params(p)
+    kd = rast.kd_partition(dp, 3)
+    eye = np.array([5.0, 0.0, 0.0])
+    cam = scenes.make_camera(scenes.look_at(eye, eye + np.array([1.0, 0.0, 0.0])), eye, 64, 48, bg=(0.1, 0.1, 0.1))
+    st = rast.forward(dp, kd, [cam], EPS_T)
+    assert st.bins_struct.n_instances == 0
+    assert torch.all(st.T_final == 1.0)
+    g = rast.backward(st, dp, torch.ones_like(st.image))
+    for k in raster.PARAM_KEYS:
+        assert torch.count_nonzero(g[k]) == 0, k
+
+
+def test_screen_filling_gaussian(rast):
+    """One Gaussian covering the whole image plus a few small ones, K = 4."""
+    p = scenes.scene_uniform(64, seed=3, D=0, mu_s=-3.0, extent=0.3)
+    p["means"][:, 0] = 0.0
+    p["log_scales"][:, 0] = np.log(2.0)
+    p["opacity"][0] = 3.0
+    dp = device_params(p)
+    kd = rast.kd_partition(dp, 2)
+    cam = scenes.orbit_camera(2.0, 0.4, 0.2, 96, 80, z_near=0.1)
+    st = rast.forward(dp, kd, [cam], EPS_T)
+    okd = oracle.kd_partition(p["means"], p["log_scales"], 2)
+    order, _ = oracle.cell_order(2, okd["split"], cam["o"])
+    pr = oracle.project(p, cam, okd, 0)
+    assert pr["count"][0] >= 30 * 4 / 4  # spans every tile
+    r = oracle.render(pr, cam, okd, order, oracle.all_pixels(96, 80), EPS_T)
+    img = st.image.cpu().numpy().reshape(3, -1).T
+    assert np.abs(img - r["img"]).max() <= 2e-4
+
+
+def test_centres_on_split_planes(rast):
+    """Many centres share coordinates, so split values coincide with centres and
+    with each other; bit-exact tree and parity of the image."""
+    rng = np.random.default_rng(4)
+    n = 3000
+    p = scenes.scene_uniform(n, seed=5, D=1, mu_s=-3.5, extent=0.5)
+    grid = np.round(p["means"] * 4) / 4          # coordinates on a 0.25 grid
+    p["means"] = grid.astype(np.float32)
+    dp = device_params(p)
+    kd = rast.kd_partition(dp, 3)
+    okd = oracle.kd_partition(p["means"], p["log_scales"], 3)
+    assert np.array_equal(kd.split.cpu().numpy()[:7].view(np.uint32), okd["split"].view(np.uint32))
+    assert np.array_equal(kd.center_cell.cpu().numpy(), okd["center_cell"])
+    on_plane = np.isin(p["means"][0], okd["split"][:1]).sum()
+    assert on_plane > 10
+    cam = scenes.orbit_camera(2.2, 0.7, 0.35, 120, 90)
+    st = rast.forward(dp, kd, [cam], EPS_T)
+    order, _ = oracle.cell_order(3, okd["split"], cam["o"])
+    pr = oracle.project(p, cam, okd, 0)
+    r = oracle.render(pr, cam, okd, order, oracle.all_pixels(120, 90), EPS_T)
+    assert np.abs(st.image.cpu().numpy().reshape(3, -1).T - r["img"]).max() <= 2e-4
+
+
+# ---------------------------------------------------------------- full size
+@pytest.fixture(scope="module")
+def full(rast):
+    log("config 2 at full size: 1M Gaussians, 1600x1060, K = 8")
+    p, cam, tgt, L = scenes.config2()
+    dp = device_params(p)
+    kd = rast.kd_partition(dp, L)
+    st = rast.forward(dp, kd, [cam], EPS_T)
+    torch.cuda.synchronize()
+    okd = oracle.kd_partition(p["means"], p["log_scales"], L)
+    order, rank_of = oracle.cell_order(L, okd["split"], cam["o"])
+    log("oracle projection of 1M Gaussians")
+    pr = oracle.project(p, cam, okd, 0)
+    return p, cam, L, dp, kd, st, okd, order, pr
+
+
+def test_full_size_sampled_pixels(full):
+    p, cam, L, dp, kd, st, okd, order, pr = full
+    n = p["means"].shape[1]
+    assert np.array_equal(st.proj["count"][:n].cpu().numpy().view(np.uint32), pr["count"])
+    W, H = cam["W"], cam["H"]
+    rng = np.random.default_rng(123)
+    pix = np.stack([rng.integers(0, W, 1500), rng.integers(0, H, 1500)], 1).astype(np.int32)
+    # include the ragged last tile row (1060 = 66 * 16 + 4)
+    pix[:50, 1] = H - 1 - rng.integers(0, 4, 50)
+    log("oracle on %d sampled pixels of the full view" % len(pix))
+    r = oracle.render(pr, cam, okd, order, pix, EPS_T)
+    idx = pix[:, 1] * W + pix[:, 0]
+    img = st.image.cpu().numpy().reshape(3, -1).T[idx]
+    Tf = st.T_final.cpu().numpy()[idx]
+    partC, partT, _ = gpu_partials_dense(st)
+    err = max(np.abs(img - r["img"]).max(), np.abs(Tf - r["T"]).max(), np.abs(partC[idx] - r["partC"]).max(),
+              np.abs(partT[idx] - r["partT"]).max())
+    log("full size: max err over image, T, partials = %.2e (contributors per pixel up to %d)" % (err, r["ncon"].max()))
+    assert err <= 2e-4
+
+
+def test_full_size_sampled_gradients(full, rast):
+    """Gradients of sum(w * image) for 24 Gaussians with small footprints; the
+    oracle covers every pixel of their rectangles."""
+    p, cam, L, dp, kd, st, okd, order, pr = full
+    W, H = cam["W"], cam["H"]
+    rng = np.random.default_rng(77)
+    w = rng.normal(size=(3, H * W)).astype(np.float32) * 1e-3
+    g = rast.backward(st, dp, torch.from_numpy(w.ravel()).cuda())
+    dproj = g["_dproj"].view(9, -1).cpu().numpy()
+    vis = np.nonzero(pr["vis"])[0]
+    area = (pr["rect"][vis, 1] - pr["rect"][vis, 0] + 1) * (pr["rect"][vis, 3] - pr["rect"][vis, 2] + 1)
+    small = vis[(area >= 9) & (area <= 400)]
+    chosen = rng.choice(small, 24, replace=False)
+    pix = []
+    for i in chosen:
+        x0, x1, y0, y1 = pr["rect"][i]
+        yy, xx = np.meshgrid(np.arange(y0, y1 + 1), np.arange(x0, x1 + 1), indexing="ij")
+        pix.append(np.stack([xx.ravel(), yy.ravel()], 1))
+    pix = np.unique(np.concatenate(pix), axis=0).astype(np.int32)
+    log("oracle backward over %d pixels covering %d Gaussians" % (len(pix), len(chosen)))
+    idx = pix[:, 1] * W + pix[:, 0]
+    g2d = oracle.render_bwd(pr, cam, okd, order, pix, w[:, idx].T.astype(np.float64), None, EPS_T)
+    ref = g2d[chosen]
+    got = dproj[:, chosen].T
+    ok, info = grad_close(got, ref, 1e-3, "d_proj (24 Gaussians)")
+    log(str(info))
+    assert ok, info
+
+
+def test_full_resolution_loss(rast):
+    rng = np.random.default_rng(6)
+    x = rng.uniform(size=(3, 1060, 1600)).astype(np.float32)
+    y = rng.uniform(size=(3, 1060, 1600)).astype(np.float32)
+    lv, d = rast.loss(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), 0.2)
+    ol, od = oracle.loss(x.astype(np.float64), y.astype(np.float64), 0.2)
+    assert abs(lv.item() - ol) <= 1e-5 * abs(ol)
+    ok, info = grad_close(d.cpu().numpy(), od, 1e-3, "dimage 1600x1060")
+    assert ok, info
