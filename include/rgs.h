@@ -115,7 +115,8 @@ typedef struct {
                               Gaussians (empty cell: +inf / -inf), or NULL to skip */
 } rgs_kdtree;
 
-/* Per-(view, Gaussian) projection output. */
+/* Per-(view, Gaussian) projection output.  Where count is 0 (culled) only
+   count is written: rec, rect and cellmask hold whatever the buffers held. */
 typedef struct {
     float *rec;         /* [V*N][12]: mx, my, ca, cb, cc, alpha, tau, z, r, g, b, flags */
     int16_t *rect;      /* [V*N][4]: sample-pixel rectangle x_lo, x_hi, y_lo, y_hi */
@@ -191,6 +192,19 @@ int64_t rgs_total_tiles(const rgs_camera *cams, int32_t n_views);
 size_t rgs_kd_partition_workspace(int64_t n, int32_t L);
 rgs_status rgs_kd_partition(const rgs_gaussians *g, int32_t L, float d_factor, const rgs_kdtree *kd,
                             void *ws, size_t ws_bytes, rgs_stream stream);
+
+/* A copy of the Gaussians grouped by cell (Sec. 3.3: sub-model k holds the
+ * Gaussians of its cell): out[j] = in[perm[j]], cells ascending, and inside
+ * a cell along a Morton curve over the cell's bounds (8 bits per axis),
+ * ties in gid order.  kd must come from rgs_kd_partition on `in` with
+ * cell_bounds set; `out` has the same n and sh_degree and shares no buffer
+ * with `in`; perm ([N] int32, device) may be NULL.  Running rgs_kd_partition
+ * on `out` gives the same splits, boxes and counts (the tree depends only on
+ * the set of centres).  Views that cannot see a cell then skip a contiguous
+ * range of Gaussians, whose parameters projection never reads. */
+size_t rgs_group_by_cell_workspace(int64_t n);
+rgs_status rgs_group_by_cell(const rgs_gaussians *in, const rgs_kdtree *kd, int32_t L, const rgs_gaussians *out,
+                             int32_t *perm, void *ws, size_t ws_bytes, rgs_stream stream);
 
 /* [host] The order in which any ray from campos visits the cells (Eq. 5's
  * permutation o_l): in-order traversal, near child first, near = left iff

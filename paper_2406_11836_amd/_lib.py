@@ -69,6 +69,8 @@ _SIGS = {
     "rgs_kd_partition_workspace": (sz, [i64, i32]),
     "rgs_kd_partition": (i32, [P(Gaussians), i32, f32, P(KdTree), vp, sz, vp]),
     "rgs_cell_order": (i32, [i32, vp, vp, vp, vp]),
+    "rgs_group_by_cell_workspace": (sz, [i64]),
+    "rgs_group_by_cell": (i32, [P(Gaussians), P(KdTree), i32, P(Gaussians), vp, vp, sz, vp]),
     "rgs_project_sh": (i32, [P(Gaussians), P(Camera), i32, vp, P(KdTree), P(Projected), vp]),
     "rgs_bin_sort_workspace": (sz, [i64, i32, i64, i32, i64]),
     "rgs_bin_sort": (i32, [P(Projected), i64, P(Camera), i32, vp, i32, P(Bins), P(i64), vp, sz, vp]),

@@ -24,6 +24,9 @@ rgs_status project_launch(const rgs_gaussians* g, const ViewTable* vt, const flo
 rgs_status project_bwd_launch(const float* dproj, const rgs_gaussians* g, const uint32_t* count, const ViewTable* vt,
                               const rgs_gaussians_grad* out, hipStream_t s);
 size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t capacity);
+size_t group_ws_bytes(int64_t n);
+rgs_status group_by_cell(const rgs_gaussians* in, const rgs_kdtree* kd, int L, const rgs_gaussians* out, int32_t* perm,
+                         void* ws, size_t ws_bytes, hipStream_t s);
 rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt_dev, int L, int64_t total_tiles,
                     rgs_bins* bins, int64_t* n_required, void* ws, size_t ws_bytes, hipStream_t s);
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
@@ -151,6 +154,21 @@ rgs_status rgs_kd_partition(const rgs_gaussians* g, int32_t L, float d_factor, c
     if (!ws || ws_bytes < kd_ws_bytes(g->n, L)) return RGS_E_ARG;
     if (g->n > 0x7fffffff) return RGS_E_UNSUPPORTED;
     return kd_partition(g, L, d_factor, kd, ws, S(stream));
+}
+
+size_t rgs_group_by_cell_workspace(int64_t n) { return n < 0 ? 0 : group_ws_bytes(n); }
+
+rgs_status rgs_group_by_cell(const rgs_gaussians* in, const rgs_kdtree* kd, int32_t L, const rgs_gaussians* out,
+                             int32_t* perm, void* ws, size_t ws_bytes, rgs_stream stream) {
+    if (!gauss_ok(in) || !gauss_ok(out) || !kd || L < 0 || L > RGS_MAX_L) return RGS_E_ARG;
+    if (out->n != in->n || out->sh_degree != in->sh_degree) return RGS_E_ARG;
+    if (in->n > 0 && (!kd->center_cell || !kd->cell_bounds)) return RGS_E_ARG;
+    if (in->n > 0 && (out->means == in->means || out->sh == in->sh || out->quats == in->quats ||
+                      out->log_scales == in->log_scales || out->opacity == in->opacity))
+        return RGS_E_ARG;
+    if (!ws || ws_bytes < group_ws_bytes(in->n)) return RGS_E_ARG;
+    if (in->n > 0x7fffffff) return RGS_E_UNSUPPORTED;
+    return group_by_cell(in, kd, L, out, perm, ws, ws_bytes, S(stream));
 }
 
 static void order_rec(int nd, int depth, int L, const float* split, const float* o, int32_t* order, int* pos) {

@@ -16,21 +16,67 @@ namespace rgs {
 
 static constexpr int BN_THREADS = 256;
 
-__global__ __launch_bounds__(BN_THREADS) void k_vis_flags(const uint32_t* __restrict__ count, int64_t m,
-                                                          uint32_t* __restrict__ flag) {
-    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (i < m) flag[i] = count[i] > 0u ? 1u : 0u;
+// Visible-pair compaction in (view, gid) order: VC_TILE consecutive entries
+// per block; the counts are read twice (tile sums, then the ordered write),
+// 8 bytes per (view, Gaussian) entry in all.
+static constexpr int VC_ITEMS = 16;
+static constexpr int VC_TILE = BN_THREADS * VC_ITEMS;
+
+__global__ __launch_bounds__(BN_THREADS) void k_vis_count(const uint32_t* __restrict__ count, int64_t m,
+                                                          uint32_t* __restrict__ tile_sum) {
+    __shared__ uint32_t s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * VC_TILE;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < VC_ITEMS; ++k) {
+        const int64_t i = base + k * BN_THREADS + threadIdx.x;
+        c += (i < m && count[i] != 0u) ? 1u : 0u;
+    }
+    c = wave_sum_u32(c);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
 }
 
+// Entry i = base + k * 256 + t is the k-th item of thread t, so index order is
+// (k, wave, lane) order: one exclusive scan over the 64 (k, wave) ballot
+// counts gives every wave's offset for every k.
 __global__ __launch_bounds__(BN_THREADS) void k_vis_compact(const uint32_t* __restrict__ count,
-                                                            const uint32_t* __restrict__ pos, const float* __restrict__ rec,
-                                                            int64_t m, uint32_t* __restrict__ zkey,
-                                                            uint32_t* __restrict__ src_out) {
-    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (i >= m || count[i] == 0u) return;
-    const uint32_t p = pos[i];
-    zkey[p] = __float_as_uint(rec[i * RGS_REC_FLOATS + 7]);
-    src_out[p] = (uint32_t)i;
+                                                            const float* __restrict__ rec, int64_t m,
+                                                            const uint32_t* __restrict__ tile_off,
+                                                            uint32_t* __restrict__ zkey, uint32_t* __restrict__ src_out) {
+    __shared__ uint32_t s_c[VC_ITEMS * 4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * VC_TILE;
+    uint32_t fl = 0;
+#pragma unroll
+    for (int k = 0; k < VC_ITEMS; ++k) {
+        const int64_t i = base + k * BN_THREADS + threadIdx.x;
+        const bool f = i < m && count[i] != 0u;
+        fl |= (f ? 1u : 0u) << k;
+        const uint64_t b = __ballot(f);
+        if (lane == 0) s_c[k * 4 + w] = (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    if (w == 0) {
+        const uint32_t v = s_c[lane];
+        const uint32_t inc = wave_incl_scan(v);
+        s_c[lane] = inc - v;  // lane = k * 4 + wave: every lane read its value before any write
+    }
+    __syncthreads();
+    const uint32_t t0 = tile_off[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < VC_ITEMS; ++k) {
+        const bool f = (fl >> k) & 1u;
+        const uint64_t b = __ballot(f);
+        if (f) {
+            const int64_t i = base + k * BN_THREADS + threadIdx.x;
+            const uint32_t p = t0 + s_c[k * 4 + w] + (uint32_t)__popcll(b & lt_mask);
+            zkey[p] = __float_as_uint(rec[i * RGS_REC_FLOATS + 7]);
+            src_out[p] = (uint32_t)i;
+        }
+    }
 }
 
 __global__ __launch_bounds__(BN_THREADS) void k_view_keys(const uint32_t* __restrict__ src, const uint32_t* __restrict__ n_dev,
@@ -46,13 +92,17 @@ __global__ __launch_bounds__(BN_THREADS) void k_pair_counts(const uint32_t* __re
                                                             int32_t* __restrict__ pair_rank, uint32_t* __restrict__ cnt) {
     int64_t r = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
     if (r >= m_max) return;
-    if (r < (int64_t)*n_dev) {
+    const int64_t np = (int64_t)*n_dev;
+    if (r < np) {
         const uint32_t s = pair_src[r];
         pair_rank[s] = (int32_t)r;
         cnt[r] = count[s];
-    } else {
-        cnt[r] = 0u;
     }
+}
+
+// pair_off[pairs] = total instances.
+__global__ void k_pair_off_tail(uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ cnt) {
+    if (threadIdx.x == 0) pair_off[cnt[0]] = cnt[1];
 }
 
 // Position of the c-th set bit (0-based) of a 64-bit mask.
@@ -257,11 +307,13 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     auto grid = [](int64_t k) { return dim3((unsigned)((k + BN_THREADS - 1) / BN_THREADS > 0 ? (k + BN_THREADS - 1) / BN_THREADS : 1)); };
 
     // 1. visible pairs in (view, gid) order, then stable sorts by depth and by view
-    if (m > 0) hipLaunchKernelGGL(k_vis_flags, grid(m), dim3(BN_THREADS), 0, s, proj->count, m, flag);
-    if ((st = exclusive_scan_u32(flag, pos, m, &cnt[0], sws, s)) != RGS_OK) return st;
+    const int64_t vtiles = (m + VC_TILE - 1) / VC_TILE;
     if (m > 0)
-        hipLaunchKernelGGL(k_vis_compact, grid(m), dim3(BN_THREADS), 0, s, proj->count, pos, proj->rec, m, zkey,
-                           bins->pair_src);
+        hipLaunchKernelGGL(k_vis_count, dim3((unsigned)vtiles), dim3(BN_THREADS), 0, s, proj->count, m, pos);
+    if ((st = scan_tile_sums(pos, DevN{nullptr, m, 1, 1}, VC_TILE, &cnt[0], s)) != RGS_OK) return st;
+    if (m > 0)
+        hipLaunchKernelGGL(k_vis_compact, dim3((unsigned)vtiles), dim3(BN_THREADS), 0, s, proj->count, proj->rec, m, pos,
+                           zkey, bins->pair_src);
     RGS_LAUNCH_CHECK();
     if ((st = radix_sort_u32_u32_dev(zkey, bins->pair_src, zkey_alt, src_alt, &cnt[0], m, 32, rws, s)) != RGS_OK)
         return st;
@@ -274,8 +326,9 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     // 2. instance offsets per ordered pair; the instance count goes to the host
     if (m > 0) hipLaunchKernelGGL(k_pair_counts, grid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], m, proj->count,
                                   bins->pair_rank, flag);
-    if ((st = exclusive_scan_u32(flag, bins->pair_off, m, &cnt[1], sws, s)) != RGS_OK) return st;
-    RGS_HIP_CHECK(hipMemcpyAsync(bins->pair_off + m, &cnt[1], sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if ((st = exclusive_scan_u32_dev(flag, bins->pair_off, DevN{&cnt[0], m, 1, 1}, m, &cnt[1], sws, s)) != RGS_OK)
+        return st;
+    hipLaunchKernelGGL(k_pair_off_tail, dim3(1), dim3(64), 0, s, bins->pair_off, cnt);
     uint32_t h_cnt[2] = {0u, 0u};
     RGS_HIP_CHECK(hipMemcpyAsync(h_cnt, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     RGS_HIP_CHECK(hipStreamSynchronize(s));

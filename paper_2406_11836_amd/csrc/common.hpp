@@ -79,6 +79,12 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
@@ -125,10 +131,27 @@ struct WsCarver {
 
 // Device-wide primitives (sort.hip).
 namespace rgs {
+// An element count known on the host, or read on the device: ceil(*p / div) * mul.
+struct DevN {
+    const uint32_t* p;
+    int64_t host;
+    uint32_t div, mul;
+    __device__ __forceinline__ int64_t get() const {
+        if (!p) return host;
+        const int64_t v = (int64_t)*p;
+        return ((v + (int64_t)div - 1) / (int64_t)div) * (int64_t)mul;
+    }
+};
 size_t scan_ws_bytes(int64_t n);
 // out[i] = sum_{j<i} in[j]; if total != nullptr, *total (device) = sum of all.
 rgs_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* ws,
                               hipStream_t s);
+// The same over the first dn.get() elements (n_max bounds the grid).
+rgs_status exclusive_scan_u32_dev(const uint32_t* in, uint32_t* out, DevN dn, int64_t n_max, uint32_t* total, void* ws,
+                                  hipStream_t s);
+// Block-level tile scan pieces, for callers that produce the tile sums themselves:
+// exclusive scan (in place) of the sums of the first ceil(dn.get() / tile) tiles.
+rgs_status scan_tile_sums(uint32_t* partial, DevN dn, int64_t tile, uint32_t* total, hipStream_t s);
 size_t radix_ws_bytes(int64_t n);
 // Stable LSD sort of (key, value) by key bits [0, bits); the result ends in
 // keys/vals (the alt buffers are scratch of the same size).

@@ -235,8 +235,7 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
     const float logit = g.opacity[i];
     float f[3 * nc];
-#pragma unroll
-    for (int k = 0; k < 3 * nc; ++k) f[k] = g.sh[(int64_t)k * n + i];
+    bool have_sh = false;  // SH coefficients are read once, for the first view that needs them
     const int L = vt->L;
     for (int v = 0; v < vt->n_views; ++v) {
         if (!((view_ok >> v) & 1u)) continue;
@@ -248,13 +247,14 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
         bool ok = p.vis && rect32(p, V, r);
         float4* rec = reinterpret_cast<float4*>(out.rec + src * RGS_REC_FLOATS);
         if (!ok) {
+            // only the count is defined for a culled pair
             out.count[src] = 0u;
-            out.cellmask[src] = 0ull;
-            reinterpret_cast<uint2*>(out.rect)[src] = make_uint2(0u, 0u);
-            rec[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rec[2] = make_float4(0.f, 0.f, 0.f, 0.f);
             continue;
+        }
+        if (!have_sh) {
+#pragma unroll
+            for (int k = 0; k < 3 * nc; ++k) f[k] = g.sh[(int64_t)k * n + i];
+            have_sh = true;
         }
         const uint64_t mask = cellset32(p, r, V, L, split);
         const uint32_t ntx = (uint32_t)((r[1] >> 4) - (r[0] >> 4) + 1);

@@ -60,6 +60,49 @@ __device__ __forceinline__ uint32_t quad_mask(uint2 rr, int tx, int ty) {
     return m;
 }
 
+// Can a pixel centre of the 8x8 quadrant whose first pixel is (x0, y0) pass
+// the fp32 decision d^2 <= tau?  The minimum of the quadratic form over the
+// box of the quadrant's pixel centres is 0 if the mean is inside, else the
+// least of its four edge minima (a convex function of one variable each,
+// minimised at the clamped stationary point).  Against the fp32 sequence
+// used per pixel the test adds a margin of 2^-18 (ca dx^2 + cc dy^2) at the
+// box's far corner, above the rounding error of both evaluations (a few ulp
+// of |ca dx^2| + 2|cb dx dy| + |cc dy^2| <= 2 (ca dx^2 + cc dy^2)), plus
+// 2^-20 tau: a quadrant is only dropped when no pixel can contribute.
+__device__ __forceinline__ bool quad_hits(float mx, float my, float ca, float cb, float cc, float tau, float x0,
+                                          float y0) {
+    const float lx = (x0 + 0.5f) - mx, hx = (x0 + 7.5f) - mx;
+    const float ly = (y0 + 0.5f) - my, hy = (y0 + 7.5f) - my;
+    if (lx <= 0.0f && hx >= 0.0f && ly <= 0.0f && hy >= 0.0f) return true;
+    const float ica = __builtin_amdgcn_rcpf(ca), icc = __builtin_amdgcn_rcpf(cc);
+    float qmin = INFINITY;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float ex = e ? hx : lx;  // vertical edge dx = ex
+        const float dy = fminf(fmaxf(-(cb * ex) * icc, ly), hy);
+        qmin = fminf(qmin, (ca * ex) * ex + dy * (2.0f * cb * ex + cc * dy));
+        const float ey = e ? hy : ly;  // horizontal edge dy = ey
+        const float dx = fminf(fmaxf(-(cb * ey) * ica, lx), hx);
+        qmin = fminf(qmin, (cc * ey) * ey + dx * (2.0f * cb * ey + ca * dx));
+    }
+    const float far = ca * fmaxf(lx * lx, hx * hx) + cc * fmaxf(ly * ly, hy * hy);
+    return qmin <= tau + 0x1p-18f * far + 0x1p-20f * tau;
+}
+
+// Quadrant mask of a Gaussian's rectangle (quad_mask) with the quadrants its
+// ellipse d^2 <= tau cannot reach removed.
+__device__ __forceinline__ uint32_t quad_mask_ellipse(uint2 rr, int tx, int ty, float mx, float my, float ca, float cb,
+                                                      float cc, float tau) {
+    uint32_t m = quad_mask(rr, tx, ty);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if ((m >> q) & 1u) {
+            const float x0 = (float)(tx * 16 + (q & 1) * 8), y0 = (float)(ty * 16 + (q >> 1) * 8);
+            if (!quad_hits(mx, my, ca, cb, cc, tau, x0, y0)) m &= ~(1u << q);
+        }
+    return m;
+}
+
 // Forward: one 256-thread block per slot; wave w owns the 8x8 quadrant
 // (w & 1, w >> 1) of the tile, one pixel per lane.  Records are staged 256 at
 // a time in LDS, each with the quadrant mask of its rectangle so that a wave
@@ -118,12 +161,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
             float4 a = rp[0];
             const float4 b = rp[1], cl = rp[2];
+            const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
+            sM[tid] = (quad_mask_ellipse(rr, tx, ty, a.x, a.y, a.z, a.w, b.x, b.z) << 1) | (__float_as_uint(cl.w) & 1u);
             a.w = 2.0f * a.w;  // 2 cb (exact)
             sA[tid] = a;
             sB[tid] = b;
             sCl[tid] = cl;
-            const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
-            sM[tid] = (quad_mask(rr, tx, ty) << 1) | (__float_as_uint(cl.w) & 1u);
             if (stats) sR[tid] = rr;
         }
         __syncthreads();
@@ -215,31 +258,47 @@ rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, co
 
 // ------------------------------------------------------------------ backward
 // Sum of g[0..8] over the wave: values 0..7 by reduce-scatter over lane bits
-// 5, 4, 3 (each lane exchanges the half it does not keep) and a full sum over
-// bits 2, 1, 0, so lane 8v ends with value v; value 8 ends in lane 63.
+// 5, 4, 3 and a full sum over bits 2, 1, 0, so lane 8v ends with value v;
+// value 8 ends in lane 63.  Bits 5 and 4 use the gfx950 lane-swap
+// instructions: swapping the upper 32 lanes of x with the lower 32 lanes of y
+// leaves, in both outputs, x's half where lane bit 5 is clear and y's half
+// where it is set, with the partner lane's copy in the other output, so one
+// add reduces over bit 5 without a select; the 16-lane swap does the same for
+// bit 4.  Bit 3 is a row rotation by 8 (DPP), bits 2..0 quad permutes and a
+// half-row mirror; no exchange goes through LDS.
+__device__ __forceinline__ float swap32_sum(float x, float y) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                                   false, false);
+    unsigned a = r[0], b = r[1];
+    asm volatile("" : "+v"(a), "+v"(b));  // keeps the two results apart (r[0] + r[1] otherwise folds to 2 r[0])
+    return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
+}
+
+__device__ __forceinline__ float swap16_sum(float x, float y) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                                   false, false);
+    unsigned a = r[0], b = r[1];
+    asm volatile("" : "+v"(a), "+v"(b));  // keeps the two results apart (r[0] + r[1] otherwise folds to 2 r[0])
+    return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
+}
+
+#define RGS_DPP(v, ctrl) __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (v)), (ctrl), 0xf, 0xf, false))
+
 __device__ __forceinline__ void wave_sum9(const float* g, int lane, float* out_v, float* out_8) {
     *out_8 = wave_sum_to_lane63(g[8]);
-    const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
     float q4[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float keep = h5 ? g[4 + k] : g[k];
-        const float give = h5 ? g[k] : g[4 + k];
-        q4[k] = keep + __shfl_xor(give, 32, 64);
-    }
-    float q2[2];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float keep = h4 ? q4[2 + k] : q4[k];
-        const float give = h4 ? q4[k] : q4[2 + k];
-        q2[k] = keep + __shfl_xor(give, 16, 64);
-    }
-    float q1 = (h3 ? q2[1] : q2[0]) + __shfl_xor(h3 ? q2[0] : q2[1], 8, 64);
-    q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0xb1, 0xf, 0xf, false));  // xor 1
-    q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0x4e, 0xf, 0xf, false));  // xor 2
-    q1 += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, q1), 0x141, 0xf, 0xf, false)); // half-row mirror
+    for (int k = 0; k < 4; ++k) q4[k] = swap32_sum(g[k], g[4 + k]);  // bit 5 clear keeps k, set keeps 4 + k
+    const float q20 = swap16_sum(q4[0], q4[2]);                      // bit 4 clear keeps 4 h5 + 0, set + 2
+    const float q21 = swap16_sum(q4[1], q4[3]);
+    const bool h3 = (lane & 8) != 0;
+    float q1 = (h3 ? q21 : q20) + RGS_DPP(h3 ? q20 : q21, 0x128);     // row_ror:8 = lane xor 8 within a row
+    q1 += RGS_DPP(q1, 0xb1);                                          // quad_perm [1,0,3,2]
+    q1 += RGS_DPP(q1, 0x4e);                                          // quad_perm [2,3,0,1]
+    q1 += RGS_DPP(q1, 0x141);                                         // row_half_mirror
     *out_v = q1;
 }
+#undef RGS_DPP
 
 // Backward: same block layout as the forward (wave w = quadrant w, one pixel
 // per lane).  Batches of 64 instances are walked back to front from the
@@ -310,11 +369,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
             const uint32_t src = (uint32_t)(vv >> 32);
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
             const float4 cl = rp[2];
-            sA[tid] = rp[0];
-            sB[tid] = rp[1];
+            const float4 a = rp[0], b = rp[1];
+            sA[tid] = a;
+            sB[tid] = b;
             sCl[tid] = cl;
             const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
-            sM[tid] = (quad_mask(rr, tx, ty) << 1) | (__float_as_uint(cl.w) & 1u);
+            sM[tid] = (quad_mask_ellipse(rr, tx, ty, a.x, a.y, a.z, a.w, b.x, b.z) << 1) | (__float_as_uint(cl.w) & 1u);
             sJ[tid] = (uint32_t)vv;
         }
         for (int k = tid; k < 4 * NB * 9; k += 256) (&sG[0][0][0])[k] = 0.f;

@@ -39,10 +39,12 @@ __device__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* s_wave /*[4]*/, ui
     return tot;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in, DevN dn,
                                                               uint32_t* __restrict__ partial) {
     __shared__ uint32_t s_wave[4];
+    const int64_t n = dn.get();
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    if (base >= n) return;  // uniform per block
     uint32_t acc = 0;
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         int64_t i = base + k * SCAN_THREADS + threadIdx.x;
@@ -53,10 +55,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// Exclusive scan of the tile sums, in place; total to *total if non-null.
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(uint32_t* __restrict__ partial, int64_t m,
+// Exclusive scan, in place, of the sums of the first ceil(dn / tile) tiles;
+// the total to *total if non-null.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(uint32_t* __restrict__ partial, DevN dn, int64_t tile,
                                                                 uint32_t* __restrict__ total) {
     __shared__ uint32_t s_wave[4];
+    const int64_t m = (dn.get() + tile - 1) / tile;
     uint32_t carry = 0;
     for (int64_t b = 0; b < m; b += SCAN_THREADS) {
         int64_t i = b + threadIdx.x;
@@ -69,12 +73,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(uint32_t* __rest
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __restrict__ in, int64_t n,
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __restrict__ in, DevN dn,
                                                              const uint32_t* __restrict__ partial,
                                                              uint32_t* __restrict__ out) {
     __shared__ uint32_t s[SCAN_TILE + SCAN_TILE / 32];
     __shared__ uint32_t s_wave[4];
+    const int64_t n = dn.get();
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    if (base >= n) return;  // uniform per block
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         int li = k * SCAN_THREADS + threadIdx.x;
         int64_t i = base + li;
@@ -106,18 +112,30 @@ size_t scan_ws_bytes(int64_t n) {
     return (size_t)(tiles + 1) * sizeof(uint32_t) + 256;
 }
 
-rgs_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* ws,
-                              hipStream_t s) {
-    int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+rgs_status scan_tile_sums(uint32_t* partial, DevN dn, int64_t tile, uint32_t* total, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, dn, tile, total);
+    return launch_check();
+}
+
+rgs_status exclusive_scan_u32_dev(const uint32_t* in, uint32_t* out, DevN dn, int64_t n_max, uint32_t* total, void* ws,
+                                  hipStream_t s) {
     uint32_t* partial = reinterpret_cast<uint32_t*>(ws);
-    if (n <= 0) {
-        if (total) hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, (int64_t)0, total);
+    if (n_max <= 0) {
+        const DevN zero{nullptr, 0, 1, 1};
+        if (total) hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, zero, (int64_t)SCAN_TILE,
+                                      total);
         return launch_check();
     }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, n, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, tiles, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, n, partial, out);
+    const int64_t tiles = (n_max + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, dn, partial);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, dn, (int64_t)SCAN_TILE, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, dn, partial, out);
     return launch_check();
+}
+
+rgs_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* ws,
+                              hipStream_t s) {
+    return exclusive_scan_u32_dev(in, out, DevN{nullptr, n, 1, 1}, n, total, ws, s);
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -135,6 +153,9 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restri
                                                         uint32_t* __restrict__ hist, int ntiles) {
     __shared__ uint32_t s_h[256];
     const int64_t n = rs_n(n_host, n_dev);
+    // with a device count the table is [256][tiles in use]
+    if (n_dev) ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
+    if ((int)blockIdx.x >= ntiles) return;  // uniform per block
     s_h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
@@ -161,6 +182,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
     __shared__ V s_vals[RS_TILE];
 
     const int64_t n = rs_n(n_host, n_dev);
+    if (n_dev) ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
+    if ((int)blockIdx.x >= ntiles) return;  // uniform per block
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int k = threadIdx.x; k < 4 * 256; k += RS_THREADS) (&s_cnt[0][0])[k] = 0;
@@ -226,6 +249,17 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
     }
 }
 
+template <typename V>
+__global__ __launch_bounds__(256) void k_rs_copy(const uint32_t* __restrict__ ki, const V* __restrict__ vi,
+                                                 int64_t n_host, const uint32_t* __restrict__ n_dev,
+                                                 uint32_t* __restrict__ ko, V* __restrict__ vo) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < rs_n(n_host, n_dev)) {
+        ko[i] = ki[i];
+        vo[i] = vi[i];
+    }
+}
+
 size_t radix_ws_bytes(int64_t n) {
     int64_t tiles = (n + RS_TILE - 1) / RS_TILE;
     if (tiles < 1) tiles = 1;
@@ -250,7 +284,8 @@ static rgs_status radix_sort_impl(uint32_t* keys, V* vals, uint32_t* keys_alt, V
         int shift = 8 * p;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(RS_THREADS), 0, s, ki, n, n_dev, shift, hist,
                            (int)tiles);
-        rgs_status st = exclusive_scan_u32(hist, offs, 256 * tiles, nullptr, scan_ws, s);
+        const DevN tn{n_dev, 256 * tiles, (uint32_t)RS_TILE, 256u};
+        rgs_status st = exclusive_scan_u32_dev(hist, offs, tn, 256 * tiles, nullptr, scan_ws, s);
         if (st != RGS_OK) return st;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<V>), dim3((unsigned)tiles), dim3(RS_THREADS), 0, s, ki, vi,
                            n, n_dev, shift, offs, (int)tiles, ko, vo);
@@ -259,10 +294,10 @@ static rgs_status radix_sort_impl(uint32_t* keys, V* vals, uint32_t* keys_alt, V
         V* tv = vi; vi = vo; vo = tv;
     }
     if (ki != keys) {
-        // odd number of passes: copy back
-        int64_t cnt = n;
-        RGS_HIP_CHECK(hipMemcpyAsync(keys, ki, cnt * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-        RGS_HIP_CHECK(hipMemcpyAsync(vals, vi, cnt * sizeof(V), hipMemcpyDeviceToDevice, s));
+        // odd number of passes: copy back (the elements in use only)
+        const unsigned g = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_copy<V>), dim3(g), dim3(256), 0, s, ki, vi, n, n_dev, keys, vals);
+        RGS_LAUNCH_CHECK();
     }
     return RGS_OK;
 }

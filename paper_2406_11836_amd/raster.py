@@ -153,6 +153,21 @@ class Rasterizer:
         kd.cell_bounds_host = kd.cell_bounds.cpu().numpy().reshape(6, K).copy()
         return kd
 
+    def group_by_cell(self, params, kd: KD):
+        """Copy of the parameters grouped by KD cell (Morton order inside a
+        cell) and its permutation perm (new index -> old gid, int32)."""
+        n = int(params["means"].shape[1])
+        out = {k: torch.empty_like(params[k]) for k in PARAM_KEYS}
+        out["sh_degree"] = int(params["sh_degree"])
+        perm = self._empty(n, torch.int32)
+        ws_bytes = self.lib.rgs_group_by_cell_workspace(n)
+        ws = self._empty(ws_bytes, torch.uint8)
+        gi, go = gaussians_struct(params), gaussians_struct(out)
+        ks = kd.struct()
+        L.check("rgs_group_by_cell", self.lib.rgs_group_by_cell(C.byref(gi), C.byref(ks), kd.L, C.byref(go), _p(perm),
+                                                                 _p(ws), ws_bytes, _stream()))
+        return out, perm
+
     def cell_ranks(self, kd: KD, cams) -> np.ndarray:
         K = 1 << kd.L
         ranks = np.zeros((len(cams), K), np.int32)
