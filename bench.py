@@ -98,8 +98,9 @@ def cpu_baseline(p, cam, L, target_s: float):
 
 
 def serving(args):
-    """Continuous-batching server against the one-view-at-a-time plain (K = 1)
-    path on the same Poisson traces (first 100 requests of each are warm-up)."""
+    """Continuous-batching server (K = 64 with cell culling, and K = 1) against
+    the one-view-at-a-time plain (K = 1) path on the same Poisson traces (first
+    100 requests of each are warm-up)."""
     import torch
 
     from paper_2406_11836_amd import raster, scenes, serve
@@ -122,9 +123,11 @@ def serving(args):
            "scene_prep_s": round(prep_s, 2), "rates": {}}
     for rate in [float(x) for x in args.serve_rates.split(",")]:
         res = {}
-        for name, kd, kw in (("batched", kd64, dict(max_batch=8, workers=2, cull=True)),
+        for name, kd, kw in (("batched", kd64, dict(max_batch=8, workers=1, cull=True)),
+                             ("batched_K1", kd1, dict(max_batch=8, workers=1, cull=False)),
                              ("plain", kd1, dict(max_batch=1, workers=1, cull=False))):
             reqs = serve.serve_trace(rate, args.serve_requests, seed=int(30 + rate))
+            torch.cuda.empty_cache()  # the previous server's buffers go back to the device
             srv = serve.Server(p, kd, **kw)
             srv.run(reqs)
             res[name] = serve.latency_stats(reqs, 100, srv)

@@ -17,6 +17,7 @@
  *     buffer, including workspaces sized by the *_workspace() queries; the
  *     library never allocates and keeps no state between calls, so calls on
  *     different streams with disjoint buffers may run concurrently.
+ *     Workspaces must be 256-byte aligned (any hipMalloc'd pointer is).
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and
  *     the call returns without waiting, except rgs_bin_sort, which copies one
  *     counter to the host (the instance count) and therefore waits once.

@@ -60,6 +60,11 @@ static bool cams_ok(const rgs_camera* cams, int32_t n_views) {
     return true;
 }
 
+// A workspace: non-null, 256-byte aligned, at least `need` bytes.
+static bool ws_ok(const void* ws, size_t have, size_t need) {
+    return ws && (reinterpret_cast<uintptr_t>(ws) & 255u) == 0 && have >= need;
+}
+
 static bool gauss_ok(const rgs_gaussians* g) {
     if (!g || g->n < 0 || g->sh_degree < 0 || g->sh_degree > 3) return false;
     if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity || !g->sh)) return false;
@@ -151,7 +156,7 @@ rgs_status rgs_kd_partition(const rgs_gaussians* g, int32_t L, float d_factor, c
     if (!gauss_ok(g) || !kd || L < 0 || L > RGS_MAX_L || !kd->split || !kd->box_lo || !kd->box_hi || !kd->counts)
         return RGS_E_ARG;
     if (g->n > 0 && !kd->center_cell) return RGS_E_ARG;
-    if (!ws || ws_bytes < kd_ws_bytes(g->n, L)) return RGS_E_ARG;
+    if (!ws_ok(ws, ws_bytes, kd_ws_bytes(g->n, L))) return RGS_E_ARG;
     if (g->n > 0x7fffffff) return RGS_E_UNSUPPORTED;
     return kd_partition(g, L, d_factor, kd, ws, S(stream));
 }
@@ -166,7 +171,7 @@ rgs_status rgs_group_by_cell(const rgs_gaussians* in, const rgs_kdtree* kd, int3
     if (in->n > 0 && (out->means == in->means || out->sh == in->sh || out->quats == in->quats ||
                       out->log_scales == in->log_scales || out->opacity == in->opacity))
         return RGS_E_ARG;
-    if (!ws || ws_bytes < group_ws_bytes(in->n)) return RGS_E_ARG;
+    if (!ws_ok(ws, ws_bytes, group_ws_bytes(in->n))) return RGS_E_ARG;
     if (in->n > 0x7fffffff) return RGS_E_UNSUPPORTED;
     return group_by_cell(in, kd, L, out, perm, ws, ws_bytes, S(stream));
 }
@@ -219,7 +224,7 @@ rgs_status rgs_bin_sort(const rgs_projected* proj, int64_t n, const rgs_camera* 
         !ws)
         return RGS_E_ARG;
     const int64_t T = rgs_total_tiles(cams, n_views);
-    if (ws_bytes < bin_ws_bytes(n, n_views, T, L, bins->capacity)) return RGS_E_ARG;
+    if (!ws_ok(ws, ws_bytes, bin_ws_bytes(n, n_views, T, L, bins->capacity))) return RGS_E_ARG;
     if ((int64_t)n_views * n >= 0x7fffffffLL || bins->capacity >= 0xffffffffLL || (T << L) >= 0x7fffffffLL)
         return RGS_E_UNSUPPORTED;
     return bin_sort(proj, n, n_views, reinterpret_cast<const ViewTable*>(views_dev), L, T, bins, n_required, ws, ws_bytes,
@@ -258,7 +263,7 @@ size_t rgs_loss_workspace(int32_t H, int32_t W) {
 rgs_status rgs_loss_l1_ssim(const float* image, const float* target, int32_t H, int32_t W, float ssim_weight, float* loss,
                             float* d_image, void* ws, size_t ws_bytes, rgs_stream stream) {
     if (!image || !target || !loss || !d_image || !ws || H <= 0 || W <= 0 || !isfinite(ssim_weight)) return RGS_E_ARG;
-    if (ws_bytes < loss_ws_bytes(H, W)) return RGS_E_ARG;
+    if (!ws_ok(ws, ws_bytes, loss_ws_bytes(H, W))) return RGS_E_ARG;
     if (d_image == image || d_image == target) return RGS_E_ARG;
     return loss_launch(image, target, H, W, ssim_weight, loss, d_image, ws, S(stream));
 }
@@ -286,7 +291,7 @@ rgs_status rgs_render_partial_bwd(const rgs_partials_grad* dparts, const rgs_par
     if (!dparts || !dparts->dC || !dparts->dT || !parts || !parts->T || !parts->last || !bins_ok(bins) || !proj_ok(proj) ||
         n < 0 || !cams_ok(cams, n_views) || !views_dev || !kd || !kd->box_lo || !kd->box_hi || !d_proj || !ws)
         return RGS_E_ARG;
-    if (ws_bytes < render_bwd_ws_bytes(bins->capacity)) return RGS_E_ARG;
+    if (!ws_ok(ws, ws_bytes, render_bwd_ws_bytes(bins->capacity))) return RGS_E_ARG;
     return render_bwd_launch(dparts, parts, bins, proj, n, n_views, reinterpret_cast<const ViewTable*>(views_dev), kd,
                              d_proj, ws, slot_bound_of(bins, cams, n_views, kd->L), S(stream));
 }

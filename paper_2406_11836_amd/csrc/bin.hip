@@ -81,8 +81,9 @@ __global__ __launch_bounds__(BN_THREADS) void k_vis_compact(const uint32_t* __re
 
 __global__ __launch_bounds__(BN_THREADS) void k_view_keys(const uint32_t* __restrict__ src, const uint32_t* __restrict__ n_dev,
                                                           int64_t n_gauss, uint32_t* __restrict__ vkey) {
-    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (i < (int64_t)*n_dev) vkey[i] = (uint32_t)(src[i] / (uint64_t)n_gauss);
+    const int64_t np = (int64_t)*n_dev;
+    for (int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x; i < np; i += (int64_t)gridDim.x * BN_THREADS)
+        vkey[i] = (uint32_t)(src[i] / (uint64_t)n_gauss);
 }
 
 // Per ordered pair: its rank, and its instance count (for the offsets scan).
@@ -90,10 +91,8 @@ __global__ __launch_bounds__(BN_THREADS) void k_pair_counts(const uint32_t* __re
                                                             const uint32_t* __restrict__ n_dev, int64_t m_max,
                                                             const uint32_t* __restrict__ count,
                                                             int32_t* __restrict__ pair_rank, uint32_t* __restrict__ cnt) {
-    int64_t r = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (r >= m_max) return;
     const int64_t np = (int64_t)*n_dev;
-    if (r < np) {
+    for (int64_t r = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x; r < np; r += (int64_t)gridDim.x * BN_THREADS) {
         const uint32_t s = pair_src[r];
         pair_rank[s] = (int32_t)r;
         cnt[r] = count[s];
@@ -130,41 +129,42 @@ __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict_
     __shared__ uint2 s_rect[BN_THREADS];
     __shared__ uint64_t s_mask[BN_THREADS];
     const int64_t npairs = (int64_t)*n_dev;
-    const int64_t r0 = (int64_t)blockIdx.x * BN_THREADS;
-    if (r0 >= npairs) return;
-    const int nb = (int)((npairs - r0) < BN_THREADS ? (npairs - r0) : BN_THREADS);
-    const int t = threadIdx.x;
-    if (t < nb) {
-        const uint32_t src = pair_src[r0 + t];
-        s_src[t] = src;
-        s_rect[t] = reinterpret_cast<const uint2*>(rect)[src];
-        s_mask[t] = cellmask[src];
-        s_off[t] = pair_off[r0 + t];
-    }
-    if (t == 0) s_off[nb] = pair_off[r0 + nb];
-    __syncthreads();
-    const uint32_t j0 = s_off[0], j1 = s_off[nb];
-    const int L = vt->L;
-    for (uint32_t j = j0 + t; j < j1; j += BN_THREADS) {
-        // last pair with s_off[p] <= j
-        int lo = 0, hi = nb - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
+    for (int64_t r0 = (int64_t)blockIdx.x * BN_THREADS; r0 < npairs; r0 += (int64_t)gridDim.x * BN_THREADS) {
+        const int nb = (int)((npairs - r0) < BN_THREADS ? (npairs - r0) : BN_THREADS);
+        const int t = threadIdx.x;
+        if (t < nb) {
+            const uint32_t src = pair_src[r0 + t];
+            s_src[t] = src;
+            s_rect[t] = reinterpret_cast<const uint2*>(rect)[src];
+            s_mask[t] = cellmask[src];
+            s_off[t] = pair_off[r0 + t];
         }
-        const uint32_t src = s_src[lo];
-        const uint2 rr = s_rect[lo];
-        const int x0 = (int)(int16_t)(rr.x & 0xffffu) >> 4, x1 = (int)(int16_t)(rr.x >> 16) >> 4;
-        const int y0 = (int)(int16_t)(rr.y & 0xffffu) >> 4, y1 = (int)(int16_t)(rr.y >> 16) >> 4;
-        const uint32_t ntx = (uint32_t)(x1 - x0 + 1), ntiles = ntx * (uint32_t)(y1 - y0 + 1);
-        const uint32_t q = j - s_off[lo];
-        const uint32_t c = q / ntiles, tt = q - c * ntiles;
-        const uint32_t ty = (uint32_t)y0 + tt / ntx, tx = (uint32_t)x0 + tt % ntx;
-        const int v = (int)(src / (uint64_t)n_gauss);
-        const ViewParams& V = vt->v[v];
-        const int cell = nth_set_bit(s_mask[lo], (int)c);
-        keys[j] = ((V.tile_offset + ty * (uint32_t)V.tiles_x + tx) << L) | (uint32_t)V.rank_of_cell[cell];
-        vals[j] = ((uint64_t)src << 32) | j;
+        if (t == 0) s_off[nb] = pair_off[r0 + nb];
+        __syncthreads();
+        const uint32_t j0 = s_off[0], j1 = s_off[nb];
+        const int L = vt->L;
+        for (uint32_t j = j0 + t; j < j1; j += BN_THREADS) {
+            // last pair with s_off[p] <= j
+            int lo = 0, hi = nb - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
+            }
+            const uint32_t src = s_src[lo];
+            const uint2 rr = s_rect[lo];
+            const int x0 = (int)(int16_t)(rr.x & 0xffffu) >> 4, x1 = (int)(int16_t)(rr.x >> 16) >> 4;
+            const int y0 = (int)(int16_t)(rr.y & 0xffffu) >> 4, y1 = (int)(int16_t)(rr.y >> 16) >> 4;
+            const uint32_t ntx = (uint32_t)(x1 - x0 + 1), ntiles = ntx * (uint32_t)(y1 - y0 + 1);
+            const uint32_t q = j - s_off[lo];
+            const uint32_t c = q / ntiles, tt = q - c * ntiles;
+            const uint32_t ty = (uint32_t)y0 + tt / ntx, tx = (uint32_t)x0 + tt % ntx;
+            const int v = (int)(src / (uint64_t)n_gauss);
+            const ViewParams& V = vt->v[v];
+            const int cell = nth_set_bit(s_mask[lo], (int)c);
+            keys[j] = ((V.tile_offset + ty * (uint32_t)V.tiles_x + tx) << L) | (uint32_t)V.rank_of_cell[cell];
+            vals[j] = ((uint64_t)src << 32) | j;
+        }
+        __syncthreads();  // LDS is reused by the next chunk
     }
 }
 
@@ -239,15 +239,30 @@ __global__ void k_slot_class_offsets(const uint32_t* __restrict__ cls_cnt, uint3
     }
 }
 
+// Slots are placed class by class; within a block, positions come from LDS
+// counters and one global reservation per (block, class), so the global
+// atomics do not serialise on a handful of class counters.  The order inside
+// a class is the launch order only and does not affect any result.
 __global__ __launch_bounds__(BN_THREADS) void k_slot_class_place(const uint32_t* __restrict__ slot_range,
                                                                  const uint32_t* __restrict__ n_slots,
                                                                  uint32_t* __restrict__ cls_off,
                                                                  uint32_t* __restrict__ slot_order) {
+    __shared__ uint32_t s_c[32], s_base[32];
+    if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
+    __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (s >= (int64_t)*n_slots) return;
-    const uint32_t len = slot_range[2 * s + 1] - slot_range[2 * s];
-    const uint32_t p = atomicAdd(&cls_off[31 - __clz(len | 1u)], 1u);
-    slot_order[p] = (uint32_t)s;
+    const bool ok = s < (int64_t)*n_slots;
+    int cls = 0;
+    uint32_t local = 0;
+    if (ok) {
+        const uint32_t len = slot_range[2 * s + 1] - slot_range[2 * s];
+        cls = 31 - __clz(len | 1u);
+        local = atomicAdd(&s_c[cls], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && s_c[threadIdx.x]) s_base[threadIdx.x] = atomicAdd(&cls_off[threadIdx.x], s_c[threadIdx.x]);
+    __syncthreads();
+    if (ok) slot_order[s_base[cls] + local] = (uint32_t)s;
 }
 
 size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t capacity) {
@@ -305,6 +320,11 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     uint32_t* cnt = bins->counters;  // [0] pairs [1] instances [2] slots
     rgs_status st;
     auto grid = [](int64_t k) { return dim3((unsigned)((k + BN_THREADS - 1) / BN_THREADS > 0 ? (k + BN_THREADS - 1) / BN_THREADS : 1)); };
+    // kernels over the visible pairs read their count on the device: capped grid, loops inside
+    auto dgrid = [](int64_t k) {
+        const int64_t b = (k + BN_THREADS - 1) / BN_THREADS;
+        return dim3((unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b)));
+    };
 
     // 1. visible pairs in (view, gid) order, then stable sorts by depth and by view
     const int64_t vtiles = (m + VC_TILE - 1) / VC_TILE;
@@ -318,13 +338,13 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     if ((st = radix_sort_u32_u32_dev(zkey, bins->pair_src, zkey_alt, src_alt, &cnt[0], m, 32, rws, s)) != RGS_OK)
         return st;
     if (n_views > 1) {
-        hipLaunchKernelGGL(k_view_keys, grid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], n, zkey);
+        hipLaunchKernelGGL(k_view_keys, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], n, zkey);
         if ((st = radix_sort_u32_u32_dev(zkey, bins->pair_src, zkey_alt, src_alt, &cnt[0], m, bits_for(n_views), rws, s)) !=
             RGS_OK)
             return st;
     }
     // 2. instance offsets per ordered pair; the instance count goes to the host
-    if (m > 0) hipLaunchKernelGGL(k_pair_counts, grid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], m, proj->count,
+    if (m > 0) hipLaunchKernelGGL(k_pair_counts, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], m, proj->count,
                                   bins->pair_rank, flag);
     if ((st = exclusive_scan_u32_dev(flag, bins->pair_off, DevN{&cnt[0], m, 1, 1}, m, &cnt[1], sws, s)) != RGS_OK)
         return st;
@@ -340,7 +360,7 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
 
     // 3. emit and sort instances by (tile, rank)
     if (m > 0)
-        hipLaunchKernelGGL(k_emit, grid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], bins->pair_off, proj->rect,
+        hipLaunchKernelGGL(k_emit, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], bins->pair_off, proj->rect,
                            proj->cellmask, n, vt_dev, bins->keys, bins->vals);
     RGS_LAUNCH_CHECK();
     const int key_bits = L + bits_for((uint64_t)total_tiles);

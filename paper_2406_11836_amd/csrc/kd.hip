@@ -136,6 +136,12 @@ __global__ void k_kd_boxes(const float* __restrict__ split, int L, float* __rest
     counts[k] = 0;
 }
 
+// Leaf of every centre, per-leaf counts, ownership masks and per-leaf
+// inflated bounds.  Grid-stride blocks: counts and bounds are reduced in LDS
+// (integer keys, so min/max are exact and order-independent) and each block
+// issues one global atomic per (leaf, face) it touched.
+static constexpr int KD_LEAF_BLOCKS = 1024;
+
 __global__ __launch_bounds__(KD_THREADS) void k_kd_leaves(const int32_t* __restrict__ node, int64_t n, int L,
                                                           const float* __restrict__ means,
                                                           const float* __restrict__ log_scales, float d_factor,
@@ -143,42 +149,53 @@ __global__ __launch_bounds__(KD_THREADS) void k_kd_leaves(const int32_t* __restr
                                                           int32_t* __restrict__ center_cell, int32_t* __restrict__ counts,
                                                           uint32_t* __restrict__ own_mask, uint32_t* __restrict__ bounds_key) {
     __shared__ int32_t s_cnt[RGS_MAXK];
+    __shared__ uint32_t s_bk[6 * RGS_MAXK];
     const int K = 1 << L;
-    if (threadIdx.x < K) s_cnt[threadIdx.x] = 0;
+    for (int t = threadIdx.x; t < K; t += KD_THREADS) s_cnt[t] = 0;
+    for (int t = threadIdx.x; t < 6 * K; t += KD_THREADS) s_bk[t] = (t < 3 * K) ? 0xffffffffu : 0u;
     __syncthreads();
-    int64_t i = (int64_t)blockIdx.x * KD_THREADS + threadIdx.x;
-    const int leaf = i < n ? node[i] - (K - 1) : 0;
-    if (i < n) atomicAdd(&s_cnt[leaf], 1);
-    __syncthreads();
-    if (threadIdx.x < K && s_cnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], s_cnt[threadIdx.x]);
-    if (i >= n) return;
-    center_cell[i] = leaf;
-    if (!own_mask && !bounds_key) return;
-    // D_i = d_factor * max scale; transcendental in fp64, rounded once
-    const float s0 = (float)exp((double)log_scales[i]);
-    const float s1 = (float)exp((double)log_scales[n + i]);
-    const float s2 = (float)exp((double)log_scales[2 * n + i]);
-    const float Di = d_factor * fmaxf(fmaxf(s0, s1), s2);
-    const float u[3] = {means[i], means[n + i], means[2 * n + i]};
-    if (bounds_key) {
-        // order-preserving integer keys: min/max with integer atomics (deterministic)
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(&bounds_key[a * K + leaf], f2key(u[a] - Di));
-            atomicMax(&bounds_key[(3 + a) * K + leaf], f2key(u[a] + Di));
-        }
-    }
-    if (!own_mask) return;
     const int Wm = (K + 31) / 32;
-    uint32_t m[2] = {0u, 0u};
-    for (int k = 0; k < K; ++k) {
-        bool in = true;
-        for (int a = 0; a < 3; ++a) {
-            if (!((lo[a * K + k] - u[a]) <= Di)) in = false;
-            if (!((u[a] - hi[a * K + k]) <= Di)) in = false;
+    for (int64_t i = (int64_t)blockIdx.x * KD_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * KD_THREADS) {
+        const int leaf = node[i] - (K - 1);
+        atomicAdd(&s_cnt[leaf], 1);
+        center_cell[i] = leaf;
+        if (!own_mask && !bounds_key) continue;
+        // D_i = d_factor * max scale; transcendental in fp64, rounded once
+        const float s0 = (float)exp((double)log_scales[i]);
+        const float s1 = (float)exp((double)log_scales[n + i]);
+        const float s2 = (float)exp((double)log_scales[2 * n + i]);
+        const float Di = d_factor * fmaxf(fmaxf(s0, s1), s2);
+        const float u[3] = {means[i], means[n + i], means[2 * n + i]};
+        if (bounds_key) {
+            for (int a = 0; a < 3; ++a) {
+                atomicMin(&s_bk[a * K + leaf], f2key(u[a] - Di));
+                atomicMax(&s_bk[(3 + a) * K + leaf], f2key(u[a] + Di));
+            }
         }
-        if (in) m[k >> 5] |= 1u << (k & 31);
+        if (!own_mask) continue;
+        uint32_t m[2] = {0u, 0u};
+        for (int k = 0; k < K; ++k) {
+            bool in = true;
+            for (int a = 0; a < 3; ++a) {
+                if (!((lo[a * K + k] - u[a]) <= Di)) in = false;
+                if (!((u[a] - hi[a * K + k]) <= Di)) in = false;
+            }
+            if (in) m[k >> 5] |= 1u << (k & 31);
+        }
+        for (int w = 0; w < Wm; ++w) own_mask[i * Wm + w] = m[w];
     }
-    for (int w = 0; w < Wm; ++w) own_mask[i * Wm + w] = m[w];
+    __syncthreads();
+    for (int t = threadIdx.x; t < K; t += KD_THREADS)
+        if (s_cnt[t]) atomicAdd(&counts[t], s_cnt[t]);
+    if (bounds_key)
+        for (int t = threadIdx.x; t < 6 * K; t += KD_THREADS) {
+            const uint32_t v = s_bk[t];
+            if (t < 3 * K) {
+                if (v != 0xffffffffu) atomicMin(&bounds_key[t], v);
+            } else if (v != 0u) {
+                atomicMax(&bounds_key[t], v);
+            }
+        }
 }
 
 __global__ void k_kd_bounds_init(uint32_t* __restrict__ bk, int K) {
@@ -231,8 +248,9 @@ rgs_status kd_partition(const rgs_gaussians* g, int L, float d_factor, const rgs
     }
     hipLaunchKernelGGL(k_kd_boxes, dim3(1), dim3(64), 0, s, kd->split, L, kd->box_lo, kd->box_hi, kd->counts);
     if (kd->cell_bounds) hipLaunchKernelGGL(k_kd_bounds_init, dim3(1), dim3(384), 0, s, bk, K);
+    const unsigned gridL = gridN < (unsigned)KD_LEAF_BLOCKS ? gridN : (unsigned)KD_LEAF_BLOCKS;
     if (n > 0)
-        hipLaunchKernelGGL(k_kd_leaves, dim3(gridN), dim3(KD_THREADS), 0, s, node, n, L, g->means, g->log_scales, d_factor,
+        hipLaunchKernelGGL(k_kd_leaves, dim3(gridL), dim3(KD_THREADS), 0, s, node, n, L, g->means, g->log_scales, d_factor,
                            kd->box_lo, kd->box_hi, kd->center_cell, kd->counts, kd->own_mask,
                            kd->cell_bounds ? bk : nullptr);
     if (kd->cell_bounds) hipLaunchKernelGGL(k_kd_bounds_final, dim3(1), dim3(384), 0, s, bk, K, kd->cell_bounds);

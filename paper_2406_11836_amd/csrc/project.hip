@@ -79,12 +79,21 @@ struct Proj32 {
     bool vis;
 };
 
-// The fixed-order fp32 decision path (see the file comment).
-__device__ __forceinline__ void proj32(float mu0, float mu1, float mu2, float ls0, float ls1, float ls2, float qw,
-                                       float qx, float qy, float qz, float logit, const ViewParams& V, Proj32& p) {
-    p.vis = false;
+// The fixed-order fp32 decision path (see the file comment), in two parts:
+// the view-independent activations and 3D covariance (once per Gaussian),
+// then the per-view projection.  The split changes no operation or order.
+struct Pre32 {
+    float alpha, tau;
+    float S[6];  // 3D covariance: 00, 01, 02, 11, 12, 22 (the product is exactly symmetric)
+    bool ok;     // quaternion non-zero
+};
+
+__device__ __forceinline__ void pre32(float ls0, float ls1, float ls2, float qw, float qx, float qy, float qz,
+                                      float logit, Pre32& q) {
+    q.ok = false;
     const float s0 = (float)exp((double)ls0), s1 = (float)exp((double)ls1), s2 = (float)exp((double)ls2);
-    const float alpha = (float)(1.0 / (1.0 + exp(-(double)logit)));
+    q.alpha = (float)(1.0 / (1.0 + exp(-(double)logit)));
+    q.tau = fminf(9.0f, (float)(2.0 * log(255.0 * (double)q.alpha)));
     const float qq = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
     if (!(qq > 0.0f)) return;
     const float qn = sqrtf(qq);
@@ -100,15 +109,26 @@ __device__ __forceinline__ void proj32(float mu0, float mu1, float mu2, float ls
     r[2][1] = 2.0f * (y * z + w * x);
     r[2][2] = 1.0f - 2.0f * (x * x + y * y);
     const float sc[3] = {s0, s1, s2};
-    float M[3][3], S[3][3];
+    float M[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) M[a][b] = r[a][b] * sc[b];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) S[a][b] = (M[a][0] * M[b][0] + M[a][1] * M[b][1]) + M[a][2] * M[b][2];
+    auto cov = [&](int a, int b) { return (M[a][0] * M[b][0] + M[a][1] * M[b][1]) + M[a][2] * M[b][2]; };
+    q.S[0] = cov(0, 0);
+    q.S[1] = cov(0, 1);
+    q.S[2] = cov(0, 2);
+    q.S[3] = cov(1, 1);
+    q.S[4] = cov(1, 2);
+    q.S[5] = cov(2, 2);
+    q.ok = true;
+}
+
+__device__ __forceinline__ void proj32(float mu0, float mu1, float mu2, const Pre32& q, const ViewParams& V,
+                                       Proj32& p) {
+    p.vis = false;
+    if (!q.ok) return;
+    const float S[3][3] = {{q.S[0], q.S[1], q.S[2]}, {q.S[1], q.S[3], q.S[4]}, {q.S[2], q.S[4], q.S[5]}};
     float tc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) tc[a] = ((V.R[3 * a] * mu0 + V.R[3 * a + 1] * mu1) + V.R[3 * a + 2] * mu2) + V.t[a];
@@ -140,12 +160,11 @@ __device__ __forceinline__ void proj32(float mu0, float mu1, float mu2, float ls
     p.mx = V.fx * xz + V.cx;
     p.my = V.fy * yz + V.cy;
     p.z = zc;
-    p.alpha = alpha;
+    p.alpha = q.alpha;
     p.s00 = s00;
     p.s11 = s11;
-    const float tau = fminf(9.0f, (float)(2.0 * log(255.0 * (double)alpha)));
-    p.tau = tau;
-    if (!(tau >= 0.0f)) return;
+    p.tau = q.tau;
+    if (!(q.tau >= 0.0f)) return;
     if (!(isfinite(p.mx) && isfinite(p.my))) return;
     p.vis = true;
 }
@@ -234,6 +253,8 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
     const float ls0 = g.log_scales[i], ls1 = g.log_scales[n + i], ls2 = g.log_scales[2 * n + i];
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
     const float logit = g.opacity[i];
+    Pre32 pre;
+    pre32(ls0, ls1, ls2, qw, qx, qy, qz, logit, pre);
     float f[3 * nc];
     bool have_sh = false;  // SH coefficients are read once, for the first view that needs them
     const int L = vt->L;
@@ -242,7 +263,7 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
         const ViewParams& V = vt->v[v];
         const int64_t src = (int64_t)v * n + i;
         Proj32 p;
-        proj32(mu0, mu1, mu2, ls0, ls1, ls2, qw, qx, qy, qz, logit, V, p);
+        proj32(mu0, mu1, mu2, pre, V, p);
         int r[4] = {0, 0, 0, 0};
         bool ok = p.vis && rect32(p, V, r);
         float4* rec = reinterpret_cast<float4*>(out.rec + src * RGS_REC_FLOATS);

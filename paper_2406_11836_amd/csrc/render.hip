@@ -17,14 +17,15 @@
 // recovers the transmittance before every contribution from a reciprocal,
 // sums each instance's gradient over every wave's 64 pixels with a
 // reduce-scatter butterfly (no atomics), adds the four quadrant sums in a
-// fixed order and stores one 9-float record at the instance's emission
-// position; a second kernel sums each pair's records (contiguous by
-// construction) in a fixed order.
+// fixed order and stores one record (9 floats, padded to 48 bytes) at the
+// instance's emission position; a segmented reduction then sums each pair's
+// records (contiguous by construction) in a fixed order.
 #include "common.hpp"
 
 namespace rgs {
 
 static constexpr int RD_BATCH = 64;
+static constexpr int RD_REC = 12;  // floats per backward record: 9 used, padded to 48 bytes
 
 struct SlotGeom {
     int v, px, py0, cell;
@@ -94,7 +95,7 @@ __device__ __forceinline__ bool quad_hits(float mx, float my, float ca, float cb
 __device__ __forceinline__ uint32_t quad_mask_ellipse(uint2 rr, int tx, int ty, float mx, float my, float ca, float cb,
                                                       float cc, float tau) {
     uint32_t m = quad_mask(rr, tx, ty);
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < 4; ++q)
         if ((m >> q) & 1u) {
             const float x0 = (float)(tx * 16 + (q & 1) * 8), y0 = (float)(ty * 16 + (q >> 1) * 8);
@@ -351,7 +352,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
     const float gC0 = valid ? dC[(size_t)slot * 768 + p] : 0.f;
     const float gC1 = valid ? dC[(size_t)slot * 768 + 256 + p] : 0.f;
     const float gC2 = valid ? dC[(size_t)slot * 768 + 512 + p] : 0.f;
-    float B0 = 0.f, B1 = 0.f, B2 = 0.f;
+    // gB = <dC_k, B>, where B is the colour blended behind the current
+    // instance (the suffix of Eq. 3): the only way B enters the gradient
+    float gB = 0.f;
     const uint32_t wmax = wave_max_u32(last);
     if (lane == 0) s_max[w] = wmax;
     __syncthreads();
@@ -359,8 +362,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
     const uint32_t len = end - begin;
     // instances never reached by any pixel get zero records
     for (uint32_t k = bmax + tid; k < len; k += 256) {
-        float* rp = records + (size_t)(uint32_t)vals[begin + k] * 9;
-        for (int c = 0; c < 9; ++c) rp[c] = 0.f;
+        float4* rp = reinterpret_cast<float4*>(records + (size_t)(uint32_t)vals[begin + k] * RD_REC);
+        rp[0] = rp[1] = rp[2] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     const uint32_t qbit = 1u << (w + 1);
     for (int bstart = bmax == 0 ? -1 : (int)(((bmax - 1) / NB) * NB); bstart >= 0; bstart -= NB) {
@@ -410,24 +413,24 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
                     const float sgm = fminf(0.99f, aG);
                     const float rom = __builtin_amdgcn_rcpf(1.0f - sgm);
                     const float Tb = Tcur * rom;  // transmittance before this contribution
-                    const float dot = gC0 * (cl.x - B0) + gC1 * (cl.y - B1) + gC2 * (cl.z - B2);
+                    const float dot = fmaf(gC2, cl.z, fmaf(gC1, cl.y, gC0 * cl.x)) - gB;  // <dC, c - B>
                     const float dsg = Tb * dot - gTf * rom;
                     const float wc = Tb * sgm;
                     g[6] = wc * gC0;
                     g[7] = wc * gC1;
                     g[8] = wc * gC2;
-                    B0 = fmaf(sgm, cl.x - B0, B0);
-                    B1 = fmaf(sgm, cl.y - B1, B1);
-                    B2 = fmaf(sgm, cl.z - B2, B2);
+                    gB = fmaf(sgm, dot, gB);  // B <- B + sigma (c - B)
                     Tcur = Tb;
                     if (aG < 0.99f) {
-                        const float dd2 = -0.5f * aG * dsg;
+                        // raw sums; the conic and the constant factors are applied per
+                        // instance after the reduction (dL/d(d^2) = -q / 2)
+                        const float q = aG * dsg;
                         g[5] = dsg * G;
-                        g[0] = -dd2 * 2.0f * (a.z * dx + a.w * dy);
-                        g[1] = -dd2 * 2.0f * (a.w * dx + b.x * dy);
-                        g[2] = dd2 * dx * dx;
-                        g[3] = dd2 * 2.0f * dx * dy;
-                        g[4] = dd2 * dy * dy;
+                        g[0] = q * dx;
+                        g[1] = q * dy;
+                        g[2] = g[0] * dx;
+                        g[3] = g[0] * dy;
+                        g[4] = g[1] * dy;
                     }
                 }
             }
@@ -438,52 +441,186 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
             if (lane == 63) sG[w][t][8] = s8;
         }
         __syncthreads();
-        for (int k = tid; k < NB * 9; k += 256) {
-            const int t = k / 9, c = k % 9;
-            if ((uint32_t)bstart + t < bmax)
-                records[(size_t)sJ[t] * 9 + c] = (sG[0][t][c] + sG[1][t][c]) + (sG[2][t][c] + sG[3][t][c]);
+        if (tid < NB && (uint32_t)bstart + tid < bmax) {
+            // S_c = sum over the four quadrants, in a fixed order
+            const int t = tid;
+            float S[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) S[c] = (sG[0][t][c] + sG[1][t][c]) + (sG[2][t][c] + sG[3][t][c]);
+            const float4 a = sA[t];
+            const float cc = sB[t].x;
+            float4* rp = reinterpret_cast<float4*>(records + (size_t)sJ[t] * RD_REC);
+            // d mx = sum q (ca dx + cb dy), d my = sum q (cb dx + cc dy); d ca, d cb, d cc
+            // carry dL/d(d^2) = -q / 2 (d cb counts the cross term twice); then d alpha, colour
+            rp[0] = make_float4(a.z * S[0] + a.w * S[1], a.w * S[0] + cc * S[1], -0.5f * S[2], -S[3]);
+            rp[1] = make_float4(-0.5f * S[4], S[5], S[6], S[7]);
+            rp[2] = make_float4(S[8], 0.f, 0.f, 0.f);
         }
         __syncthreads();
     }
 }
 
-// Per (view, Gaussian) pair: sum its instance records in emission order.
-__global__ __launch_bounds__(256) void k_pair_reduce(const float* __restrict__ records, const uint32_t* __restrict__ count,
+// Per (view, Gaussian) pair: sum of its instance records.  The records of a
+// pair are contiguous (emission order), so the sum is a segmented reduction
+// over the instance array, balanced over instances:
+//  1. k_pair_seg: a wave takes 64 consecutive records; the pairs covering
+//     them come from one binary search (first pair) and one coalesced load
+//     of the next 64 pair offsets; a segmented inclusive scan (fixed tree of
+//     shuffles) sums each pair's records within the wave.  Pairs complete in
+//     the wave are written to psum[rank]; the wave's first segment (pair
+//     begun before it) and last segment (pair going on after it) are kept as
+//     wave partials.
+//  2. k_pair_gather: thread per (view, Gaussian): zero if culled, else the
+//     pair's sum from psum, or, for a pair spanning several waves, its tail
+//     partial + whole-wave partials + head partial, in instance order.
+__global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ records, const uint32_t* __restrict__ pair_off,
+                                                  const uint32_t* __restrict__ counters, float* __restrict__ psum,
+                                                  float* __restrict__ wpart) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t n_pairs = counters[0], n_inst = counters[1];
+    const int64_t j0 = w * 64;
+    if (j0 >= (int64_t)n_inst) return;  // uniform per wave
+    const int64_t j = j0 + lane;
+    const bool valid = j < (int64_t)n_inst;
+    // first pair: the last r with pair_off[r] <= j0
+    uint32_t r0 = 0;
+    if (lane == 0) {
+        uint32_t lo = 0, hi = n_pairs - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if ((int64_t)pair_off[mid] <= j0) lo = mid; else hi = mid - 1;
+        }
+        r0 = lo;
+    }
+    r0 = (uint32_t)__shfl((int)r0, 0, 64);
+    // starts of the next 64 pairs (increasing); pos = how many start at or before j
+    const uint32_t rk = r0 + 1u + (uint32_t)lane;
+    const int64_t bk = rk < n_pairs ? (int64_t)pair_off[rk] : INT64_MAX;
+    int pos = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+        const int64_t bv = __shfl(bk, pos + step - 1, 64);
+        if (bv <= j) pos += step;
+    }
+    const int pos_prev = __shfl_up(pos, 1, 64);
+    const uint64_t heads = __ballot(lane == 0 || pos != pos_prev);
+    const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int seg0 = 63 - __builtin_clzll(heads & le_mask);  // first lane of this lane's segment
+    float v[9];
+    if (valid) {
+        const float4* rp = reinterpret_cast<const float4*>(records + (size_t)j * RD_REC);
+        const float4 x = rp[0], y = rp[1];
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+        v[8] = rp[2].x;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) v[c] = 0.f;
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const bool take = lane - d >= seg0;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const float u = __shfl_up(v[c], d, 64);
+            if (take) v[c] += u;
+        }
+    }
+    const int pos_next = __shfl_down(pos, 1, 64);
+    const bool next_valid = lane < 63 && j + 1 < (int64_t)n_inst;
+    const bool seg_end = valid && (!next_valid || pos_next != pos);
+    if (!seg_end) return;
+    const uint32_t r = r0 + (uint32_t)pos;
+    const bool began_before = (int64_t)pair_off[r] < j0;
+    const bool goes_on = (int64_t)pair_off[r + 1] > j0 + 64;
+    const float4 o0 = make_float4(v[0], v[1], v[2], v[3]), o1 = make_float4(v[4], v[5], v[6], v[7]),
+                 o2 = make_float4(v[8], 0.f, 0.f, 0.f);
+    if (!began_before && !goes_on) {
+        float4* q = reinterpret_cast<float4*>(psum + (size_t)r * RD_REC);
+        q[0] = o0; q[1] = o1; q[2] = o2;
+    }
+    if (began_before) {
+        float4* q = reinterpret_cast<float4*>(wpart + ((size_t)w * 2 + 0) * RD_REC);
+        q[0] = o0; q[1] = o1; q[2] = o2;
+    }
+    if (goes_on) {
+        float4* q = reinterpret_cast<float4*>(wpart + ((size_t)w * 2 + 1) * RD_REC);
+        q[0] = o0; q[1] = o1; q[2] = o2;
+    }
+}
+
+__device__ __forceinline__ void acc_rec(const float* __restrict__ p, float4& a0, float4& a1, float& a8) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+    const float4 x = q[0], y = q[1];
+    a0.x += x.x; a0.y += x.y; a0.z += x.z; a0.w += x.w;
+    a1.x += y.x; a1.y += y.y; a1.z += y.z; a1.w += y.w;
+    a8 += q[2].x;
+}
+
+__global__ __launch_bounds__(256) void k_pair_gather(const float* __restrict__ psum, const float* __restrict__ wpart,
+                                                     const uint32_t* __restrict__ count,
                                                      const int32_t* __restrict__ pair_rank,
                                                      const uint32_t* __restrict__ pair_off, int64_t m,
                                                      float* __restrict__ dproj) {
     const int64_t sidx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (sidx >= m) return;
-    float acc[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) acc[c] = 0.f;
+    float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
+    float a8 = 0.f;
     if (count[sidx] > 0u) {
         const int32_t r = pair_rank[sidx];
         const uint32_t b = pair_off[r], e = pair_off[r + 1];
-        for (uint32_t j = b; j < e; ++j) {
-            const float* rp = records + (size_t)j * 9;
-#pragma unroll
-            for (int c = 0; c < 9; ++c) acc[c] += rp[c];
+        const uint32_t wb = b >> 6, we = (e - 1u) >> 6;
+        if (wb == we) {
+            acc_rec(psum + (size_t)r * RD_REC, a0, a1, a8);
+        } else {
+            acc_rec(wpart + ((size_t)wb * 2 + 1) * RD_REC, a0, a1, a8);      // tail of the first wave
+            for (uint32_t w = wb + 1; w < we; ++w) acc_rec(wpart + (size_t)w * 2 * RD_REC, a0, a1, a8);  // whole waves
+            acc_rec(wpart + (size_t)we * 2 * RD_REC, a0, a1, a8);           // head of the last wave
         }
     }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) dproj[c * m + sidx] = acc[c];
+    dproj[0 * m + sidx] = a0.x;
+    dproj[1 * m + sidx] = a0.y;
+    dproj[2 * m + sidx] = a0.z;
+    dproj[3 * m + sidx] = a0.w;
+    dproj[4 * m + sidx] = a1.x;
+    dproj[5 * m + sidx] = a1.y;
+    dproj[6 * m + sidx] = a1.z;
+    dproj[7 * m + sidx] = a1.w;
+    dproj[8 * m + sidx] = a8;
 }
 
-size_t render_bwd_ws_bytes(int64_t capacity) { return (size_t)(capacity > 0 ? capacity : 1) * 9 * sizeof(float) + 256; }
+// Backward workspace: records and per-pair sums (pairs <= instances <= capacity)
+// of 48 bytes each, and two 48-byte partials per 64 instances.
+size_t render_bwd_ws_bytes(int64_t capacity) {
+    const size_t c = (size_t)(capacity > 0 ? capacity : 1);
+    const size_t rec = c * RD_REC * sizeof(float);
+    const size_t wp = ((c + 63) / 64) * 2 * RD_REC * sizeof(float);
+    return ((rec + 255) & ~size_t(255)) * 2 + wp + 256;
+}
 
 rgs_status render_bwd_launch(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
                              const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt,
                              const rgs_kdtree* kd, float* dproj, void* ws, int64_t slot_bound, hipStream_t s) {
+    const size_t c = (size_t)(bins->capacity > 0 ? bins->capacity : 1);
+    const size_t rec_bytes = (c * RD_REC * sizeof(float) + 255) & ~size_t(255);
     float* records = reinterpret_cast<float*>(ws);
+    float* psum = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + rec_bytes);
+    float* wpart = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + 2 * rec_bytes);
     if (slot_bound > 0)
         hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect, bins->vals,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
                            parts->T, parts->last, dparts->dC, dparts->dT, records);
     RGS_LAUNCH_CHECK();
     const int64_t m = (int64_t)n_views * n;
+    // one wave per 64 instances up to the capacity; waves past the device-side
+    // instance count return at once
+    if (bins->capacity > 0)
+        hipLaunchKernelGGL(k_pair_seg, dim3((unsigned)((bins->capacity + 255) / 256)), dim3(256), 0, s, records,
+                           bins->pair_off, bins->counters, psum, wpart);
+    RGS_LAUNCH_CHECK();
     if (m > 0)
-        hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, records, proj->count,
+        hipLaunchKernelGGL(k_pair_gather, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, psum, wpart, proj->count,
                            bins->pair_rank, bins->pair_off, m, dproj);
     return launch_check();
 }

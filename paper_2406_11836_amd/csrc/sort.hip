@@ -17,6 +17,8 @@ namespace rgs {
 
 // ------------------------------------------------------------------ scan
 static constexpr int SCAN_THREADS = 256;
+// Grid cap for kernels whose element count is read on the device.
+static constexpr unsigned DEV_GRID = 2048;
 static constexpr int SCAN_ITEMS = 16;
 static constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
@@ -43,16 +45,17 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __
                                                               uint32_t* __restrict__ partial) {
     __shared__ uint32_t s_wave[4];
     const int64_t n = dn.get();
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    if (base >= n) return;  // uniform per block
-    uint32_t acc = 0;
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int64_t i = base + k * SCAN_THREADS + threadIdx.x;
-        if (i < n) acc += in[i];
+    for (int64_t tile = blockIdx.x; tile * SCAN_TILE < n; tile += gridDim.x) {
+        const int64_t base = tile * SCAN_TILE;
+        uint32_t acc = 0;
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            int64_t i = base + k * SCAN_THREADS + threadIdx.x;
+            if (i < n) acc += in[i];
+        }
+        uint32_t ex;
+        uint32_t tot = block_excl_scan_256(acc, s_wave, &ex);
+        if (threadIdx.x == 0) partial[tile] = tot;
     }
-    uint32_t ex;
-    uint32_t tot = block_excl_scan_256(acc, s_wave, &ex);
-    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
 // Exclusive scan, in place, of the sums of the first ceil(dn / tile) tiles;
@@ -79,31 +82,33 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __r
     __shared__ uint32_t s[SCAN_TILE + SCAN_TILE / 32];
     __shared__ uint32_t s_wave[4];
     const int64_t n = dn.get();
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    if (base >= n) return;  // uniform per block
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int li = k * SCAN_THREADS + threadIdx.x;
-        int64_t i = base + li;
-        s[skew(li)] = i < n ? in[i] : 0u;
-    }
-    __syncthreads();
-    uint32_t v[SCAN_ITEMS], acc = 0;
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        v[k] = s[skew(threadIdx.x * SCAN_ITEMS + k)];
-        acc += v[k];
-    }
-    uint32_t ex;
-    block_excl_scan_256(acc, s_wave, &ex);
-    uint32_t run = partial[blockIdx.x] + ex;
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        s[skew(threadIdx.x * SCAN_ITEMS + k)] = run;
-        run += v[k];
-    }
-    __syncthreads();
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int li = k * SCAN_THREADS + threadIdx.x;
-        int64_t i = base + li;
-        if (i < n) out[i] = s[skew(li)];
+    for (int64_t tile = blockIdx.x; tile * SCAN_TILE < n; tile += gridDim.x) {
+        const int64_t base = tile * SCAN_TILE;
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            int li = k * SCAN_THREADS + threadIdx.x;
+            int64_t i = base + li;
+            s[skew(li)] = i < n ? in[i] : 0u;
+        }
+        __syncthreads();
+        uint32_t v[SCAN_ITEMS], acc = 0;
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            v[k] = s[skew(threadIdx.x * SCAN_ITEMS + k)];
+            acc += v[k];
+        }
+        uint32_t ex;
+        block_excl_scan_256(acc, s_wave, &ex);
+        uint32_t run = partial[tile] + ex;
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            s[skew(threadIdx.x * SCAN_ITEMS + k)] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            int li = k * SCAN_THREADS + threadIdx.x;
+            int64_t i = base + li;
+            if (i < n) out[i] = s[skew(li)];
+        }
+        __syncthreads();  // LDS is reused by the next tile
     }
 }
 
@@ -127,9 +132,10 @@ rgs_status exclusive_scan_u32_dev(const uint32_t* in, uint32_t* out, DevN dn, in
         return launch_check();
     }
     const int64_t tiles = (n_max + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, dn, partial);
+    const unsigned grid = (unsigned)(dn.p && tiles > DEV_GRID ? DEV_GRID : tiles);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(SCAN_THREADS), 0, s, in, dn, partial);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, dn, (int64_t)SCAN_TILE, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, dn, partial, out);
+    hipLaunchKernelGGL(k_scan_apply, dim3(grid), dim3(SCAN_THREADS), 0, s, in, dn, partial, out);
     return launch_check();
 }
 
@@ -148,6 +154,8 @@ __device__ __forceinline__ int64_t rs_n(int64_t n, const uint32_t* n_dev) {
     return n_dev ? (int64_t)*n_dev : n;
 }
 
+// Blocks loop over tiles (with a device-side count the grid is capped and
+// sized for the largest possible count, so no block is launched only to exit).
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n_host,
                                                         const uint32_t* __restrict__ n_dev, int shift,
                                                         uint32_t* __restrict__ hist, int ntiles) {
@@ -155,16 +163,18 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restri
     const int64_t n = rs_n(n_host, n_dev);
     // with a device count the table is [256][tiles in use]
     if (n_dev) ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
-    if ((int)blockIdx.x >= ntiles) return;  // uniform per block
-    s_h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int k = 0; k < RS_ITEMS; ++k) {
-        int64_t i = base + k * RS_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & 0xffu], 1u);
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        s_h[threadIdx.x] = 0;
+        __syncthreads();
+        const int64_t base = (int64_t)tile * RS_TILE;
+        for (int k = 0; k < RS_ITEMS; ++k) {
+            int64_t i = base + k * RS_THREADS + threadIdx.x;
+            if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & 0xffu], 1u);
+        }
+        __syncthreads();
+        hist[(int64_t)threadIdx.x * ntiles + tile] = s_h[threadIdx.x];
+        __syncthreads();
     }
-    __syncthreads();
-    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = s_h[threadIdx.x];
 }
 
 template <typename V>
@@ -183,69 +193,71 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
 
     const int64_t n = rs_n(n_host, n_dev);
     if (n_dev) ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
-    if ((int)blockIdx.x >= ntiles) return;  // uniform per block
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int k = threadIdx.x; k < 4 * 256; k += RS_THREADS) (&s_cnt[0][0])[k] = 0;
-    __syncthreads();
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        for (int k = threadIdx.x; k < 4 * 256; k += RS_THREADS) (&s_cnt[0][0])[k] = 0;
+        __syncthreads();
 
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    const int64_t tile_n = (n - base) < RS_TILE ? (n - base) : RS_TILE;
-    uint32_t key[RS_ITEMS];
-    V val[RS_ITEMS];
-    uint32_t rank[RS_ITEMS];
-    for (int k = 0; k < RS_ITEMS; ++k) {
-        const int64_t i = base + (int64_t)w * RS_WAVE_ITEMS + k * 64 + lane;
-        const bool valid = i < n;
-        key[k] = valid ? keys_in[i] : 0u;
-        val[k] = valid ? vals_in[i] : V(0);
-        const uint32_t d = (key[k] >> shift) & 0xffu;
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
+        const int64_t base = (int64_t)tile * RS_TILE;
+        const int64_t tile_n = (n - base) < RS_TILE ? (n - base) : RS_TILE;
+        uint32_t key[RS_ITEMS];
+        V val[RS_ITEMS];
+        uint32_t rank[RS_ITEMS];
+        for (int k = 0; k < RS_ITEMS; ++k) {
+            const int64_t i = base + (int64_t)w * RS_WAVE_ITEMS + k * 64 + lane;
+            const bool valid = i < n;
+            key[k] = valid ? keys_in[i] : 0u;
+            val[k] = valid ? vals_in[i] : V(0);
+            const uint32_t d = (key[k] >> shift) & 0xffu;
+            uint64_t m = __ballot(valid);
+    #pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+            uint32_t prior = 0;
+            if (valid) prior = s_cnt[w][d];
+            rank[k] = prior + (uint32_t)__popcll(m & lt_mask);
+            // the highest lane of each digit group publishes the new count
+            if (valid && (m >> lane) == 1ull) s_cnt[w][d] = prior + (uint32_t)__popcll(m);
+            if (!valid) rank[k] = 0xffffffffu;
         }
-        uint32_t prior = 0;
-        if (valid) prior = s_cnt[w][d];
-        rank[k] = prior + (uint32_t)__popcll(m & lt_mask);
-        // the highest lane of each digit group publishes the new count
-        if (valid && (m >> lane) == 1ull) s_cnt[w][d] = prior + (uint32_t)__popcll(m);
-        if (!valid) rank[k] = 0xffffffffu;
-    }
-    __syncthreads();
-    {
-        const int d = threadIdx.x;
-        const uint32_t c0 = s_cnt[0][d], c1 = s_cnt[1][d], c2 = s_cnt[2][d], c3 = s_cnt[3][d];
-        s_cnt[0][d] = 0;
-        s_cnt[1][d] = c0;
-        s_cnt[2][d] = c0 + c1;
-        s_cnt[3][d] = c0 + c1 + c2;
-        const uint32_t tot = c0 + c1 + c2 + c3;
-        s_goff[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
-        uint32_t ex;
-        block_excl_scan_256(tot, s_wave, &ex);
-        s_dstart[d] = ex;
-    }
-    __syncthreads();
-    for (int k = 0; k < RS_ITEMS; ++k) {
-        if (rank[k] == 0xffffffffu) continue;
-        const uint32_t d = (key[k] >> shift) & 0xffu;
-        const uint32_t p = s_dstart[d] + s_cnt[w][d] + rank[k];
-        s_keys[p] = key[k];
-        s_vals[p] = val[k];
-    }
-    __syncthreads();
-    for (int k = 0; k < RS_ITEMS; ++k) {
-        const int p = k * RS_THREADS + threadIdx.x;
-        if (p < tile_n) {
-            const uint32_t kk = s_keys[p];
-            const uint32_t d = (kk >> shift) & 0xffu;
-            const uint32_t o = s_goff[d] + ((uint32_t)p - s_dstart[d]);
-            keys_out[o] = kk;
-            vals_out[o] = s_vals[p];
+        __syncthreads();
+        {
+            const int d = threadIdx.x;
+            const uint32_t c0 = s_cnt[0][d], c1 = s_cnt[1][d], c2 = s_cnt[2][d], c3 = s_cnt[3][d];
+            s_cnt[0][d] = 0;
+            s_cnt[1][d] = c0;
+            s_cnt[2][d] = c0 + c1;
+            s_cnt[3][d] = c0 + c1 + c2;
+            const uint32_t tot = c0 + c1 + c2 + c3;
+            s_goff[d] = offsets[(int64_t)d * ntiles + tile];
+            uint32_t ex;
+            block_excl_scan_256(tot, s_wave, &ex);
+            s_dstart[d] = ex;
         }
+        __syncthreads();
+        for (int k = 0; k < RS_ITEMS; ++k) {
+            if (rank[k] == 0xffffffffu) continue;
+            const uint32_t d = (key[k] >> shift) & 0xffu;
+            const uint32_t p = s_dstart[d] + s_cnt[w][d] + rank[k];
+            s_keys[p] = key[k];
+            s_vals[p] = val[k];
+        }
+        __syncthreads();
+        for (int k = 0; k < RS_ITEMS; ++k) {
+            const int p = k * RS_THREADS + threadIdx.x;
+            if (p < tile_n) {
+                const uint32_t kk = s_keys[p];
+                const uint32_t d = (kk >> shift) & 0xffu;
+                const uint32_t o = s_goff[d] + ((uint32_t)p - s_dstart[d]);
+                keys_out[o] = kk;
+                vals_out[o] = s_vals[p];
+            }
+        }
+        __syncthreads();  // LDS is reused by the next tile
     }
 }
 
@@ -253,8 +265,8 @@ template <typename V>
 __global__ __launch_bounds__(256) void k_rs_copy(const uint32_t* __restrict__ ki, const V* __restrict__ vi,
                                                  int64_t n_host, const uint32_t* __restrict__ n_dev,
                                                  uint32_t* __restrict__ ko, V* __restrict__ vo) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < rs_n(n_host, n_dev)) {
+    const int64_t n = rs_n(n_host, n_dev);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         ko[i] = ki[i];
         vo[i] = vi[i];
     }
@@ -278,16 +290,17 @@ static rgs_status radix_sort_impl(uint32_t* keys, V* vals, uint32_t* keys_alt, V
     uint32_t* offs = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + hpad);
     void* scan_ws = reinterpret_cast<char*>(ws) + 2 * hpad;
     int passes = (bits + 7) / 8;
+    const unsigned grid = (unsigned)(n_dev && tiles > DEV_GRID ? DEV_GRID : tiles);
     uint32_t *ki = keys, *ko = keys_alt;
     V *vi = vals, *vo = vals_alt;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)tiles), dim3(RS_THREADS), 0, s, ki, n, n_dev, shift, hist,
+        hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(RS_THREADS), 0, s, ki, n, n_dev, shift, hist,
                            (int)tiles);
         const DevN tn{n_dev, 256 * tiles, (uint32_t)RS_TILE, 256u};
         rgs_status st = exclusive_scan_u32_dev(hist, offs, tn, 256 * tiles, nullptr, scan_ws, s);
         if (st != RGS_OK) return st;
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<V>), dim3((unsigned)tiles), dim3(RS_THREADS), 0, s, ki, vi,
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<V>), dim3(grid), dim3(RS_THREADS), 0, s, ki, vi,
                            n, n_dev, shift, offs, (int)tiles, ko, vo);
         RGS_LAUNCH_CHECK();
         uint32_t* tk = ki; ki = ko; ko = tk;
@@ -295,7 +308,8 @@ static rgs_status radix_sort_impl(uint32_t* keys, V* vals, uint32_t* keys_alt, V
     }
     if (ki != keys) {
         // odd number of passes: copy back (the elements in use only)
-        const unsigned g = (unsigned)((n + 255) / 256);
+        const int64_t g0 = (n + 255) / 256;
+        const unsigned g = (unsigned)(g0 > DEV_GRID * 8 ? DEV_GRID * 8 : g0);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_copy<V>), dim3(g), dim3(256), 0, s, ki, vi, n, n_dev, keys, vals);
         RGS_LAUNCH_CHECK();
     }

@@ -126,13 +126,31 @@ class FwdState:
 
 
 class Rasterizer:
-    def __init__(self, device: str = "cuda"):
+    """reuse=True keeps the forward pass's buffers between calls (grow-only, one
+    set per Rasterizer): no allocation once warm, but a FwdState is only valid
+    until the next forward call on the same Rasterizer.  For serving loops."""
+
+    def __init__(self, device: str = "cuda", reuse: bool = False):
         self.lib = L.load()
         self.device = torch.device(device)
         self.capacity_hint = 0
+        self.reuse = reuse
+        self._pool = {}
 
     def _empty(self, n, dtype):
         return torch.empty(int(max(n, 1)), dtype=dtype, device=self.device)
+
+    def _buf(self, key, n, dtype):
+        if not self.reuse:
+            return self._empty(n, dtype)
+        esz = torch.empty(0, dtype=dtype).element_size()
+        nbytes = int(max(n, 1)) * esz
+        t = self._pool.get(key)
+        if t is None or t.numel() < nbytes:
+            self._pool.pop(key, None)
+            t = torch.empty(int(nbytes * 1.25) + 256, dtype=torch.uint8, device=self.device)
+            self._pool[key] = t
+        return t[:nbytes].view(dtype)
 
     # ------------------------------------------------------------ KD tree
     def kd_partition(self, params, Ldepth: int, d_factor: float = 3.0, own_mask: bool = True) -> KD:
@@ -197,7 +215,7 @@ class Rasterizer:
         cam_arr = L.camera_array(cams)
         stream = _stream()
         ranks = self.cell_ranks(kd, cams)
-        views = self._empty(lib.rgs_views_bytes(), torch.uint8)
+        views = self._buf("views", lib.rgs_views_bytes(), torch.uint8)
         vis = None if cell_visible is None else np.ascontiguousarray(cell_visible, np.uint64)
         L.check("rgs_views_upload", lib.rgs_views_upload(cam_arr, V, kd.L, ranks.ctypes.data_as(C.c_void_p),
                                                          None if vis is None else vis.ctypes.data_as(C.c_void_p),
@@ -206,32 +224,32 @@ class Rasterizer:
         g = gaussians_struct(params)
         ks = kd.struct()
         m = V * n
-        proj = dict(rec=self._empty(m * L.REC_FLOATS, torch.float32), rect=self._empty(m * 4, torch.int16),
-                    cellmask=self._empty(m, torch.int64), count=self._empty(m, torch.int32))
+        proj = dict(rec=self._buf("rec", m * L.REC_FLOATS, torch.float32), rect=self._buf("rect", m * 4, torch.int16),
+                    cellmask=self._buf("cellmask", m, torch.int64), count=self._buf("count", m, torch.int32))
         ps = L.Projected(proj["rec"].data_ptr(), proj["rect"].data_ptr(), proj["cellmask"].data_ptr(),
                          proj["count"].data_ptr())
         L.check("rgs_project_sh", lib.rgs_project_sh(C.byref(g), cam_arr, V, _p(views), C.byref(ks), C.byref(ps), stream))
         _mark(marks, "project")
         T = int(lib.rgs_total_tiles(cam_arr, V))
         K = 1 << kd.L
-        bins = dict(pair_src=self._empty(m, torch.int32), pair_off=self._empty(m + 1, torch.int32),
-                    pair_rank=self._empty(m, torch.int32), tile_slot=self._empty(T + 1, torch.int32),
-                    counters=torch.zeros(4, dtype=torch.int32, device=self.device))
+        bins = dict(pair_src=self._buf("pair_src", m, torch.int32), pair_off=self._buf("pair_off", m + 1, torch.int32),
+                    pair_rank=self._buf("pair_rank", m, torch.int32), tile_slot=self._buf("tile_slot", T + 1, torch.int32),
+                    counters=self._buf("counters", 4, torch.int32).zero_())
         cap = max(self.capacity_hint, 1)
         while True:
             slot_cap = min(cap, T * K)
-            bins["keys"] = self._empty(cap, torch.int32)
-            bins["vals"] = self._empty(cap, torch.int64)
-            bins["slot_key"] = self._empty(slot_cap, torch.int32)
-            bins["slot_range"] = self._empty(2 * slot_cap, torch.int32)
-            bins["slot_order"] = self._empty(slot_cap, torch.int32)
+            bins["keys"] = self._buf("keys", cap, torch.int32)
+            bins["vals"] = self._buf("vals", cap, torch.int64)
+            bins["slot_key"] = self._buf("slot_key", slot_cap, torch.int32)
+            bins["slot_range"] = self._buf("slot_range", 2 * slot_cap, torch.int32)
+            bins["slot_order"] = self._buf("slot_order", slot_cap, torch.int32)
             bs = L.Bins()
             bs.capacity, bs.slot_capacity = cap, slot_cap
             for k in ("keys", "vals", "pair_src", "pair_off", "pair_rank", "slot_key", "slot_range", "tile_slot",
                       "slot_order", "counters"):
                 setattr(bs, k, bins[k].data_ptr())
             ws_bytes = lib.rgs_bin_sort_workspace(n, V, T, kd.L, cap)
-            ws = self._empty(ws_bytes, torch.uint8)
+            ws = self._buf("bin_ws", ws_bytes, torch.uint8)
             need = C.c_int64(0)
             st = lib.rgs_bin_sort(C.byref(ps), n, cam_arr, V, _p(views), kd.L, C.byref(bs), C.byref(need), _p(ws),
                                   ws_bytes, stream)
@@ -249,15 +267,15 @@ class Rasterizer:
             # actual slot count instead (one small device-to-host read)
             slot_cap = max(int(bins["counters"][2].item()), 1)
             bs.slot_capacity = slot_cap
-        parts = dict(C=self._empty(slot_cap * 768, torch.float32), T=self._empty(slot_cap * 256, torch.float32),
-                     last=self._empty(slot_cap * 256, torch.int32))
+        parts = dict(C=self._buf("C", slot_cap * 768, torch.float32), T=self._buf("T", slot_cap * 256, torch.float32),
+                     last=self._buf("last", slot_cap * 256, torch.int32))
         pt = L.Partials(parts["C"].data_ptr(), parts["T"].data_ptr(), parts["last"].data_ptr())
         L.check("rgs_render_partial", lib.rgs_render_partial(C.byref(ps), n, C.byref(bs), cam_arr, V, _p(views),
                                                              C.byref(ks), float(eps_T), C.byref(pt), _p(stats), stream))
         _mark(marks, "render_fwd")
         npix = sum(int(c["W"]) * int(c["H"]) for c in cams)
-        image = self._empty(3 * npix, torch.float32)
-        T_final = self._empty(npix, torch.float32)
+        image = self._buf("image", 3 * npix, torch.float32)
+        T_final = self._buf("T_final", npix, torch.float32)
         L.check("rgs_merge_partials", lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam_arr, V, _p(views), _p(image),
                                                              _p(T_final), stream))
         _mark(marks, "merge")

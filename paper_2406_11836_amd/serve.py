@@ -6,9 +6,12 @@ a dispatcher replays a request trace in real time, admits arrived requests
 into the next batch whenever a worker (one HIP stream each) is free and the
 batch's memory estimate fits the budget, and renders the batch with one call
 sequence (projection for all views at once, then binning, partial render and
-merge).  Requests that arrive while batches are on the GPU wait for the next
-free worker, so batches overlap on the device.  Per view, KD cells whose
-inflated bounds miss the padded view frustum are culled before projection.
+merge).  Requests that arrive while a batch is on the GPU wait for the next
+free worker.  One worker is the default: a batch of views at this scale
+fills the GPU by itself, and two concurrent batches on one device were
+measured to run many times slower than one after the other (their working
+sets of tens of GB compete).  Per view, KD cells whose inflated bounds miss
+the padded view frustum are culled before projection.
 
 Latency of a request = host time at which its batch completed - its
 scheduled arrival time.  The plain path for comparison is the same trace,
@@ -67,7 +70,7 @@ def frustum_cell_mask(cam, cell_bounds: np.ndarray, pad_px: float = 8.0, pad_rel
 
 
 class Server:
-    def __init__(self, params, kd: raster.KD, *, max_batch: int = 8, workers: int = 2, eps_T: float = 5e-5,
+    def __init__(self, params, kd: raster.KD, *, max_batch: int = 8, workers: int = 1, eps_T: float = 5e-5,
                  cull: bool = True, mem_budget: float | None = None, keep_images: bool = False,
                  device: str = "cuda"):
         self.params = params
@@ -80,10 +83,13 @@ class Server:
         self.device = torch.device(device)
         self.n = int(params["means"].shape[1])
         if mem_budget is None:
+            # device memory not in use: free plus what torch's cache holds unused
             free, _ = torch.cuda.mem_get_info(self.device)
-            mem_budget = 0.6 * free
+            cached = torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
+            mem_budget = 0.6 * (free + cached)
         self.mem_budget = float(mem_budget)
         self.batch_hist = collections.Counter()
+        self.batch_log = []  # (views, pixels, seconds on the worker) per completed batch
         self.peak_mem_est = 0.0
         self.busy_s = 0.0
 
@@ -93,12 +99,19 @@ class Server:
         px = float(cam["W"]) * float(cam["H"])
         return self.n * 104.0 + px * 320.0
 
-    def _worker(self, wid, jobs: queue.Queue, done: queue.Queue):
+    def _worker(self, wid, jobs: queue.Queue, done: queue.Queue, warm_cams):
         try:
             dev = self.device if self.device.index is not None else torch.device("cuda", torch.cuda.current_device())
             torch.cuda.set_device(dev)
             stream = torch.cuda.Stream(device=dev)  # default priority
-            rast = raster.Rasterizer(str(dev))
+            rast = raster.Rasterizer(str(dev), reuse=True)  # no allocation per batch once warm
+            if warm_cams:
+                # size the buffers for the largest batch before the trace starts
+                with torch.cuda.stream(stream):
+                    masks = [frustum_cell_mask(c, self.kd.cell_bounds_host) for c in warm_cams] if self.cull else None
+                    rast.forward(self.params, self.kd, warm_cams, self.eps_T, cell_visible=masks)
+                    stream.synchronize()
+            done.put((wid, None, 0.0, None))  # ready
         except BaseException as e:  # report set-up failures too
             done.put((wid, [], 0.0, e))
             return
@@ -131,10 +144,18 @@ class Server:
         done.  Raises if a worker fails or nothing completes for stall_timeout_s."""
         jobs = [queue.Queue() for _ in range(self.n_workers)]
         done: queue.Queue = queue.Queue()
-        threads = [threading.Thread(target=self._worker, args=(w, jobs[w], done), daemon=True)
+        # warm-up batch: the trace's largest views, as many as a batch holds
+        warm = sorted((r.cam for r in reqs), key=lambda c: -int(c["W"]) * int(c["H"]))[: self.max_batch]
+        threads = [threading.Thread(target=self._worker, args=(w, jobs[w], done, warm), daemon=True)
                    for w in range(self.n_workers)]
         for t in threads:
             t.start()
+        for _ in range(self.n_workers):
+            w, b, _, err = done.get()
+            if err is not None:
+                for q in jobs:
+                    q.put(None)
+                raise RuntimeError("render worker %d failed to start" % w) from err
         idle = list(range(self.n_workers))
         inflight_mem = {w: 0.0 for w in range(self.n_workers)}
         pending: collections.deque = collections.deque()
@@ -158,6 +179,7 @@ class Server:
                         raise RuntimeError("render worker %d failed" % w) from err
                     finished += len(b)
                     self.busy_s += dt
+                    self.batch_log.append((len(b), sum(int(r.cam["W"]) * int(r.cam["H"]) for r in b), dt))
                     inflight_mem[w] = 0.0
                     idle.append(w)
                     last_progress = now

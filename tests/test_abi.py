@@ -104,6 +104,24 @@ def test_argument_errors_enqueue_nothing(lib):
     assert lib.rgs_views_upload(bad, 1, 2, rk.ctypes.data_as(C.c_void_p), None, None, None) == E
     o = np.zeros(3, np.float32)
     assert lib.rgs_cell_order(7, None, o.ctypes.data_as(C.c_void_p), None, None) == E
+    # workspaces must be 256-byte aligned (checked before anything is enqueued)
+    fake = C.c_void_p(0x100000)
+    assert lib.rgs_loss_l1_ssim(fake, fake, 4, 4, 0.2, fake, fake, C.c_void_p(0x100000 + 16), 1 << 30, None) == E
+    # grouping by cell: needs cell bounds, distinct output buffers and matching sizes
+    gi, go = L.Gaussians(), L.Gaussians()
+    for x, base in ((gi, 0x100000), (go, 0x900000)):
+        x.n, x.sh_degree = 10, 0
+        x.means, x.log_scales, x.quats, x.opacity, x.sh = (base + 0x1000 * k for k in range(5))
+    kd2 = L.KdTree()
+    kd2.center_cell = 0x200000
+    big = 1 << 30
+    assert lib.rgs_group_by_cell(C.byref(gi), C.byref(kd2), 2, C.byref(go), None, fake, big, None) == E  # no cell_bounds
+    kd2.cell_bounds = 0x300000
+    assert lib.rgs_group_by_cell(C.byref(gi), C.byref(kd2), 2, C.byref(gi), None, fake, big, None) == E  # in == out
+    go.n = 11
+    assert lib.rgs_group_by_cell(C.byref(gi), C.byref(kd2), 2, C.byref(go), None, fake, big, None) == E  # n differs
+    go.n = 10
+    assert lib.rgs_group_by_cell(C.byref(gi), C.byref(kd2), 2, C.byref(go), None, fake, 16, None) == E  # small ws
 
 
 def test_struct_layouts_match_header(tmp_path):
