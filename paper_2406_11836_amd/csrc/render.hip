@@ -464,8 +464,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
 // pair are contiguous (emission order), so the sum is a segmented reduction
 // over the instance array, balanced over instances:
 //  1. k_pair_seg: a wave takes 64 consecutive records; the pairs covering
-//     them come from one binary search (first pair) and one coalesced load
-//     of the next 64 pair offsets; a segmented inclusive scan (fixed tree of
+//     them come from the wave's first pair (k_wave_first) and one coalesced
+//     load of the next 64 pair offsets; a segmented inclusive scan (fixed tree of
 //     shuffles) sums each pair's records within the wave.  Pairs complete in
 //     the wave are written to psum[rank]; the wave's first segment (pair
 //     begun before it) and last segment (pair going on after it) are kept as
@@ -473,8 +473,21 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
 //  2. k_pair_gather: thread per (view, Gaussian): zero if culled, else the
 //     pair's sum from psum, or, for a pair spanning several waves, its tail
 //     partial + whole-wave partials + head partial, in instance order.
+// first_pair[w] = the pair holding instance 64 w: each pair writes the waves
+// that start inside it (one thread per pair, grid-stride over the device count).
+__global__ __launch_bounds__(256) void k_wave_first(const uint32_t* __restrict__ pair_off,
+                                                    const uint32_t* __restrict__ counters,
+                                                    uint32_t* __restrict__ first_pair) {
+    const int64_t np = counters[0];
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < np; r += (int64_t)gridDim.x * 256) {
+        const uint32_t b = pair_off[r], e = pair_off[r + 1];
+        for (uint32_t w = (b + 63u) >> 6; (w << 6) < e; ++w) first_pair[w] = (uint32_t)r;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ records, const uint32_t* __restrict__ pair_off,
-                                                  const uint32_t* __restrict__ counters, float* __restrict__ psum,
+                                                  const uint32_t* __restrict__ counters,
+                                                  const uint32_t* __restrict__ first_pair, float* __restrict__ psum,
                                                   float* __restrict__ wpart) {
     const int lane = threadIdx.x & 63;
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -483,17 +496,7 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
     if (j0 >= (int64_t)n_inst) return;  // uniform per wave
     const int64_t j = j0 + lane;
     const bool valid = j < (int64_t)n_inst;
-    // first pair: the last r with pair_off[r] <= j0
-    uint32_t r0 = 0;
-    if (lane == 0) {
-        uint32_t lo = 0, hi = n_pairs - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if ((int64_t)pair_off[mid] <= j0) lo = mid; else hi = mid - 1;
-        }
-        r0 = lo;
-    }
-    r0 = (uint32_t)__shfl((int)r0, 0, 64);
+    const uint32_t r0 = first_pair[w];  // the pair holding instance j0
     // starts of the next 64 pairs (increasing); pos = how many start at or before j
     const uint32_t rk = r0 + 1u + (uint32_t)lane;
     const int64_t bk = rk < n_pairs ? (int64_t)pair_off[rk] : INT64_MAX;
@@ -591,12 +594,13 @@ __global__ __launch_bounds__(256) void k_pair_gather(const float* __restrict__ p
 }
 
 // Backward workspace: records and per-pair sums (pairs <= instances <= capacity)
-// of 48 bytes each, and two 48-byte partials per 64 instances.
+// of 48 bytes each, two 48-byte partials and the first pair per 64 instances.
 size_t render_bwd_ws_bytes(int64_t capacity) {
     const size_t c = (size_t)(capacity > 0 ? capacity : 1);
     const size_t rec = c * RD_REC * sizeof(float);
-    const size_t wp = ((c + 63) / 64) * 2 * RD_REC * sizeof(float);
-    return ((rec + 255) & ~size_t(255)) * 2 + wp + 256;
+    const size_t nw = (c + 63) / 64;
+    const size_t wp = nw * 2 * RD_REC * sizeof(float);
+    return ((rec + 255) & ~size_t(255)) * 2 + ((wp + 255) & ~size_t(255)) + nw * sizeof(uint32_t) + 256;
 }
 
 rgs_status render_bwd_launch(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
@@ -607,6 +611,9 @@ rgs_status render_bwd_launch(const rgs_partials_grad* dparts, const rgs_partials
     float* records = reinterpret_cast<float*>(ws);
     float* psum = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + rec_bytes);
     float* wpart = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + 2 * rec_bytes);
+    const size_t nw = (c + 63) / 64;
+    uint32_t* first_pair = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(wpart) +
+                                                       ((nw * 2 * RD_REC * sizeof(float) + 255) & ~size_t(255)));
     if (slot_bound > 0)
         hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect, bins->vals,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
@@ -615,9 +622,13 @@ rgs_status render_bwd_launch(const rgs_partials_grad* dparts, const rgs_partials
     const int64_t m = (int64_t)n_views * n;
     // one wave per 64 instances up to the capacity; waves past the device-side
     // instance count return at once
-    if (bins->capacity > 0)
+    if (bins->capacity > 0) {
+        const int64_t pb = (bins->capacity + 255) / 256;
+        hipLaunchKernelGGL(k_wave_first, dim3((unsigned)(pb < 2048 ? pb : 2048)), dim3(256), 0, s, bins->pair_off,
+                           bins->counters, first_pair);
         hipLaunchKernelGGL(k_pair_seg, dim3((unsigned)((bins->capacity + 255) / 256)), dim3(256), 0, s, records,
-                           bins->pair_off, bins->counters, psum, wpart);
+                           bins->pair_off, bins->counters, first_pair, psum, wpart);
+    }
     RGS_LAUNCH_CHECK();
     if (m > 0)
         hipLaunchKernelGGL(k_pair_gather, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, psum, wpart, proj->count,
