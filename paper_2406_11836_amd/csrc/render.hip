@@ -108,6 +108,7 @@ __device__ __forceinline__ uint32_t quad_mask_ellipse(uint2 rr, int tx, int ty, 
 // (w & 1, w >> 1) of the tile, one pixel per lane.  Records are staged 256 at
 // a time in LDS, each with the quadrant mask of its rectangle so that a wave
 // skips Gaussians that cannot touch its quadrant with a scalar branch.
+template <bool STATS>
 __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ rec, const int16_t* __restrict__ rect,
                                                     const uint64_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ slot_key,
@@ -168,36 +169,28 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
             sA[tid] = a;
             sB[tid] = b;
             sCl[tid] = cl;
-            if (stats) sR[tid] = rr;
+            if (STATS) sR[tid] = rr;
         }
         __syncthreads();
         if ((s_alive[0] | s_alive[1] | s_alive[2] | s_alive[3]) == 0u) break;
         const int nb = (int)((end - base) < (uint32_t)NB ? (end - base) : (uint32_t)NB);
         if (alive != 0ull) {
-            // Gaussians of this batch whose rectangle meets the wave's quadrant,
-            // walked in order with the next one's LDS loads issued early
+            // Gaussians of this batch whose footprint can reach the wave's
+            // quadrant, walked in order (other waves hide the LDS latency)
 #pragma unroll
             for (int k = 0; k < NB / 64; ++k) {
                 const int tl = k * 64 + lane;
                 uint64_t rel = __ballot(tl < nb && (sM[tl] & qbit) != 0u);
-                if (rel == 0ull) continue;
-                int t = k * 64 + (int)__builtin_ctzll(rel);
-                float4 a = sA[t], b = sB[t];
                 while (rel) {
-                    const int tc = t;
-                    const float4 ac = a, bc = b;
+                    const int tc = k * 64 + (int)__builtin_ctzll(rel);
                     rel &= rel - 1ull;
-                    if (rel) {
-                        t = k * 64 + (int)__builtin_ctzll(rel);
-                        a = sA[t];
-                        b = sB[t];
-                    }
+                    const float4 ac = sA[tc], bc = sB[tc];
                     const float dx = fxp - ac.x;
                     const float A = (ac.z * dx) * dx;
                     const float B = ac.w * dx;
                     const float dy = fyp - ac.y;
                     const float d2 = fmaf(dy, fmaf(bc.x, dy, B), A);
-                    if (stats && fyp != INFINITY) {
+                    if (STATS && fyp != INFINITY) {
                         // pairs the method must test: pixel inside the Gaussian's rectangle
                         const uint2 rr = sR[tc];
                         const bool inr = px >= (int)(int16_t)(rr.x & 0xffffu) && px <= (int)(int16_t)(rr.x >> 16) &&
@@ -212,7 +205,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
                                         (x2 < bhi2);
                         if (!in) continue;
                     }
-                    if (stats) ++n_con;
+                    if (STATS) ++n_con;
                     const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
                     const float sg = fminf(0.99f, bc.y * G);
                     const float wgt = sg * T;
@@ -227,7 +220,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
         }
         __syncthreads();
     }
-    if (stats) {
+    if (STATS) {
         unsigned long long e = n_eval, c = n_con;
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) {
@@ -251,9 +244,14 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
                              float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s) {
     if (slot_bound <= 0) return RGS_OK;
-    hipLaunchKernelGGL(k_render_fwd, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect, bins->vals,
-                       bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
-                       eps_T, out->C, out->T, out->last, reinterpret_cast<unsigned long long*>(stats));
+    if (stats)
+        hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect,
+                           bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
+                           kd->box_hi, eps_T, out->C, out->T, out->last, reinterpret_cast<unsigned long long*>(stats));
+    else
+        hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect,
+                           bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
+                           kd->box_hi, eps_T, out->C, out->T, out->last, nullptr);
     return launch_check();
 }
 
@@ -393,48 +391,45 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
             const uint32_t pos1 = (uint32_t)(bstart + t) + 1u;  // this instance's index + 1
             const float4 a = sA[t];
             const float4 b = sB[t];
-            float g[9];
-#pragma unroll
-            for (int c = 0; c < 9; ++c) g[c] = 0.f;
-            bool contrib = false;
             const float dx = fxp - a.x, dy = fyp - a.y;
             const float d2 = fmaf(dy, fmaf(b.x, dy, (2.0f * a.w) * dx), (a.z * dx) * dx);
-            if (pos1 <= last && d2 <= b.z) {
-                const float4 cl = sCl[t];
-                bool in = true;
-                if (!(__float_as_uint(cl.w) & 1u)) {
-                    const float x0 = fmaf(b.w, D0, o0), x1 = fmaf(b.w, D1, o1), x2 = fmaf(b.w, D2, o2);
-                    in = (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) && (x2 < bhi2);
-                }
-                if (in) {
-                    contrib = true;
-                    const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
-                    const float aG = b.y * G;
-                    const float sgm = fminf(0.99f, aG);
-                    const float rom = __builtin_amdgcn_rcpf(1.0f - sgm);
-                    const float Tb = Tcur * rom;  // transmittance before this contribution
-                    const float dot = fmaf(gC2, cl.z, fmaf(gC1, cl.y, gC0 * cl.x)) - gB;  // <dC, c - B>
-                    const float dsg = Tb * dot - gTf * rom;
-                    const float wc = Tb * sgm;
-                    g[6] = wc * gC0;
-                    g[7] = wc * gC1;
-                    g[8] = wc * gC2;
-                    gB = fmaf(sgm, dot, gB);  // B <- B + sigma (c - B)
-                    Tcur = Tb;
-                    if (aG < 0.99f) {
-                        // raw sums; the conic and the constant factors are applied per
-                        // instance after the reduction (dL/d(d^2) = -q / 2)
-                        const float q = aG * dsg;
-                        g[5] = dsg * G;
-                        g[0] = q * dx;
-                        g[1] = q * dy;
-                        g[2] = g[0] * dx;
-                        g[3] = g[0] * dy;
-                        g[4] = g[1] * dy;
-                    }
-                }
-            }
+            bool contrib = pos1 <= last && d2 <= b.z;
             if (__ballot(contrib) == 0ull) continue;
+            const float4 cl = sCl[t];
+            if (!(__float_as_uint(cl.w) & 1u)) {  // not interior to the cell: the indicator of Eq. 6
+                const float x0 = fmaf(b.w, D0, o0), x1 = fmaf(b.w, D1, o1), x2 = fmaf(b.w, D2, o2);
+                contrib = contrib && (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
+                          (x2 < bhi2);
+                if (__ballot(contrib) == 0ull) continue;
+            }
+            // Branch-free over the wave: a lane that does not contribute takes
+            // sigma = 0, so 1 / (1 - sigma) = 1 exactly, T and <dC, B> stay as
+            // they are, and every gradient term below is zero.
+            const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
+            const float aG = b.y * G;
+            const float sgm = contrib ? fminf(0.99f, aG) : 0.0f;
+            const float rom = __builtin_amdgcn_rcpf(1.0f - sgm);
+            const float Tb = Tcur * rom;  // transmittance before this contribution
+            const float dot = fmaf(gC2, cl.z, fmaf(gC1, cl.y, gC0 * cl.x)) - gB;  // <dC, c - B>
+            const float dsg = Tb * dot - gTf * rom;
+            const float wc = Tb * sgm;
+            float g[9];
+            g[6] = wc * gC0;
+            g[7] = wc * gC1;
+            g[8] = wc * gC2;
+            gB = fmaf(sgm, dot, gB);  // B <- B + sigma (c - B)
+            Tcur = Tb;
+            // clamped at 0.99: no gradient to alpha or the footprint.  Raw sums;
+            // the conic and constant factors are applied per instance after the
+            // reduction (dL/d(d^2) = -q / 2)
+            const float dsg_g = (contrib && aG < 0.99f) ? dsg : 0.0f;
+            const float q = aG * dsg_g;
+            g[5] = dsg_g * G;
+            g[0] = q * dx;
+            g[1] = q * dy;
+            g[2] = g[0] * dx;
+            g[3] = g[0] * dy;
+            g[4] = g[1] * dy;
             float sv, s8;
             wave_sum9(g, lane, &sv, &s8);
             if ((lane & 7) == 0) sG[w][t][lane >> 3] = sv;
