@@ -77,7 +77,7 @@ __device__ __forceinline__ bool quad_hits(float mx, float my, float ca, float cb
     if (lx <= 0.0f && hx >= 0.0f && ly <= 0.0f && hy >= 0.0f) return true;
     const float ica = __builtin_amdgcn_rcpf(ca), icc = __builtin_amdgcn_rcpf(cc);
     float qmin = INFINITY;
-#pragma unroll
+#pragma unroll 1
     for (int e = 0; e < 2; ++e) {
         const float ex = e ? hx : lx;  // vertical edge dx = ex
         const float dy = fminf(fmaxf(-(cb * ex) * icc, ly), hy);
@@ -304,7 +304,7 @@ __device__ __forceinline__ void wave_sum9(const float* g, int lane, float* out_v
 // block's largest `last`; every wave sums each instance's gradient over its
 // 64 pixels (zero when culled or not contributing) into LDS, and the four
 // quadrant sums are added in a fixed order into the instance's record.
-__global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ rec, const int16_t* __restrict__ rect,
+__global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__ rec, const int16_t* __restrict__ rect,
                                                     const uint64_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
@@ -316,7 +316,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
                                                     const float* __restrict__ dT, float* __restrict__ records) {
     constexpr int NB = 64;
     __shared__ float4 sA[NB], sB[NB], sCl[NB];
-    __shared__ uint32_t sM[NB], sJ[NB];
+    __shared__ uint2 sR[NB];
+    __shared__ uint32_t sJ[NB];
     __shared__ float sG[4][NB][9];
     __shared__ uint32_t s_max[4];
     if (blockIdx.x >= counters[2]) return;
@@ -363,7 +364,6 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
         float4* rp = reinterpret_cast<float4*>(records + (size_t)(uint32_t)vals[begin + k] * RD_REC);
         rp[0] = rp[1] = rp[2] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    const uint32_t qbit = 1u << (w + 1);
     for (int bstart = bmax == 0 ? -1 : (int)(((bmax - 1) / NB) * NB); bstart >= 0; bstart -= NB) {
         if (tid < NB && (uint32_t)bstart + tid < bmax) {
             const uint64_t vv = vals[begin + bstart + tid];
@@ -374,17 +374,22 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float* __restrict__ re
             sA[tid] = a;
             sB[tid] = b;
             sCl[tid] = cl;
-            const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
-            sM[tid] = (quad_mask_ellipse(rr, tx, ty, a.x, a.y, a.z, a.w, b.x, b.z) << 1) | (__float_as_uint(cl.w) & 1u);
+            sR[tid] = reinterpret_cast<const uint2*>(rect)[src];
             sJ[tid] = (uint32_t)vv;
         }
         for (int k = tid; k < 4 * NB * 9; k += 256) (&sG[0][0][0])[k] = 0.f;
         __syncthreads();
         // Gaussians of this batch below the wave's largest `last` whose
-        // rectangle meets the wave's quadrant, walked back to front
+        // footprint can reach the wave's quadrant (each wave tests its own
+        // quadrant, one record per lane), walked back to front
         const int tl = lane;
-        uint64_t rel = __ballot((uint32_t)(bstart + tl) + 1u <= wmax && (uint32_t)(bstart + tl) < bmax &&
-                                (sM[tl] & qbit) != 0u);
+        bool hit = (uint32_t)(bstart + tl) + 1u <= wmax && (uint32_t)(bstart + tl) < bmax;
+        if (hit) {
+            const float4 a = sA[tl], b = sB[tl];
+            hit = ((quad_mask(sR[tl], tx, ty) >> w) & 1u) &&
+                  quad_hits(a.x, a.y, a.z, a.w, b.x, b.z, (float)(tx * 16 + (w & 1) * 8), (float)(ty * 16 + (w >> 1) * 8));
+        }
+        uint64_t rel = __ballot(hit);
         while (rel) {
             const int t = 63 - (int)__builtin_clzll(rel);
             rel &= ~(1ull << t);

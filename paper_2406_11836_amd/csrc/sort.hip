@@ -5,8 +5,9 @@
 // global loads and stores stay coalesced.
 //
 // Radix sort: 8-bit digits, least significant first.  Per pass a histogram
-// kernel counts digits per 2048-key tile (LDS atomics on integers), the
-// digit-major table [256][tiles] is scanned, and a scatter kernel ranks each
+// kernel counts digits per 2048-key tile (LDS atomics on integers), one
+// block per digit scans that digit's row of the [256][tiles] table (the
+// digit bases come from the 256 row totals), and a scatter kernel ranks each
 // key stably inside its tile: every wave walks its strip in order, finds the
 // lanes sharing its digit with eight ballots, and keeps a running count per
 // digit in LDS; keys are then reordered in LDS by digit so that the global
@@ -177,16 +178,51 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restri
     }
 }
 
+// Per digit d (one block each): exclusive scan over tiles of the digit's row
+// hist[d][*] into offs[d][*], and the row total into dtot[d].  The scatter
+// adds the digit's base (an exclusive scan of the 256 totals, done in LDS).
+__global__ __launch_bounds__(RS_THREADS) void k_rs_colscan(const uint32_t* __restrict__ hist, int64_t n_host,
+                                                           const uint32_t* __restrict__ n_dev, int ntiles,
+                                                           uint32_t* __restrict__ offs, uint32_t* __restrict__ dtot) {
+    __shared__ uint32_t s_wave[4];
+    const int64_t n = rs_n(n_host, n_dev);
+    if (n_dev) ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
+    const int64_t row = (int64_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (int t0 = 0; t0 < ntiles; t0 += RS_THREADS * 4) {
+        uint32_t v[4], acc = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int t = t0 + threadIdx.x * 4 + k;
+            v[k] = t < ntiles ? hist[row + t] : 0u;
+            acc += v[k];
+        }
+        uint32_t ex;
+        const uint32_t tot = block_excl_scan_256(acc, s_wave, &ex);
+        uint32_t run = carry + ex;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int t = t0 + threadIdx.x * 4 + k;
+            if (t < ntiles) offs[row + t] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
+}
+
 template <typename V>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ keys_in,
                                                            const V* __restrict__ vals_in, int64_t n_host,
                                                            const uint32_t* __restrict__ n_dev, int shift,
-                                                           const uint32_t* __restrict__ offsets, int ntiles,
+                                                           const uint32_t* __restrict__ offsets,
+                                                           const uint32_t* __restrict__ dtot, int ntiles,
                                                            uint32_t* __restrict__ keys_out,
                                                            V* __restrict__ vals_out) {
     __shared__ uint32_t s_cnt[4][256];  // per-wave running digit counts, then wave prefixes
     __shared__ uint32_t s_dstart[256];  // tile-local start of each digit
     __shared__ uint32_t s_goff[256];    // global start of each digit for this tile
+    __shared__ uint32_t s_dbase[256];   // global start of each digit
     __shared__ uint32_t s_wave[4];
     __shared__ uint32_t s_keys[RS_TILE];
     __shared__ V s_vals[RS_TILE];
@@ -195,6 +231,11 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
     if (n_dev) ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if ((int)blockIdx.x < ntiles) {  // uniform per block
+        uint32_t ex;
+        block_excl_scan_256(dtot[threadIdx.x], s_wave, &ex);
+        s_dbase[threadIdx.x] = ex;
+    }
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         for (int k = threadIdx.x; k < 4 * 256; k += RS_THREADS) (&s_cnt[0][0])[k] = 0;
         __syncthreads();
@@ -233,7 +274,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
             s_cnt[2][d] = c0 + c1;
             s_cnt[3][d] = c0 + c1 + c2;
             const uint32_t tot = c0 + c1 + c2 + c3;
-            s_goff[d] = offsets[(int64_t)d * ntiles + tile];
+            s_goff[d] = s_dbase[d] + offsets[(int64_t)d * ntiles + tile];
             uint32_t ex;
             block_excl_scan_256(tot, s_wave, &ex);
             s_dstart[d] = ex;
@@ -276,7 +317,7 @@ size_t radix_ws_bytes(int64_t n) {
     int64_t tiles = (n + RS_TILE - 1) / RS_TILE;
     if (tiles < 1) tiles = 1;
     size_t h = (size_t)256 * tiles * sizeof(uint32_t);
-    return 2 * ((h + 255) & ~size_t(255)) + scan_ws_bytes(256 * tiles) + 512;
+    return 2 * ((h + 255) & ~size_t(255)) + 256 * sizeof(uint32_t) + 512;
 }
 
 template <typename V>
@@ -288,7 +329,7 @@ static rgs_status radix_sort_impl(uint32_t* keys, V* vals, uint32_t* keys_alt, V
     size_t hpad = (h + 255) & ~size_t(255);
     uint32_t* hist = reinterpret_cast<uint32_t*>(ws);
     uint32_t* offs = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + hpad);
-    void* scan_ws = reinterpret_cast<char*>(ws) + 2 * hpad;
+    uint32_t* dtot = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + 2 * hpad);  // [256]
     int passes = (bits + 7) / 8;
     const unsigned grid = (unsigned)(n_dev && tiles > DEV_GRID ? DEV_GRID : tiles);
     uint32_t *ki = keys, *ko = keys_alt;
@@ -297,11 +338,9 @@ static rgs_status radix_sort_impl(uint32_t* keys, V* vals, uint32_t* keys_alt, V
         int shift = 8 * p;
         hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(RS_THREADS), 0, s, ki, n, n_dev, shift, hist,
                            (int)tiles);
-        const DevN tn{n_dev, 256 * tiles, (uint32_t)RS_TILE, 256u};
-        rgs_status st = exclusive_scan_u32_dev(hist, offs, tn, 256 * tiles, nullptr, scan_ws, s);
-        if (st != RGS_OK) return st;
+        hipLaunchKernelGGL(k_rs_colscan, dim3(256), dim3(RS_THREADS), 0, s, hist, n, n_dev, (int)tiles, offs, dtot);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<V>), dim3(grid), dim3(RS_THREADS), 0, s, ki, vi,
-                           n, n_dev, shift, offs, (int)tiles, ko, vo);
+                           n, n_dev, shift, offs, dtot, (int)tiles, ko, vo);
         RGS_LAUNCH_CHECK();
         uint32_t* tk = ki; ki = ko; ko = tk;
         V* tv = vi; vi = vo; vo = tv;
