@@ -29,12 +29,20 @@ if ROOT not in sys.path:
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X fp32 vector (256 CU x 2.4 GHz; counts packed FMA)
 HBM_PEAK_GBS = 8000.0
+# algorithmic work per (pixel, instance) pair of the partial render (row a5)
 FLOP_PER_EVAL_PAIR = 7.0          # dy, two FMA for d^2, compare, plus the per-column dx terms / 4
 FLOP_PER_CONTRIB_PAIR = 14.0      # exp argument, exp, alpha G, clamp, weight, 3 FMA colour, 1 - s, T update, stop test
+# ... and of its backward (row a9): the same decision per re-tested pair, and per contributing pair
+# exp argument, exp, alpha G, clamp, 1 - s, reciprocal, T before (7), <dC, c> - <dC, B> (6),
+# d sigma (3), weight and 3 colour terms (4), <dC, B> update (2), q and d alpha (2), 5 raw sums (5)
+# = 29, plus 9 for the pair's share of the per-wave sum of 9 values over 64 lanes
+FLOP_BWD_EVAL_PAIR = 7.0
+FLOP_BWD_CONTRIB_PAIR = 38.0
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_render_fwd_1M_1600x1060_K8_hbm.txt")
+TRAFFIC_FILES = {k: os.path.join(HERE, "profiles", "%s_1M_1600x1060_K8_hbm.txt" % k)
+                 for k in ("k_render_fwd", "k_render_bwd")}
 RENDER_SOURCES = ("paper_2406_11836_amd/csrc/render.hip", "paper_2406_11836_amd/csrc/common.hpp")
 
 
@@ -47,13 +55,13 @@ def render_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(kernel: str):
     """HBM bytes per k_render_fwd launch from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a copy of
     known size); None when absent or when the kernel sources changed since."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILES[kernel]) as fh:
             for line in fh:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
@@ -252,18 +260,20 @@ def main():
     eps_T = 5e-5
     ssim_w = 0.2
 
-    def step(marks=None, stats=None):
+    def step(marks=None, stats=None, bstats=None):
         st = rast.forward(dp, kd, [cam], eps_T, stats=stats, marks=marks)
         lv, d = rast.loss(st.image.view(3, H, W), target, ssim_w)
         raster._mark(marks, "loss")
-        g = rast.backward(st, dp, d.view(-1), None, marks=marks)
+        g = rast.backward(st, dp, d.view(-1), None, marks=marks, stats=bstats)
         return st, g, lv
 
-    # pair statistics of the render (one extra untimed pass)
+    # pair statistics of the forward and backward render (one extra untimed pass)
     stats = torch.zeros(2, dtype=torch.int64, device="cuda")
-    st0, _, lv0 = step(stats=stats)
+    bstats = torch.zeros(2, dtype=torch.int64, device="cuda")
+    st0, _, lv0 = step(stats=stats, bstats=bstats)
     torch.cuda.synchronize()
     n_eval, n_con = (int(v) for v in stats.cpu().tolist())
+    nb_eval, nb_con = (int(v) for v in bstats.cpu().tolist())
     n_inst = int(st0.bins_struct.n_instances)
     n_slots = int(st0.bins["counters"][2].item())
     n_vis = int(st0.bins["counters"][0].item())
@@ -293,14 +303,23 @@ def main():
     stages = {k: float(np.mean([ea.elapsed_time(eb) for ea, eb in v])) for k, v in stage_ms.items()}
 
     mpix = (W * H) / (ms_step * 1e-3) / 1e6
-    # roofline of the dominant kernel (render forward: one kernel per call)
+    # roofline of the dominant kernel: the partial-render backward (one kernel per
+    # call of rgs_render_partial_bwd_records, timed by events on its stream)
+    t_rb = stages["render_bwd"] * 1e-3
+    flops_b = FLOP_BWD_EVAL_PAIR * nb_eval + FLOP_BWD_CONTRIB_PAIR * nb_con
+    ach_b = flops_b / t_rb / 1e12
+    roof = {"kernel": "k_render_bwd", "bound": "alu", "achieved": round(ach_b, 3),
+            "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach_b / FP32_VECTOR_PEAK_TFLOPS, 4),
+            "traffic": measured_traffic("k_render_bwd"), "algorithmic_flop": flops_b, "pairs_tested": nb_eval,
+            "pairs_contributing": nb_con, "avg_ms": round(stages["render_bwd"], 4)}
+    # the partial-render forward, for comparison
     t_rf = stages["render_fwd"] * 1e-3
     flops = FLOP_PER_EVAL_PAIR * n_eval + FLOP_PER_CONTRIB_PAIR * n_con
     achieved = flops / t_rf / 1e12
-    roof = {"kernel": "k_render_fwd", "bound": "alu", "achieved": round(achieved, 3),
-            "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": measured_traffic(), "algorithmic_flop": flops, "pairs_in_rect": n_eval, "pairs_contributing": n_con,
-            "avg_ms": round(stages["render_fwd"], 4)}
+    roof_f = {"kernel": "k_render_fwd", "bound": "alu", "achieved": round(achieved, 3),
+              "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+              "traffic": measured_traffic("k_render_fwd"), "algorithmic_flop": flops, "pairs_in_rect": n_eval,
+              "pairs_contributing": n_con, "avg_ms": round(stages["render_fwd"], 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -322,6 +341,7 @@ def main():
         "loss": round(float(lv0.item()), 6),
         "wall_s": round(wall, 3),
         "roofline": roof,
+        "roofline_render_fwd": roof_f,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

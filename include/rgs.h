@@ -51,7 +51,7 @@ extern "C" {
 #define RGS_TILE 16       /* screen tiles are 16 x 16 pixels */
 #define RGS_MAX_L 6       /* K = 2^L <= 64 cells */
 #define RGS_MAX_VIEWS 16  /* views per call */
-#define RGS_REC_FLOATS 12 /* floats per projected render record */
+#define RGS_REC_FLOATS 16 /* floats per projected render record (64 bytes, one aligned line) */
 
 typedef int32_t rgs_status;
 enum {
@@ -119,7 +119,9 @@ typedef struct {
 /* Per-(view, Gaussian) projection output.  Where count is 0 (culled) only
    count is written: rec, rect and cellmask hold whatever the buffers held. */
 typedef struct {
-    float *rec;         /* [V*N][12]: mx, my, ca, cb, cc, alpha, tau, z, r, g, b, flags */
+    float *rec;         /* [V*N][16]: mx, my, ca, cb | cc, alpha, tau, z | r, g, b, flags |
+                           rect as two uint32 (x_lo | x_hi << 16, y_lo | y_hi << 16), 0, 0;
+                           64-byte aligned: the render kernels fetch one line per instance */
     int16_t *rect;      /* [V*N][4]: sample-pixel rectangle x_lo, x_hi, y_lo, y_hi */
     uint64_t *cellmask; /* [V*N]: cells the footprint can reach (bit k = cell k) */
     uint32_t *count;    /* [V*N]: instances = |cellmask| * tiles in rect; 0 = culled */
@@ -305,6 +307,22 @@ rgs_status rgs_render_partial_bwd(const rgs_partials_grad *dparts, const rgs_par
                                   const rgs_camera *cams, int32_t n_views, const void *views_dev,
                                   const rgs_kdtree *kd, float *d_proj, void *ws, size_t ws_bytes,
                                   rgs_stream stream);
+
+/* The same in two calls (the backward's blend and its reduction, Sec. 3.4),
+ * so that each can be timed on its own.  rgs_render_partial_bwd_records
+ * writes the per-instance records into ws (same workspace and arguments as
+ * above, minus d_proj); stats, if not NULL, points to two device uint64
+ * counters incremented by the (pixel, instance) pairs tested (pixel inside
+ * the rectangle, at or before its last contributor) and the contributing
+ * pairs.  rgs_pair_reduce then sums each pair's records from the same ws into
+ * d_proj ([9][V*N], as above). */
+rgs_status rgs_render_partial_bwd_records(const rgs_partials_grad *dparts, const rgs_partials *parts,
+                                          const rgs_bins *bins, const rgs_projected *proj, int64_t n,
+                                          const rgs_camera *cams, int32_t n_views, const void *views_dev,
+                                          const rgs_kdtree *kd, void *ws, size_t ws_bytes, uint64_t *stats,
+                                          rgs_stream stream);
+rgs_status rgs_pair_reduce(const rgs_bins *bins, const rgs_projected *proj, int64_t n, int32_t n_views,
+                           float *d_proj, void *ws, size_t ws_bytes, rgs_stream stream);
 
 /* Projection backward: chain rule from d_proj to the parameters, summed over
  * the views.  Exact derivative: zero through the colour clamp, the clamp of

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "librgs.so")
 RGS_OK, RGS_E_ARG, RGS_E_CAPACITY, RGS_E_HIP, RGS_E_UNSUPPORTED = 0, -1, -2, -3, -4
 RGS_MAX_VIEWS = 16
 RGS_MAX_L = 6
-REC_FLOATS = 12
+REC_FLOATS = 16
 
 vp = C.c_void_p
 i32, i64, f32, sz = C.c_int32, C.c_int64, C.c_float, C.c_size_t
@@ -82,6 +82,9 @@ _SIGS = {
     "rgs_render_bwd_workspace": (sz, [i64]),
     "rgs_render_partial_bwd": (i32, [P(PartialsGrad), P(Partials), P(Bins), P(Projected), i64, P(Camera), i32, vp,
                                      P(KdTree), vp, vp, sz, vp]),
+    "rgs_render_partial_bwd_records": (i32, [P(PartialsGrad), P(Partials), P(Bins), P(Projected), i64, P(Camera), i32, vp,
+                                           P(KdTree), vp, sz, vp, vp]),
+    "rgs_pair_reduce": (i32, [P(Bins), P(Projected), i64, i32, vp, vp, sz, vp]),
     "rgs_project_sh_bwd": (i32, [vp, P(Gaussians), P(Projected), P(Camera), i32, vp, P(GaussiansGrad), vp]),
 }
 

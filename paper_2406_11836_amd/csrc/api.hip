@@ -32,9 +32,11 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
                              float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s);
 size_t render_bwd_ws_bytes(int64_t capacity);
-rgs_status render_bwd_launch(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
-                             const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt,
-                             const rgs_kdtree* kd, float* dproj, void* ws, int64_t slot_bound, hipStream_t s);
+rgs_status render_bwd_records_launch(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
+                                     const rgs_projected* proj, const ViewTable* vt, const rgs_kdtree* kd, void* ws,
+                                     uint64_t* stats, int64_t slot_bound, hipStream_t s);
+rgs_status pair_reduce_launch(const rgs_bins* bins, const rgs_projected* proj, int64_t n, int n_views, float* dproj,
+                              void* ws, hipStream_t s);
 rgs_status merge_fwd_launch(const rgs_partials* parts, const rgs_bins* bins, const ViewTable* vt, int64_t total_tiles,
                             float* image, float* T_final, hipStream_t s);
 rgs_status merge_bwd_launch(const float* dimage, const float* dTfinal, const rgs_partials* parts, const rgs_bins* bins,
@@ -284,16 +286,42 @@ size_t rgs_render_bwd_workspace(int64_t capacity) {
     return render_bwd_ws_bytes(capacity);
 }
 
+static bool bwd_args_ok(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
+                        const rgs_projected* proj, int64_t n, const rgs_camera* cams, int32_t n_views,
+                        const void* views_dev, const rgs_kdtree* kd, const void* ws, size_t ws_bytes) {
+    if (!dparts || !dparts->dC || !dparts->dT || !parts || !parts->T || !parts->last || !bins_ok(bins) || !proj_ok(proj) ||
+        n < 0 || !cams_ok(cams, n_views) || !views_dev || !kd || !kd->box_lo || !kd->box_hi)
+        return false;
+    return ws_ok(ws, ws_bytes, render_bwd_ws_bytes(bins->capacity));
+}
+
+rgs_status rgs_render_partial_bwd_records(const rgs_partials_grad* dparts, const rgs_partials* parts,
+                                          const rgs_bins* bins, const rgs_projected* proj, int64_t n,
+                                          const rgs_camera* cams, int32_t n_views, const void* views_dev,
+                                          const rgs_kdtree* kd, void* ws, size_t ws_bytes, uint64_t* stats,
+                                          rgs_stream stream) {
+    if (!bwd_args_ok(dparts, parts, bins, proj, n, cams, n_views, views_dev, kd, ws, ws_bytes)) return RGS_E_ARG;
+    return render_bwd_records_launch(dparts, parts, bins, proj, reinterpret_cast<const ViewTable*>(views_dev), kd, ws,
+                                     stats, slot_bound_of(bins, cams, n_views, kd->L), S(stream));
+}
+
+rgs_status rgs_pair_reduce(const rgs_bins* bins, const rgs_projected* proj, int64_t n, int32_t n_views, float* d_proj,
+                           void* ws, size_t ws_bytes, rgs_stream stream) {
+    if (!bins_ok(bins) || !proj_ok(proj) || n < 0 || n_views < 1 || n_views > RGS_MAX_VIEWS || !d_proj) return RGS_E_ARG;
+    if (!ws_ok(ws, ws_bytes, render_bwd_ws_bytes(bins->capacity))) return RGS_E_ARG;
+    return pair_reduce_launch(bins, proj, n, n_views, d_proj, ws, S(stream));
+}
+
 rgs_status rgs_render_partial_bwd(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
                                   const rgs_projected* proj, int64_t n, const rgs_camera* cams, int32_t n_views,
                                   const void* views_dev, const rgs_kdtree* kd, float* d_proj, void* ws, size_t ws_bytes,
                                   rgs_stream stream) {
-    if (!dparts || !dparts->dC || !dparts->dT || !parts || !parts->T || !parts->last || !bins_ok(bins) || !proj_ok(proj) ||
-        n < 0 || !cams_ok(cams, n_views) || !views_dev || !kd || !kd->box_lo || !kd->box_hi || !d_proj || !ws)
+    if (!bwd_args_ok(dparts, parts, bins, proj, n, cams, n_views, views_dev, kd, ws, ws_bytes) || !d_proj)
         return RGS_E_ARG;
-    if (!ws_ok(ws, ws_bytes, render_bwd_ws_bytes(bins->capacity))) return RGS_E_ARG;
-    return render_bwd_launch(dparts, parts, bins, proj, n, n_views, reinterpret_cast<const ViewTable*>(views_dev), kd,
-                             d_proj, ws, slot_bound_of(bins, cams, n_views, kd->L), S(stream));
+    rgs_status st = render_bwd_records_launch(dparts, parts, bins, proj, reinterpret_cast<const ViewTable*>(views_dev),
+                                              kd, ws, nullptr, slot_bound_of(bins, cams, n_views, kd->L), S(stream));
+    if (st != RGS_OK) return st;
+    return pair_reduce_launch(bins, proj, n, n_views, d_proj, ws, S(stream));
 }
 
 rgs_status rgs_project_sh_bwd(const float* d_proj, const rgs_gaussians* g, const rgs_projected* proj,

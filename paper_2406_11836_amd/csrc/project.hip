@@ -303,6 +303,7 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
         rec[0] = make_float4(p.mx, p.my, p.ca, p.cb);
         rec[1] = make_float4(p.cc, p.alpha, p.tau, p.z);
         rec[2] = make_float4(col[0], col[1], col[2], __uint_as_float(flags));
+        rec[3] = make_float4(__uint_as_float(rx), __uint_as_float(ry), 0.f, 0.f);  // the rectangle, for the render kernels
     }
 }
 

@@ -109,7 +109,7 @@ __device__ __forceinline__ uint32_t quad_mask_ellipse(uint2 rr, int tx, int ty, 
 // a time in LDS, each with the quadrant mask of its rectangle so that a wave
 // skips Gaussians that cannot touch its quadrant with a scalar branch.
 template <bool STATS>
-__global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ rec, const int16_t* __restrict__ rect,
+__global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ rec,
                                                     const uint64_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
@@ -162,8 +162,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
             const uint32_t src = (uint32_t)(vals[idx] >> 32);
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
             float4 a = rp[0];
-            const float4 b = rp[1], cl = rp[2];
-            const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
+            const float4 b = rp[1], cl = rp[2], r4 = rp[3];
+            const uint2 rr = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
             sM[tid] = (quad_mask_ellipse(rr, tx, ty, a.x, a.y, a.z, a.w, b.x, b.z) << 1) | (__float_as_uint(cl.w) & 1u);
             a.w = 2.0f * a.w;  // 2 cb (exact)
             sA[tid] = a;
@@ -245,11 +245,11 @@ rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, co
                              float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s) {
     if (slot_bound <= 0) return RGS_OK;
     if (stats)
-        hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect,
+        hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec,
                            bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
                            kd->box_hi, eps_T, out->C, out->T, out->last, reinterpret_cast<unsigned long long*>(stats));
     else
-        hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect,
+        hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec,
                            bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
                            kd->box_hi, eps_T, out->C, out->T, out->last, nullptr);
     return launch_check();
@@ -304,7 +304,8 @@ __device__ __forceinline__ void wave_sum9(const float* g, int lane, float* out_v
 // block's largest `last`; every wave sums each instance's gradient over its
 // 64 pixels (zero when culled or not contributing) into LDS, and the four
 // quadrant sums are added in a fixed order into the instance's record.
-__global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__ rec, const int16_t* __restrict__ rect,
+template <bool STATS>
+__global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__ rec,
                                                     const uint64_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
@@ -313,7 +314,8 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
                                                     const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
                                                     const float* __restrict__ box_hi, const float* __restrict__ partT,
                                                     const uint32_t* __restrict__ partLast, const float* __restrict__ dC,
-                                                    const float* __restrict__ dT, float* __restrict__ records) {
+                                                    const float* __restrict__ dT, float* __restrict__ records,
+                                                    unsigned long long* __restrict__ stats) {
     constexpr int NB = 64;
     __shared__ float4 sA[NB], sB[NB], sCl[NB];
     __shared__ uint2 sR[NB];
@@ -354,6 +356,7 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
     // gB = <dC_k, B>, where B is the colour blended behind the current
     // instance (the suffix of Eq. 3): the only way B enters the gradient
     float gB = 0.f;
+    uint32_t n_eval = 0u, n_con = 0u;
     const uint32_t wmax = wave_max_u32(last);
     if (lane == 0) s_max[w] = wmax;
     __syncthreads();
@@ -370,11 +373,11 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
             const uint32_t src = (uint32_t)(vv >> 32);
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
             const float4 cl = rp[2];
-            const float4 a = rp[0], b = rp[1];
+            const float4 a = rp[0], b = rp[1], r4 = rp[3];
             sA[tid] = a;
             sB[tid] = b;
             sCl[tid] = cl;
-            sR[tid] = reinterpret_cast<const uint2*>(rect)[src];
+            sR[tid] = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
             sJ[tid] = (uint32_t)vv;
         }
         for (int k = tid; k < 4 * NB * 9; k += 256) (&sG[0][0][0])[k] = 0.f;
@@ -399,6 +402,12 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
             const float dx = fxp - a.x, dy = fyp - a.y;
             const float d2 = fmaf(dy, fmaf(b.x, dy, (2.0f * a.w) * dx), (a.z * dx) * dx);
             bool contrib = pos1 <= last && d2 <= b.z;
+            if (STATS && pos1 <= last) {
+                // pairs the backward must re-test: pixel inside the rectangle, at or before its last contributor
+                const uint2 rr = sR[t];
+                n_eval += (px >= (int)(int16_t)(rr.x & 0xffffu) && px <= (int)(int16_t)(rr.x >> 16) &&
+                           py >= (int)(int16_t)(rr.y & 0xffffu) && py <= (int)(int16_t)(rr.y >> 16)) ? 1u : 0u;
+            }
             if (__ballot(contrib) == 0ull) continue;
             const float4 cl = sCl[t];
             if (!(__float_as_uint(cl.w) & 1u)) {  // not interior to the cell: the indicator of Eq. 6
@@ -410,6 +419,7 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
             // Branch-free over the wave: a lane that does not contribute takes
             // sigma = 0, so 1 / (1 - sigma) = 1 exactly, T and <dC, B> stay as
             // they are, and every gradient term below is zero.
+            if (STATS) n_con += contrib ? 1u : 0u;
             const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
             const float aG = b.y * G;
             const float sgm = contrib ? fminf(0.99f, aG) : 0.0f;
@@ -457,6 +467,18 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
             rp[2] = make_float4(S[8], 0.f, 0.f, 0.f);
         }
         __syncthreads();
+    }
+    if (STATS) {
+        unsigned long long e = n_eval, c = n_con;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            e += __shfl_xor(e, d, 64);
+            c += __shfl_xor(c, d, 64);
+        }
+        if (lane == 0) {
+            atomicAdd(&stats[0], e);
+            atomicAdd(&stats[1], c);
+        }
     }
 }
 
@@ -603,36 +625,60 @@ size_t render_bwd_ws_bytes(int64_t capacity) {
     return ((rec + 255) & ~size_t(255)) * 2 + ((wp + 255) & ~size_t(255)) + nw * sizeof(uint32_t) + 256;
 }
 
-rgs_status render_bwd_launch(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
-                             const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt,
-                             const rgs_kdtree* kd, float* dproj, void* ws, int64_t slot_bound, hipStream_t s) {
+struct BwdWs {
+    float *records, *psum, *wpart;
+    uint32_t* first_pair;
+};
+
+static BwdWs carve_bwd(const rgs_bins* bins, void* ws) {
     const size_t c = (size_t)(bins->capacity > 0 ? bins->capacity : 1);
     const size_t rec_bytes = (c * RD_REC * sizeof(float) + 255) & ~size_t(255);
-    float* records = reinterpret_cast<float*>(ws);
-    float* psum = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + rec_bytes);
-    float* wpart = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + 2 * rec_bytes);
+    BwdWs w;
+    w.records = reinterpret_cast<float*>(ws);
+    w.psum = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + rec_bytes);
+    w.wpart = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + 2 * rec_bytes);
     const size_t nw = (c + 63) / 64;
-    uint32_t* first_pair = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(wpart) +
-                                                       ((nw * 2 * RD_REC * sizeof(float) + 255) & ~size_t(255)));
-    if (slot_bound > 0)
-        hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, proj->rect, bins->vals,
+    w.first_pair = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(w.wpart) +
+                                               ((nw * 2 * RD_REC * sizeof(float) + 255) & ~size_t(255)));
+    return w;
+}
+
+// The partial-render backward alone: per-instance records into the workspace.
+rgs_status render_bwd_records_launch(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
+                                     const rgs_projected* proj, const ViewTable* vt, const rgs_kdtree* kd, void* ws,
+                                     uint64_t* stats, int64_t slot_bound, hipStream_t s) {
+    const BwdWs w = carve_bwd(bins, ws);
+    if (slot_bound <= 0) return RGS_OK;
+    if (stats)
+        hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, bins->vals,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
-                           parts->T, parts->last, dparts->dC, dparts->dT, records);
-    RGS_LAUNCH_CHECK();
+                           parts->T, parts->last, dparts->dC, dparts->dT, w.records,
+                           reinterpret_cast<unsigned long long*>(stats));
+    else
+        hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, bins->vals,
+                           bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
+                           parts->T, parts->last, dparts->dC, dparts->dT, w.records, nullptr);
+    return launch_check();
+}
+
+// The per-pair sums of the records in the workspace.
+rgs_status pair_reduce_launch(const rgs_bins* bins, const rgs_projected* proj, int64_t n, int n_views, float* dproj,
+                              void* ws, hipStream_t s) {
+    const BwdWs w = carve_bwd(bins, ws);
     const int64_t m = (int64_t)n_views * n;
     // one wave per 64 instances up to the capacity; waves past the device-side
     // instance count return at once
     if (bins->capacity > 0) {
         const int64_t pb = (bins->capacity + 255) / 256;
         hipLaunchKernelGGL(k_wave_first, dim3((unsigned)(pb < 2048 ? pb : 2048)), dim3(256), 0, s, bins->pair_off,
-                           bins->counters, first_pair);
-        hipLaunchKernelGGL(k_pair_seg, dim3((unsigned)((bins->capacity + 255) / 256)), dim3(256), 0, s, records,
-                           bins->pair_off, bins->counters, first_pair, psum, wpart);
+                           bins->counters, w.first_pair);
+        hipLaunchKernelGGL(k_pair_seg, dim3((unsigned)((bins->capacity + 255) / 256)), dim3(256), 0, s, w.records,
+                           bins->pair_off, bins->counters, w.first_pair, w.psum, w.wpart);
     }
     RGS_LAUNCH_CHECK();
     if (m > 0)
-        hipLaunchKernelGGL(k_pair_gather, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, psum, wpart, proj->count,
-                           bins->pair_rank, bins->pair_off, m, dproj);
+        hipLaunchKernelGGL(k_pair_gather, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, w.psum, w.wpart,
+                           proj->count, bins->pair_rank, bins->pair_off, m, dproj);
     return launch_check();
 }
 

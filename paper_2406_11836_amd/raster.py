@@ -285,7 +285,9 @@ class Rasterizer:
 
     # ------------------------------------------------------------ backward
     def backward(self, st: FwdState, params, d_image: torch.Tensor, d_T_final: torch.Tensor | None = None,
-                 marks: list | None = None):
+                 marks: list | None = None, stats: torch.Tensor | None = None):
+        """stats: optional int64 device tensor [2] (pairs re-tested, contributing pairs of the
+        partial-render backward), incremented."""
         lib = self.lib
         _mark(marks, "bwd_start")
         V = len(st.cams)
@@ -306,10 +308,13 @@ class Rasterizer:
         dproj = self._empty(9 * m, torch.float32)
         ws_bytes = lib.rgs_render_bwd_workspace(bs.capacity)
         ws = self._empty(ws_bytes, torch.uint8)
-        L.check("rgs_render_partial_bwd", lib.rgs_render_partial_bwd(C.byref(pgs), C.byref(pt), C.byref(bs), C.byref(ps),
-                                                                     st.n, st.cam_arr, V, _p(st.views), C.byref(ks),
-                                                                     _p(dproj), _p(ws), ws_bytes, stream))
+        L.check("rgs_render_partial_bwd_records",
+                lib.rgs_render_partial_bwd_records(C.byref(pgs), C.byref(pt), C.byref(bs), C.byref(ps), st.n, st.cam_arr,
+                                                   V, _p(st.views), C.byref(ks), _p(ws), ws_bytes, _p(stats), stream))
         _mark(marks, "render_bwd")
+        L.check("rgs_pair_reduce", lib.rgs_pair_reduce(C.byref(bs), C.byref(ps), st.n, V, _p(dproj), _p(ws), ws_bytes,
+                                                       stream))
+        _mark(marks, "pair_reduce")
         grads = {k: torch.empty_like(params[k]) for k in PARAM_KEYS}
         gg = L.GaussiansGrad(*[grads[k].data_ptr() for k in PARAM_KEYS])
         g = gaussians_struct(params)

@@ -91,7 +91,7 @@ def test_kd_partition_full_size_1m(rast):
 def test_project_bit_exact(name, rast):
     p, cam, tgt, L, dp, kd, st, okd, order, rank_of, pr = run_case(name, rast)
     n = p["means"].shape[1]
-    rec = st.proj["rec"][: n * 12].view(n, 12).cpu().numpy()
+    rec = st.proj["rec"][: n * 16].view(n, 16).cpu().numpy()
     cnt = st.proj["count"][:n].cpu().numpy().view(np.uint32)
     assert np.array_equal(cnt, pr["count"]), "instance counts"
     vis = pr["vis"] == 1
@@ -99,6 +99,10 @@ def test_project_bit_exact(name, rast):
     assert np.array_equal(st.proj["cellmask"][:n].cpu().numpy().view(np.uint64)[vis], pr["cellmask"][vis])
     rect = st.proj["rect"][: 4 * n].view(n, 4).cpu().numpy().astype(np.int32)
     assert np.array_equal(rect[vis], pr["rect"][vis])
+    # the render record carries the same rectangle (x_lo | x_hi << 16, y_lo | y_hi << 16)
+    packed = rec[vis][:, 12:14].view(np.uint32)
+    unpack = np.stack([packed[:, 0] & 0xffff, packed[:, 0] >> 16, packed[:, 1] & 0xffff, packed[:, 1] >> 16], 1)
+    assert np.array_equal(unpack.astype(np.int16).astype(np.int32), pr["rect"][vis])
     # decision quantities: mx, my, ca, cb, cc, tau, z, alpha
     gpu_dec = rec[vis][:, [0, 1, 2, 3, 4, 6, 7, 5]]
     assert np.array_equal(gpu_dec.view(np.uint32), pr["dec32"][vis].view(np.uint32))
@@ -216,6 +220,30 @@ def test_backward_parity(name, rast):
         ok, info = grad_close(g[k].cpu().numpy(), og[k], 1e-3, k)
         log(str(info))
         assert ok, info
+
+
+def test_combined_backward_equals_split_calls(rast):
+    """rgs_render_partial_bwd (one call) gives the same per-pair gradients, bit
+    for bit, as rgs_render_partial_bwd_records followed by rgs_pair_reduce."""
+    import ctypes as C
+    from paper_2406_11836_amd import _lib as L
+    p, cam, tgt, Ld, dp, kd, st, okd, order, rank_of, pr = run_case("mini2", rast)
+    d = torch.from_numpy(np.random.default_rng(3).normal(size=st.image.numel()).astype(np.float32)).cuda()
+    g = rast.backward(st, dp, d)
+    torch.cuda.synchronize()
+    lib = rast.lib
+    pgs = L.PartialsGrad(g["_dparts"]["dC"].data_ptr(), g["_dparts"]["dT"].data_ptr())
+    pt, ps, ks, bs = st.parts_struct(), st.proj_struct(), st.kd.struct(), st.bins_struct
+    m = st.n
+    dproj = torch.empty(9 * m, dtype=torch.float32, device="cuda")
+    ws_bytes = lib.rgs_render_bwd_workspace(bs.capacity)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    L.check("rgs_render_partial_bwd", lib.rgs_render_partial_bwd(
+        C.byref(pgs), C.byref(pt), C.byref(bs), C.byref(ps), st.n, st.cam_arr, 1, C.c_void_p(st.views.data_ptr()),
+        C.byref(ks), C.c_void_p(dproj.data_ptr()), C.c_void_p(ws.data_ptr()), ws_bytes,
+        C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    torch.cuda.synchronize()
+    assert torch.equal(dproj, g["_dproj"][: 9 * m])
 
 
 def test_deterministic_runs(rast):
