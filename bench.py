@@ -260,8 +260,9 @@ def main():
     eps_T = 5e-5
     ssim_w = 0.2
 
-    def step(marks=None, stats=None, bstats=None):
-        st = rast.forward(dp, kd, [cam], eps_T, stats=stats, marks=marks)
+    def step(marks=None, stats=None, bstats=None, no_sync=True):
+        # binning without a host wait: the capacity comes from the statistics pass
+        st = rast.forward(dp, kd, [cam], eps_T, stats=stats, marks=marks, no_sync=no_sync)
         lv, d = rast.loss(st.image.view(3, H, W), target, ssim_w)
         raster._mark(marks, "loss")
         g = rast.backward(st, dp, d.view(-1), None, marks=marks, stats=bstats)
@@ -270,7 +271,7 @@ def main():
     # pair statistics of the forward and backward render (one extra untimed pass)
     stats = torch.zeros(2, dtype=torch.int64, device="cuda")
     bstats = torch.zeros(2, dtype=torch.int64, device="cuda")
-    st0, _, lv0 = step(stats=stats, bstats=bstats)
+    st0, _, lv0 = step(stats=stats, bstats=bstats, no_sync=False)
     torch.cuda.synchronize()
     n_eval, n_con = (int(v) for v in stats.cpu().tolist())
     nb_eval, nb_con = (int(v) for v in bstats.cpu().tolist())
@@ -289,9 +290,10 @@ def main():
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t_start.record()
+    last = None
     for _ in range(args.steps):
         marks = []
-        step(marks=marks)
+        last = step(marks=marks)
         for (a, ea), (b, eb) in zip(marks[:-1], marks[1:]):
             if b in ("bwd_start",):
                 continue
@@ -300,6 +302,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_step = t_start.elapsed_time(t_end) / args.steps
+    if last[0].overflow():
+        raise RuntimeError("instance capacity exceeded in a timed step")
     stages = {k: float(np.mean([ea.elapsed_time(eb) for ea, eb in v])) for k, v in stage_ms.items()}
 
     mpix = (W * H) / (ms_step * 1e-3) / 1e6

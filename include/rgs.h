@@ -20,7 +20,8 @@
  *     Workspaces must be 256-byte aligned (any hipMalloc'd pointer is).
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and
  *     the call returns without waiting, except rgs_bin_sort, which copies one
- *     counter to the host (the instance count) and therefore waits once.
+ *     counter to the host (the instance count) and therefore waits once
+ *     (rgs_bin_sort_async does not).
  *   - Argument errors are reported synchronously (RGS_E_ARG) and enqueue
  *     nothing.  A failed kernel launch returns RGS_E_HIP and records the HIP
  *     error code (rgs_last_hip_error, per thread).  Faults inside kernels
@@ -140,7 +141,7 @@ typedef struct {
     uint32_t *slot_range;   /* [slot_capacity][2] begin, end into keys/vals */
     uint32_t *tile_slot;    /* [total_tiles+1] first slot of each global tile (slots of a tile are in view order) */
     uint32_t *slot_order;   /* [slot_capacity] slots by decreasing size class (the render launch order) */
-    uint32_t *counters;     /* [4]: pairs, instances, slots, 0 */
+    uint32_t *counters;     /* [4]: pairs, instances, slots, required instances if over capacity (async) */
     int64_t n_instances;    /* [out, host] */
 } rgs_bins;
 
@@ -175,6 +176,12 @@ size_t rgs_views_bytes(void);
 rgs_status rgs_views_upload(const rgs_camera *cams, int32_t n_views, int32_t L,
                             const int32_t *rank_of, const uint64_t *cell_visible, void *views_dev,
                             rgs_stream stream);
+/* [host] The same table written to host memory (views_host: rgs_views_bytes()
+ * bytes), for a caller that copies it to the device itself, e.g. from pinned
+ * memory without waiting (rgs_views_upload waits for its stream so that its
+ * stack copy has been consumed). */
+rgs_status rgs_views_pack(const rgs_camera *cams, int32_t n_views, int32_t L, const int32_t *rank_of,
+                          const uint64_t *cell_visible, void *views_host);
 /* [host] total 16x16 tiles over the views. */
 int64_t rgs_total_tiles(const rgs_camera *cams, int32_t n_views);
 
@@ -244,6 +251,20 @@ size_t rgs_bin_sort_workspace(int64_t n, int32_t n_views, int64_t total_tiles, i
 rgs_status rgs_bin_sort(const rgs_projected *proj, int64_t n, const rgs_camera *cams, int32_t n_views,
                         const void *views_dev, int32_t L, rgs_bins *bins, int64_t *n_required,
                         void *ws, size_t ws_bytes, rgs_stream stream);
+
+/* The same without waiting on the host (for a pass whose buffers were sized by
+ * an earlier one, e.g. a training step): the instance count stays on the
+ * device and grids are sized by the capacities, so the host can enqueue the
+ * rest of the pass at once.  Requires bins->slot_capacity >=
+ * min(bins->capacity, total_tiles << L).  If the instances exceed
+ * bins->capacity, counters[3] receives the required count and counters[0..2]
+ * are zeroed: every later call of the pass finds no work and writes no more
+ * than the background, and the caller must grow the buffers and redo the
+ * pass.  counters[3] == 0 means the pass is valid.  Sets bins->n_instances to
+ * -1 (unknown on the host). */
+rgs_status rgs_bin_sort_async(const rgs_projected *proj, int64_t n, const rgs_camera *cams, int32_t n_views,
+                              const void *views_dev, int32_t L, rgs_bins *bins, void *ws, size_t ws_bytes,
+                              rgs_stream stream);
 
 /* ------------------------------------------------------------------ */
 /* Partial render (Eq. 3, Eq. 4, Eq. 6)                                 */

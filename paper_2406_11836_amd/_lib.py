@@ -65,6 +65,7 @@ _SIGS = {
     "rgs_last_hip_error": (i32, []),
     "rgs_views_bytes": (sz, []),
     "rgs_views_upload": (i32, [P(Camera), i32, i32, vp, vp, vp, vp]),
+    "rgs_views_pack": (i32, [P(Camera), i32, i32, vp, vp, vp]),
     "rgs_total_tiles": (i64, [P(Camera), i32]),
     "rgs_kd_partition_workspace": (sz, [i64, i32]),
     "rgs_kd_partition": (i32, [P(Gaussians), i32, f32, P(KdTree), vp, sz, vp]),
@@ -74,6 +75,7 @@ _SIGS = {
     "rgs_project_sh": (i32, [P(Gaussians), P(Camera), i32, vp, P(KdTree), P(Projected), vp]),
     "rgs_bin_sort_workspace": (sz, [i64, i32, i64, i32, i64]),
     "rgs_bin_sort": (i32, [P(Projected), i64, P(Camera), i32, vp, i32, P(Bins), P(i64), vp, sz, vp]),
+    "rgs_bin_sort_async": (i32, [P(Projected), i64, P(Camera), i32, vp, i32, P(Bins), vp, sz, vp]),
     "rgs_render_partial": (i32, [P(Projected), i64, P(Bins), P(Camera), i32, vp, P(KdTree), f32, P(Partials), vp, vp]),
     "rgs_merge_partials": (i32, [P(Partials), P(Bins), P(Camera), i32, vp, vp, vp, vp]),
     "rgs_loss_workspace": (sz, [i32, i32]),

@@ -28,7 +28,7 @@ size_t group_ws_bytes(int64_t n);
 rgs_status group_by_cell(const rgs_gaussians* in, const rgs_kdtree* kd, int L, const rgs_gaussians* out, int32_t* perm,
                          void* ws, size_t ws_bytes, hipStream_t s);
 rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt_dev, int L, int64_t total_tiles,
-                    rgs_bins* bins, int64_t* n_required, void* ws, size_t ws_bytes, hipStream_t s);
+                    rgs_bins* bins, int64_t* n_required, bool sync, void* ws, size_t ws_bytes, hipStream_t s);
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
                              float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s);
 size_t render_bwd_ws_bytes(int64_t capacity);
@@ -103,9 +103,9 @@ int64_t rgs_total_tiles(const rgs_camera* cams, int32_t n_views) {
     return t;
 }
 
-rgs_status rgs_views_upload(const rgs_camera* cams, int32_t n_views, int32_t L, const int32_t* rank_of,
-                            const uint64_t* cell_visible, void* views_dev, rgs_stream stream) {
-    if (!cams_ok(cams, n_views) || L < 0 || L > RGS_MAX_L || !rank_of || !views_dev) return RGS_E_ARG;
+rgs_status rgs_views_pack(const rgs_camera* cams, int32_t n_views, int32_t L, const int32_t* rank_of,
+                          const uint64_t* cell_visible, void* views_host) {
+    if (!cams_ok(cams, n_views) || L < 0 || L > RGS_MAX_L || !rank_of || !views_host) return RGS_E_ARG;
     const int K = 1 << L;
     ViewTable vt;
     memset(&vt, 0, sizeof(vt));
@@ -142,6 +142,16 @@ rgs_status rgs_views_upload(const rgs_camera* cams, int32_t n_views, int32_t L, 
         if (p.cell_visible != full) vt.culled = 1u;
     }
     vt.total_tiles = tile_off;
+    memcpy(views_host, &vt, sizeof(vt));
+    return RGS_OK;
+}
+
+rgs_status rgs_views_upload(const rgs_camera* cams, int32_t n_views, int32_t L, const int32_t* rank_of,
+                            const uint64_t* cell_visible, void* views_dev, rgs_stream stream) {
+    if (!views_dev) return RGS_E_ARG;
+    ViewTable vt;
+    const rgs_status st = rgs_views_pack(cams, n_views, L, rank_of, cell_visible, &vt);
+    if (st != RGS_OK) return st;
     RGS_HIP_CHECK(hipMemcpyAsync(views_dev, &vt, sizeof(vt), hipMemcpyHostToDevice, S(stream)));
     // the host copy lives on this stack frame: make sure it has been consumed
     RGS_HIP_CHECK(hipStreamSynchronize(S(stream)));
@@ -229,13 +239,31 @@ rgs_status rgs_bin_sort(const rgs_projected* proj, int64_t n, const rgs_camera* 
     if (!ws_ok(ws, ws_bytes, bin_ws_bytes(n, n_views, T, L, bins->capacity))) return RGS_E_ARG;
     if ((int64_t)n_views * n >= 0x7fffffffLL || bins->capacity >= 0xffffffffLL || (T << L) >= 0x7fffffffLL)
         return RGS_E_UNSUPPORTED;
-    return bin_sort(proj, n, n_views, reinterpret_cast<const ViewTable*>(views_dev), L, T, bins, n_required, ws, ws_bytes,
-                    S(stream));
+    return bin_sort(proj, n, n_views, reinterpret_cast<const ViewTable*>(views_dev), L, T, bins, n_required, true, ws,
+                    ws_bytes, S(stream));
 }
 
+rgs_status rgs_bin_sort_async(const rgs_projected* proj, int64_t n, const rgs_camera* cams, int32_t n_views,
+                              const void* views_dev, int32_t L, rgs_bins* bins, void* ws, size_t ws_bytes,
+                              rgs_stream stream) {
+    if (!proj_ok(proj) || n < 0 || !cams_ok(cams, n_views) || !views_dev || L < 0 || L > RGS_MAX_L || !bins_ok(bins))
+        return RGS_E_ARG;
+    const int64_t T = rgs_total_tiles(cams, n_views);
+    if (!ws_ok(ws, ws_bytes, bin_ws_bytes(n, n_views, T, L, bins->capacity))) return RGS_E_ARG;
+    if ((int64_t)n_views * n >= 0x7fffffffLL || bins->capacity >= 0xffffffffLL || (T << L) >= 0x7fffffffLL)
+        return RGS_E_UNSUPPORTED;
+    const int64_t dense = T << L;
+    if (bins->slot_capacity < (bins->capacity < dense ? bins->capacity : dense)) return RGS_E_ARG;
+    return bin_sort(proj, n, n_views, reinterpret_cast<const ViewTable*>(views_dev), L, T, bins, nullptr, false, ws,
+                    ws_bytes, S(stream));
+}
+
+// Grid bound for the per-slot kernels: slots <= min(instances, tiles x cells);
+// with the instance count left on the device (n_instances < 0), the capacity.
 static int64_t slot_bound_of(const rgs_bins* bins, const rgs_camera* cams, int32_t n_views, int L) {
     const int64_t dense = rgs_total_tiles(cams, n_views) << L;
-    int64_t b = bins->n_instances < dense ? bins->n_instances : dense;
+    const int64_t ni = bins->n_instances >= 0 ? bins->n_instances : bins->capacity;
+    int64_t b = ni < dense ? ni : dense;
     return b < bins->slot_capacity ? b : bins->slot_capacity;
 }
 

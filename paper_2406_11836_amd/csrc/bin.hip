@@ -174,13 +174,30 @@ __global__ __launch_bounds__(BN_THREADS) void k_fill_u32(uint32_t* __restrict__ 
 }
 
 // Slot boundaries on the dense (tile, rank) table.
-__global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __restrict__ keys, int64_t n_inst,
+__global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __restrict__ keys,
+                                                            const uint32_t* __restrict__ n_dev,
                                                             uint32_t* __restrict__ dstart, uint32_t* __restrict__ dend) {
-    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (i >= n_inst) return;
-    const uint32_t k = keys[i];
-    if (i == 0 || keys[i - 1] != k) dstart[k] = (uint32_t)i;
-    if (i == n_inst - 1 || keys[i + 1] != k) dend[k] = (uint32_t)(i + 1);
+    const int64_t n_inst = (int64_t)*n_dev;
+    for (int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x; i < n_inst; i += (int64_t)gridDim.x * BN_THREADS) {
+        const uint32_t k = keys[i];
+        if (i == 0 || keys[i - 1] != k) dstart[k] = (uint32_t)i;
+        if (i == n_inst - 1 || keys[i + 1] != k) dend[k] = (uint32_t)(i + 1);
+    }
+}
+
+// Without a host copy of the instance count: if it exceeds the capacity,
+// record it in counters[3] and zero the pair, instance and slot counts so that
+// every later kernel of the pass finds no work; else counters[3] = 0.
+__global__ void k_capacity_guard(uint32_t* __restrict__ cnt, int64_t capacity) {
+    if (threadIdx.x != 0) return;
+    if ((int64_t)cnt[1] > capacity) {
+        cnt[3] = cnt[1];
+        cnt[0] = 0u;
+        cnt[1] = 0u;
+        cnt[2] = 0u;
+    } else {
+        cnt[3] = 0u;
+    }
 }
 
 __global__ __launch_bounds__(BN_THREADS) void k_slot_flags(const uint32_t* __restrict__ dstart, int64_t m,
@@ -295,7 +312,7 @@ static inline int bits_for(uint64_t v) {  // bits needed to represent values < v
 }
 
 rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt_dev, int L,
-                    int64_t total_tiles, rgs_bins* bins, int64_t* n_required, void* ws, size_t ws_bytes,
+                    int64_t total_tiles, rgs_bins* bins, int64_t* n_required, bool sync, void* ws, size_t ws_bytes,
                     hipStream_t s) {
     const int64_t m = (int64_t)n_views * n;
     const int64_t dense = total_tiles << L;
@@ -349,14 +366,23 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     if ((st = exclusive_scan_u32_dev(flag, bins->pair_off, DevN{&cnt[0], m, 1, 1}, m, &cnt[1], sws, s)) != RGS_OK)
         return st;
     hipLaunchKernelGGL(k_pair_off_tail, dim3(1), dim3(64), 0, s, bins->pair_off, cnt);
-    uint32_t h_cnt[2] = {0u, 0u};
-    RGS_HIP_CHECK(hipMemcpyAsync(h_cnt, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    RGS_HIP_CHECK(hipStreamSynchronize(s));
-    const int64_t n_inst = h_cnt[1];
-    bins->n_instances = n_inst;
-    if (n_required) *n_required = n_inst;
-    const int64_t slot_bound = n_inst < dense ? n_inst : dense;
-    if (n_inst > bins->capacity || slot_bound > bins->slot_capacity) return RGS_E_CAPACITY;
+    int64_t n_inst, slot_bound;
+    if (sync) {
+        uint32_t h_cnt[2] = {0u, 0u};
+        RGS_HIP_CHECK(hipMemcpyAsync(h_cnt, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        RGS_HIP_CHECK(hipStreamSynchronize(s));
+        n_inst = h_cnt[1];
+        bins->n_instances = n_inst;
+        if (n_required) *n_required = n_inst;
+        slot_bound = n_inst < dense ? n_inst : dense;
+        if (n_inst > bins->capacity || slot_bound > bins->slot_capacity) return RGS_E_CAPACITY;
+    } else {
+        // the count stays on the device; grids are sized by the capacity
+        hipLaunchKernelGGL(k_capacity_guard, dim3(1), dim3(64), 0, s, cnt, bins->capacity);
+        bins->n_instances = -1;
+        n_inst = bins->capacity;
+        slot_bound = n_inst < dense ? n_inst : dense;
+    }
 
     // 3. emit and sort instances by (tile, rank)
     if (m > 0)
@@ -365,12 +391,13 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     RGS_LAUNCH_CHECK();
     const int key_bits = L + bits_for((uint64_t)total_tiles);
     if (key_bits > 32) return RGS_E_UNSUPPORTED;
-    if ((st = radix_sort_u32_u64(bins->keys, bins->vals, keys_alt, vals_alt, n_inst, key_bits, rws, s)) != RGS_OK)
-        return st;
+    if (sync) st = radix_sort_u32_u64(bins->keys, bins->vals, keys_alt, vals_alt, n_inst, key_bits, rws, s);
+    else st = radix_sort_u32_u64_dev(bins->keys, bins->vals, keys_alt, vals_alt, &cnt[1], n_inst, key_bits, rws, s);
+    if (st != RGS_OK) return st;
 
     // 4. slots
     hipLaunchKernelGGL(k_fill_u32, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, 0xffffffffu);
-    if (n_inst > 0) hipLaunchKernelGGL(k_slot_bounds, grid(n_inst), dim3(BN_THREADS), 0, s, bins->keys, n_inst, dstart, dend);
+    if (n_inst > 0) hipLaunchKernelGGL(k_slot_bounds, dgrid(n_inst), dim3(BN_THREADS), 0, s, bins->keys, &cnt[1], dstart, dend);
     hipLaunchKernelGGL(k_slot_flags, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, dflag);
     if ((st = exclusive_scan_u32(dflag, sidx, dense, &cnt[2], sws, s)) != RGS_OK) return st;
     hipLaunchKernelGGL(k_slot_compact, grid(dense), dim3(BN_THREADS), 0, s, dstart, dend, sidx, dense, bins->slot_key,

@@ -160,6 +160,8 @@ rgs_status radix_sort_u32_u64(uint32_t* keys, uint64_t* vals, uint32_t* keys_alt
 rgs_status radix_sort_u32_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                               int64_t n, int bits, void* ws, hipStream_t s);
 // The same, with n read on the device (upper bound n_max for the grid).
+rgs_status radix_sort_u32_u64_dev(uint32_t* keys, uint64_t* vals, uint32_t* keys_alt, uint64_t* vals_alt,
+                                  const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s);
 rgs_status radix_sort_u32_u32_dev(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                                   const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s);
 }  // namespace rgs

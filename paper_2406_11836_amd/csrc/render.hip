@@ -586,14 +586,15 @@ __device__ __forceinline__ void acc_rec(const float* __restrict__ p, float4& a0,
 __global__ __launch_bounds__(256) void k_pair_gather(const float* __restrict__ psum, const float* __restrict__ wpart,
                                                      const uint32_t* __restrict__ count,
                                                      const int32_t* __restrict__ pair_rank,
-                                                     const uint32_t* __restrict__ pair_off, int64_t m,
+                                                     const uint32_t* __restrict__ pair_off,
+                                                     const uint32_t* __restrict__ n_pairs, int64_t m,
                                                      float* __restrict__ dproj) {
     const int64_t sidx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (sidx >= m) return;
     float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
     float a8 = 0.f;
-    if (count[sidx] > 0u) {
-        const int32_t r = pair_rank[sidx];
+    const int32_t r = count[sidx] > 0u ? pair_rank[sidx] : -1;
+    if (r >= 0 && (uint32_t)r < n_pairs[0]) {  // a pass that ran out of capacity has no pairs
         const uint32_t b = pair_off[r], e = pair_off[r + 1];
         const uint32_t wb = b >> 6, we = (e - 1u) >> 6;
         if (wb == we) {
@@ -678,7 +679,7 @@ rgs_status pair_reduce_launch(const rgs_bins* bins, const rgs_projected* proj, i
     RGS_LAUNCH_CHECK();
     if (m > 0)
         hipLaunchKernelGGL(k_pair_gather, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, w.psum, w.wpart,
-                           proj->count, bins->pair_rank, bins->pair_off, m, dproj);
+                           proj->count, bins->pair_rank, bins->pair_off, bins->counters, m, dproj);
     return launch_check();
 }
 

@@ -363,6 +363,10 @@ rgs_status radix_sort_u32_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt
                               int bits, void* ws, hipStream_t s) {
     return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, nullptr, bits, ws, s);
 }
+rgs_status radix_sort_u32_u64_dev(uint32_t* keys, uint64_t* vals, uint32_t* keys_alt, uint64_t* vals_alt,
+                                  const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s) {
+    return radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n_max, n_dev, bits, ws, s);
+}
 rgs_status radix_sort_u32_u32_dev(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                                   const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s) {
     return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n_max, n_dev, bits, ws, s);

@@ -109,6 +109,11 @@ class FwdState:
         s.cellmask, s.count = self.proj["cellmask"].data_ptr(), self.proj["count"].data_ptr()
         return s
 
+    def overflow(self) -> int:
+        """Instances required beyond the capacity by an asynchronous binning
+        (0: the pass is valid).  Reads one device counter."""
+        return int(self.bins["counters"][3].item())
+
     def parts_struct(self) -> L.Partials:
         s = L.Partials()
         s.C, s.T, s.last = self.parts["C"].data_ptr(), self.parts["T"].data_ptr(), self.parts["last"].data_ptr()
@@ -202,7 +207,7 @@ class Rasterizer:
 
     # ------------------------------------------------------------ forward
     def forward(self, params, kd: KD, cams, eps_T: float = 5e-5, stats: torch.Tensor | None = None,
-                marks: list | None = None, cell_visible=None) -> FwdState:
+                marks: list | None = None, cell_visible=None, no_sync: bool = False) -> FwdState:
         """stats: optional int64 device tensor [2] (evaluated, contributing pairs), incremented.
         marks: optional list receiving (stage, event) pairs at stage ends.
         cell_visible: optional per-view uint64 masks of the KD cells that may reach each view."""
@@ -215,11 +220,16 @@ class Rasterizer:
         cam_arr = L.camera_array(cams)
         stream = _stream()
         ranks = self.cell_ranks(kd, cams)
-        views = self._buf("views", lib.rgs_views_bytes(), torch.uint8)
+        vb = lib.rgs_views_bytes()
+        views = self._buf("views", vb, torch.uint8)
         vis = None if cell_visible is None else np.ascontiguousarray(cell_visible, np.uint64)
-        L.check("rgs_views_upload", lib.rgs_views_upload(cam_arr, V, kd.L, ranks.ctypes.data_as(C.c_void_p),
-                                                         None if vis is None else vis.ctypes.data_as(C.c_void_p),
-                                                         _p(views), stream))
+        # packed on the host into pinned memory and copied on the stream without waiting
+        # (torch's pinned allocator does not reuse the block before the copy is done)
+        host = torch.empty(vb, dtype=torch.uint8, pin_memory=True)
+        L.check("rgs_views_pack", lib.rgs_views_pack(cam_arr, V, kd.L, ranks.ctypes.data_as(C.c_void_p),
+                                                     None if vis is None else vis.ctypes.data_as(C.c_void_p),
+                                                     C.c_void_p(host.data_ptr())))
+        views.copy_(host, non_blocking=True)
         _mark(marks, "views")
         g = gaussians_struct(params)
         ks = kd.struct()
@@ -236,6 +246,9 @@ class Rasterizer:
                     pair_rank=self._buf("pair_rank", m, torch.int32), tile_slot=self._buf("tile_slot", T + 1, torch.int32),
                     counters=self._buf("counters", 4, torch.int32).zero_())
         cap = max(self.capacity_hint, 1)
+        # no host wait in binning when an earlier pass sized the buffers and the
+        # slot bound stays small (the caller checks FwdState.overflow())
+        use_async = no_sync and self.capacity_hint > 0 and min(cap, T * K) <= (1 << 18)
         while True:
             slot_cap = min(cap, T * K)
             bins["keys"] = self._buf("keys", cap, torch.int32)
@@ -251,6 +264,10 @@ class Rasterizer:
             ws_bytes = lib.rgs_bin_sort_workspace(n, V, T, kd.L, cap)
             ws = self._buf("bin_ws", ws_bytes, torch.uint8)
             need = C.c_int64(0)
+            if use_async:
+                L.check("rgs_bin_sort_async", lib.rgs_bin_sort_async(C.byref(ps), n, cam_arr, V, _p(views), kd.L,
+                                                                     C.byref(bs), _p(ws), ws_bytes, stream))
+                break
             st = lib.rgs_bin_sort(C.byref(ps), n, cam_arr, V, _p(views), kd.L, C.byref(bs), C.byref(need), _p(ws),
                                   ws_bytes, stream)
             if st == L.RGS_E_CAPACITY:
@@ -262,7 +279,7 @@ class Rasterizer:
         _mark(marks, "bin_sort")
         n_inst = int(bs.n_instances)
         slot_cap = int(bs.slot_capacity)
-        if slot_cap > (1 << 18):
+        if slot_cap > (1 << 18) and not use_async:
             # large bound (many views / tiles): size the partial maps by the
             # actual slot count instead (one small device-to-host read)
             slot_cap = max(int(bins["counters"][2].item()), 1)

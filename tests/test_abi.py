@@ -104,6 +104,15 @@ def test_argument_errors_enqueue_nothing(lib):
     assert lib.rgs_views_upload(bad, 1, 2, rk.ctypes.data_as(C.c_void_p), None, None, None) == E
     o = np.zeros(3, np.float32)
     assert lib.rgs_cell_order(7, None, o.ctypes.data_as(C.c_void_p), None, None) == E
+    # the host-side view table: packs on the CPU, rejects bad cell ranks
+    host = np.zeros(lib.rgs_views_bytes(), np.uint8)
+    rk4 = np.array([0, 1, 2, 3], np.int32)
+    assert lib.rgs_views_pack(cam, 1, 2, rk4.ctypes.data_as(C.c_void_p), None, host.ctypes.data_as(C.c_void_p)) == 0
+    assert host.any()
+    bad_rk = np.array([0, 1, 2, 4], np.int32)
+    assert lib.rgs_views_pack(cam, 1, 2, bad_rk.ctypes.data_as(C.c_void_p), None,
+                              host.ctypes.data_as(C.c_void_p)) == E
+    assert lib.rgs_views_pack(cam, 1, 2, rk4.ctypes.data_as(C.c_void_p), None, None) == E
     # workspaces must be 256-byte aligned (checked before anything is enqueued)
     fake = C.c_void_p(0x100000)
     assert lib.rgs_loss_l1_ssim(fake, fake, 4, 4, 0.2, fake, fake, C.c_void_p(0x100000 + 16), 1 << 30, None) == E

@@ -246,6 +246,34 @@ def test_combined_backward_equals_split_calls(rast):
     assert torch.equal(dproj, g["_dproj"][: 9 * m])
 
 
+def test_async_binning_equals_sync():
+    """Binning without the host wait gives the same image and gradients, bit for
+    bit, once an earlier pass sized the buffers; a pass over capacity reports the
+    required count and renders only the background."""
+    from paper_2406_11836_amd import raster
+    r = raster.Rasterizer()
+    p, cam, tgt, Ld, dp, kd, st, okd, order, rank_of, pr = run_case("mini2", r)
+    a = r.forward(dp, kd, [cam], EPS_T)                    # synchronous (sets the capacity)
+    b = r.forward(dp, kd, [cam], EPS_T, no_sync=True)      # asynchronous
+    assert b.bins_struct.n_instances == -1
+    assert b.overflow() == 0
+    assert torch.equal(a.image, b.image) and torch.equal(a.T_final, b.T_final)
+    d = torch.from_numpy(np.random.default_rng(2).normal(size=a.image.numel()).astype(np.float32)).cuda()
+    ga, gb = r.backward(a, dp, d), r.backward(b, dp, d)
+    for k in raster.PARAM_KEYS:
+        assert torch.equal(ga[k], gb[k]), k
+    need = int(a.bins_struct.n_instances)
+    r.capacity_hint = need // 3
+    c = r.forward(dp, kd, [cam], EPS_T, no_sync=True)
+    assert c.overflow() == need
+    bg = torch.tensor(cam.get("bg", (0.0, 0.0, 0.0)), dtype=torch.float32,
+                      device="cuda").repeat_interleave(cam["W"] * cam["H"])
+    assert torch.equal(c.image, bg) and torch.all(c.T_final == 1.0)
+    r.capacity_hint = 0
+    e = r.forward(dp, kd, [cam], EPS_T)                    # grown again, synchronously
+    assert torch.equal(e.image, a.image)
+
+
 def test_deterministic_runs(rast):
     p, cam, tgt, L, dp, kd, st, okd, order, rank_of, pr = run_case("mini2", rast)
     a = rast.forward(dp, kd, [cam], EPS_T)
