@@ -61,53 +61,74 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
         sy[k] = in ? yc[(int64_t)gy * W + gx] : 0.f;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < TW * TS; k += LS_THREADS) {
-        const int r = k / TS, c = k % TS;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+    // horizontal pass: a thread takes 4 consecutive outputs of one row from a
+    // 14-value window in registers (the taps of each output in the same order)
+    for (int k = threadIdx.x; k < TW * (TS / 4); k += LS_THREADS) {
+        const int r = k >> 3, c0 = (k & 7) * 4;
+        float xv[14], yv[14];
 #pragma unroll
-        for (int t = 0; t < 11; ++t) {
-            const float xv = sx[r * TW + c + t], yv = sy[r * TW + c + t], w = win.w[t];
-            a0 = fmaf(w, xv, a0);
-            a1 = fmaf(w, yv, a1);
-            a2 = fmaf(w, xv * xv, a2);
-            a3 = fmaf(w, yv * yv, a3);
-            a4 = fmaf(w, xv * yv, a4);
+        for (int j = 0; j < 14; ++j) {
+            xv[j] = sx[r * TW + c0 + j];
+            yv[j] = sy[r * TW + c0 + j];
         }
-        hm[0][k] = a0; hm[1][k] = a1; hm[2][k] = a2; hm[3][k] = a3; hm[4][k] = a4;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+#pragma unroll
+            for (int t = 0; t < 11; ++t) {
+                const float xa = xv[o + t], ya = yv[o + t], w = win.w[t];
+                a0 = fmaf(w, xa, a0);
+                a1 = fmaf(w, ya, a1);
+                a2 = fmaf(w, xa * xa, a2);
+                a3 = fmaf(w, ya * ya, a3);
+                a4 = fmaf(w, xa * ya, a4);
+            }
+            const int q = r * TS + c0 + o;
+            hm[0][q] = a0; hm[1][q] = a1; hm[2][q] = a2; hm[3][q] = a3; hm[4][q] = a4;
+        }
     }
     __syncthreads();
     float l1 = 0.f, ss = 0.f;
-    for (int k = threadIdx.x; k < TS * TS; k += LS_THREADS) {
-        const int r = k / TS, c = k % TS;
-        const int gy = y0 + r, gx = x0 + c;
-        if (gy >= H || gx >= W) continue;
-        float mu_x = 0.f, mu_y = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+    // vertical pass: thread (column c, row group) takes 4 consecutive rows
+    {
+        const int c = threadIdx.x & 31, r0 = (threadIdx.x >> 5) * 4;
+        float mom[5][4];
 #pragma unroll
-        for (int t = 0; t < 11; ++t) {
-            const int q = (r + t) * TS + c;
-            const float w = win.w[t];
-            mu_x = fmaf(w, hm[0][q], mu_x);
-            mu_y = fmaf(w, hm[1][q], mu_y);
-            exx = fmaf(w, hm[2][q], exx);
-            eyy = fmaf(w, hm[3][q], eyy);
-            exy = fmaf(w, hm[4][q], exy);
+        for (int mm = 0; mm < 5; ++mm) {
+            float hv[14];
+#pragma unroll
+            for (int j = 0; j < 14; ++j) hv[j] = hm[mm][(r0 + j) * TS + c];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                float a = 0.f;
+#pragma unroll
+                for (int t = 0; t < 11; ++t) a = fmaf(win.w[t], hv[o + t], a);
+                mom[mm][o] = a;
+            }
         }
-        const float C1 = 1e-4f, C2 = 9e-4f;
-        const float A1 = 2.f * mu_x * mu_y + C1;
-        const float A2 = 2.f * (exy - mu_x * mu_y) + C2;
-        const float B1 = mu_x * mu_x + mu_y * mu_y + C1;
-        const float B2 = (exx - mu_x * mu_x) + (eyy - mu_y * mu_y) + C2;
-        const float Nn = A1 * A2, Dd = B1 * B2;
-        const float iD = 1.f / Dd;
-        ss += Nn * iD;
-        const float dN = 2.f * mu_y * A2 - 2.f * mu_y * A1;
-        const float dD = 2.f * mu_x * B2 - 2.f * mu_x * B1;
-        const int64_t i = ch * HW + (int64_t)gy * W + gx;
-        const int64_t m = 3 * HW;
-        d3[i] = (dN * Dd - Nn * dD) * iD * iD;
-        d3[m + i] = -Nn * B1 * iD * iD;
-        d3[2 * m + i] = 2.f * A1 * iD;
-        l1 += fabsf(sx[(r + HALO) * TW + c + HALO] - sy[(r + HALO) * TW + c + HALO]);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int r = r0 + o;
+            const int gy = y0 + r, gx = x0 + c;
+            if (gy >= H || gx >= W) continue;
+            const float mu_x = mom[0][o], mu_y = mom[1][o], exx = mom[2][o], eyy = mom[3][o], exy = mom[4][o];
+            const float C1 = 1e-4f, C2 = 9e-4f;
+            const float A1 = 2.f * mu_x * mu_y + C1;
+            const float A2 = 2.f * (exy - mu_x * mu_y) + C2;
+            const float B1 = mu_x * mu_x + mu_y * mu_y + C1;
+            const float B2 = (exx - mu_x * mu_x) + (eyy - mu_y * mu_y) + C2;
+            const float Nn = A1 * A2, Dd = B1 * B2;
+            const float iD = 1.f / Dd;
+            ss += Nn * iD;
+            const float dN = 2.f * mu_y * A2 - 2.f * mu_y * A1;
+            const float dD = 2.f * mu_x * B2 - 2.f * mu_x * B1;
+            const int64_t i = ch * HW + (int64_t)gy * W + gx;
+            const int64_t m = 3 * HW;
+            d3[i] = (dN * Dd - Nn * dD) * iD * iD;
+            d3[m + i] = -Nn * B1 * iD * iD;
+            d3[2 * m + i] = 2.f * A1 * iD;
+            l1 += fabsf(sx[(r + HALO) * TW + c + HALO] - sy[(r + HALO) * TW + c + HALO]);
+        }
     }
     l1 = wave_sum(l1);
     ss = wave_sum(ss);
@@ -143,38 +164,49 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __re
         sd[2][k] = in ? d3[2 * m + i] : 0.f;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < TW * TS; k += LS_THREADS) {
-        const int r = k / TS, c = k % TS;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int k = threadIdx.x; k < TW * (TS / 4); k += LS_THREADS) {
+        const int r = k >> 3, c0 = (k & 7) * 4;
 #pragma unroll
-        for (int t = 0; t < 11; ++t) {
-            const int q = r * TW + c + t;
-            const float w = win.w[t];
-            a0 = fmaf(w, sd[0][q], a0);
-            a1 = fmaf(w, sd[1][q], a1);
-            a2 = fmaf(w, sd[2][q], a2);
+        for (int mm = 0; mm < 3; ++mm) {
+            float v[14];
+#pragma unroll
+            for (int j = 0; j < 14; ++j) v[j] = sd[mm][r * TW + c0 + j];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                float a = 0.f;
+#pragma unroll
+                for (int t = 0; t < 11; ++t) a = fmaf(win.w[t], v[o + t], a);
+                hm[mm][r * TS + c0 + o] = a;
+            }
         }
-        hm[0][k] = a0; hm[1][k] = a1; hm[2][k] = a2;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < TS * TS; k += LS_THREADS) {
-        const int r = k / TS, c = k % TS;
-        const int gy = y0 + r, gx = x0 + c;
-        if (gy >= H || gx >= W) continue;
-        float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    {
+        const int c = threadIdx.x & 31, r0 = (threadIdx.x >> 5) * 4;
+        float gm[3][4];
 #pragma unroll
-        for (int t = 0; t < 11; ++t) {
-            const int q = (r + t) * TS + c;
-            const float w = win.w[t];
-            g0 = fmaf(w, hm[0][q], g0);
-            g1 = fmaf(w, hm[1][q], g1);
-            g2 = fmaf(w, hm[2][q], g2);
+        for (int mm = 0; mm < 3; ++mm) {
+            float hv[14];
+#pragma unroll
+            for (int j = 0; j < 14; ++j) hv[j] = hm[mm][(r0 + j) * TS + c];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                float a = 0.f;
+#pragma unroll
+                for (int t = 0; t < 11; ++t) a = fmaf(win.w[t], hv[o + t], a);
+                gm[mm][o] = a;
+            }
         }
-        const int64_t i = ch * HW + (int64_t)gy * W + gx;
-        const float xv = x[i], yv = y[i];
-        const float d = xv - yv;
-        const float l1g = (float)((d > 0.f) - (d < 0.f)) * invN;
-        dx[i] = l1g + sc * (g0 + 2.f * xv * g1 + yv * g2);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int gy = y0 + r0 + o, gx = x0 + c;
+            if (gy >= H || gx >= W) continue;
+            const int64_t i = ch * HW + (int64_t)gy * W + gx;
+            const float xv = x[i], yv = y[i];
+            const float d = xv - yv;
+            const float l1g = (float)((d > 0.f) - (d < 0.f)) * invN;
+            dx[i] = l1g + sc * (gm[0][o] + 2.f * xv * gm[1][o] + yv * gm[2][o]);
+        }
     }
 }
 
