@@ -170,3 +170,28 @@ def test_full_resolution_loss(rast):
     assert abs(lv.item() - ol) <= 1e-5 * abs(ol)
     ok, info = grad_close(d.cpu().numpy(), od, 1e-3, "dimage 1600x1060")
     assert ok, info
+
+
+def test_sixteen_views_sixty_four_cells(rast):
+    """The largest batch and partition the ABI takes (16 views, L = 6): every
+    pixel of every (ragged) view against the oracle, and one view rendered
+    alone bit-identical to the same view inside the batch."""
+    p = scenes.scene_clusters(20000, seed=61, D=2)
+    sizes = [(48 + 8 * k, 32 + 5 * (k % 4)) for k in range(16)]
+    cams = [scenes.orbit_camera(4.0, 0.4 * k, np.radians(10 + 3 * k), W, H, z_near=0.2, bg=(0.1, 0.02 * k, 0.3))
+            for k, (W, H) in enumerate(sizes)]
+    dp = device_params(p)
+    kd = rast.kd_partition(dp, 6)
+    st = rast.forward(dp, kd, cams, EPS_T)
+    okd = oracle.kd_partition(p["means"], p["log_scales"], 6)
+    worst = 0.0
+    for v, (cam, (img, Tf)) in enumerate(zip(cams, st.images())):
+        order, _ = oracle.cell_order(6, okd["split"], cam["o"])
+        pr = oracle.project(p, cam, okd, 0)
+        r = oracle.render(pr, cam, okd, order, oracle.all_pixels(cam["W"], cam["H"]), EPS_T)
+        worst = max(worst, float(np.abs(img.cpu().numpy().reshape(3, -1).T - r["img"]).max()),
+                    float(np.abs(Tf.cpu().numpy().ravel() - r["T"]).max()))
+    log("16 views, K = 64: max err %.2e" % worst)
+    assert worst <= 2e-4
+    alone = rast.forward(dp, kd, [cams[7]], EPS_T)
+    assert torch.equal(alone.image, st.images()[7][0].reshape(-1))
