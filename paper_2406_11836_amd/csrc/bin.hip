@@ -119,6 +119,14 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int c) {
 // instances in chunks of 256; each thread finds its pair by binary search and
 // decodes (cell, tile) from the index inside the pair (cells ascending, tiles
 // row-major), so writes are coalesced whatever the per-pair counts.
+// a / b for a, b < 2^24: float estimate, then exact integer correction.
+__device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
+    uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
+    while (q * b > a) --q;
+    while ((q + 1u) * b <= a) ++q;
+    return q;
+}
+
 __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict__ pair_src, const uint32_t* __restrict__ n_dev,
                                                      const uint32_t* __restrict__ pair_off, const int16_t* __restrict__ rect,
                                                      const uint64_t* __restrict__ cellmask, int64_t n_gauss,
@@ -126,23 +134,35 @@ __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict_
                                                      uint64_t* __restrict__ vals) {
     __shared__ uint32_t s_off[BN_THREADS + 1];
     __shared__ uint32_t s_src[BN_THREADS];
-    __shared__ uint2 s_rect[BN_THREADS];
     __shared__ uint64_t s_mask[BN_THREADS];
+    // per pair: first tile (global id of the rectangle's top-left tile), tiles per
+    // row of the rectangle and per cell, view's tiles per row
+    __shared__ uint32_t s_tile0[BN_THREADS], s_ntx[BN_THREADS], s_ntiles[BN_THREADS], s_vtx[BN_THREADS];
+    __shared__ uint8_t s_view[BN_THREADS];
     const int64_t npairs = (int64_t)*n_dev;
+    const int L = vt->L;
     for (int64_t r0 = (int64_t)blockIdx.x * BN_THREADS; r0 < npairs; r0 += (int64_t)gridDim.x * BN_THREADS) {
         const int nb = (int)((npairs - r0) < BN_THREADS ? (npairs - r0) : BN_THREADS);
         const int t = threadIdx.x;
         if (t < nb) {
             const uint32_t src = pair_src[r0 + t];
+            const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
+            const int x0 = (int)(int16_t)(rr.x & 0xffffu) >> 4, x1 = (int)(int16_t)(rr.x >> 16) >> 4;
+            const int y0 = (int)(int16_t)(rr.y & 0xffffu) >> 4, y1 = (int)(int16_t)(rr.y >> 16) >> 4;
+            const int v = (int)(src / (uint64_t)n_gauss);  // once per pair
+            const ViewParams& V = vt->v[v];
             s_src[t] = src;
-            s_rect[t] = reinterpret_cast<const uint2*>(rect)[src];
             s_mask[t] = cellmask[src];
             s_off[t] = pair_off[r0 + t];
+            s_ntx[t] = (uint32_t)(x1 - x0 + 1);
+            s_ntiles[t] = (uint32_t)(x1 - x0 + 1) * (uint32_t)(y1 - y0 + 1);
+            s_tile0[t] = V.tile_offset + (uint32_t)y0 * (uint32_t)V.tiles_x + (uint32_t)x0;
+            s_vtx[t] = (uint32_t)V.tiles_x;
+            s_view[t] = (uint8_t)v;
         }
         if (t == 0) s_off[nb] = pair_off[r0 + nb];
         __syncthreads();
         const uint32_t j0 = s_off[0], j1 = s_off[nb];
-        const int L = vt->L;
         for (uint32_t j = j0 + t; j < j1; j += BN_THREADS) {
             // last pair with s_off[p] <= j
             int lo = 0, hi = nb - 1;
@@ -150,19 +170,13 @@ __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict_
                 const int mid = (lo + hi + 1) >> 1;
                 if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
             }
-            const uint32_t src = s_src[lo];
-            const uint2 rr = s_rect[lo];
-            const int x0 = (int)(int16_t)(rr.x & 0xffffu) >> 4, x1 = (int)(int16_t)(rr.x >> 16) >> 4;
-            const int y0 = (int)(int16_t)(rr.y & 0xffffu) >> 4, y1 = (int)(int16_t)(rr.y >> 16) >> 4;
-            const uint32_t ntx = (uint32_t)(x1 - x0 + 1), ntiles = ntx * (uint32_t)(y1 - y0 + 1);
+            const uint32_t ntx = s_ntx[lo], ntiles = s_ntiles[lo];
             const uint32_t q = j - s_off[lo];
-            const uint32_t c = q / ntiles, tt = q - c * ntiles;
-            const uint32_t ty = (uint32_t)y0 + tt / ntx, tx = (uint32_t)x0 + tt % ntx;
-            const int v = (int)(src / (uint64_t)n_gauss);
-            const ViewParams& V = vt->v[v];
+            const uint32_t c = udiv_small(q, ntiles), tt = q - c * ntiles;
+            const uint32_t ty = udiv_small(tt, ntx), tx = tt - ty * ntx;
             const int cell = nth_set_bit(s_mask[lo], (int)c);
-            keys[j] = ((V.tile_offset + ty * (uint32_t)V.tiles_x + tx) << L) | (uint32_t)V.rank_of_cell[cell];
-            vals[j] = ((uint64_t)src << 32) | j;
+            keys[j] = ((s_tile0[lo] + ty * s_vtx[lo] + tx) << L) | (uint32_t)vt->v[s_view[lo]].rank_of_cell[cell];
+            vals[j] = ((uint64_t)s_src[lo] << 32) | j;
         }
         __syncthreads();  // LDS is reused by the next chunk
     }

@@ -180,9 +180,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
 #pragma unroll
             for (int k = 0; k < NB / 64; ++k) {
                 const int tl = k * 64 + lane;
-                uint64_t rel = __ballot(tl < nb && (sM[tl] & qbit) != 0u);
+                const uint32_t mk = tl < nb ? sM[tl] : 0u;
+                uint64_t rel = __ballot((mk & qbit) != 0u);
+                const uint64_t inside = __ballot((mk & 1u) != 0u);  // footprint in one cell: no indicator test
                 while (rel) {
-                    const int tc = k * 64 + (int)__builtin_ctzll(rel);
+                    const int bit = (int)__builtin_ctzll(rel);
+                    const int tc = k * 64 + bit;
                     rel &= rel - 1ull;
                     const float4 ac = sA[tc], bc = sB[tc];
                     const float dx = fxp - ac.x;
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
                     }
                     if (!(d2 <= bc.z)) continue;
                     const float4 cl = sCl[tc];
-                    if (!(__float_as_uint(cl.w) & 1u)) {
+                    if (!((inside >> bit) & 1ull)) {
                         const float x0 = fmaf(bc.w, D0, o0), x1 = fmaf(bc.w, D1, o1), x2 = fmaf(bc.w, D2, o2);
                         const bool in = (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
                                         (x2 < bhi2);
@@ -393,6 +396,7 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
                   quad_hits(a.x, a.y, a.z, a.w, b.x, b.z, (float)(tx * 16 + (w & 1) * 8), (float)(ty * 16 + (w >> 1) * 8));
         }
         uint64_t rel = __ballot(hit);
+        const uint64_t inside = __ballot(hit && (__float_as_uint(sCl[tl].w) & 1u));  // in one cell: no indicator test
         while (rel) {
             const int t = 63 - (int)__builtin_clzll(rel);
             rel &= ~(1ull << t);
@@ -410,7 +414,7 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
             }
             if (__ballot(contrib) == 0ull) continue;
             const float4 cl = sCl[t];
-            if (!(__float_as_uint(cl.w) & 1u)) {  // not interior to the cell: the indicator of Eq. 6
+            if (!((inside >> t) & 1ull)) {  // not interior to the cell: the indicator of Eq. 6
                 const float x0 = fmaf(b.w, D0, o0), x1 = fmaf(b.w, D1, o1), x2 = fmaf(b.w, D2, o2);
                 contrib = contrib && (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
                           (x2 < bhi2);
