@@ -223,14 +223,14 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2100)
     ap.add_argument("--serve-rates", type=str, default="50,200,800")
     ap.add_argument("--batched", action="store_true",
-                    help="16-view batched step (4M Gaussians) against 16 sequential plain K=1 passes")
+                    help="16-view batched step (4M Gaussians): one fused pass against 16 sequential passes, at K=16 and K=1")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the cross-GPU merge would be an "
-              "all-to-all of partial maps by screen strip; see the design notes). Run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library's kernels run on one device and there is no multi-GPU "
+              "path (the cross-GPU merge would be an all-to-all of partial maps by screen strip). "
+              "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -60,7 +60,7 @@ enum {
     RGS_E_ARG = -1,         /* invalid argument; nothing enqueued */
     RGS_E_CAPACITY = -2,    /* caller buffers too small; see *n_required */
     RGS_E_HIP = -3,         /* a HIP call failed; see rgs_last_hip_error() */
-    RGS_E_UNSUPPORTED = -4  /* size outside what this build supports */
+    RGS_E_UNSUPPORTED = -4  /* size outside what the library supports */
 };
 
 typedef void *rgs_stream; /* hipStream_t */
