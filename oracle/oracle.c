@@ -270,7 +270,8 @@ void orc_cell_order(int L, const float *split, const double *o, int32_t *order, 
  *   rect[4]   pixel rectangle x_lo, x_hi, y_lo, y_hi (decision mode)
  *   vis       1 if the Gaussian survives culling (decision mode)
  *   cellmask  KD leaves the footprint can touch (decision mode)
- *   count     |cellmask| * tiles in rect (tile = 16 px)
+ *   count     |cellmask| * tiles (16 px) in the row spans of row_span32
+ *             (decision mode; exact64 mode: every tile of the rectangle)
  * Conic (ca, cb, cc) is the inverse of the screen covariance:
  * d^2 = ca dx^2 + 2 cb dx dy + cc dy^2.                                 */
 
@@ -435,6 +436,61 @@ static int rect64(const P64 *p, const Cam *c, int rect[4]) {
     return 1;
 }
 
+/* Tile columns [*c0, *c1] of tile row ty (16 px rows) that hold a pixel
+ * centre of the rectangle able to satisfy d^2 <= tau; *c0 > *c1 when none.
+ * Decision mode only: fp32, fixed order, no contraction.
+ *
+ * With q(dx, dy) = ca dx^2 + 2 cb dx dy + cc dy^2 and det = ca cc - cb^2,
+ * the chord of {q <= tau} at height dy is dx = (-cb dy +- sqrt(ca tau -
+ * det dy^2)) / ca.  Its right end is concave in dy and largest at the
+ * ellipse's rightmost point dy_r = -cb sqrt(tau / (cc det)); its left end
+ * is convex and smallest at -dy_r.  Over the row's band of pixel-centre
+ * heights [ly, hy] the x-extent is therefore the chord ends taken at
+ * clamp(dy_r) and clamp(-dy_r).  The ellipse is enlarged before that:
+ * det' = det - 2^-18 ca cc (above the rounding of det, which is at most
+ * about 2^-22 ca cc) and tau' = tau (1 + 2^-16 ca cc / det') (above the
+ * rounding of the per-pixel test, whose terms sum to at most 4 tau ca cc /
+ * det inside the ellipse), and the ends are padded by 1/64 px plus 2^-16
+ * of their magnitude.  Strongly elongated footprints (det' <= 2^-10 ca cc)
+ * and non-finite intermediate values keep the whole row of the rectangle. */
+static void row_span32(const float *d, const int r[4], int ty, int *c0, int *c1) {
+    float mx = d[0], my = d[1], ca = d[2], cb = d[3], cc = d[4], tau = d[5];
+    int y0 = ty * 16 > r[2] ? ty * 16 : r[2];
+    int y1 = ty * 16 + 15 < r[3] ? ty * 16 + 15 : r[3];
+    float ly = ((float)y0 + 0.5f) - my, hy = ((float)y1 + 0.5f) - my;
+    float lo = (float)r[0], hi = (float)r[1];
+    float pcc = ca * cc;
+    float detp = (pcc - cb * cb) - 0x1p-18f * pcc;
+    if (detp > 0x1p-10f * pcc) {
+        float taup = tau + tau * (0x1p-16f * (pcc / detp));
+        float dyr = -(cb * sqrtf(taup / (cc * detp)));
+        float dR = fminf(fmaxf(dyr, ly), hy), dL = fminf(fmaxf(-dyr, ly), hy);
+        float wR = fmaxf(ca * taup - detp * (dR * dR), 0.0f);
+        float wL = fmaxf(ca * taup - detp * (dL * dL), 0.0f);
+        float xr = mx + (sqrtf(wR) - cb * dR) / ca;
+        float xl = mx - (sqrtf(wL) + cb * dL) / ca;
+        float pr = 0x1p-6f + 0x1p-16f * (fabsf(mx) + fabsf(xr - mx));
+        float pl = 0x1p-6f + 0x1p-16f * (fabsf(mx) + fabsf(xl - mx));
+        /* NaN compares false in fmaxf/fminf: the rectangle's bound stays */
+        lo = fmaxf(ceilf((xl - pl) - 0.5f), lo);
+        hi = fminf(floorf((xr + pr) - 0.5f), hi);
+    }
+    if (!(lo <= hi)) { *c0 = 1; *c1 = 0; return; }
+    *c0 = (int)lo >> 4;
+    *c1 = (int)hi >> 4;
+}
+
+/* Tiles per cell of a decision-mode pair: the row spans summed. */
+static int64_t tiles32(const float *d, const int r[4]) {
+    int64_t t = 0;
+    for (int ty = r[2] >> 4; ty <= (r[3] >> 4); ty++) {
+        int c0, c1;
+        row_span32(d, r, ty, &c0, &c1);
+        if (c0 <= c1) t += c1 - c0 + 1;
+    }
+    return t;
+}
+
 /* KD leaves whose box meets [lo, hi) per axis (half-open boxes). */
 static void kd_collect(int nd, int depth, int L, const float *split, const float lo[3],
                        const float hi[3], uint64_t *mask) {
@@ -532,7 +588,10 @@ int orc_project(int64_t n, int D, const double *means, const double *log_scales,
         vis[i] = (uint8_t)ok;
         for (int k = 0; k < 4; k++) rect[4 * i + k] = ok ? r[k] : 0;
         cellmask[i] = ok ? mask : 0;
-        count[i] = ok ? (uint32_t)(popcount64(mask) * ((r[1] >> 4) - (r[0] >> 4) + 1) * ((r[3] >> 4) - (r[2] >> 4) + 1)) : 0;
+        /* instances: cells x tiles; in decision mode the tiles are the row
+         * spans of row_span32, in exact64 mode the whole rectangle */
+        int64_t nt = mode == 0 ? tiles32(d, r) : (int64_t)((r[1] >> 4) - (r[0] >> 4) + 1) * ((r[3] >> 4) - (r[2] >> 4) + 1);
+        count[i] = ok ? (uint32_t)(popcount64(mask) * nt) : 0;
     }
     return 0;
 }
@@ -548,11 +607,12 @@ static int cmp_inst(const void *a, const void *b) {
     return (x->gid > y->gid) - (x->gid < y->gid);
 }
 
-/* One instance per (Gaussian, cell in its cell set, 16x16 tile in its
- * rectangle), keyed (tile << rank_bits | rank of the cell in the view's
- * order) and sorted by (key, depth, gid).  Depth is the fp32 camera z of
- * the decision path; ties go to the smaller gid.  Returns the count, or
- * the negated required capacity if cap is too small.                   */
+/* One instance per (Gaussian, cell in its cell set, 16x16 tile of its
+ * rectangle inside the row spans of row_span32), keyed (tile << rank_bits
+ * | rank of the cell in the view's order) and sorted by (key, depth, gid).
+ * Depth is the fp32 camera z of the decision path; ties go to the smaller
+ * gid.  Returns the count, or the negated required capacity if cap is too
+ * small.                                                                */
 int64_t orc_bins(int64_t n, const float *dec32, const int32_t *rect, const uint8_t *vis,
                  const uint64_t *cellmask, const int32_t *rank_of, int L, int tiles_x,
                  int64_t cap, uint32_t *keys, uint32_t *gids) {
@@ -561,9 +621,7 @@ int64_t orc_bins(int64_t n, const float *dec32, const int32_t *rect, const uint8
     int64_t tot = 0;
     for (int64_t i = 0; i < n; i++) {
         if (!vis[i]) continue;
-        int ntx = (rect[4 * i + 1] >> 4) - (rect[4 * i] >> 4) + 1;
-        int nty = (rect[4 * i + 3] >> 4) - (rect[4 * i + 2] >> 4) + 1;
-        tot += (int64_t)popcount64(cellmask[i]) * ntx * nty;
+        tot += (int64_t)popcount64(cellmask[i]) * tiles32(dec32 + 8 * i, rect + 4 * i);
     }
     if (tot > cap) return -tot;
     Inst *v = (Inst *)malloc(sizeof(Inst) * (tot > 0 ? tot : 1));
@@ -574,12 +632,15 @@ int64_t orc_bins(int64_t n, const float *dec32, const int32_t *rect, const uint8
         uint32_t zk; memcpy(&zk, &z, 4);
         for (int k = 0; k < K; k++) {
             if (!((cellmask[i] >> k) & 1)) continue;
-            for (int ty = rect[4 * i + 2] >> 4; ty <= (rect[4 * i + 3] >> 4); ty++)
-                for (int tx = rect[4 * i] >> 4; tx <= (rect[4 * i + 1] >> 4); tx++) {
+            for (int ty = rect[4 * i + 2] >> 4; ty <= (rect[4 * i + 3] >> 4); ty++) {
+                int c0, c1;
+                row_span32(dec32 + 8 * i, rect + 4 * i, ty, &c0, &c1);
+                for (int tx = c0; tx <= c1; tx++) {
                     uint32_t tile = (uint32_t)(ty * tiles_x + tx);
                     v[m].key = (tile << rb) | (uint32_t)rank_of[k];
                     v[m].zkey = zk; v[m].gid = (uint32_t)i; m++;
                 }
+            }
         }
     }
     qsort(v, (size_t)m, sizeof(Inst), cmp_inst);

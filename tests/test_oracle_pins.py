@@ -322,6 +322,101 @@ def test_rect_boundary_sample_included(orc, mode):
         assert pr["rect"][0, 1] >= xs
 
 
+def _random_footprints(rng, n, W, H):
+    """Decision-path footprints (fp32 conic, tau, rectangle as the projection
+    pads it) from random screen covariances, aspect ratios up to 10^4."""
+    lam1 = np.exp(rng.uniform(np.log(0.3), np.log(3000.0), n))
+    lam2 = lam1 / np.exp(rng.uniform(0.0, np.log(1e4), n))
+    lam2 = np.maximum(lam2, 0.3)
+    th = rng.uniform(0, np.pi, n)
+    c, s = np.cos(th), np.sin(th)
+    s00 = (c * c * lam1 + s * s * lam2).astype(np.float32)
+    s01 = (c * s * (lam1 - lam2)).astype(np.float32)
+    s11 = (s * s * lam1 + c * c * lam2).astype(np.float32)
+    det = (s00 * s11 - s01 * s01).astype(np.float32)
+    ca, cb, cc = s11 / det, -s01 / det, s00 / det
+    tau = rng.uniform(0.05, 9.0, n).astype(np.float32)
+    mx = rng.uniform(-30, W + 30, n).astype(np.float32)
+    my = rng.uniform(-30, H + 30, n).astype(np.float32)
+    ex = np.sqrt(tau * s00) * np.float32(1.00001) + np.float32(1e-3)
+    ey = np.sqrt(tau * s11) * np.float32(1.00001) + np.float32(1e-3)
+    xl = np.maximum(np.ceil(mx - ex - 0.5), 0); xh = np.minimum(np.floor(mx + ex - 0.5), W - 1)
+    yl = np.maximum(np.ceil(my - ey - 0.5), 0); yh = np.minimum(np.floor(my + ey - 0.5), H - 1)
+    ok = (xl <= xh) & (yl <= yh) & (det > 0)
+    dec = np.zeros((n, 8), np.float32)
+    dec[:, 0], dec[:, 1], dec[:, 2], dec[:, 3], dec[:, 4], dec[:, 5] = mx, my, ca, cb, cc, tau
+    dec[:, 6] = rng.uniform(1, 10, n)
+    rect = np.stack([xl, xh, yl, yh], 1).astype(np.int32)
+    return dec[ok], rect[ok]
+
+
+def test_tile_spans_conservative_and_tight(orc):
+    """Row spans of the instance lists: every pixel centre of the rectangle
+    within the ellipse (enlarged beyond what fp32 rounding of the per-pixel
+    test can reach) lies in a listed tile, and every listed tile comes within
+    0.1 px of the ellipse (footprints with aspect ratio below ~10^3)."""
+    rng = np.random.default_rng(7)
+    W = H = 256
+    dec, rect = _random_footprints(rng, 3000, W, H)
+    n = len(dec)
+    pr = dict(n=n, dec32=dec, rect=rect, vis=np.ones(n, np.uint8), cellmask=np.ones(n, np.uint64),
+              count=np.full(n, 10**6, np.uint32))
+    keys, gids = orc.bins(pr, np.zeros(1, np.int32), 0, W // 16)
+    kept = {}
+    for k, g in zip(keys.tolist(), gids.tolist()):
+        kept.setdefault(g, set()).add(k)
+    n_pix = n_tiles = n_rect_tiles = n_elong = 0
+    for i in range(n):
+        mx, my, ca, cb, cc, tau = [float(v) for v in dec[i, :6]]
+        xl, xh, yl, yh = [int(v) for v in rect[i]]
+        pcc = ca * cc
+        det = pcc - cb * cb
+        X, Y = np.meshgrid(np.arange(xl, xh + 1) + 0.5, np.arange(yl, yh + 1) + 0.5)
+        dx, dy = X - mx, Y - my
+        q = ca * dx * dx + 2 * cb * dx * dy + cc * dy * dy
+        inside = q <= tau * (1 + 2.0 ** -19 * pcc / det)
+        tiles = set(((Y[inside].astype(int) >> 4) * (W // 16) + (X[inside].astype(int) >> 4)).tolist())
+        got = kept.get(i, set())
+        assert tiles <= got, i
+        n_pix += int(inside.sum())
+        n_rect_tiles += ((xh >> 4) - (xl >> 4) + 1) * ((yh >> 4) - (yl >> 4) + 1)
+        n_tiles += len(got)
+        if pcc / det > 2.0 ** 9:
+            n_elong += 1
+            continue
+        for t in got:
+            ty, tx = divmod(t, W // 16)
+            assert (xl >> 4) <= tx <= (xh >> 4) and (yl >> 4) <= ty <= (yh >> 4)
+            # minimum of q over the tile's pixel-centre box inside the rectangle, grown by 0.1 px
+            bx0 = max(tx * 16, xl) + 0.4 - mx; bx1 = min(tx * 16 + 15, xh) + 0.6 - mx
+            by0 = max(ty * 16, yl) + 0.4 - my; by1 = min(ty * 16 + 15, yh) + 0.6 - my
+            if bx0 <= 0 <= bx1 and by0 <= 0 <= by1:
+                continue
+            qm = math.inf
+            for ex in (bx0, bx1):
+                ey = min(max(-cb * ex / cc, by0), by1)
+                qm = min(qm, ca * ex * ex + 2 * cb * ex * ey + cc * ey * ey)
+            for ey in (by0, by1):
+                ex = min(max(-cb * ey / ca, bx0), bx1)
+                qm = min(qm, ca * ex * ex + 2 * cb * ex * ey + cc * ey * ey)
+            assert qm <= tau * (1 + 1e-3), (i, t)
+    assert n_pix > 10**5 and n_elong > 10
+    assert n_tiles < 0.9 * n_rect_tiles  # the spans drop tiles the rectangle holds
+
+
+def test_instance_count_matches_lists(orc):
+    """count (cells x span tiles) sums to the length of the instance lists."""
+    p = _tiny_scene(300, seed=3, mu_s=-2.0)
+    kd = orc.kd_partition(p["means"], p["log_scales"], 2)
+    cam = scenes.orbit_camera(2.0, 0.7, 0.2, 96, 80)
+    order, rank_of = orc.cell_order(2, kd["split"], cam["o"])
+    pr = orc.project(p, cam, kd, 0)
+    keys, gids = orc.bins(pr, rank_of, 2, (96 + 15) // 16)
+    assert len(keys) == int(pr["count"].astype(np.int64).sum()) > 1000
+    per = np.bincount(gids.astype(np.int64), minlength=pr["n"])
+    assert np.array_equal(per, pr["count"].astype(np.int64))
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_cell_sets_conservative(orc, mode):
     """Keeping each Gaussian only in its emitted cells changes no partial."""
