@@ -121,11 +121,17 @@ typedef struct {
    count is written: rec, rect and cellmask hold whatever the buffers held. */
 typedef struct {
     float *rec;         /* [V*N][16]: mx, my, ca, cb | cc, alpha, tau, z | r, g, b, flags |
-                           rect as two uint32 (x_lo | x_hi << 16, y_lo | y_hi << 16), 0, 0;
+                           rect as two uint32 (x_lo | x_hi << 16, y_lo | y_hi << 16), then
+                           the row-span descriptor as two uint32 (low word first): for a
+                           rectangle of <= 8 tile rows and <= 15 tile columns, byte k =
+                           (tiles of row k) << 4 | (its first column - the rectangle's
+                           first tile column), else all ones;
                            64-byte aligned: the render kernels fetch one line per instance */
     int16_t *rect;      /* [V*N][4]: sample-pixel rectangle x_lo, x_hi, y_lo, y_hi */
     uint64_t *cellmask; /* [V*N]: cells the footprint can reach (bit k = cell k) */
-    uint32_t *count;    /* [V*N]: instances = |cellmask| * tiles in rect; 0 = culled */
+    uint32_t *count;    /* [V*N]: instances = |cellmask| * tiles of the rectangle that the
+                           footprint's ellipse can reach (per tile row, the span of columns
+                           holding a pixel centre of the padded ellipse); 0 = culled */
 } rgs_projected;
 
 /* Tile/cell instance lists and slots (one slot per non-empty (tile, cell)). */

@@ -4,7 +4,8 @@
 //    and sorted stably by the fp32 bits of their camera depth (positive
 //    floats order like their bits), then by view: (view, z, gid) order.
 // 2. Each pair emits, contiguously and in that order, one instance per
-//    (cell of its cell set, tile of its rectangle), keyed
+//    (cell of its cell set, tile of its rectangle that the footprint can
+//    reach: the row spans of the projection), keyed
 //    (global tile << L) | rank of the cell in the view's merge order.
 // 3. A stable LSD radix sort on the key alone keeps every (tile, cell)
 //    group in depth order, so the sort never looks at the depth bits.
@@ -114,11 +115,6 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int c) {
     return base + __ffs(w) - 1;
 }
 
-// Instance emission, balanced over instances: a block takes 256 consecutive
-// ordered pairs, prefix-sums their counts in LDS and walks the block's
-// instances in chunks of 256; each thread finds its pair by binary search and
-// decodes (cell, tile) from the index inside the pair (cells ascending, tiles
-// row-major), so writes are coalesced whatever the per-pair counts.
 // a / b for a, b < 2^24: float estimate, then exact integer correction.
 __device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
     uint32_t q = (uint32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
@@ -127,17 +123,25 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
     return q;
 }
 
+// Instance emission, balanced over instances: a block takes 256 consecutive
+// ordered pairs, stages their offsets in LDS and walks the block's instances
+// in chunks of 256; each thread finds its pair by binary search and decodes
+// (cell, tile) from the index inside the pair (cells ascending, then the row
+// spans' tiles top to bottom, left to right), so writes are coalesced
+// whatever the per-pair counts.  Small rectangles carry their spans in the
+// record's descriptor; larger ones recompute them with the projection's code.
 __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict__ pair_src, const uint32_t* __restrict__ n_dev,
-                                                     const uint32_t* __restrict__ pair_off, const int16_t* __restrict__ rect,
+                                                     const uint32_t* __restrict__ pair_off, const float* __restrict__ rec,
                                                      const uint64_t* __restrict__ cellmask, int64_t n_gauss,
                                                      const ViewTable* __restrict__ vt, uint32_t* __restrict__ keys,
                                                      uint64_t* __restrict__ vals) {
     __shared__ uint32_t s_off[BN_THREADS + 1];
     __shared__ uint32_t s_src[BN_THREADS];
     __shared__ uint64_t s_mask[BN_THREADS];
-    // per pair: first tile (global id of the rectangle's top-left tile), tiles per
-    // row of the rectangle and per cell, view's tiles per row
-    __shared__ uint32_t s_tile0[BN_THREADS], s_ntx[BN_THREADS], s_ntiles[BN_THREADS], s_vtx[BN_THREADS];
+    __shared__ uint64_t s_desc[BN_THREADS];  // row-span descriptor, or RGS_NO_SPANS
+    __shared__ uint2 s_rect[BN_THREADS];     // packed rectangle of the record
+    // per pair: tiles per cell, the view's first global tile and tiles per row
+    __shared__ uint32_t s_nt[BN_THREADS], s_vto[BN_THREADS], s_vtx[BN_THREADS];
     __shared__ uint8_t s_view[BN_THREADS];
     const int64_t npairs = (int64_t)*n_dev;
     const int L = vt->L;
@@ -146,36 +150,76 @@ __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict_
         const int t = threadIdx.x;
         if (t < nb) {
             const uint32_t src = pair_src[r0 + t];
-            const uint2 rr = reinterpret_cast<const uint2*>(rect)[src];
-            const int x0 = (int)(int16_t)(rr.x & 0xffffu) >> 4, x1 = (int)(int16_t)(rr.x >> 16) >> 4;
-            const int y0 = (int)(int16_t)(rr.y & 0xffffu) >> 4, y1 = (int)(int16_t)(rr.y >> 16) >> 4;
+            const float4 r4 = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS)[3];
+            const uint64_t m = cellmask[src];
             const int v = (int)(src / (uint64_t)n_gauss);  // once per pair
             const ViewParams& V = vt->v[v];
             s_src[t] = src;
-            s_mask[t] = cellmask[src];
+            s_mask[t] = m;
+            s_rect[t] = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
+            s_desc[t] = (uint64_t)__float_as_uint(r4.z) | ((uint64_t)__float_as_uint(r4.w) << 32);
             s_off[t] = pair_off[r0 + t];
-            s_ntx[t] = (uint32_t)(x1 - x0 + 1);
-            s_ntiles[t] = (uint32_t)(x1 - x0 + 1) * (uint32_t)(y1 - y0 + 1);
-            s_tile0[t] = V.tile_offset + (uint32_t)y0 * (uint32_t)V.tiles_x + (uint32_t)x0;
+            s_vto[t] = V.tile_offset;
             s_vtx[t] = (uint32_t)V.tiles_x;
             s_view[t] = (uint8_t)v;
         }
         if (t == 0) s_off[nb] = pair_off[r0 + nb];
+        if (t > nb) s_off[t] = 0xffffffffu;  // past the chunk: above every instance index
+        __syncthreads();
+        // tiles per cell = the pair's instances / its cells (no second gather of the counts)
+        if (t < nb) s_nt[t] = (s_off[t + 1] - s_off[t]) / (uint32_t)__popcll(s_mask[t]);
         __syncthreads();
         const uint32_t j0 = s_off[0], j1 = s_off[nb];
         for (uint32_t j = j0 + t; j < j1; j += BN_THREADS) {
-            // last pair with s_off[p] <= j
-            int lo = 0, hi = nb - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
-            }
-            const uint32_t ntx = s_ntx[lo], ntiles = s_ntiles[lo];
+            // last pair with s_off[p] <= j (offsets increase; entries past nb are ~0)
+            int lo = 0;
+#pragma unroll
+            for (int step = BN_THREADS / 2; step > 0; step >>= 1)
+                if (s_off[lo + step] <= j) lo += step;
+            const uint32_t nt = s_nt[lo];
             const uint32_t q = j - s_off[lo];
-            const uint32_t c = udiv_small(q, ntiles), tt = q - c * ntiles;
-            const uint32_t ty = udiv_small(tt, ntx), tx = tt - ty * ntx;
+            const uint32_t c = udiv_small(q, nt);
+            const uint32_t tt = q - c * nt;  // index among the pair's tiles, rows top to bottom
+            const uint2 rr = s_rect[lo];
+            const int x_lo = (int)(int16_t)(rr.x & 0xffffu), x_hi = (int)(int16_t)(rr.x >> 16);
+            const int y_lo = (int)(int16_t)(rr.y & 0xffffu), y_hi = (int)(int16_t)(rr.y >> 16);
+            const int tx0 = x_lo >> 4, ty0 = y_lo >> 4;
+            int tx = tx0, ty = ty0;
+            const uint64_t desc = s_desc[lo];
+            if (desc != RGS_NO_SPANS) {
+                // row of tile tt by byte-wise prefix sums of the 8 row lengths
+                // (each < 16, total < 128): byte k of `pre` = tiles in rows 0..k,
+                // and the high bit of byte k of `ge` is set iff pre_k > tt
+                constexpr uint64_t ONES = 0x0101010101010101ull, HIGH = 0x8080808080808080ull;
+                const uint64_t lens = (desc >> 4) & 0x0f0f0f0f0f0f0f0full;
+                const uint64_t pre = lens * ONES;
+                const uint64_t ge = ((pre | HIGH) - (uint64_t)(tt + 1u) * ONES) & HIGH;
+                const int k = ge ? (__builtin_ctzll(ge) >> 3) : 7;
+                const uint32_t before = ((uint32_t)(pre >> (8 * k)) & 0xffu) - ((uint32_t)(lens >> (8 * k)) & 0xffu);
+                tx = tx0 + (int)((uint32_t)(desc >> (8 * k)) & 15u) + (int)(tt - before);
+                ty = ty0 + k;
+            } else {
+                // large rectangle: the spans are recomputed from the record
+                const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)s_src[lo] * RGS_REC_FLOATS);
+                const float4 a = rp[0], b = rp[1];
+                SpanPre sp;
+                span_pre(a.x, a.y, a.z, a.w, b.x, b.z, sp);
+                uint32_t rem = tt;
+#pragma unroll 1
+                for (int y = ty0; y <= (y_hi >> 4); ++y) {
+                    const int2 cs = row_span(sp, x_lo, x_hi, y_lo, y_hi, y);
+                    const uint32_t len = cs.x <= cs.y ? (uint32_t)(cs.y - cs.x + 1) : 0u;
+                    if (rem < len) {
+                        tx = cs.x + (int)rem;
+                        ty = y;
+                        break;
+                    }
+                    rem -= len;
+                }
+            }
             const int cell = nth_set_bit(s_mask[lo], (int)c);
-            keys[j] = ((s_tile0[lo] + ty * s_vtx[lo] + tx) << L) | (uint32_t)vt->v[s_view[lo]].rank_of_cell[cell];
+            keys[j] = ((s_vto[lo] + (uint32_t)ty * s_vtx[lo] + (uint32_t)tx) << L) |
+                      (uint32_t)vt->v[s_view[lo]].rank_of_cell[cell];
             vals[j] = ((uint64_t)s_src[lo] << 32) | j;
         }
         __syncthreads();  // LDS is reused by the next chunk
@@ -400,7 +444,7 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
 
     // 3. emit and sort instances by (tile, rank)
     if (m > 0)
-        hipLaunchKernelGGL(k_emit, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], bins->pair_off, proj->rect,
+        hipLaunchKernelGGL(k_emit, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], bins->pair_off, proj->rec,
                            proj->cellmask, n, vt_dev, bins->keys, bins->vals);
     RGS_LAUNCH_CHECK();
     const int key_bits = L + bits_for((uint64_t)total_tiles);

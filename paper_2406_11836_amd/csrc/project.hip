@@ -255,8 +255,6 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
     const float logit = g.opacity[i];
     Pre32 pre;
     pre32(ls0, ls1, ls2, qw, qx, qy, qz, logit, pre);
-    float f[3 * nc];
-    bool have_sh = false;  // SH coefficients are read once, for the first view that needs them
     const int L = vt->L;
     for (int v = 0; v < vt->n_views; ++v) {
         if (!((view_ok >> v) & 1u)) continue;
@@ -272,15 +270,22 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
             out.count[src] = 0u;
             continue;
         }
-        if (!have_sh) {
-#pragma unroll
-            for (int k = 0; k < 3 * nc; ++k) f[k] = g.sh[(int64_t)k * n + i];
-            have_sh = true;
-        }
         const uint64_t mask = cellset32(p, r, V, L, split);
-        const uint32_t ntx = (uint32_t)((r[1] >> 4) - (r[0] >> 4) + 1);
-        const uint32_t nty = (uint32_t)((r[3] >> 4) - (r[2] >> 4) + 1);
-        out.count[src] = (uint32_t)__popcll(mask) * ntx * nty;
+        // tiles per cell: the row spans of the footprint inside the rectangle
+        SpanPre sp;
+        span_pre(p.mx, p.my, p.ca, p.cb, p.cc, p.tau, sp);
+        const int tx0 = r[0] >> 4, ty0 = r[2] >> 4, ty1 = r[3] >> 4;
+        const bool small = ty1 - ty0 < 8 && (r[1] >> 4) - tx0 < 15;
+        uint64_t desc = small ? 0ull : RGS_NO_SPANS;
+        uint32_t nt = 0;
+#pragma unroll 1
+        for (int ty = ty0; ty <= ty1; ++ty) {
+            const int2 cs = row_span(sp, r[0], r[1], r[2], r[3], ty);
+            const uint32_t len = cs.x <= cs.y ? (uint32_t)(cs.y - cs.x + 1) : 0u;
+            nt += len;
+            if (small && len) desc |= (uint64_t)((len << 4) | (uint32_t)(cs.x - tx0)) << (8 * (ty - ty0));
+        }
+        out.count[src] = (uint32_t)__popcll(mask) * nt;
         out.cellmask[src] = mask;
         const uint32_t rx = ((uint32_t)(uint16_t)r[0]) | ((uint32_t)(uint16_t)r[1] << 16);
         const uint32_t ry = ((uint32_t)(uint16_t)r[2]) | ((uint32_t)(uint16_t)r[3] << 16);
@@ -291,19 +296,29 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
         dx *= inv; dy *= inv; dz *= inv;
         float Y[16];
         sh_eval(D, dx, dy, dz, Y);
-        float col[3];
+        // SH coefficients are streamed from memory (only views that keep the
+        // Gaussian read them; a later view hits the cache), not held in
+        // registers across the view loop, so that more waves fit per SIMD
+        float col[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float acc = 0.5f;
+        for (int l = 0; l <= D; ++l) {
+            // one band at a time: the empty asm keeps the compiler from
+            // hoisting every band's loads (and their registers) up front
+            asm volatile("" ::: "memory");
 #pragma unroll
-            for (int j = 0; j < nc; ++j) acc = fmaf(f[3 * j + ch], Y[j], acc);
-            col[ch] = fmaxf(acc, 0.0f);
+            for (int j = l * l; j < (l + 1) * (l + 1); ++j)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(g.sh[(int64_t)(3 * j + ch) * n + i], Y[j], col[ch]);
         }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) col[ch] = fmaxf(col[ch], 0.0f);
         const uint32_t flags = (__popcll(mask) == 1) ? 1u : 0u;
         rec[0] = make_float4(p.mx, p.my, p.ca, p.cb);
         rec[1] = make_float4(p.cc, p.alpha, p.tau, p.z);
         rec[2] = make_float4(col[0], col[1], col[2], __uint_as_float(flags));
-        rec[3] = make_float4(__uint_as_float(rx), __uint_as_float(ry), 0.f, 0.f);  // the rectangle, for the render kernels
+        // the rectangle (render kernels) and the row-span descriptor (emission)
+        rec[3] = make_float4(__uint_as_float(rx), __uint_as_float(ry), __uint_as_float((uint32_t)desc),
+                             __uint_as_float((uint32_t)(desc >> 32)));
     }
 }
 
