@@ -115,7 +115,7 @@ def project(params, cam, kd, mode: int = 0):
     D = int(params["sh_degree"])
     n = means.shape[1]
     nn = max(n, 1)
-    dec = np.zeros((nn, 8), np.float32)
+    dec = np.zeros((nn, 10), np.float32)
     val = np.zeros((nn, 12), np.float64)
     rect = np.zeros((nn, 4), np.int32)
     vis = np.zeros(nn, np.uint8)

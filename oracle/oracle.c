@@ -21,9 +21,10 @@
  *
  * Two modes for the discrete decisions (which Gaussian touches which pixel,
  * in which cell, the screen rectangle, the cell set):
- *   mode 0 (mirror32): decisions are taken in fp32 with a fixed operation
- *            order, the precision the GPU kernels use, so that integer
- *            outputs can be compared bit for bit;
+ *   mode 0 (mirror32): decisions follow the GPU kernels' fixed operation
+ *            sequence (an fp64 covariance chain rounded once to fp32, then
+ *            fp32 tests), so that integer outputs can be compared bit for
+ *            bit;
  *   mode 1 (exact64):  decisions are taken in fp64.
  * Values (sigma, colour, blending, merge, gradients) are always fp64.
  * Compile with -ffp-contract=off and without -ffast-math.
@@ -265,7 +266,8 @@ void orc_cell_order(int L, const float *split, const double *o, int32_t *order, 
 /* projection (Sec. 3.1)                                               */
 /* ------------------------------------------------------------------ */
 /* Output per Gaussian:
- *   dec32[8]  fp32 decision quantities: mx, my, ca, cb, cc, tau, z, alpha
+ *   dec32[10] fp32 decision quantities: mx, my, ca, cb, cc, tau, z, alpha, k, e
+ *             (d^2 = ca (dx + k dy)^2 + e dy^2; cb, cc for reference)
  *   val[12]   fp64 values: mx, my, ca, cb, cc, alpha, z, r, g, b, tau, det
  *   rect[4]   pixel rectangle x_lo, x_hi, y_lo, y_hi (decision mode)
  *   vis       1 if the Gaussian survives culling (decision mode)
@@ -342,67 +344,82 @@ static void proj64(int64_t n, int D, const double *means, const double *ls, cons
 /* fp32 decision path with a fixed operation order (mirror32).  Every
  * step below is one IEEE binary32 operation; transcendentals are taken in
  * fp64 and rounded once to fp32.                                       */
-typedef struct { float mx, my, ca, cb, cc, tau, z, alpha; int vis; float s00, s11; } P32;
+typedef struct { float mx, my, ca, cb, cc, tau, z, alpha, k, e, rk; int vis; float s00, s11; } P32;
 
+/* Decision-mode projection.  Inputs are the fp32 parameters and camera;
+ * the scale and opacity activations are fp64 transcendentals rounded once
+ * to fp32.  Everything from the quaternion to the inverse of the screen
+ * covariance runs in fp64 (+, -, *, /, sqrt only: IEEE correctly rounded,
+ * so any machine gets the same bits) and is rounded once to fp32: the
+ * inverse of a nearly singular covariance (a needle-like footprint) keeps
+ * its accuracy, which an fp32 product chain does not.  The quadratic form
+ * is kept in a factored, cancellation-free shape,
+ *     d^2 = ca u^2 + e dy^2,  u = dx + k dy,
+ * with ca = s11/det, k = -s01/s11 and e = 1/s11 (ca cc - cb^2 = ca e);
+ * cb and cc are also returned for reference.  rk = sqrt(1 + k^2 ca/e) =
+ * sqrt(s00 s11 / det) measures the elongation.                          */
 static void proj32(int64_t n, const double *means, const double *ls, const double *q,
                    const double *op, const Cam *c, int64_t i, P32 *p) {
     memset(p, 0, sizeof(*p));
-    float mu0 = (float)means[i], mu1 = (float)means[n + i], mu2 = (float)means[2 * n + i];
+    double mu0 = (float)means[i], mu1 = (float)means[n + i], mu2 = (float)means[2 * n + i];
     float s0 = (float)exp((double)(float)ls[i]);
     float s1 = (float)exp((double)(float)ls[n + i]);
     float s2 = (float)exp((double)(float)ls[2 * n + i]);
     float alpha = (float)(1.0 / (1.0 + exp(-(double)(float)op[i])));
-    float qw = (float)q[i], qx = (float)q[n + i], qy = (float)q[2 * n + i], qz = (float)q[3 * n + i];
-    float qq = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
-    if (!(qq > 0.0f)) return;
-    float qn = sqrtf(qq);
-    float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
-    float r[3][3];
-    r[0][0] = 1.0f - 2.0f * (y * y + z * z);
-    r[0][1] = 2.0f * (x * y - w * z);
-    r[0][2] = 2.0f * (x * z + w * y);
-    r[1][0] = 2.0f * (x * y + w * z);
-    r[1][1] = 1.0f - 2.0f * (x * x + z * z);
-    r[1][2] = 2.0f * (y * z - w * x);
-    r[2][0] = 2.0f * (x * z - w * y);
-    r[2][1] = 2.0f * (y * z + w * x);
-    r[2][2] = 1.0f - 2.0f * (x * x + y * y);
-    float sc[3] = {s0, s1, s2};
-    float M[3][3], S[3][3];
+    double qw = (float)q[i], qx = (float)q[n + i], qy = (float)q[2 * n + i], qz = (float)q[3 * n + i];
+    double qq = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    if (!(qq > 0.0)) return;
+    double qn = sqrt(qq);
+    double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+    double r[3][3];
+    r[0][0] = 1.0 - 2.0 * (y * y + z * z);
+    r[0][1] = 2.0 * (x * y - w * z);
+    r[0][2] = 2.0 * (x * z + w * y);
+    r[1][0] = 2.0 * (x * y + w * z);
+    r[1][1] = 1.0 - 2.0 * (x * x + z * z);
+    r[1][2] = 2.0 * (y * z - w * x);
+    r[2][0] = 2.0 * (x * z - w * y);
+    r[2][1] = 2.0 * (y * z + w * x);
+    r[2][2] = 1.0 - 2.0 * (x * x + y * y);
+    double sc[3] = {s0, s1, s2};
+    double M[3][3], S[3][3];
     for (int a = 0; a < 3; a++) for (int b = 0; b < 3; b++) M[a][b] = r[a][b] * sc[b];
     for (int a = 0; a < 3; a++) for (int b = 0; b < 3; b++)
         S[a][b] = (M[a][0] * M[b][0] + M[a][1] * M[b][1]) + M[a][2] * M[b][2];
-    float R[9];
+    double R[9];
     for (int k = 0; k < 9; k++) R[k] = (float)c->R[k];
-    float tc[3];
+    double tc[3];
     for (int a = 0; a < 3; a++)
-        tc[a] = ((R[3 * a] * mu0 + R[3 * a + 1] * mu1) + R[3 * a + 2] * mu2) + (float)c->t[a];
-    float zc = tc[2];
-    if (!(zc > (float)c->znear)) return;
-    float fx = (float)c->fx, fy = (float)c->fy, cx = (float)c->cx, cy = (float)c->cy;
+        tc[a] = ((R[3 * a] * mu0 + R[3 * a + 1] * mu1) + R[3 * a + 2] * mu2) + (double)(float)c->t[a];
+    double zc = tc[2];
+    if (!(zc > (double)(float)c->znear)) return;
+    float fx32 = (float)c->fx, fy32 = (float)c->fy, cx32 = (float)c->cx, cy32 = (float)c->cy;
     float Wf = (float)c->W, Hf = (float)c->H;
-    float gx = 1.3f * (fmaxf(cx, Wf - cx) / fx);
-    float gy = 1.3f * (fmaxf(cy, Hf - cy) / fy);
-    float xz = tc[0] / zc, yz = tc[1] / zc;
-    float xg = fminf(fmaxf(xz, -gx), gx) * zc;
-    float yg = fminf(fmaxf(yz, -gy), gy) * zc;
-    float zz = zc * zc;
-    float J00 = fx / zc, J02 = -(fx * xg) / zz, J11 = fy / zc, J12 = -(fy * yg) / zz;
-    float T[2][3], U[2][3];
+    double gx = 1.3f * (fmaxf(cx32, Wf - cx32) / fx32);
+    double gy = 1.3f * (fmaxf(cy32, Hf - cy32) / fy32);
+    double fx = fx32, fy = fy32, cx = cx32, cy = cy32;
+    double xz = tc[0] / zc, yz = tc[1] / zc;
+    double xg = fmin(fmax(xz, -gx), gx) * zc;
+    double yg = fmin(fmax(yz, -gy), gy) * zc;
+    double zz = zc * zc;
+    double J00 = fx / zc, J02 = -(fx * xg) / zz, J11 = fy / zc, J12 = -(fy * yg) / zz;
+    double T[2][3], U[2][3];
     for (int b = 0; b < 3; b++) {
         T[0][b] = J00 * R[b] + J02 * R[6 + b];
         T[1][b] = J11 * R[3 + b] + J12 * R[6 + b];
     }
     for (int a = 0; a < 2; a++) for (int b = 0; b < 3; b++)
         U[a][b] = (T[a][0] * S[0][b] + T[a][1] * S[1][b]) + T[a][2] * S[2][b];
-    float s00 = ((U[0][0] * T[0][0] + U[0][1] * T[0][1]) + U[0][2] * T[0][2]) + 0.3f;
-    float s01 = (U[0][0] * T[1][0] + U[0][1] * T[1][1]) + U[0][2] * T[1][2];
-    float s11 = ((U[1][0] * T[1][0] + U[1][1] * T[1][1]) + U[1][2] * T[1][2]) + 0.3f;
-    float det = s00 * s11 - s01 * s01;
-    if (!(det > 0.0f)) return;
-    p->ca = s11 / det; p->cb = -s01 / det; p->cc = s00 / det;
-    p->mx = fx * xz + cx; p->my = fy * yz + cy;
-    p->z = zc; p->alpha = alpha; p->s00 = s00; p->s11 = s11;
+    double s00 = ((U[0][0] * T[0][0] + U[0][1] * T[0][1]) + U[0][2] * T[0][2]) + 0.3;
+    double s01 = (U[0][0] * T[1][0] + U[0][1] * T[1][1]) + U[0][2] * T[1][2];
+    double s11 = ((U[1][0] * T[1][0] + U[1][1] * T[1][1]) + U[1][2] * T[1][2]) + 0.3;
+    double det = s00 * s11 - s01 * s01;
+    if (!(det > 0.0)) return;
+    p->ca = (float)(s11 / det); p->cb = (float)(-s01 / det); p->cc = (float)(s00 / det);
+    p->k = (float)(-s01 / s11); p->e = (float)(1.0 / s11);
+    p->rk = sqrtf(1.0f + (p->k * p->k) * (p->ca / p->e));
+    p->mx = (float)(fx * xz + cx); p->my = (float)(fy * yz + cy);
+    p->z = (float)zc; p->alpha = alpha; p->s00 = (float)s00; p->s11 = (float)s11;
     float tau = fminf(9.0f, (float)(2.0 * log(255.0 * (double)alpha)));
     p->tau = tau;
     if (!(tau >= 0.0f)) return;
@@ -412,11 +429,16 @@ static void proj32(int64_t n, const double *means, const double *ls, const doubl
 
 /* Screen rectangle of sample pixels that can satisfy d^2 <= tau: the
  * ellipse's x-extent is sqrt(tau * s00) (min over dy of d^2 is
- * dx^2 / s00), padded by a relative 1e-5 and 1e-3 px against rounding.
+ * dx^2 / s00).  Padding: 1e-3 px, a relative 1e-5, and a relative
+ * 2^-20 rk.  The per-pixel test in fp32 evaluates u = dx + k dy with an
+ * absolute error up to about 2^-24 |dx|, which moves ca u^2 near the edge
+ * by up to about 2^-23 tau rk (ca s00 = rk^2); the ellipse of the rounded
+ * (ca, k, e) is within a few 2^-24 of the exact one.
  * Returns 0 when the rectangle is empty.                                */
 static int rect32(const P32 *p, const Cam *c, int rect[4]) {
-    float ex = sqrtf(p->tau * p->s00) * 1.00001f + 1e-3f;
-    float ey = sqrtf(p->tau * p->s11) * 1.00001f + 1e-3f;
+    float pad = 1.00001f + 0x1p-20f * p->rk;
+    float ex = sqrtf(p->tau * p->s00) * pad + 1e-3f;
+    float ey = sqrtf(p->tau * p->s11) * pad + 1e-3f;
     float xlo = fmaxf(ceilf((p->mx - ex) - 0.5f), 0.0f);
     float xhi = fminf(floorf((p->mx + ex) - 0.5f), (float)(c->W - 1));
     float ylo = fmaxf(ceilf((p->my - ey) - 0.5f), 0.0f);
@@ -438,43 +460,37 @@ static int rect64(const P64 *p, const Cam *c, int rect[4]) {
 
 /* Tile columns [*c0, *c1] of tile row ty (16 px rows) that hold a pixel
  * centre of the rectangle able to satisfy d^2 <= tau; *c0 > *c1 when none.
- * Decision mode only: fp32, fixed order, no contraction.
+ * Decision mode only: fp32, fixed order, no contraction; d is a dec32 row.
  *
- * With q(dx, dy) = ca dx^2 + 2 cb dx dy + cc dy^2 and det = ca cc - cb^2,
- * the chord of {q <= tau} at height dy is dx = (-cb dy +- sqrt(ca tau -
- * det dy^2)) / ca.  Its right end is concave in dy and largest at the
- * ellipse's rightmost point dy_r = -cb sqrt(tau / (cc det)); its left end
- * is convex and smallest at -dy_r.  Over the row's band of pixel-centre
- * heights [ly, hy] the x-extent is therefore the chord ends taken at
- * clamp(dy_r) and clamp(-dy_r).  The ellipse is enlarged before that:
- * det' = det - 2^-18 ca cc (above the rounding of det, which is at most
- * about 2^-22 ca cc) and tau' = tau (1 + 2^-16 ca cc / det') (above the
- * rounding of the per-pixel test, whose terms sum to at most 4 tau ca cc /
- * det inside the ellipse), and the ends are padded by 1/64 px plus 2^-16
- * of their magnitude.  Strongly elongated footprints (det' <= 2^-10 ca cc)
- * and non-finite intermediate values keep the whole row of the rectangle. */
+ * In the factored form d^2 = ca u^2 + e dy^2, u = dx + k dy, the chord of
+ * {d^2 <= tau} at height dy is dx = -k dy +- sqrt((tau - e dy^2) / ca).
+ * Its right end is concave in dy and largest at the height of the
+ * ellipse's rightmost point, dy_r = -k sqrt(ca tau / (e (e + k^2 ca)));
+ * its left end is convex and smallest at -dy_r.  Over the row's band of
+ * pixel-centre heights [ly, hy] the x-extent is therefore the chord ends
+ * at clamp(dy_r) and clamp(-dy_r).  tau is enlarged to tau (1 + 2^-18
+ * (1 + rk)), above what rounding of the per-pixel test can accept (see
+ * rect32), and the ends are padded by 1/64 px plus 2^-16 of their size.
+ * Every term is a sum of non-negative parts: no cancellation for any
+ * elongation.  A non-finite end keeps the rectangle's bound.            */
 static void row_span32(const float *d, const int r[4], int ty, int *c0, int *c1) {
-    float mx = d[0], my = d[1], ca = d[2], cb = d[3], cc = d[4], tau = d[5];
+    float mx = d[0], my = d[1], ca = d[2], tau = d[5], k = d[8], e = d[9];
+    float rk = sqrtf(1.0f + (k * k) * (ca / e));
+    float taup = tau + tau * (0x1p-18f * (1.0f + rk));
+    float dyr = -(k * sqrtf((ca * taup) / (e * (e + (k * k) * ca))));
     int y0 = ty * 16 > r[2] ? ty * 16 : r[2];
     int y1 = ty * 16 + 15 < r[3] ? ty * 16 + 15 : r[3];
     float ly = ((float)y0 + 0.5f) - my, hy = ((float)y1 + 0.5f) - my;
-    float lo = (float)r[0], hi = (float)r[1];
-    float pcc = ca * cc;
-    float detp = (pcc - cb * cb) - 0x1p-18f * pcc;
-    if (detp > 0x1p-10f * pcc) {
-        float taup = tau + tau * (0x1p-16f * (pcc / detp));
-        float dyr = -(cb * sqrtf(taup / (cc * detp)));
-        float dR = fminf(fmaxf(dyr, ly), hy), dL = fminf(fmaxf(-dyr, ly), hy);
-        float wR = fmaxf(ca * taup - detp * (dR * dR), 0.0f);
-        float wL = fmaxf(ca * taup - detp * (dL * dL), 0.0f);
-        float xr = mx + (sqrtf(wR) - cb * dR) / ca;
-        float xl = mx - (sqrtf(wL) + cb * dL) / ca;
-        float pr = 0x1p-6f + 0x1p-16f * (fabsf(mx) + fabsf(xr - mx));
-        float pl = 0x1p-6f + 0x1p-16f * (fabsf(mx) + fabsf(xl - mx));
-        /* NaN compares false in fmaxf/fminf: the rectangle's bound stays */
-        lo = fmaxf(ceilf((xl - pl) - 0.5f), lo);
-        hi = fminf(floorf((xr + pr) - 0.5f), hi);
-    }
+    float dR = fminf(fmaxf(dyr, ly), hy), dL = fminf(fmaxf(-dyr, ly), hy);
+    float wR = fmaxf(taup - e * (dR * dR), 0.0f);
+    float wL = fmaxf(taup - e * (dL * dL), 0.0f);
+    float xr = mx + (sqrtf(wR / ca) - k * dR);
+    float xl = mx - (sqrtf(wL / ca) + k * dL);
+    float pr = 0x1p-6f + 0x1p-16f * (fabsf(mx) + fabsf(xr - mx));
+    float pl = 0x1p-6f + 0x1p-16f * (fabsf(mx) + fabsf(xl - mx));
+    /* NaN compares false in fmaxf/fminf: the rectangle's bound stays */
+    float lo = fmaxf(ceilf((xl - pl) - 0.5f), (float)r[0]);
+    float hi = fminf(floorf((xr + pr) - 0.5f), (float)r[1]);
     if (!(lo <= hi)) { *c0 = 1; *c1 = 0; return; }
     *c0 = (int)lo >> 4;
     *c1 = (int)hi >> 4;
@@ -568,9 +584,9 @@ int orc_project(int64_t n, int D, const double *means, const double *log_scales,
         P32 p32; P64 p64; int r[4] = {0, -1, 0, -1};
         proj32(n, means, log_scales, quats, opac, &c, i, &p32);
         proj64(n, D, means, log_scales, quats, opac, sh, &c, i, &p64);
-        float *d = dec32 + 8 * i;
+        float *d = dec32 + 10 * i;
         d[0] = p32.mx; d[1] = p32.my; d[2] = p32.ca; d[3] = p32.cb; d[4] = p32.cc;
-        d[5] = p32.tau; d[6] = p32.z; d[7] = p32.alpha;
+        d[5] = p32.tau; d[6] = p32.z; d[7] = p32.alpha; d[8] = p32.k; d[9] = p32.e;
         double *v = val + 12 * i;
         v[0] = p64.mx; v[1] = p64.my; v[2] = p64.ca; v[3] = p64.cb; v[4] = p64.cc;
         v[5] = p64.alpha; v[6] = p64.z; v[7] = p64.rgb[0]; v[8] = p64.rgb[1]; v[9] = p64.rgb[2];
@@ -621,20 +637,20 @@ int64_t orc_bins(int64_t n, const float *dec32, const int32_t *rect, const uint8
     int64_t tot = 0;
     for (int64_t i = 0; i < n; i++) {
         if (!vis[i]) continue;
-        tot += (int64_t)popcount64(cellmask[i]) * tiles32(dec32 + 8 * i, rect + 4 * i);
+        tot += (int64_t)popcount64(cellmask[i]) * tiles32(dec32 + 10 * i, rect + 4 * i);
     }
     if (tot > cap) return -tot;
     Inst *v = (Inst *)malloc(sizeof(Inst) * (tot > 0 ? tot : 1));
     int64_t m = 0;
     for (int64_t i = 0; i < n; i++) {
         if (!vis[i]) continue;
-        float z = dec32[8 * i + 6];
+        float z = dec32[10 * i + 6];
         uint32_t zk; memcpy(&zk, &z, 4);
         for (int k = 0; k < K; k++) {
             if (!((cellmask[i] >> k) & 1)) continue;
             for (int ty = rect[4 * i + 2] >> 4; ty <= (rect[4 * i + 3] >> 4); ty++) {
                 int c0, c1;
-                row_span32(dec32 + 8 * i, rect + 4 * i, ty, &c0, &c1);
+                row_span32(dec32 + 10 * i, rect + 4 * i, ty, &c0, &c1);
                 for (int tx = c0; tx <= c1; tx++) {
                     uint32_t tile = (uint32_t)(ty * tiles_x + tx);
                     v[m].key = (tile << rb) | (uint32_t)rank_of[k];
@@ -698,13 +714,13 @@ static int64_t collect(const Scene *s, int px, int py, Contrib **out) {
         if (!s->vis[i]) continue;
         const int32_t *r = s->rect + 4 * i;
         if (px < r[0] || px > r[1] || py < r[2] || py > r[3]) continue;
-        const float *d = s->dec32 + 8 * i;
+        const float *d = s->dec32 + 10 * i;
         const double *vv = s->val + 12 * i;
         int hit; double z; int cell;
         if (s->mode == 0) {
             float dx = u32 - d[0], dy = v32 - d[1];
-            float A = (d[2] * dx) * dx, B = (2.0f * d[3]) * dx;
-            float d2 = fmaf(dy, fmaf(d[4], dy, B), A);
+            float u = fmaf(d[8], dy, dx);
+            float d2 = fmaf(d[9] * dy, dy, (d[2] * u) * u);
             hit = (d2 <= d[5]);
             z = d[6];
             if (hit) {

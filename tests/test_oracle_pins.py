@@ -303,6 +303,42 @@ def test_rect_conservative_brute_force(orc):
     assert checked > 500
 
 
+def test_rect_conservative_elongated(orc):
+    """Needle-like footprints (s00 s11 / det up to ~10^6): the rectangle holds
+    every pixel centre whose d^2 = ca (dx + k dy)^2 + e dy^2 (fp64 on the fp32
+    decision values) is at most tau (1 + 2^-21 (1 + rk)), rk = sqrt(1 + k^2
+    ca / e) -- the most the fp32 per-pixel test can accept."""
+    rng = np.random.default_rng(5)
+    n = 20000
+    p = scenes.scene_uniform(n, seed=11, D=0, mu_s=-3.0, extent=0.6)
+    ls = p["log_scales"].copy()
+    ls[0] += rng.uniform(0, 4.0, n).astype(np.float32)
+    ls[1] -= rng.uniform(0, 4.0, n).astype(np.float32)
+    ls[2] -= rng.uniform(0, 4.0, n).astype(np.float32)
+    p["log_scales"] = ls
+    W, H = 640, 480
+    cam = scenes.orbit_camera(1.6, 0.4, 0.3, W, H, z_near=0.05)
+    pr = orc.project(p, cam, kd_trivial(), 0)
+    n_checked = 0
+    kmax = 0.0
+    for i in np.nonzero(pr["vis"])[0]:
+        mx, my, ca, tau, k, e = [float(pr["dec32"][i, c]) for c in (0, 1, 2, 5, 8, 9)]
+        xl, xh, yl, yh = [int(v) for v in pr["rect"][i]]
+        rk = math.sqrt(1 + k * k * ca / e)
+        kmax = max(kmax, rk * rk)
+        if rk < 30:  # rounding margins below the rectangle's fixed padding
+            continue
+        x0, x1, y0, y1 = max(xl - 3, 0), min(xh + 3, W - 1), max(yl - 3, 0), min(yh + 3, H - 1)
+        X, Y = np.meshgrid(np.arange(x0, x1 + 1) + 0.5, np.arange(y0, y1 + 1) + 0.5)
+        dx, dy = X - mx, Y - my
+        q = ca * (dx + k * dy) ** 2 + e * dy * dy
+        inside = q <= tau * (1 + 2.0 ** -21 * (1 + rk))
+        in_rect = (X - 0.5 >= xl) & (X - 0.5 <= xh) & (Y - 0.5 >= yl) & (Y - 0.5 <= yh)
+        assert not np.any(inside & ~in_rect), i
+        n_checked += int(inside.sum())
+    assert kmax > 1e5 and n_checked > 10**4
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_rect_boundary_sample_included(orc, mode):
     """A sample exactly on the ellipse's extreme x (d^2 = tau) lies in the rectangle."""
@@ -333,8 +369,11 @@ def _random_footprints(rng, n, W, H):
     s00 = (c * c * lam1 + s * s * lam2).astype(np.float32)
     s01 = (c * s * (lam1 - lam2)).astype(np.float32)
     s11 = (s * s * lam1 + c * c * lam2).astype(np.float32)
-    det = (s00 * s11 - s01 * s01).astype(np.float32)
-    ca, cb, cc = s11 / det, -s01 / det, s00 / det
+    s00_, s01_, s11_ = s00.astype(np.float64), s01.astype(np.float64), s11.astype(np.float64)
+    det64 = s00_ * s11_ - s01_ * s01_
+    det = det64.astype(np.float32)
+    ca, cb, cc = (s11_ / det64).astype(np.float32), (-s01_ / det64).astype(np.float32), (s00_ / det64).astype(np.float32)
+    kk, ee = (-s01_ / s11_).astype(np.float32), (1.0 / s11_).astype(np.float32)
     tau = rng.uniform(0.05, 9.0, n).astype(np.float32)
     mx = rng.uniform(-30, W + 30, n).astype(np.float32)
     my = rng.uniform(-30, H + 30, n).astype(np.float32)
@@ -343,18 +382,20 @@ def _random_footprints(rng, n, W, H):
     xl = np.maximum(np.ceil(mx - ex - 0.5), 0); xh = np.minimum(np.floor(mx + ex - 0.5), W - 1)
     yl = np.maximum(np.ceil(my - ey - 0.5), 0); yh = np.minimum(np.floor(my + ey - 0.5), H - 1)
     ok = (xl <= xh) & (yl <= yh) & (det > 0)
-    dec = np.zeros((n, 8), np.float32)
+    dec = np.zeros((n, 10), np.float32)
     dec[:, 0], dec[:, 1], dec[:, 2], dec[:, 3], dec[:, 4], dec[:, 5] = mx, my, ca, cb, cc, tau
     dec[:, 6] = rng.uniform(1, 10, n)
+    dec[:, 8], dec[:, 9] = kk, ee
     rect = np.stack([xl, xh, yl, yh], 1).astype(np.int32)
     return dec[ok], rect[ok]
 
 
 def test_tile_spans_conservative_and_tight(orc):
     """Row spans of the instance lists: every pixel centre of the rectangle
-    within the ellipse (enlarged beyond what fp32 rounding of the per-pixel
-    test can reach) lies in a listed tile, and every listed tile comes within
-    0.1 px of the ellipse (footprints with aspect ratio below ~10^3)."""
+    within the ellipse d^2 = ca (dx + k dy)^2 + e dy^2 <= tau, enlarged to
+    tau (1 + 2^-20 (1 + rk)) (twice what fp32 rounding of the per-pixel test
+    can accept), lies in a listed tile, and every listed tile comes within
+    0.1 px of the ellipse."""
     rng = np.random.default_rng(7)
     W = H = 256
     dec, rect = _random_footprints(rng, 3000, W, H)
@@ -367,23 +408,21 @@ def test_tile_spans_conservative_and_tight(orc):
         kept.setdefault(g, set()).add(k)
     n_pix = n_tiles = n_rect_tiles = n_elong = 0
     for i in range(n):
-        mx, my, ca, cb, cc, tau = [float(v) for v in dec[i, :6]]
+        mx, my, ca, tau, k, e = [float(dec[i, c]) for c in (0, 1, 2, 5, 8, 9)]
+        cb, cc = k * ca, e + k * k * ca
+        rk = math.sqrt(1 + k * k * ca / e)
         xl, xh, yl, yh = [int(v) for v in rect[i]]
-        pcc = ca * cc
-        det = pcc - cb * cb
         X, Y = np.meshgrid(np.arange(xl, xh + 1) + 0.5, np.arange(yl, yh + 1) + 0.5)
         dx, dy = X - mx, Y - my
-        q = ca * dx * dx + 2 * cb * dx * dy + cc * dy * dy
-        inside = q <= tau * (1 + 2.0 ** -19 * pcc / det)
+        q = ca * (dx + k * dy) ** 2 + e * dy * dy
+        inside = q <= tau * (1 + 2.0 ** -20 * (1 + rk))
         tiles = set(((Y[inside].astype(int) >> 4) * (W // 16) + (X[inside].astype(int) >> 4)).tolist())
         got = kept.get(i, set())
         assert tiles <= got, i
         n_pix += int(inside.sum())
         n_rect_tiles += ((xh >> 4) - (xl >> 4) + 1) * ((yh >> 4) - (yl >> 4) + 1)
         n_tiles += len(got)
-        if pcc / det > 2.0 ** 9:
-            n_elong += 1
-            continue
+        n_elong += rk > 10
         for t in got:
             ty, tx = divmod(t, W // 16)
             assert (xl >> 4) <= tx <= (xh >> 4) and (yl >> 4) <= ty <= (yh >> 4)
@@ -551,6 +590,31 @@ def test_merged_equals_plain_mirror32_config1(orc):
     pix = orc.all_pixels(256, 256)[::7]
     r = orc.render(pr, cam, kd, order, pix, 0.0)
     assert np.abs(r["img"] - r["plain"]).max() < 1e-12
+
+
+def test_mirror32_decisions_match_exact64(orc):
+    """The fp32 decision path (factored quadratic form, fp64 covariance chain)
+    against the exact64 one on anisotropic, rotated Gaussians: the per-pixel
+    contributor sets may differ only where d^2 is within rounding of tau, so
+    the images agree to within a few boundary contributions (sigma ~ 1/255)."""
+    rng = np.random.default_rng(21)
+    n = 400
+    p = scenes.scene_uniform(n, seed=22, D=0, mu_s=-2.6, extent=0.5)
+    ls = p["log_scales"].copy()
+    ls[0] += rng.uniform(0, 2.5, n).astype(np.float32)
+    ls[1] -= rng.uniform(0, 2.5, n).astype(np.float32)
+    p["log_scales"] = ls
+    q = rng.normal(size=(4, n)).astype(np.float32)
+    p["quats"] = q
+    cam = scenes.orbit_camera(2.0, 0.5, 0.35, 96, 80)
+    kd = kd_trivial()
+    order = np.zeros(1, np.int32)
+    pix = orc.all_pixels(96, 80)
+    a = orc.render(orc.project(p, cam, kd, 0), cam, kd, order, pix, 0.0)
+    b = orc.render(orc.project(p, cam, kd, 1), cam, kd, order, pix, 0.0)
+    d = np.abs(a["img"] - b["img"])
+    assert np.count_nonzero(a["ncon"]) > 0.8 * len(pix)
+    assert d.max() < 0.02 and np.mean(d > 1e-6) < 0.01
 
 
 def test_k1_is_identity(orc):
