@@ -120,7 +120,9 @@ typedef struct {
 /* Per-(view, Gaussian) projection output.  Where count is 0 (culled) only
    count is written: rec, rect and cellmask hold whatever the buffers held. */
 typedef struct {
-    float *rec;         /* [V*N][16]: mx, my, ca, cb | cc, alpha, tau, z | r, g, b, flags |
+    float *rec;         /* [V*N][16]: mx, my, ca, k | e, alpha, tau, z | r, g, b, flags |
+                           (footprint d^2 = ca (dx + k dy)^2 + e dy^2, i.e. the conic
+                           ca, cb = k ca, cc = e + k cb, with dx = x + 0.5 - mx) |
                            rect as two uint32 (x_lo | x_hi << 16, y_lo | y_hi << 16), then
                            the row-span descriptor as two uint32 (low word first): for a
                            rectangle of <= 8 tile rows and <= 15 tile columns, byte k =

@@ -200,6 +200,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict_
                 ty = ty0 + k;
             } else {
                 // large rectangle: the spans are recomputed from the record
+                // (mx, my, ca, k | e, alpha, tau, z)
                 const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)s_src[lo] * RGS_REC_FLOATS);
                 const float4 a = rp[0], b = rp[1];
                 SpanPre sp;

@@ -54,33 +54,31 @@ __device__ __forceinline__ float key2f(uint32_t k) {
 // contraction, IEEE division and square root, so that the projection's
 // instance count and the emission's tile list agree bit for bit).
 //
-// With q(dx, dy) = ca dx^2 + 2 cb dx dy + cc dy^2 and det = ca cc - cb^2, the
-// chord of {q <= tau} at height dy runs from (-cb dy - w) / ca to (-cb dy + w)
-// / ca, w = sqrt(ca tau - det dy^2).  Its right end is concave in dy, largest
-// at the height of the rightmost point dy_r = -cb sqrt(tau / (cc det)); its
+// With the factored quadratic form d^2 = ca u^2 + e dy^2, u = dx + k dy, the
+// chord of {d^2 <= tau} at height dy runs from -k dy - w to -k dy + w, w =
+// sqrt((tau - e dy^2) / ca).  Its right end is concave in dy, largest at the
+// height of the rightmost point dy_r = -k sqrt(ca tau / (e (e + k^2 ca))); its
 // left end is convex, smallest at -dy_r.  A tile row's band of pixel-centre
 // heights [ly, hy] thus meets the ellipse between the chord ends at
-// clamp(-dy_r) and clamp(dy_r).  The ellipse is grown first: det' = det -
-// 2^-18 ca cc (the rounding of det is below 2^-22 ca cc) and tau' = tau (1 +
-// 2^-16 ca cc / det') (the per-pixel test's terms sum to at most 4 tau ca cc /
-// det inside the ellipse, so its rounding stays far below that), and the ends
-// are padded by 1/64 px plus 2^-16 of their magnitude.  Footprints with det'
-// <= 2^-10 ca cc and non-finite values keep the rectangle's whole row.
+// clamp(-dy_r) and clamp(dy_r).  tau is enlarged to tau (1 + 2^-18 (1 + rk)),
+// rk = sqrt(1 + k^2 ca / e), above what the fp32 per-pixel test can accept
+// (its rounding of u moves ca u^2 by at most about 2^-21 tau (1 + rk)), and
+// the ends are padded by 1/64 px plus 2^-16 of their magnitude.  All terms
+// are sums of non-negative parts, so no elongation loses accuracy; a
+// non-finite end keeps the rectangle's bound.
 struct SpanPre {
-    float mx, my, ca, cb, taup, detp, dyr;
-    bool ok;
+    float mx, my, ca, k, e, taup, dyr;
 };
 
-__device__ __forceinline__ void span_pre(float mx, float my, float ca, float cb, float cc, float tau, SpanPre& s) {
+__device__ __forceinline__ void span_pre(float mx, float my, float ca, float k, float e, float tau, SpanPre& s) {
     s.mx = mx;
     s.my = my;
     s.ca = ca;
-    s.cb = cb;
-    const float pcc = ca * cc;
-    s.detp = (pcc - cb * cb) - 0x1p-18f * pcc;
-    s.ok = s.detp > 0x1p-10f * pcc;
-    s.taup = tau + tau * (0x1p-16f * (pcc / s.detp));
-    s.dyr = -(cb * sqrtf(s.taup / (cc * s.detp)));
+    s.k = k;
+    s.e = e;
+    const float rk = sqrtf(1.0f + (k * k) * (ca / e));
+    s.taup = tau + tau * (0x1p-18f * (1.0f + rk));
+    s.dyr = -(k * sqrtf((ca * s.taup) / (e * (e + (k * k) * ca))));
 }
 
 // Tile columns (c0, c1) of tile row ty inside the rectangle [x_lo, x_hi] x
@@ -88,19 +86,16 @@ __device__ __forceinline__ void span_pre(float mx, float my, float ca, float cb,
 __device__ __forceinline__ int2 row_span(const SpanPre& s, int x_lo, int x_hi, int y_lo, int y_hi, int ty) {
     const int y0 = max(ty * 16, y_lo), y1 = min(ty * 16 + 15, y_hi);
     const float ly = ((float)y0 + 0.5f) - s.my, hy = ((float)y1 + 0.5f) - s.my;
-    float lo = (float)x_lo, hi = (float)x_hi;
-    if (s.ok) {
-        const float dR = fminf(fmaxf(s.dyr, ly), hy), dL = fminf(fmaxf(-s.dyr, ly), hy);
-        const float wR = fmaxf(s.ca * s.taup - s.detp * (dR * dR), 0.0f);
-        const float wL = fmaxf(s.ca * s.taup - s.detp * (dL * dL), 0.0f);
-        const float xr = s.mx + (sqrtf(wR) - s.cb * dR) / s.ca;
-        const float xl = s.mx - (sqrtf(wL) + s.cb * dL) / s.ca;
-        const float pr = 0x1p-6f + 0x1p-16f * (fabsf(s.mx) + fabsf(xr - s.mx));
-        const float pl = 0x1p-6f + 0x1p-16f * (fabsf(s.mx) + fabsf(xl - s.mx));
-        // a NaN end leaves the rectangle's bound (fmaxf/fminf drop NaN)
-        lo = fmaxf(ceilf((xl - pl) - 0.5f), lo);
-        hi = fminf(floorf((xr + pr) - 0.5f), hi);
-    }
+    const float dR = fminf(fmaxf(s.dyr, ly), hy), dL = fminf(fmaxf(-s.dyr, ly), hy);
+    const float wR = fmaxf(s.taup - s.e * (dR * dR), 0.0f);
+    const float wL = fmaxf(s.taup - s.e * (dL * dL), 0.0f);
+    const float xr = s.mx + (sqrtf(wR / s.ca) - s.k * dR);
+    const float xl = s.mx - (sqrtf(wL / s.ca) + s.k * dL);
+    const float pr = 0x1p-6f + 0x1p-16f * (fabsf(s.mx) + fabsf(xr - s.mx));
+    const float pl = 0x1p-6f + 0x1p-16f * (fabsf(s.mx) + fabsf(xl - s.mx));
+    // a NaN end leaves the rectangle's bound (fmaxf/fminf drop NaN)
+    const float lo = fmaxf(ceilf((xl - pl) - 0.5f), (float)x_lo);
+    const float hi = fminf(floorf((xr + pr) - 0.5f), (float)x_hi);
     if (!(lo <= hi)) return make_int2(1, 0);
     return make_int2((int)lo >> 4, (int)hi >> 4);
 }

@@ -4,9 +4,10 @@
 // One thread per Gaussian loops over the views, so the parameters (up to
 // 59 floats) are read from HBM once per batch of views; loads and the
 // structure-of-arrays stores are coalesced.  The decision path (activations,
-// covariance, EWA, conic, screen mean, tau, rectangle, cell set) is written
-// as single IEEE binary32 operations in a fixed order with no contraction;
-// its transcendentals are computed in fp64 and rounded once, so the integer
+// covariance, EWA, conic, screen mean, tau, rectangle, cell set) is a fixed
+// sequence of IEEE operations with no contraction: the covariance chain in
+// fp64 (+, -, *, /, sqrt), rounded once to fp32, then fp32 tests; its
+// transcendentals are computed in fp64 and rounded once, so the integer
 // outputs (rectangle, cell set, count) are reproducible on any IEEE machine.
 #include "common.hpp"
 
@@ -75,41 +76,46 @@ __device__ __forceinline__ void sh_grad(int D, float x, float y, float z, float 
 }
 
 struct Proj32 {
-    float mx, my, ca, cb, cc, tau, z, alpha, s00, s11;
+    float mx, my, ca, k, e, tau, z, alpha, s00, s11, rk;
     bool vis;
 };
 
-// The fixed-order fp32 decision path (see the file comment), in two parts:
-// the view-independent activations and 3D covariance (once per Gaussian),
-// then the per-view projection.  The split changes no operation or order.
+// The decision path in two parts: the view-independent activations and 3D
+// covariance (once per Gaussian), then the per-view projection.  From the
+// quaternion to the inverse of the screen covariance everything runs in
+// fp64 (+, -, *, /, sqrt: correctly rounded, so the bits match any IEEE
+// machine) and is rounded once to fp32, so that a nearly singular screen
+// covariance (a needle-like footprint) keeps an accurate inverse.  The
+// scale and opacity activations are fp64 transcendentals rounded to fp32.
 struct Pre32 {
     float alpha, tau;
-    float S[6];  // 3D covariance: 00, 01, 02, 11, 12, 22 (the product is exactly symmetric)
-    bool ok;     // quaternion non-zero
+    double S[6];  // 3D covariance: 00, 01, 02, 11, 12, 22 (the product is exactly symmetric)
+    bool ok;      // quaternion non-zero
 };
 
-__device__ __forceinline__ void pre32(float ls0, float ls1, float ls2, float qw, float qx, float qy, float qz,
+__device__ __forceinline__ void pre32(float ls0, float ls1, float ls2, float qw32, float qx32, float qy32, float qz32,
                                       float logit, Pre32& q) {
     q.ok = false;
     const float s0 = (float)exp((double)ls0), s1 = (float)exp((double)ls1), s2 = (float)exp((double)ls2);
     q.alpha = (float)(1.0 / (1.0 + exp(-(double)logit)));
     q.tau = fminf(9.0f, (float)(2.0 * log(255.0 * (double)q.alpha)));
-    const float qq = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
-    if (!(qq > 0.0f)) return;
-    const float qn = sqrtf(qq);
-    const float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
-    float r[3][3];
-    r[0][0] = 1.0f - 2.0f * (y * y + z * z);
-    r[0][1] = 2.0f * (x * y - w * z);
-    r[0][2] = 2.0f * (x * z + w * y);
-    r[1][0] = 2.0f * (x * y + w * z);
-    r[1][1] = 1.0f - 2.0f * (x * x + z * z);
-    r[1][2] = 2.0f * (y * z - w * x);
-    r[2][0] = 2.0f * (x * z - w * y);
-    r[2][1] = 2.0f * (y * z + w * x);
-    r[2][2] = 1.0f - 2.0f * (x * x + y * y);
-    const float sc[3] = {s0, s1, s2};
-    float M[3][3];
+    const double qw = qw32, qx = qx32, qy = qy32, qz = qz32;
+    const double qq = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    if (!(qq > 0.0)) return;
+    const double qn = sqrt(qq);
+    const double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+    double r[3][3];
+    r[0][0] = 1.0 - 2.0 * (y * y + z * z);
+    r[0][1] = 2.0 * (x * y - w * z);
+    r[0][2] = 2.0 * (x * z + w * y);
+    r[1][0] = 2.0 * (x * y + w * z);
+    r[1][1] = 1.0 - 2.0 * (x * x + z * z);
+    r[1][2] = 2.0 * (y * z - w * x);
+    r[2][0] = 2.0 * (x * z - w * y);
+    r[2][1] = 2.0 * (y * z + w * x);
+    r[2][2] = 1.0 - 2.0 * (x * x + y * y);
+    const double sc[3] = {s0, s1, s2};
+    double M[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -124,55 +130,70 @@ __device__ __forceinline__ void pre32(float ls0, float ls1, float ls2, float qw,
     q.ok = true;
 }
 
-__device__ __forceinline__ void proj32(float mu0, float mu1, float mu2, const Pre32& q, const ViewParams& V,
+// Per view: camera transform, EWA (Jacobian clamped to 1.3x the half field of
+// view), screen covariance + 0.3 I and its inverse in the factored form
+// d^2 = ca (dx + k dy)^2 + e dy^2 with ca = s11/det, k = -s01/s11, e = 1/s11.
+__device__ __forceinline__ void proj32(float mu0f, float mu1f, float mu2f, const Pre32& q, const ViewParams& V,
                                        Proj32& p) {
     p.vis = false;
     if (!q.ok) return;
-    const float S[3][3] = {{q.S[0], q.S[1], q.S[2]}, {q.S[1], q.S[3], q.S[4]}, {q.S[2], q.S[4], q.S[5]}};
-    float tc[3];
+    const double S[3][3] = {{q.S[0], q.S[1], q.S[2]}, {q.S[1], q.S[3], q.S[4]}, {q.S[2], q.S[4], q.S[5]}};
+    const double mu0 = mu0f, mu1 = mu1f, mu2 = mu2f;
+    double R[9];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) tc[a] = ((V.R[3 * a] * mu0 + V.R[3 * a + 1] * mu1) + V.R[3 * a + 2] * mu2) + V.t[a];
-    const float zc = tc[2];
-    if (!(zc > V.znear)) return;
-    const float xz = tc[0] / zc, yz = tc[1] / zc;
-    const float xg = fminf(fmaxf(xz, -V.gx), V.gx) * zc;
-    const float yg = fminf(fmaxf(yz, -V.gy), V.gy) * zc;
-    const float zz = zc * zc;
-    const float J00 = V.fx / zc, J02 = -(V.fx * xg) / zz, J11 = V.fy / zc, J12 = -(V.fy * yg) / zz;
-    float T[2][3], U[2][3];
+    for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+    double tc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) tc[a] = ((R[3 * a] * mu0 + R[3 * a + 1] * mu1) + R[3 * a + 2] * mu2) + (double)V.t[a];
+    const double zc = tc[2];
+    if (!(zc > (double)V.znear)) return;
+    const double fx = V.fx, fy = V.fy, gx = V.gx, gy = V.gy;
+    const double xz = tc[0] / zc, yz = tc[1] / zc;
+    const double xg = fmin(fmax(xz, -gx), gx) * zc;
+    const double yg = fmin(fmax(yz, -gy), gy) * zc;
+    const double zz = zc * zc;
+    const double J00 = fx / zc, J02 = -(fx * xg) / zz, J11 = fy / zc, J12 = -(fy * yg) / zz;
+    double T[2][3], U[2][3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        T[0][b] = J00 * V.R[b] + J02 * V.R[6 + b];
-        T[1][b] = J11 * V.R[3 + b] + J12 * V.R[6 + b];
+        T[0][b] = J00 * R[b] + J02 * R[6 + b];
+        T[1][b] = J11 * R[3 + b] + J12 * R[6 + b];
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) U[a][b] = (T[a][0] * S[0][b] + T[a][1] * S[1][b]) + T[a][2] * S[2][b];
-    const float s00 = ((U[0][0] * T[0][0] + U[0][1] * T[0][1]) + U[0][2] * T[0][2]) + 0.3f;
-    const float s01 = (U[0][0] * T[1][0] + U[0][1] * T[1][1]) + U[0][2] * T[1][2];
-    const float s11 = ((U[1][0] * T[1][0] + U[1][1] * T[1][1]) + U[1][2] * T[1][2]) + 0.3f;
-    const float det = s00 * s11 - s01 * s01;
-    if (!(det > 0.0f)) return;
-    p.ca = s11 / det;
-    p.cb = -s01 / det;
-    p.cc = s00 / det;
-    p.mx = V.fx * xz + V.cx;
-    p.my = V.fy * yz + V.cy;
-    p.z = zc;
+    const double s00 = ((U[0][0] * T[0][0] + U[0][1] * T[0][1]) + U[0][2] * T[0][2]) + 0.3;
+    const double s01 = (U[0][0] * T[1][0] + U[0][1] * T[1][1]) + U[0][2] * T[1][2];
+    const double s11 = ((U[1][0] * T[1][0] + U[1][1] * T[1][1]) + U[1][2] * T[1][2]) + 0.3;
+    const double det = s00 * s11 - s01 * s01;
+    if (!(det > 0.0)) return;
+    p.ca = (float)(s11 / det);
+    p.k = (float)(-s01 / s11);
+    p.e = (float)(1.0 / s11);
+    p.rk = sqrtf(1.0f + (p.k * p.k) * (p.ca / p.e));
+    p.mx = (float)(fx * xz + (double)V.cx);
+    p.my = (float)(fy * yz + (double)V.cy);
+    p.z = (float)zc;
     p.alpha = q.alpha;
-    p.s00 = s00;
-    p.s11 = s11;
+    p.s00 = (float)s00;
+    p.s11 = (float)s11;
     p.tau = q.tau;
     if (!(q.tau >= 0.0f)) return;
     if (!(isfinite(p.mx) && isfinite(p.my))) return;
     p.vis = true;
 }
 
-// Sample-pixel rectangle of the footprint d^2 <= tau (padded against rounding).
+// Sample-pixel rectangle of the footprint d^2 <= tau.  Its half-widths
+// sqrt(tau s00), sqrt(tau s11) are padded by 1e-3 px, a relative 1e-5 and a
+// relative 2^-20 rk: the fp32 per-pixel test rounds u = dx + k dy with an
+// absolute error up to about 2^-24 (|dx| + |k dy|), which near the long tip of
+// an elongated footprint moves ca u^2 by up to about 2^-21 tau rk (ca s00 =
+// rk^2); the ellipse of the rounded (ca, k, e) is within a few 2^-24 of s00.
 __device__ __forceinline__ bool rect32(const Proj32& p, const ViewParams& V, int r[4]) {
-    const float ex = sqrtf(p.tau * p.s00) * 1.00001f + 1e-3f;
-    const float ey = sqrtf(p.tau * p.s11) * 1.00001f + 1e-3f;
+    const float pad = 1.00001f + 0x1p-20f * p.rk;
+    const float ex = sqrtf(p.tau * p.s00) * pad + 1e-3f;
+    const float ey = sqrtf(p.tau * p.s11) * pad + 1e-3f;
     const float xlo = fmaxf(ceilf((p.mx - ex) - 0.5f), 0.0f);
     const float xhi = fminf(floorf((p.mx + ex) - 0.5f), (float)(V.W - 1));
     const float ylo = fmaxf(ceilf((p.my - ey) - 0.5f), 0.0f);
@@ -230,7 +251,7 @@ __device__ __forceinline__ uint64_t cellset32(const Proj32& p, const int r[4], c
 }
 
 template <int D>
-__global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const ViewTable* __restrict__ vt,
+__global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, const ViewTable* __restrict__ vt,
                                                         const float* __restrict__ split,
                                                         const int32_t* __restrict__ center_cell, rgs_projected out) {
     const int64_t n = g.n;
@@ -273,7 +294,7 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
         const uint64_t mask = cellset32(p, r, V, L, split);
         // tiles per cell: the row spans of the footprint inside the rectangle
         SpanPre sp;
-        span_pre(p.mx, p.my, p.ca, p.cb, p.cc, p.tau, sp);
+        span_pre(p.mx, p.my, p.ca, p.k, p.e, p.tau, sp);
         const int tx0 = r[0] >> 4, ty0 = r[2] >> 4, ty1 = r[3] >> 4;
         const bool small = ty1 - ty0 < 8 && (r[1] >> 4) - tx0 < 15;
         uint64_t desc = small ? 0ull : RGS_NO_SPANS;
@@ -313,8 +334,8 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project(rgs_gaussians g, const V
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) col[ch] = fmaxf(col[ch], 0.0f);
         const uint32_t flags = (__popcll(mask) == 1) ? 1u : 0u;
-        rec[0] = make_float4(p.mx, p.my, p.ca, p.cb);
-        rec[1] = make_float4(p.cc, p.alpha, p.tau, p.z);
+        rec[0] = make_float4(p.mx, p.my, p.ca, p.k);
+        rec[1] = make_float4(p.e, p.alpha, p.tau, p.z);
         rec[2] = make_float4(col[0], col[1], col[2], __uint_as_float(flags));
         // the rectangle (render kernels) and the row-span descriptor (emission)
         rec[3] = make_float4(__uint_as_float(rx), __uint_as_float(ry), __uint_as_float((uint32_t)desc),

@@ -4,11 +4,14 @@
 // One 256-thread block per slot (tile t, cell k); wave w owns the 8x8
 // quadrant (w & 1, w >> 1) of the 16x16 tile, one pixel per lane.  The
 // contribute decision d^2 <= tau uses the exact fp32 operation sequence the
-// CPU oracle mirrors:
-//   dx = (x + 0.5) - mx, A = (ca dx) dx, B = (2 cb) dx,
-//   d^2 = fma(dy, fma(cc, dy, B), A),          dy = (y + 0.5) - my.
-// Gaussian records are staged through LDS (one coalesced 48-byte record per
-// thread) with a 4-bit mask of the quadrants their rectangle meets, and read
+// CPU oracle mirrors, on the factored form of the quadratic (no cancellation
+// for elongated footprints):
+//   dx = (x + 0.5) - mx, dy = (y + 0.5) - my, u = fma(k, dy, dx),
+//   d^2 = fma(e dy, dy, (ca u) u).
+// The conic (ca, cb, cc) = (ca, k ca, e + k cb) is rebuilt per instance where
+// the quadrant test and the gradients need it.  Gaussian records are staged
+// through LDS (one coalesced 64-byte record per thread) with a 4-bit mask of
+// the quadrants their rectangle meets, and read
 // back as wave-uniform broadcasts; a wave skips Gaussians outside its
 // quadrant with a scalar branch.  A pixel stops after the contribution that
 // takes its T_k below eps_T; the block leaves once all 256 pixels stopped.
@@ -161,11 +164,11 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
         if (idx < end) {
             const uint32_t src = (uint32_t)(vals[idx] >> 32);
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
-            float4 a = rp[0];
+            const float4 a = rp[0];
             const float4 b = rp[1], cl = rp[2], r4 = rp[3];
             const uint2 rr = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
-            sM[tid] = (quad_mask_ellipse(rr, tx, ty, a.x, a.y, a.z, a.w, b.x, b.z) << 1) | (__float_as_uint(cl.w) & 1u);
-            a.w = 2.0f * a.w;  // 2 cb (exact)
+            const float cb = a.w * a.z, cc = b.x + a.w * cb;  // conic from (ca, k, e)
+            sM[tid] = (quad_mask_ellipse(rr, tx, ty, a.x, a.y, a.z, cb, cc, b.z) << 1) | (__float_as_uint(cl.w) & 1u);
             sA[tid] = a;
             sB[tid] = b;
             sCl[tid] = cl;
@@ -188,11 +191,9 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
                     const int tc = k * 64 + bit;
                     rel &= rel - 1ull;
                     const float4 ac = sA[tc], bc = sB[tc];
-                    const float dx = fxp - ac.x;
-                    const float A = (ac.z * dx) * dx;
-                    const float B = ac.w * dx;
-                    const float dy = fyp - ac.y;
-                    const float d2 = fmaf(dy, fmaf(bc.x, dy, B), A);
+                    const float dx = fxp - ac.x, dy = fyp - ac.y;
+                    const float u = fmaf(ac.w, dy, dx);  // d^2 = ca u^2 + e dy^2
+                    const float d2 = fmaf(bc.x * dy, dy, (ac.z * u) * u);
                     if (STATS && fyp != INFINITY) {
                         // pairs the method must test: pixel inside the Gaussian's rectangle
                         const uint2 rr = sR[tc];
@@ -392,8 +393,9 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
         bool hit = (uint32_t)(bstart + tl) + 1u <= wmax && (uint32_t)(bstart + tl) < bmax;
         if (hit) {
             const float4 a = sA[tl], b = sB[tl];
+            const float cb = a.w * a.z, cc = b.x + a.w * cb;  // conic from (ca, k, e)
             hit = ((quad_mask(sR[tl], tx, ty) >> w) & 1u) &&
-                  quad_hits(a.x, a.y, a.z, a.w, b.x, b.z, (float)(tx * 16 + (w & 1) * 8), (float)(ty * 16 + (w >> 1) * 8));
+                  quad_hits(a.x, a.y, a.z, cb, cc, b.z, (float)(tx * 16 + (w & 1) * 8), (float)(ty * 16 + (w >> 1) * 8));
         }
         uint64_t rel = __ballot(hit);
         const uint64_t inside = __ballot(hit && (__float_as_uint(sCl[tl].w) & 1u));  // in one cell: no indicator test
@@ -404,7 +406,8 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
             const float4 a = sA[t];
             const float4 b = sB[t];
             const float dx = fxp - a.x, dy = fyp - a.y;
-            const float d2 = fmaf(dy, fmaf(b.x, dy, (2.0f * a.w) * dx), (a.z * dx) * dx);
+            const float u = fmaf(a.w, dy, dx);  // d^2 = ca u^2 + e dy^2
+            const float d2 = fmaf(b.x * dy, dy, (a.z * u) * u);
             bool contrib = pos1 <= last && d2 <= b.z;
             if (STATS && pos1 <= last) {
                 // pairs the backward must re-test: pixel inside the rectangle, at or before its last contributor
@@ -462,11 +465,11 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
 #pragma unroll
             for (int c = 0; c < 9; ++c) S[c] = (sG[0][t][c] + sG[1][t][c]) + (sG[2][t][c] + sG[3][t][c]);
             const float4 a = sA[t];
-            const float cc = sB[t].x;
+            const float cb = a.w * a.z, cc = sB[t].x + a.w * cb;  // conic from (ca, k, e)
             float4* rp = reinterpret_cast<float4*>(records + (size_t)sJ[t] * RD_REC);
             // d mx = sum q (ca dx + cb dy), d my = sum q (cb dx + cc dy); d ca, d cb, d cc
             // carry dL/d(d^2) = -q / 2 (d cb counts the cross term twice); then d alpha, colour
-            rp[0] = make_float4(a.z * S[0] + a.w * S[1], a.w * S[0] + cc * S[1], -0.5f * S[2], -S[3]);
+            rp[0] = make_float4(a.z * S[0] + cb * S[1], cb * S[0] + cc * S[1], -0.5f * S[2], -S[3]);
             rp[1] = make_float4(-0.5f * S[4], S[5], S[6], S[7]);
             rp[2] = make_float4(S[8], 0.f, 0.f, 0.f);
         }

@@ -95,6 +95,41 @@ def test_centres_on_split_planes(rast):
     assert np.abs(st.image.cpu().numpy().reshape(3, -1).T - r["img"]).max() <= 2e-4
 
 
+def test_needle_footprints(rast):
+    """Strongly elongated Gaussians (screen aspect up to ~10^6): rectangles,
+    counts and instance lists bit-exact, the image against the
+    oracle, which tests pixel-in-rectangle explicitly (the kernels do not)."""
+    rng = np.random.default_rng(5)
+    n = 6000
+    p = scenes.scene_uniform(n, seed=11, D=0, mu_s=-3.0, extent=0.6)
+    ls = p["log_scales"].copy()
+    ls[0] += rng.uniform(0, 4.0, n).astype(np.float32)
+    ls[1] -= rng.uniform(0, 4.0, n).astype(np.float32)
+    ls[2] -= rng.uniform(0, 4.0, n).astype(np.float32)
+    p["log_scales"] = ls
+    W, H, L = 320, 240, 2
+    cam = scenes.orbit_camera(1.6, 0.4, 0.3, W, H, z_near=0.05)
+    dp = device_params(p)
+    kd = rast.kd_partition(dp, L)
+    st = rast.forward(dp, kd, [cam], EPS_T)
+    okd = oracle.kd_partition(p["means"], p["log_scales"], L)
+    order, rank_of = oracle.cell_order(L, okd["split"], cam["o"])
+    pr = oracle.project(p, cam, okd, 0)
+    vis = pr["vis"] == 1
+    d = pr["dec32"][vis].astype(np.float64)
+    assert (1 + d[:, 8] ** 2 * d[:, 2] / d[:, 9]).max() > 1e4  # s00 s11 / det
+    assert np.array_equal(st.proj["count"][:n].cpu().numpy().view(np.uint32), pr["count"])
+    rect = st.proj["rect"][: 4 * n].view(n, 4).cpu().numpy().astype(np.int32)
+    assert np.array_equal(rect[vis], pr["rect"][vis])
+    okeys, ogids = oracle.bins(pr, rank_of, L, (W + 15) // 16)
+    n_inst = st.bins_struct.n_instances
+    keys = st.bins["keys"][:n_inst].cpu().numpy().view(np.uint32)
+    src = (st.bins["vals"][:n_inst].cpu().numpy().view(np.uint64) >> np.uint64(32)).astype(np.int64)
+    assert np.array_equal(keys, okeys) and np.array_equal(src % n, ogids.astype(np.int64))
+    r = oracle.render(pr, cam, okd, order, oracle.all_pixels(W, H), EPS_T)
+    assert np.abs(st.image.cpu().numpy().reshape(3, -1).T - r["img"]).max() <= 2e-4
+
+
 # ---------------------------------------------------------------- full size
 @pytest.fixture(scope="module")
 def full(rast):

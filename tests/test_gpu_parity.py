@@ -103,9 +103,11 @@ def test_project_bit_exact(name, rast):
     packed = rec[vis][:, 12:14].view(np.uint32)
     unpack = np.stack([packed[:, 0] & 0xffff, packed[:, 0] >> 16, packed[:, 1] & 0xffff, packed[:, 1] >> 16], 1)
     assert np.array_equal(unpack.astype(np.int16).astype(np.int32), pr["rect"][vis])
-    # decision quantities: mx, my, ca, cb, cc, tau, z, alpha
-    gpu_dec = rec[vis][:, [0, 1, 2, 3, 4, 6, 7, 5]]
-    assert np.array_equal(gpu_dec.view(np.uint32), pr["dec32"][vis].view(np.uint32))
+    # decision quantities: record (mx, my, ca, k | e, alpha, tau, z) against the
+    # oracle's (mx, my, ca, cb, cc, tau, z, alpha, k, e)
+    gpu_dec = rec[vis][:, :8]
+    ora_dec = pr["dec32"][vis][:, [0, 1, 2, 8, 9, 7, 5, 6]]
+    assert np.array_equal(gpu_dec.view(np.uint32), ora_dec.view(np.uint32))
     # colour (value path, fp32 vs fp64)
     assert np.abs(rec[vis][:, 8:11] - pr["val"][vis][:, 7:10]).max() < 2e-5
     flags = rec[:, 11].view(np.uint32)
