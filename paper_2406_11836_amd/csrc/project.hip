@@ -357,43 +357,44 @@ rgs_status project_launch(const rgs_gaussians* g, const ViewTable* vt, const flo
 }
 
 // ------------------------------------------------------------------ backward
-// Recomputes the forward in fp32 and applies the chain rule; gradients of
-// the views are summed in registers and written once per parameter.
-template <int D>
-__global__ __launch_bounds__(PJ_THREADS) void k_project_bwd(const float* __restrict__ dproj, rgs_gaussians g,
-                                                            const uint32_t* __restrict__ count,
-                                                            const ViewTable* __restrict__ vt, rgs_gaussians_grad out) {
+// Two kernels, both a thread per Gaussian looping over the views that keep
+// it, summing in registers and writing each gradient once: the geometric
+// part (rotation, 3D covariance, EWA, screen covariance and its inverse, and
+// their adjoints, plus opacity) runs in fp64 like the forward's decision
+// chain, since for a needle-like footprint the inverse of the screen
+// covariance and the conic-to-covariance adjoint -C G C lose accuracy in
+// proportion to s00 s11 / det in fp32; the SH colour part (fp32) runs after
+// it and adds its share of the mean gradient (the view direction).  Split,
+// each kernel keeps fewer registers live than one kernel doing both.
+__global__ __launch_bounds__(PJ_THREADS) void k_project_bwd_geo(const float* __restrict__ dproj, rgs_gaussians g,
+                                                                const uint32_t* __restrict__ count,
+                                                                const ViewTable* __restrict__ vt,
+                                                                rgs_gaussians_grad out) {
     const int64_t n = g.n;
     const int64_t i = (int64_t)blockIdx.x * PJ_THREADS + threadIdx.x;
     if (i >= n) return;
-    constexpr int nc = (D + 1) * (D + 1);
     const int64_t VN = (int64_t)vt->n_views * n;
-    const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
+    const double mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
     const float ls[3] = {g.log_scales[i], g.log_scales[n + i], g.log_scales[2 * n + i]};
-    const float q4[4] = {g.quats[i], g.quats[n + i], g.quats[2 * n + i], g.quats[3 * n + i]};
+    const double q4[4] = {g.quats[i], g.quats[n + i], g.quats[2 * n + i], g.quats[3 * n + i]};
     const float logit = g.opacity[i];
-    float gmu[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, gop = 0.f;
-    float gsh[3 * nc], fsh[3 * nc];
-#pragma unroll
-    for (int k = 0; k < 3 * nc; ++k) {
-        gsh[k] = 0.f;
-        fsh[k] = g.sh[(int64_t)k * n + i];
-    }
+    double gmu[3] = {0.0, 0.0, 0.0};
+    float gop = 0.f;
 
-    // view-independent quantities
-    const float s[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
-    const float alpha = 1.0f / (1.0f + expf(-logit));
-    const float qn = sqrtf(q4[0] * q4[0] + q4[1] * q4[1] + q4[2] * q4[2] + q4[3] * q4[3]);
-    const float w = q4[0] / qn, x = q4[1] / qn, y = q4[2] / qn, z = q4[3] / qn;
-    const float Rq[3][3] = {{1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
-                            {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
-                            {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
-    float M[3][3], S[3][3];
+    // view-independent quantities (the forward's values)
+    const double s[3] = {(float)exp((double)ls[0]), (float)exp((double)ls[1]), (float)exp((double)ls[2])};
+    const float alpha = (float)(1.0 / (1.0 + exp(-(double)logit)));
+    const double qn = sqrt(((q4[0] * q4[0] + q4[1] * q4[1]) + q4[2] * q4[2]) + q4[3] * q4[3]);
+    const double w = q4[0] / qn, x = q4[1] / qn, y = q4[2] / qn, z = q4[3] / qn;
+    const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                             {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                             {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+    double S[3][3];
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) M[a][b] = Rq[a][b] * s[b];
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) S[a][b] = M[a][0] * M[b][0] + M[a][1] * M[b][1] + M[a][2] * M[b][2];
-    float GS[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+        for (int b = 0; b < 3; ++b)
+            S[a][b] = ((Rq[a][0] * s[0]) * (Rq[b][0] * s[0]) + (Rq[a][1] * s[1]) * (Rq[b][1] * s[1])) +
+                      (Rq[a][2] * s[2]) * (Rq[b][2] * s[2]);
+    double GS[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     bool any = false;
 
     for (int v = 0; v < vt->n_views; ++v) {
@@ -401,69 +402,132 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project_bwd(const float* __restr
         if (count[src] == 0u) continue;
         any = true;
         const ViewParams& V = vt->v[v];
-        float gd[9];
-        for (int c = 0; c < 9; ++c) gd[c] = dproj[c * VN + src];
-        float t[3];
-        for (int a = 0; a < 3; ++a) t[a] = V.R[3 * a] * mu[0] + V.R[3 * a + 1] * mu[1] + V.R[3 * a + 2] * mu[2] + V.t[a];
-        const float zc = t[2];
-        const float xz = t[0] / zc, yz = t[1] / zc;
-        const int clx = (xz < -V.gx) ? -1 : (xz > V.gx ? 1 : 0);
-        const int cly = (yz < -V.gy) ? -1 : (yz > V.gy ? 1 : 0);
-        const float xg = clx ? (float)clx * V.gx * zc : t[0];
-        const float yg = cly ? (float)cly * V.gy * zc : t[1];
-        const float iz = 1.0f / zc, iz2 = iz * iz;
-        const float J00 = V.fx * iz, J02 = -V.fx * xg * iz2, J11 = V.fy * iz, J12 = -V.fy * yg * iz2;
-        float T[2][3];
+        float gd[6];
+        for (int c = 0; c < 6; ++c) gd[c] = dproj[c * VN + src];
+        double R[9];
+        for (int k = 0; k < 9; ++k) R[k] = V.R[k];
+        const double fx = V.fx, fy = V.fy, gx = V.gx, gy = V.gy;
+        double t[3];
+        for (int a = 0; a < 3; ++a) t[a] = ((R[3 * a] * mu[0] + R[3 * a + 1] * mu[1]) + R[3 * a + 2] * mu[2]) + (double)V.t[a];
+        const double zc = t[2];
+        const double xz = t[0] / zc, yz = t[1] / zc;
+        const int clx = (xz < -gx) ? -1 : (xz > gx ? 1 : 0);
+        const int cly = (yz < -gy) ? -1 : (yz > gy ? 1 : 0);
+        const double xg = clx ? (double)clx * gx * zc : t[0];
+        const double yg = cly ? (double)cly * gy * zc : t[1];
+        const double iz = 1.0 / zc, iz2 = iz * iz;
+        const double J00 = fx * iz, J02 = -fx * xg * iz2, J11 = fy * iz, J12 = -fy * yg * iz2;
+        double T[2][3];
         for (int b = 0; b < 3; ++b) {
-            T[0][b] = J00 * V.R[b] + J02 * V.R[6 + b];
-            T[1][b] = J11 * V.R[3 + b] + J12 * V.R[6 + b];
+            T[0][b] = J00 * R[b] + J02 * R[6 + b];
+            T[1][b] = J11 * R[3 + b] + J12 * R[6 + b];
         }
-        float TS[2][3];
+        double TS[2][3];
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 3; ++b) TS[a][b] = T[a][0] * S[0][b] + T[a][1] * S[1][b] + T[a][2] * S[2][b];
-        const float a00 = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + 0.3f;
-        const float a01 = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
-        const float a11 = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + 0.3f;
-        const float det = a00 * a11 - a01 * a01;
-        const float idet = 1.0f / det;
-        const float Cn[2][2] = {{a11 * idet, -a01 * idet}, {-a01 * idet, a00 * idet}};
+        const double a00 = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + 0.3;
+        const double a01 = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
+        const double a11 = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + 0.3;
+        const double idet = 1.0 / (a00 * a11 - a01 * a01);
+        const double Cn[2][2] = {{a11 * idet, -a01 * idet}, {-a01 * idet, a00 * idet}};
         // conic -> screen covariance: G_S2 = -Cn G_C Cn, G_C = [[ga, gb/2], [gb/2, gc]]
-        const float GC[2][2] = {{gd[2], 0.5f * gd[3]}, {0.5f * gd[3], gd[4]}};
-        float tmp[2][2], GS2[2][2];
+        const double GC[2][2] = {{gd[2], 0.5 * gd[3]}, {0.5 * gd[3], gd[4]}};
+        double tmp[2][2], GS2[2][2];
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) tmp[a][b] = Cn[a][0] * GC[0][b] + Cn[a][1] * GC[1][b];
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) GS2[a][b] = -(tmp[a][0] * Cn[0][b] + tmp[a][1] * Cn[1][b]);
         // S2 = T S T^T: G_T = 2 G_S2 T S ; G_S += T^T G_S2 T
-        float GT[2][3];
+        double GT[2][3];
         for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 3; ++b) GT[a][b] = 2.f * (GS2[a][0] * TS[0][b] + GS2[a][1] * TS[1][b]);
+            for (int b = 0; b < 3; ++b) GT[a][b] = 2.0 * (GS2[a][0] * TS[0][b] + GS2[a][1] * TS[1][b]);
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b)
                 GS[a][b] += T[0][a] * (GS2[0][0] * T[0][b] + GS2[0][1] * T[1][b]) +
                             T[1][a] * (GS2[1][0] * T[0][b] + GS2[1][1] * T[1][b]);
         // T = J R: G_J = G_T R^T (only the four non-zero entries of J vary)
-        float GJ00 = 0.f, GJ02 = 0.f, GJ11 = 0.f, GJ12 = 0.f;
+        double GJ00 = 0.0, GJ02 = 0.0, GJ11 = 0.0, GJ12 = 0.0;
         for (int b = 0; b < 3; ++b) {
-            GJ00 += GT[0][b] * V.R[b];
-            GJ02 += GT[0][b] * V.R[6 + b];
-            GJ11 += GT[1][b] * V.R[3 + b];
-            GJ12 += GT[1][b] * V.R[6 + b];
+            GJ00 += GT[0][b] * R[b];
+            GJ02 += GT[0][b] * R[6 + b];
+            GJ11 += GT[1][b] * R[3 + b];
+            GJ12 += GT[1][b] * R[6 + b];
         }
-        float gt[3] = {0.f, 0.f, 0.f};
-        const float iz3 = iz2 * iz;
-        gt[2] += -GJ00 * V.fx * iz2 - GJ11 * V.fy * iz2;
-        gt[2] += GJ02 * 2.f * V.fx * xg * iz3 + GJ12 * 2.f * V.fy * yg * iz3;
-        const float gxg = -GJ02 * V.fx * iz2, gyg = -GJ12 * V.fy * iz2;
-        if (clx) gt[2] += gxg * (float)clx * V.gx; else gt[0] += gxg;
-        if (cly) gt[2] += gyg * (float)cly * V.gy; else gt[1] += gyg;
+        double gt[3] = {0.0, 0.0, 0.0};
+        const double iz3 = iz2 * iz;
+        gt[2] += -GJ00 * fx * iz2 - GJ11 * fy * iz2;
+        gt[2] += GJ02 * 2.0 * fx * xg * iz3 + GJ12 * 2.0 * fy * yg * iz3;
+        const double gxg = -GJ02 * fx * iz2, gyg = -GJ12 * fy * iz2;
+        if (clx) gt[2] += gxg * (double)clx * gx; else gt[0] += gxg;
+        if (cly) gt[2] += gyg * (double)cly * gy; else gt[1] += gyg;
         // screen mean mx = fx t.x / z + cx
-        gt[0] += gd[0] * V.fx * iz;
-        gt[2] += -gd[0] * V.fx * t[0] * iz2;
-        gt[1] += gd[1] * V.fy * iz;
-        gt[2] += -gd[1] * V.fy * t[1] * iz2;
-        for (int a = 0; a < 3; ++a) gmu[a] += V.R[a] * gt[0] + V.R[3 + a] * gt[1] + V.R[6 + a] * gt[2];
-        // colour
+        gt[0] += gd[0] * fx * iz;
+        gt[2] += -gd[0] * fx * t[0] * iz2;
+        gt[1] += gd[1] * fy * iz;
+        gt[2] += -gd[1] * fy * t[1] * iz2;
+        for (int a = 0; a < 3; ++a) gmu[a] += R[a] * gt[0] + R[3 + a] * gt[1] + R[6 + a] * gt[2];
+        gop += gd[5] * alpha * (1.f - alpha);
+    }
+    double gls[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
+    if (any) {
+        // S = M M^T with M = Rq diag(s): G_M = 2 G_S M
+        double GR[3][3];
+        for (int b = 0; b < 3; ++b) {
+            double gs = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double GMab = 2.0 * ((GS[a][0] * (Rq[0][b] * s[b]) + GS[a][1] * (Rq[1][b] * s[b])) +
+                                           GS[a][2] * (Rq[2][b] * s[b]));
+                gs += GMab * Rq[a][b];
+                GR[a][b] = GMab * s[b];
+            }
+            gls[b] = gs * s[b];
+        }
+        double gw = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        gy += GR[0][0] * (-4.0 * y); gz += GR[0][0] * (-4.0 * z);
+        gw += GR[0][1] * (-2.0 * z); gx += GR[0][1] * (2.0 * y); gy += GR[0][1] * (2.0 * x); gz += GR[0][1] * (-2.0 * w);
+        gw += GR[0][2] * (2.0 * y); gx += GR[0][2] * (2.0 * z); gy += GR[0][2] * (2.0 * w); gz += GR[0][2] * (2.0 * x);
+        gw += GR[1][0] * (2.0 * z); gx += GR[1][0] * (2.0 * y); gy += GR[1][0] * (2.0 * x); gz += GR[1][0] * (2.0 * w);
+        gx += GR[1][1] * (-4.0 * x); gz += GR[1][1] * (-4.0 * z);
+        gw += GR[1][2] * (-2.0 * x); gx += GR[1][2] * (-2.0 * w); gy += GR[1][2] * (2.0 * z); gz += GR[1][2] * (2.0 * y);
+        gw += GR[2][0] * (-2.0 * y); gx += GR[2][0] * (2.0 * z); gy += GR[2][0] * (-2.0 * w); gz += GR[2][0] * (2.0 * x);
+        gw += GR[2][1] * (2.0 * x); gx += GR[2][1] * (2.0 * w); gy += GR[2][1] * (2.0 * z); gz += GR[2][1] * (2.0 * y);
+        gx += GR[2][2] * (-4.0 * x); gy += GR[2][2] * (-4.0 * y);
+        const double qh[4] = {w, x, y, z}, gqh[4] = {gw, gx, gy, gz};
+        const double dot = qh[0] * gqh[0] + qh[1] * gqh[1] + qh[2] * gqh[2] + qh[3] * gqh[3];
+        for (int a = 0; a < 4; ++a) gq[a] = (gqh[a] - qh[a] * dot) / qn;
+    }
+    for (int a = 0; a < 3; ++a) { out.means[a * n + i] = (float)gmu[a]; out.log_scales[a * n + i] = (float)gls[a]; }
+    for (int a = 0; a < 4; ++a) out.quats[a * n + i] = (float)gq[a];
+    out.opacity[i] = gop;
+}
+
+// SH colour part: gradients of the SH coefficients, and the view-direction
+// share of the mean gradient added to what the geometric kernel wrote.
+template <int D>
+__global__ __launch_bounds__(PJ_THREADS) void k_project_bwd_sh(const float* __restrict__ dproj, rgs_gaussians g,
+                                                               const uint32_t* __restrict__ count,
+                                                               const ViewTable* __restrict__ vt,
+                                                               rgs_gaussians_grad out) {
+    const int64_t n = g.n;
+    const int64_t i = (int64_t)blockIdx.x * PJ_THREADS + threadIdx.x;
+    if (i >= n) return;
+    constexpr int nc = (D + 1) * (D + 1);
+    const int64_t VN = (int64_t)vt->n_views * n;
+    const float mu[3] = {g.means[i], g.means[n + i], g.means[2 * n + i]};
+    float gmu[3] = {0.f, 0.f, 0.f};
+    float gsh[3 * nc], fsh[3 * nc];
+#pragma unroll
+    for (int k = 0; k < 3 * nc; ++k) {
+        gsh[k] = 0.f;
+        fsh[k] = g.sh[(int64_t)k * n + i];
+    }
+    bool any = false;
+    for (int v = 0; v < vt->n_views; ++v) {
+        const int64_t src = (int64_t)v * n + i;
+        if (count[src] == 0u) continue;
+        any = true;
+        const ViewParams& V = vt->v[v];
+        const float gd6 = dproj[6 * VN + src], gd7 = dproj[7 * VN + src], gd8 = dproj[8 * VN + src];
         float d[3] = {mu[0] - V.o[0], mu[1] - V.o[1], mu[2] - V.o[2]};
         const float dn = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         const float idn = 1.0f / dn;
@@ -472,12 +536,13 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project_bwd(const float* __restr
         sh_eval(D, dir[0], dir[1], dir[2], Y);
         sh_grad(D, dir[0], dir[1], dir[2], GY);
         float gdir[3] = {0.f, 0.f, 0.f};
+        const float gdc[3] = {gd6, gd7, gd8};
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float acc = 0.5f;
 #pragma unroll
             for (int j = 0; j < nc; ++j) acc = fmaf(fsh[3 * j + ch], Y[j], acc);
-            const float gc = (acc > 0.f) ? gd[6 + ch] : 0.f;
+            const float gc = (acc > 0.f) ? gdc[ch] : 0.f;
 #pragma unroll
             for (int j = 0; j < nc; ++j) {
                 gsh[3 * j + ch] += Y[j] * gc;
@@ -489,36 +554,9 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project_bwd(const float* __restr
         }
         const float dg = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
         for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - dir[a] * dg) * idn;
-        gop += gd[5] * alpha * (1.f - alpha);
     }
-    if (any) {
-        // S = M M^T: G_M = 2 G_S M; M = Rq diag(s)
-        float GM[3][3];
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) GM[a][b] = 2.f * (GS[a][0] * M[0][b] + GS[a][1] * M[1][b] + GS[a][2] * M[2][b]);
-        float GR[3][3];
-        for (int b = 0; b < 3; ++b) {
-            float gs = 0.f;
-            for (int a = 0; a < 3; ++a) { gs += GM[a][b] * Rq[a][b]; GR[a][b] = GM[a][b] * s[b]; }
-            gls[b] = gs * s[b];
-        }
-        float gw = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-        gy += GR[0][0] * (-4.f * y); gz += GR[0][0] * (-4.f * z);
-        gw += GR[0][1] * (-2.f * z); gx += GR[0][1] * (2.f * y); gy += GR[0][1] * (2.f * x); gz += GR[0][1] * (-2.f * w);
-        gw += GR[0][2] * (2.f * y); gx += GR[0][2] * (2.f * z); gy += GR[0][2] * (2.f * w); gz += GR[0][2] * (2.f * x);
-        gw += GR[1][0] * (2.f * z); gx += GR[1][0] * (2.f * y); gy += GR[1][0] * (2.f * x); gz += GR[1][0] * (2.f * w);
-        gx += GR[1][1] * (-4.f * x); gz += GR[1][1] * (-4.f * z);
-        gw += GR[1][2] * (-2.f * x); gx += GR[1][2] * (-2.f * w); gy += GR[1][2] * (2.f * z); gz += GR[1][2] * (2.f * y);
-        gw += GR[2][0] * (-2.f * y); gx += GR[2][0] * (2.f * z); gy += GR[2][0] * (-2.f * w); gz += GR[2][0] * (2.f * x);
-        gw += GR[2][1] * (2.f * x); gx += GR[2][1] * (2.f * w); gy += GR[2][1] * (2.f * z); gz += GR[2][1] * (2.f * y);
-        gx += GR[2][2] * (-4.f * x); gy += GR[2][2] * (-4.f * y);
-        const float qh[4] = {w, x, y, z}, gqh[4] = {gw, gx, gy, gz};
-        const float dot = qh[0] * gqh[0] + qh[1] * gqh[1] + qh[2] * gqh[2] + qh[3] * gqh[3];
-        for (int a = 0; a < 4; ++a) gq[a] = (gqh[a] - qh[a] * dot) / qn;
-    }
-    for (int a = 0; a < 3; ++a) { out.means[a * n + i] = gmu[a]; out.log_scales[a * n + i] = gls[a]; }
-    for (int a = 0; a < 4; ++a) out.quats[a * n + i] = gq[a];
-    out.opacity[i] = gop;
+    if (any)
+        for (int a = 0; a < 3; ++a) out.means[a * n + i] += gmu[a];
 #pragma unroll
     for (int k = 0; k < 3 * nc; ++k) out.sh[(int64_t)k * n + i] = gsh[k];
 }
@@ -527,11 +565,12 @@ rgs_status project_bwd_launch(const float* dproj, const rgs_gaussians* g, const 
                               const rgs_gaussians_grad* out, hipStream_t s) {
     if (g->n <= 0) return RGS_OK;
     const unsigned grid = (unsigned)((g->n + PJ_THREADS - 1) / PJ_THREADS);
+    hipLaunchKernelGGL(k_project_bwd_geo, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out);
     switch (g->sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
-        case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
-        case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
-        default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
+        case 0: hipLaunchKernelGGL(k_project_bwd_sh<0>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
+        case 1: hipLaunchKernelGGL(k_project_bwd_sh<1>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
+        case 2: hipLaunchKernelGGL(k_project_bwd_sh<2>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
+        default: hipLaunchKernelGGL(k_project_bwd_sh<3>, dim3(grid), dim3(PJ_THREADS), 0, s, dproj, *g, count, vt, *out); break;
     }
     return launch_check();
 }

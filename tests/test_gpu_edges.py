@@ -95,13 +95,12 @@ def test_centres_on_split_planes(rast):
     assert np.abs(st.image.cpu().numpy().reshape(3, -1).T - r["img"]).max() <= 2e-4
 
 
-def test_needle_footprints(rast):
-    """Strongly elongated Gaussians (screen aspect up to ~10^6): rectangles,
-    counts and instance lists bit-exact, the image against the
-    oracle, which tests pixel-in-rectangle explicitly (the kernels do not)."""
+@pytest.fixture(scope="module")
+def needles(rast):
+    """6000 strongly elongated Gaussians (s00 s11 / det up to ~10^6), SH 1."""
     rng = np.random.default_rng(5)
     n = 6000
-    p = scenes.scene_uniform(n, seed=11, D=0, mu_s=-3.0, extent=0.6)
+    p = scenes.scene_uniform(n, seed=11, D=1, mu_s=-3.0, extent=0.6)
     ls = p["log_scales"].copy()
     ls[0] += rng.uniform(0, 4.0, n).astype(np.float32)
     ls[1] -= rng.uniform(0, 4.0, n).astype(np.float32)
@@ -109,12 +108,24 @@ def test_needle_footprints(rast):
     p["log_scales"] = ls
     W, H, L = 320, 240, 2
     cam = scenes.orbit_camera(1.6, 0.4, 0.3, W, H, z_near=0.05)
+    log("needles: GPU forward")
     dp = device_params(p)
     kd = rast.kd_partition(dp, L)
     st = rast.forward(dp, kd, [cam], EPS_T)
+    torch.cuda.synchronize()
     okd = oracle.kd_partition(p["means"], p["log_scales"], L)
     order, rank_of = oracle.cell_order(L, okd["split"], cam["o"])
     pr = oracle.project(p, cam, okd, 0)
+    return p, cam, L, dp, kd, st, okd, order, rank_of, pr
+
+
+def test_needle_footprints(needles):
+    """Needles: rectangles, counts and instance lists bit-exact; the image
+    against the oracle (which tests pixel-in-rectangle explicitly, the kernels
+    do not) within 2e-4."""
+    p, cam, L, dp, kd, st, okd, order, rank_of, pr = needles
+    n = p["means"].shape[1]
+    W, H = cam["W"], cam["H"]
     vis = pr["vis"] == 1
     d = pr["dec32"][vis].astype(np.float64)
     assert (1 + d[:, 8] ** 2 * d[:, 2] / d[:, 9]).max() > 1e4  # s00 s11 / det
@@ -127,7 +138,33 @@ def test_needle_footprints(rast):
     src = (st.bins["vals"][:n_inst].cpu().numpy().view(np.uint64) >> np.uint64(32)).astype(np.int64)
     assert np.array_equal(keys, okeys) and np.array_equal(src % n, ogids.astype(np.int64))
     r = oracle.render(pr, cam, okd, order, oracle.all_pixels(W, H), EPS_T)
-    assert np.abs(st.image.cpu().numpy().reshape(3, -1).T - r["img"]).max() <= 2e-4
+    err = np.abs(st.image.cpu().numpy().reshape(3, -1).T - r["img"]).max()
+    log("needles: image max err %.2e" % err)
+    assert err <= 2e-4
+
+
+def test_needle_gradients(rast, needles):
+    """Needles: 2D and parameter gradients of a seeded linear objective within
+    1e-3 (relative) of the oracle's fp64 backward."""
+    p, cam, L, dp, kd, st, okd, order, rank_of, pr = needles
+    n = p["means"].shape[1]
+    W, H = cam["W"], cam["H"]
+    rng = np.random.default_rng(9)
+    dimg = rng.normal(size=(3, H * W)).astype(np.float32) * 1e-3
+    dTf = rng.normal(size=(H * W,)).astype(np.float32) * 1e-3
+    g = rast.backward(st, dp, torch.from_numpy(dimg.ravel()).cuda(), torch.from_numpy(dTf).cuda())
+    torch.cuda.synchronize()
+    dproj = g["_dproj"][: 9 * n].view(9, n).cpu().numpy().T
+    g2d = oracle.render_bwd(pr, cam, okd, order, oracle.all_pixels(W, H), dimg.T.astype(np.float64),
+                            dTf.astype(np.float64), EPS_T)
+    for c in range(9):
+        ok, info = grad_close(dproj[:, c], g2d[:, c], 1e-3, "d2d[%d]" % c)
+        assert ok, info
+    og = oracle.project_bwd(p, cam, pr, g2d)
+    for k in ("means", "log_scales", "quats", "opacity", "sh"):
+        ok, info = grad_close(g[k].cpu().numpy(), og[k], 1e-3, k)
+        log(str(info))
+        assert ok, info
 
 
 # ---------------------------------------------------------------- full size
