@@ -40,39 +40,40 @@ __device__ __forceinline__ void sh_eval(int D, float x, float y, float z, float*
     Y[15] = -0.5900435899266435f * x * (xx - 3.0f * yy);
 }
 
-// Gradient of the polynomial forms above w.r.t. (x, y, z).
-__device__ __forceinline__ void sh_grad(int D, float x, float y, float z, float (*G)[3]) {
-    G[0][0] = G[0][1] = G[0][2] = 0.f;
+// sum_j h_j grad Y_j (x, y, z) for the polynomial forms above, accumulated
+// into g without materialising the 16 gradients.
+__device__ __forceinline__ void sh_grad_dot(int D, float x, float y, float z, const float* h, float g[3]) {
     if (D < 1) return;
     const float c1 = 0.4886025119029199f;
-    G[1][0] = 0.f; G[1][1] = -c1; G[1][2] = 0.f;
-    G[2][0] = 0.f; G[2][1] = 0.f; G[2][2] = c1;
-    G[3][0] = -c1; G[3][1] = 0.f; G[3][2] = 0.f;
+    g[1] += -c1 * h[1];
+    g[2] += c1 * h[2];
+    g[0] += -c1 * h[3];
     if (D < 2) return;
     const float a = 1.0925484305920792f, b = 0.31539156525252005f, c = 0.5462742152960396f;
-    G[4][0] = a * y; G[4][1] = a * x; G[4][2] = 0.f;
-    G[5][0] = 0.f; G[5][1] = -a * z; G[5][2] = -a * y;
-    G[6][0] = -2.f * b * x; G[6][1] = -2.f * b * y; G[6][2] = 4.f * b * z;
-    G[7][0] = -a * z; G[7][1] = 0.f; G[7][2] = -a * x;
-    G[8][0] = 2.f * c * x; G[8][1] = -2.f * c * y; G[8][2] = 0.f;
+    g[0] += a * y * h[4]; g[1] += a * x * h[4];
+    g[1] += -a * z * h[5]; g[2] += -a * y * h[5];
+    g[0] += -2.f * b * x * h[6]; g[1] += -2.f * b * y * h[6]; g[2] += 4.f * b * z * h[6];
+    g[0] += -a * z * h[7]; g[2] += -a * x * h[7];
+    g[0] += 2.f * c * x * h[8]; g[1] += -2.f * c * y * h[8];
     if (D < 3) return;
     const float k0 = -0.5900435899266435f, k1 = 2.890611442640554f, k2 = -0.4570457994644658f,
                 k3 = 0.3731763325901154f, k5 = 1.445305721320277f;
     const float xx = x * x, yy = y * y, zz = z * z;
     // y (3x^2 - y^2)
-    G[9][0] = k0 * 6.f * x * y; G[9][1] = k0 * (3.f * xx - 3.f * yy); G[9][2] = 0.f;
+    g[0] += k0 * 6.f * x * y * h[9]; g[1] += k0 * (3.f * xx - 3.f * yy) * h[9];
     // x y z
-    G[10][0] = k1 * y * z; G[10][1] = k1 * x * z; G[10][2] = k1 * x * y;
+    g[0] += k1 * y * z * h[10]; g[1] += k1 * x * z * h[10]; g[2] += k1 * x * y * h[10];
     // y (4z^2 - x^2 - y^2)
-    G[11][0] = k2 * (-2.f * x * y); G[11][1] = k2 * (4.f * zz - xx - 3.f * yy); G[11][2] = k2 * 8.f * y * z;
+    g[0] += k2 * (-2.f * x * y) * h[11]; g[1] += k2 * (4.f * zz - xx - 3.f * yy) * h[11]; g[2] += k2 * 8.f * y * z * h[11];
     // z (2z^2 - 3x^2 - 3y^2)
-    G[12][0] = k3 * (-6.f * x * z); G[12][1] = k3 * (-6.f * y * z); G[12][2] = k3 * (6.f * zz - 3.f * xx - 3.f * yy);
+    g[0] += k3 * (-6.f * x * z) * h[12]; g[1] += k3 * (-6.f * y * z) * h[12];
+    g[2] += k3 * (6.f * zz - 3.f * xx - 3.f * yy) * h[12];
     // x (4z^2 - x^2 - y^2)
-    G[13][0] = k2 * (4.f * zz - 3.f * xx - yy); G[13][1] = k2 * (-2.f * x * y); G[13][2] = k2 * 8.f * x * z;
+    g[0] += k2 * (4.f * zz - 3.f * xx - yy) * h[13]; g[1] += k2 * (-2.f * x * y) * h[13]; g[2] += k2 * 8.f * x * z * h[13];
     // z (x^2 - y^2)
-    G[14][0] = k5 * 2.f * x * z; G[14][1] = k5 * (-2.f * y * z); G[14][2] = k5 * (xx - yy);
+    g[0] += k5 * 2.f * x * z * h[14]; g[1] += k5 * (-2.f * y * z) * h[14]; g[2] += k5 * (xx - yy) * h[14];
     // x (x^2 - 3y^2)
-    G[15][0] = k0 * (3.f * xx - 3.f * yy); G[15][1] = k0 * (-6.f * x * y); G[15][2] = 0.f;
+    g[0] += k0 * (3.f * xx - 3.f * yy) * h[15]; g[1] += k0 * (-6.f * x * y) * h[15];
 }
 
 struct Proj32 {
@@ -532,26 +533,27 @@ __global__ __launch_bounds__(PJ_THREADS) void k_project_bwd_sh(const float* __re
         const float dn = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         const float idn = 1.0f / dn;
         const float dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
-        float Y[16], GY[16][3];
+        float Y[16];
         sh_eval(D, dir[0], dir[1], dir[2], Y);
-        sh_grad(D, dir[0], dir[1], dir[2], GY);
-        float gdir[3] = {0.f, 0.f, 0.f};
         const float gdc[3] = {gd6, gd7, gd8};
+        float gc[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             float acc = 0.5f;
 #pragma unroll
             for (int j = 0; j < nc; ++j) acc = fmaf(fsh[3 * j + ch], Y[j], acc);
-            const float gc = (acc > 0.f) ? gdc[ch] : 0.f;
-#pragma unroll
-            for (int j = 0; j < nc; ++j) {
-                gsh[3 * j + ch] += Y[j] * gc;
-                const float fj = fsh[3 * j + ch] * gc;
-                gdir[0] += fj * GY[j][0];
-                gdir[1] += fj * GY[j][1];
-                gdir[2] += fj * GY[j][2];
-            }
+            gc[ch] = (acc > 0.f) ? gdc[ch] : 0.f;  // the colour's clamp at 0
         }
+        // d colour / d dir = sum_j (sum_ch gc_ch f_j,ch) grad Y_j
+        float h[16];
+#pragma unroll
+        for (int j = 0; j < nc; ++j) {
+            h[j] = (fsh[3 * j] * gc[0] + fsh[3 * j + 1] * gc[1]) + fsh[3 * j + 2] * gc[2];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) gsh[3 * j + ch] += Y[j] * gc[ch];
+        }
+        float gdir[3] = {0.f, 0.f, 0.f};
+        sh_grad_dot(D, dir[0], dir[1], dir[2], h, gdir);
         const float dg = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
         for (int a = 0; a < 3; ++a) gmu[a] += (gdir[a] - dir[a] * dg) * idn;
     }
