@@ -129,12 +129,17 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
 // (cell, tile) from the index inside the pair (cells ascending, then the row
 // spans' tiles top to bottom, left to right), so writes are coalesced
 // whatever the per-pair counts.  Small rectangles carry their spans in the
-// record's descriptor; larger ones recompute them with the projection's code.
+// record's descriptor.  For larger ones the block computes each row's span
+// once, rows spread over the threads, into an LDS pool with per-pair running
+// sums, and an instance finds its row by binary search; when a chunk's large
+// rectangles hold more rows than the pool, the chunk is taken in runs of
+// consecutive pairs whose rows fit.
 __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict__ pair_src, const uint32_t* __restrict__ n_dev,
                                                      const uint32_t* __restrict__ pair_off, const float* __restrict__ rec,
                                                      const uint64_t* __restrict__ cellmask, int64_t n_gauss,
                                                      const ViewTable* __restrict__ vt, uint32_t* __restrict__ keys,
                                                      uint64_t* __restrict__ vals) {
+    constexpr int ROWPOOL = 2048;  // rows of one run; a rectangle has at most 256 tile rows
     __shared__ uint32_t s_off[BN_THREADS + 1];
     __shared__ uint32_t s_src[BN_THREADS];
     __shared__ uint64_t s_mask[BN_THREADS];
@@ -143,87 +148,137 @@ __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict_
     // per pair: tiles per cell, the view's first global tile and tiles per row
     __shared__ uint32_t s_nt[BN_THREADS], s_vto[BN_THREADS], s_vtx[BN_THREADS];
     __shared__ uint8_t s_view[BN_THREADS];
+    __shared__ uint32_t s_rows[BN_THREADS], s_rend[BN_THREADS];  // pooled rows per pair, inclusive scan
+    __shared__ uint32_t s_rcum[ROWPOOL];  // a row's tile count, then the pair's running sum
+    __shared__ int16_t s_rc0[ROWPOOL];    // the row's first tile column
+    __shared__ uint32_t s_wsum[BN_THREADS / 64];
     const int64_t npairs = (int64_t)*n_dev;
     const int L = vt->L;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     for (int64_t r0 = (int64_t)blockIdx.x * BN_THREADS; r0 < npairs; r0 += (int64_t)gridDim.x * BN_THREADS) {
         const int nb = (int)((npairs - r0) < BN_THREADS ? (npairs - r0) : BN_THREADS);
-        const int t = threadIdx.x;
+        uint32_t rows = 0;
         if (t < nb) {
             const uint32_t src = pair_src[r0 + t];
             const float4 r4 = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS)[3];
             const uint64_t m = cellmask[src];
             const int v = (int)(src / (uint64_t)n_gauss);  // once per pair
             const ViewParams& V = vt->v[v];
+            const uint64_t desc = (uint64_t)__float_as_uint(r4.z) | ((uint64_t)__float_as_uint(r4.w) << 32);
+            const uint32_t ry = __float_as_uint(r4.y);
             s_src[t] = src;
             s_mask[t] = m;
-            s_rect[t] = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
-            s_desc[t] = (uint64_t)__float_as_uint(r4.z) | ((uint64_t)__float_as_uint(r4.w) << 32);
+            s_rect[t] = make_uint2(__float_as_uint(r4.x), ry);
+            s_desc[t] = desc;
             s_off[t] = pair_off[r0 + t];
             s_vto[t] = V.tile_offset;
             s_vtx[t] = (uint32_t)V.tiles_x;
             s_view[t] = (uint8_t)v;
+            if (desc == RGS_NO_SPANS)
+                rows = (uint32_t)(((int)(int16_t)(ry >> 16) >> 4) - ((int)(int16_t)(ry & 0xffffu) >> 4) + 1);
         }
+        s_rows[t] = rows;
         if (t == 0) s_off[nb] = pair_off[r0 + nb];
         if (t > nb) s_off[t] = 0xffffffffu;  // past the chunk: above every instance index
+        {  // inclusive scan of the pooled rows over the chunk's pairs
+            const uint32_t inc = wave_incl_scan(rows);
+            if (lane == 63) s_wsum[w] = inc;
+            __syncthreads();
+            uint32_t before = 0;
+            for (int k = 0; k < w; ++k) before += s_wsum[k];
+            s_rend[t] = before + inc;
+        }
         __syncthreads();
         // tiles per cell = the pair's instances / its cells (no second gather of the counts)
         if (t < nb) s_nt[t] = (s_off[t + 1] - s_off[t]) / (uint32_t)__popcll(s_mask[t]);
-        __syncthreads();
-        const uint32_t j0 = s_off[0], j1 = s_off[nb];
-        for (uint32_t j = j0 + t; j < j1; j += BN_THREADS) {
-            // last pair with s_off[p] <= j (offsets increase; entries past nb are ~0)
-            int lo = 0;
-#pragma unroll
-            for (int step = BN_THREADS / 2; step > 0; step >>= 1)
-                if (s_off[lo + step] <= j) lo += step;
-            const uint32_t nt = s_nt[lo];
-            const uint32_t q = j - s_off[lo];
-            const uint32_t c = udiv_small(q, nt);
-            const uint32_t tt = q - c * nt;  // index among the pair's tiles, rows top to bottom
-            const uint2 rr = s_rect[lo];
-            const int x_lo = (int)(int16_t)(rr.x & 0xffffu), x_hi = (int)(int16_t)(rr.x >> 16);
-            const int y_lo = (int)(int16_t)(rr.y & 0xffffu), y_hi = (int)(int16_t)(rr.y >> 16);
-            const int tx0 = x_lo >> 4, ty0 = y_lo >> 4;
-            int tx = tx0, ty = ty0;
-            const uint64_t desc = s_desc[lo];
-            if (desc != RGS_NO_SPANS) {
-                // row of tile tt by byte-wise prefix sums of the 8 row lengths
-                // (each < 16, total < 128): byte k of `pre` = tiles in rows 0..k,
-                // and the high bit of byte k of `ge` is set iff pre_k > tt
-                constexpr uint64_t ONES = 0x0101010101010101ull, HIGH = 0x8080808080808080ull;
-                const uint64_t lens = (desc >> 4) & 0x0f0f0f0f0f0f0f0full;
-                const uint64_t pre = lens * ONES;
-                const uint64_t ge = ((pre | HIGH) - (uint64_t)(tt + 1u) * ONES) & HIGH;
-                const int k = ge ? (__builtin_ctzll(ge) >> 3) : 7;
-                const uint32_t before = ((uint32_t)(pre >> (8 * k)) & 0xffu) - ((uint32_t)(lens >> (8 * k)) & 0xffu);
-                tx = tx0 + (int)((uint32_t)(desc >> (8 * k)) & 15u) + (int)(tt - before);
-                ty = ty0 + k;
-            } else {
-                // large rectangle: the spans are recomputed from the record
-                // (mx, my, ca, k | e, alpha, tau, z)
-                const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)s_src[lo] * RGS_REC_FLOATS);
-                const float4 a = rp[0], b = rp[1];
+        for (int p0 = 0; p0 < nb;) {
+            // the longest run of pairs from p0 whose pooled rows fit (at least p0 itself)
+            const uint32_t rbase = p0 > 0 ? s_rend[p0 - 1] : 0u;
+            int lo = p0 + 1, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_rend[mid - 1] - rbase <= (uint32_t)ROWPOOL) lo = mid; else hi = mid - 1;
+            }
+            const int p1 = lo;
+            const uint32_t nrows = s_rend[p1 - 1] - rbase;
+            // spans of the run's pooled rows, one row per thread
+            for (uint32_t r = t; r < nrows; r += BN_THREADS) {
+                const uint32_t g = rbase + r;
+                int a = p0, b = p1 - 1;  // owner: the first pair whose scan end exceeds g
+                while (a < b) {
+                    const int mid = (a + b) >> 1;
+                    if (s_rend[mid] > g) b = mid; else a = mid + 1;
+                }
+                const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)s_src[a] * RGS_REC_FLOATS);
+                const float4 ra = rp[0], rb = rp[1];
                 SpanPre sp;
-                span_pre(a.x, a.y, a.z, a.w, b.x, b.z, sp);
-                uint32_t rem = tt;
-#pragma unroll 1
-                for (int y = ty0; y <= (y_hi >> 4); ++y) {
-                    const int2 cs = row_span(sp, x_lo, x_hi, y_lo, y_hi, y);
-                    const uint32_t len = cs.x <= cs.y ? (uint32_t)(cs.y - cs.x + 1) : 0u;
-                    if (rem < len) {
-                        tx = cs.x + (int)rem;
-                        ty = y;
-                        break;
-                    }
-                    rem -= len;
+                span_pre(ra.x, ra.y, ra.z, ra.w, rb.x, rb.z, sp);
+                const uint2 rr = s_rect[a];
+                const int x_lo = (int)(int16_t)(rr.x & 0xffffu), x_hi = (int)(int16_t)(rr.x >> 16);
+                const int y_lo = (int)(int16_t)(rr.y & 0xffffu), y_hi = (int)(int16_t)(rr.y >> 16);
+                const int row = (int)(g - (s_rend[a] - s_rows[a]));
+                const int2 cs = row_span(sp, x_lo, x_hi, y_lo, y_hi, (y_lo >> 4) + row);
+                s_rcum[r] = cs.x <= cs.y ? (uint32_t)(cs.y - cs.x + 1) : 0u;
+                s_rc0[r] = (int16_t)cs.x;
+            }
+            __syncthreads();
+            if (t >= p0 && t < p1 && s_rows[t] > 0u) {  // running sums per pooled pair
+                const uint32_t b0 = s_rend[t] - s_rows[t] - rbase;
+                uint32_t run = 0;
+                for (uint32_t r = 0; r < s_rows[t]; ++r) {
+                    run += s_rcum[b0 + r];
+                    s_rcum[b0 + r] = run;
                 }
             }
-            const int cell = nth_set_bit(s_mask[lo], (int)c);
-            keys[j] = ((s_vto[lo] + (uint32_t)ty * s_vtx[lo] + (uint32_t)tx) << L) |
-                      (uint32_t)vt->v[s_view[lo]].rank_of_cell[cell];
-            vals[j] = ((uint64_t)s_src[lo] << 32) | j;
+            __syncthreads();
+            const uint32_t j0 = s_off[p0], j1 = s_off[p1];
+            for (uint32_t j = j0 + t; j < j1; j += BN_THREADS) {
+                // last pair with s_off[p] <= j (offsets increase; entries past nb are ~0)
+                int pl = 0;
+#pragma unroll
+                for (int step = BN_THREADS / 2; step > 0; step >>= 1)
+                    if (s_off[pl + step] <= j) pl += step;
+                const uint32_t nt = s_nt[pl];
+                const uint32_t q = j - s_off[pl];
+                const uint32_t c = udiv_small(q, nt);
+                const uint32_t tt = q - c * nt;  // index among the pair's tiles, rows top to bottom
+                const uint2 rr = s_rect[pl];
+                const int tx0 = (int)(int16_t)(rr.x & 0xffffu) >> 4;
+                const int ty0 = (int)(int16_t)(rr.y & 0xffffu) >> 4;
+                int tx, ty;
+                const uint64_t desc = s_desc[pl];
+                if (desc != RGS_NO_SPANS) {
+                    // row of tile tt by byte-wise prefix sums of the 8 row lengths
+                    // (each < 16, total < 128): byte k of `pre` = tiles in rows 0..k,
+                    // and the high bit of byte k of `ge` is set iff pre_k > tt
+                    constexpr uint64_t ONES = 0x0101010101010101ull, HIGH = 0x8080808080808080ull;
+                    const uint64_t lens = (desc >> 4) & 0x0f0f0f0f0f0f0f0full;
+                    const uint64_t pre = lens * ONES;
+                    const uint64_t ge = ((pre | HIGH) - (uint64_t)(tt + 1u) * ONES) & HIGH;
+                    const int k = ge ? (__builtin_ctzll(ge) >> 3) : 7;
+                    const uint32_t before = ((uint32_t)(pre >> (8 * k)) & 0xffu) - ((uint32_t)(lens >> (8 * k)) & 0xffu);
+                    tx = tx0 + (int)((uint32_t)(desc >> (8 * k)) & 15u) + (int)(tt - before);
+                    ty = ty0 + k;
+                } else {
+                    // pooled rows: the first row whose running sum exceeds tt
+                    const uint32_t b0 = s_rend[pl] - s_rows[pl] - rbase;
+                    int a = 0, b = (int)s_rows[pl] - 1;
+                    while (a < b) {
+                        const int mid = (a + b) >> 1;
+                        if (s_rcum[b0 + mid] > tt) b = mid; else a = mid + 1;
+                    }
+                    const uint32_t before = a > 0 ? s_rcum[b0 + a - 1] : 0u;
+                    tx = (int)s_rc0[b0 + a] + (int)(tt - before);
+                    ty = ty0 + a;
+                }
+                const int cell = nth_set_bit(s_mask[pl], (int)c);
+                keys[j] = ((s_vto[pl] + (uint32_t)ty * s_vtx[pl] + (uint32_t)tx) << L) |
+                          (uint32_t)vt->v[s_view[pl]].rank_of_cell[cell];
+                vals[j] = ((uint64_t)s_src[pl] << 32) | j;
+            }
+            __syncthreads();  // the pool is reused by the next run
+            p0 = p1;
         }
-        __syncthreads();  // LDS is reused by the next chunk
     }
 }
 
@@ -233,12 +288,15 @@ __global__ __launch_bounds__(BN_THREADS) void k_fill_u32(uint32_t* __restrict__ 
 }
 
 // Slot boundaries on the dense (tile, rank) table.
+// (A key at or past the table's end would mean an emission bug; it is skipped
+// rather than written out of bounds.)
 __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __restrict__ keys,
-                                                            const uint32_t* __restrict__ n_dev,
+                                                            const uint32_t* __restrict__ n_dev, int64_t dense,
                                                             uint32_t* __restrict__ dstart, uint32_t* __restrict__ dend) {
     const int64_t n_inst = (int64_t)*n_dev;
     for (int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x; i < n_inst; i += (int64_t)gridDim.x * BN_THREADS) {
         const uint32_t k = keys[i];
+        if ((int64_t)k >= dense) continue;
         if (i == 0 || keys[i - 1] != k) dstart[k] = (uint32_t)i;
         if (i == n_inst - 1 || keys[i + 1] != k) dend[k] = (uint32_t)(i + 1);
     }
@@ -456,7 +514,8 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
 
     // 4. slots
     hipLaunchKernelGGL(k_fill_u32, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, 0xffffffffu);
-    if (n_inst > 0) hipLaunchKernelGGL(k_slot_bounds, dgrid(n_inst), dim3(BN_THREADS), 0, s, bins->keys, &cnt[1], dstart, dend);
+    if (n_inst > 0)
+        hipLaunchKernelGGL(k_slot_bounds, dgrid(n_inst), dim3(BN_THREADS), 0, s, bins->keys, &cnt[1], dense, dstart, dend);
     hipLaunchKernelGGL(k_slot_flags, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, dflag);
     if ((st = exclusive_scan_u32(dflag, sidx, dense, &cnt[2], sws, s)) != RGS_OK) return st;
     hipLaunchKernelGGL(k_slot_compact, grid(dense), dim3(BN_THREADS), 0, s, dstart, dend, sidx, dense, bins->slot_key,

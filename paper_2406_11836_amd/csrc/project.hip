@@ -251,6 +251,33 @@ __device__ __forceinline__ uint64_t cellset32(const Proj32& p, const int r[4], c
     return mask;
 }
 
+// Conservative fp32 screen test ahead of the fp64 chain: false only where
+// the chain would find z <= z_near or an empty rectangle, so skipping those
+// pairs changes no output.  Bounds: tau <= 9; s00 <= (|J00| + |J02|)^2 smax^2
+// + 0.3 (camera rotation rows are unit vectors, the 3D covariance's largest
+// eigenvalue is smax^2), s11 alike; the rectangle pad's 2^-20 rk sqrt(tau s00)
+// term is below 2^-17 (Bx + By) since det >= 0.3 max(s00, s11); then 1%, 2 px
+// and 1e-5 |mx| for the fp32 evaluation.  The depth test allows the fp32
+// camera transform's rounding (< 1e-6 of the sum of its terms).
+__device__ __forceinline__ bool screen_may_hit(float mu0, float mu1, float mu2, float smax, const ViewParams& V) {
+    const float t0 = ((V.R[0] * mu0 + V.R[1] * mu1) + V.R[2] * mu2) + V.t[0];
+    const float t1 = ((V.R[3] * mu0 + V.R[4] * mu1) + V.R[5] * mu2) + V.t[1];
+    const float t2 = ((V.R[6] * mu0 + V.R[7] * mu1) + V.R[8] * mu2) + V.t[2];
+    const float az = ((fabsf(V.R[6] * mu0) + fabsf(V.R[7] * mu1)) + fabsf(V.R[8] * mu2)) + fabsf(V.t[2]);
+    if (t2 + 1e-6f * az < V.znear) return false;
+    const float iz = 1.0f / t2;
+    const float xz = t0 * iz, yz = t1 * iz;
+    const float jx = V.fx * iz * (1.0f + fabsf(fminf(fmaxf(xz, -V.gx), V.gx)));
+    const float jy = V.fy * iz * (1.0f + fabsf(fminf(fmaxf(yz, -V.gy), V.gy)));
+    const float s2 = smax * smax;
+    const float Bx = jx * jx * s2 + 0.3f, By = jy * jy * s2 + 0.3f;
+    const float mx = V.fx * xz + V.cx, my = V.fy * yz + V.cy;
+    const float ex = 3.03f * sqrtf(Bx) + 0x1p-17f * (Bx + By) + 2.0f + 1e-5f * fabsf(mx);
+    const float ey = 3.03f * sqrtf(By) + 0x1p-17f * (Bx + By) + 2.0f + 1e-5f * fabsf(my);
+    // NaN compares false: such a pair is left to the exact chain
+    return !(mx + ex < 0.0f || mx - ex > (float)V.W || my + ey < 0.0f || my - ey > (float)V.H);
+}
+
 template <int D>
 __global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, const ViewTable* __restrict__ vt,
                                                         const float* __restrict__ split,
@@ -273,6 +300,14 @@ __global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, cons
     }
     const float mu0 = g.means[i], mu1 = g.means[n + i], mu2 = g.means[2 * n + i];
     const float ls0 = g.log_scales[i], ls1 = g.log_scales[n + i], ls2 = g.log_scales[2 * n + i];
+    // pairs that cannot reach their image skip the fp64 chain (count 0, as the chain would give)
+    const float smax = expf(fmaxf(fmaxf(ls0, ls1), ls2)) * 1.001f;
+    for (int v = 0; v < vt->n_views; ++v)
+        if (((view_ok >> v) & 1u) && !screen_may_hit(mu0, mu1, mu2, smax, vt->v[v])) {
+            out.count[(int64_t)v * n + i] = 0u;
+            view_ok &= ~(1u << v);
+        }
+    if (view_ok == 0u) return;
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
     const float logit = g.opacity[i];
     Pre32 pre;
