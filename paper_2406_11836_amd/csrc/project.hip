@@ -302,12 +302,14 @@ __global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, cons
     const float ls0 = g.log_scales[i], ls1 = g.log_scales[n + i], ls2 = g.log_scales[2 * n + i];
     // pairs that cannot reach their image skip the fp64 chain (count 0, as the chain would give)
     const float smax = expf(fmaxf(fmaxf(ls0, ls1), ls2)) * 1.001f;
+    uint32_t scr = 0u;  // views whose screen test passes
     for (int v = 0; v < vt->n_views; ++v)
-        if (((view_ok >> v) & 1u) && !screen_may_hit(mu0, mu1, mu2, smax, vt->v[v])) {
-            out.count[(int64_t)v * n + i] = 0u;
-            view_ok &= ~(1u << v);
-        }
-    if (view_ok == 0u) return;
+        if (screen_may_hit(mu0, mu1, mu2, smax, vt->v[v])) scr |= 1u << v;
+    if ((view_ok & scr) == 0u) {
+        for (int v = 0; v < vt->n_views; ++v)
+            if ((view_ok >> v) & 1u) out.count[(int64_t)v * n + i] = 0u;
+        return;
+    }
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
     const float logit = g.opacity[i];
     Pre32 pre;
@@ -318,7 +320,8 @@ __global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, cons
         const ViewParams& V = vt->v[v];
         const int64_t src = (int64_t)v * n + i;
         Proj32 p;
-        proj32(mu0, mu1, mu2, pre, V, p);
+        p.vis = false;
+        if ((scr >> v) & 1u) proj32(mu0, mu1, mu2, pre, V, p);
         int r[4] = {0, 0, 0, 0};
         bool ok = p.vis && rect32(p, V, r);
         float4* rec = reinterpret_cast<float4*>(out.rec + src * RGS_REC_FLOATS);
