@@ -33,27 +33,34 @@ __global__ __launch_bounds__(LS_THREADS) void k_l1_only(const float* __restrict_
     }
 }
 
-// Tiled SSIM: one 256-thread block per 32x32 output tile of one channel,
+// Tiled SSIM: one 256-thread block per 32x16 output tile of one channel,
 // with the 5-pixel halo staged in LDS; both separable passes run from LDS.
-static constexpr int TS = 32, HALO = 5, TW = TS + 2 * HALO;  // 42
+// (32x16 rather than 32x32: 25 KB of LDS per block instead of 41 KB, so that
+// five blocks share a CU instead of three and the passes of one block
+// overlap the loads of another.)
+static constexpr int HALO = 5;
+static constexpr int TS = 32, TW = TS + 2 * HALO;       // output / staged columns (42)
+static constexpr int TSY = 16, TH = TSY + 2 * HALO;     // output / staged rows (26)
+static constexpr int RPT = TSY / 8;                      // output rows per thread in the vertical pass
+static constexpr int VWIN = RPT + 2 * HALO;              // its window of horizontal results
 
 // Forward: SSIM map terms and d SSIM / d (mu_x, E[x^2], E[xy]) per pixel,
 // plus block sums of the SSIM map and of |x - y|.
 __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __restrict__ x, const float* __restrict__ y,
                                                                int H, int W, Win11 win, float* __restrict__ d3,
                                                                float* __restrict__ part) {
-    __shared__ float sx[TW * TW], sy[TW * TW];
-    __shared__ float hm[5][TW * TS];
+    __shared__ float sx[TH * TW], sy[TH * TW];
+    __shared__ float hm[5][TH * TS];
     __shared__ float s_w[2][4];
-    const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TS - 1) / TS;
+    const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TSY - 1) / TSY;
     const int b = blockIdx.x;
     const int ch = b / (tiles_x * tiles_y);
     const int tt = b % (tiles_x * tiles_y);
-    const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TS;
+    const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TSY;
     const int64_t HW = (int64_t)H * W;
     const float* xc = x + ch * HW;
     const float* yc = y + ch * HW;
-    for (int k = threadIdx.x; k < TW * TW; k += LS_THREADS) {
+    for (int k = threadIdx.x; k < TH * TW; k += LS_THREADS) {
         const int r = k / TW, c = k % TW;
         const int gy = y0 + r - HALO, gx = x0 + c - HALO;
         const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
@@ -63,25 +70,28 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
     __syncthreads();
     // horizontal pass: a thread takes 4 consecutive outputs of one row from a
     // 14-value window in registers (the taps of each output in the same order)
-    for (int k = threadIdx.x; k < TW * (TS / 4); k += LS_THREADS) {
+    for (int k = threadIdx.x; k < TH * (TS / 4); k += LS_THREADS) {
         const int r = k >> 3, c0 = (k & 7) * 4;
-        float xv[14], yv[14];
+        float xv[14], yv[14], xx[14], yy[14], xy[14];
 #pragma unroll
         for (int j = 0; j < 14; ++j) {
             xv[j] = sx[r * TW + c0 + j];
             yv[j] = sy[r * TW + c0 + j];
+            xx[j] = xv[j] * xv[j];  // products once per input, not once per tap
+            yy[j] = yv[j] * yv[j];
+            xy[j] = xv[j] * yv[j];
         }
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
 #pragma unroll
             for (int t = 0; t < 11; ++t) {
-                const float xa = xv[o + t], ya = yv[o + t], w = win.w[t];
-                a0 = fmaf(w, xa, a0);
-                a1 = fmaf(w, ya, a1);
-                a2 = fmaf(w, xa * xa, a2);
-                a3 = fmaf(w, ya * ya, a3);
-                a4 = fmaf(w, xa * ya, a4);
+                const float w = win.w[t];
+                a0 = fmaf(w, xv[o + t], a0);
+                a1 = fmaf(w, yv[o + t], a1);
+                a2 = fmaf(w, xx[o + t], a2);
+                a3 = fmaf(w, yy[o + t], a3);
+                a4 = fmaf(w, xy[o + t], a4);
             }
             const int q = r * TS + c0 + o;
             hm[0][q] = a0; hm[1][q] = a1; hm[2][q] = a2; hm[3][q] = a3; hm[4][q] = a4;
@@ -89,17 +99,17 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
     }
     __syncthreads();
     float l1 = 0.f, ss = 0.f;
-    // vertical pass: thread (column c, row group) takes 4 consecutive rows
+    // vertical pass: thread (column c, row group) takes RPT consecutive rows
     {
-        const int c = threadIdx.x & 31, r0 = (threadIdx.x >> 5) * 4;
-        float mom[5][4];
+        const int c = threadIdx.x & 31, r0 = (threadIdx.x >> 5) * RPT;
+        float mom[5][RPT];
 #pragma unroll
         for (int mm = 0; mm < 5; ++mm) {
-            float hv[14];
+            float hv[VWIN];
 #pragma unroll
-            for (int j = 0; j < 14; ++j) hv[j] = hm[mm][(r0 + j) * TS + c];
+            for (int j = 0; j < VWIN; ++j) hv[j] = hm[mm][(r0 + j) * TS + c];
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
+            for (int o = 0; o < RPT; ++o) {
                 float a = 0.f;
 #pragma unroll
                 for (int t = 0; t < 11; ++t) a = fmaf(win.w[t], hv[o + t], a);
@@ -107,7 +117,7 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
             }
         }
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
+        for (int o = 0; o < RPT; ++o) {
             const int r = r0 + o;
             const int gy = y0 + r, gx = x0 + c;
             if (gy >= H || gx >= W) continue;
@@ -145,16 +155,16 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
 __global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __restrict__ x, const float* __restrict__ y,
                                                                const float* __restrict__ d3, int H, int W, Win11 win,
                                                                float invN, float sc, float* __restrict__ dx) {
-    __shared__ float sd[3][TW * TW];
-    __shared__ float hm[3][TW * TS];
-    const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TS - 1) / TS;
+    __shared__ float sd[3][TH * TW];
+    __shared__ float hm[3][TH * TS];
+    const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TSY - 1) / TSY;
     const int b = blockIdx.x;
     const int ch = b / (tiles_x * tiles_y);
     const int tt = b % (tiles_x * tiles_y);
-    const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TS;
+    const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TSY;
     const int64_t HW = (int64_t)H * W;
     const int64_t m = 3 * HW;
-    for (int k = threadIdx.x; k < TW * TW; k += LS_THREADS) {
+    for (int k = threadIdx.x; k < TH * TW; k += LS_THREADS) {
         const int r = k / TW, c = k % TW;
         const int gy = y0 + r - HALO, gx = x0 + c - HALO;
         const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
@@ -164,7 +174,7 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __re
         sd[2][k] = in ? d3[2 * m + i] : 0.f;
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < TW * (TS / 4); k += LS_THREADS) {
+    for (int k = threadIdx.x; k < TH * (TS / 4); k += LS_THREADS) {
         const int r = k >> 3, c0 = (k & 7) * 4;
 #pragma unroll
         for (int mm = 0; mm < 3; ++mm) {
@@ -182,15 +192,15 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __re
     }
     __syncthreads();
     {
-        const int c = threadIdx.x & 31, r0 = (threadIdx.x >> 5) * 4;
-        float gm[3][4];
+        const int c = threadIdx.x & 31, r0 = (threadIdx.x >> 5) * RPT;
+        float gm[3][RPT];
 #pragma unroll
         for (int mm = 0; mm < 3; ++mm) {
-            float hv[14];
+            float hv[VWIN];
 #pragma unroll
-            for (int j = 0; j < 14; ++j) hv[j] = hm[mm][(r0 + j) * TS + c];
+            for (int j = 0; j < VWIN; ++j) hv[j] = hm[mm][(r0 + j) * TS + c];
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
+            for (int o = 0; o < RPT; ++o) {
                 float a = 0.f;
 #pragma unroll
                 for (int t = 0; t < 11; ++t) a = fmaf(win.w[t], hv[o + t], a);
@@ -198,7 +208,7 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __re
             }
         }
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
+        for (int o = 0; o < RPT; ++o) {
             const int gy = y0 + r0 + o, gx = x0 + c;
             if (gy >= H || gx >= W) continue;
             const int64_t i = ch * HW + (int64_t)gy * W + gx;
@@ -232,7 +242,7 @@ __global__ __launch_bounds__(LS_THREADS) void k_loss_final(const float* __restri
 size_t loss_ws_bytes(int H, int W) {
     const int64_t m = 3 * (int64_t)H * W;
     const int64_t nb = (m + LS_THREADS - 1) / LS_THREADS;
-    const int64_t nt = 3 * (int64_t)((W + TS - 1) / TS) * ((H + TS - 1) / TS);
+    const int64_t nt = 3 * (int64_t)((W + TS - 1) / TS) * ((H + TSY - 1) / TSY);
     const int64_t np = nb > nt ? nb : nt;
     return (size_t)3 * m * sizeof(float) + (size_t)2 * np * sizeof(float) + 1024;
 }
@@ -241,7 +251,7 @@ rgs_status loss_launch(const float* image, const float* target, int H, int W, fl
                        void* ws, hipStream_t s) {
     const int64_t m = 3 * (int64_t)H * W;
     const int64_t nb = (m + LS_THREADS - 1) / LS_THREADS;
-    const int64_t nt = 3 * (int64_t)((W + TS - 1) / TS) * ((H + TS - 1) / TS);
+    const int64_t nt = 3 * (int64_t)((W + TS - 1) / TS) * ((H + TSY - 1) / TSY);
     WsCarver c{reinterpret_cast<char*>(ws), 0, (size_t)-1};
     float* d3 = c.take<float>(3 * m);
     float* part = c.take<float>(2 * (nb > nt ? nb : nt));
