@@ -20,7 +20,7 @@
 // recovers the transmittance before every contribution from a reciprocal,
 // sums each instance's gradient over every wave's 64 pixels with a
 // reduce-scatter butterfly (no atomics), adds the four quadrant sums in a
-// fixed order and stores one record (9 floats, padded to 48 bytes) at the
+// fixed order and stores one record (9 floats, 36 bytes) at the
 // instance's emission position; a segmented reduction then sums each pair's
 // records (contiguous by construction) in a fixed order.
 #include "common.hpp"
@@ -28,7 +28,8 @@
 namespace rgs {
 
 static constexpr int RD_BATCH = 64;
-static constexpr int RD_REC = 12;  // floats per backward record: 9 used, padded to 48 bytes
+static constexpr int RD_REC = 9;   // floats per backward record (36 bytes, read back contiguously)
+static constexpr int PS_REC = 12;  // floats per per-pair / per-wave sum (48 bytes, float4-aligned)
 
 struct SlotGeom {
     int v, px, py0, cell;
@@ -368,8 +369,9 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
     const uint32_t len = end - begin;
     // instances never reached by any pixel get zero records
     for (uint32_t k = bmax + tid; k < len; k += 256) {
-        float4* rp = reinterpret_cast<float4*>(records + (size_t)(uint32_t)vals[begin + k] * RD_REC);
-        rp[0] = rp[1] = rp[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        float* rp = records + (size_t)(uint32_t)vals[begin + k] * RD_REC;
+#pragma unroll
+        for (int c = 0; c < RD_REC; ++c) rp[c] = 0.f;
     }
     for (int bstart = bmax == 0 ? -1 : (int)(((bmax - 1) / NB) * NB); bstart >= 0; bstart -= NB) {
         if (tid < NB && (uint32_t)bstart + tid < bmax) {
@@ -466,12 +468,18 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
             for (int c = 0; c < 9; ++c) S[c] = (sG[0][t][c] + sG[1][t][c]) + (sG[2][t][c] + sG[3][t][c]);
             const float4 a = sA[t];
             const float cb = a.w * a.z, cc = sB[t].x + a.w * cb;  // conic from (ca, k, e)
-            float4* rp = reinterpret_cast<float4*>(records + (size_t)sJ[t] * RD_REC);
+            float* rp = records + (size_t)sJ[t] * RD_REC;
             // d mx = sum q (ca dx + cb dy), d my = sum q (cb dx + cc dy); d ca, d cb, d cc
             // carry dL/d(d^2) = -q / 2 (d cb counts the cross term twice); then d alpha, colour
-            rp[0] = make_float4(a.z * S[0] + cb * S[1], cb * S[0] + cc * S[1], -0.5f * S[2], -S[3]);
-            rp[1] = make_float4(-0.5f * S[4], S[5], S[6], S[7]);
-            rp[2] = make_float4(S[8], 0.f, 0.f, 0.f);
+            rp[0] = a.z * S[0] + cb * S[1];
+            rp[1] = cb * S[0] + cc * S[1];
+            rp[2] = -0.5f * S[2];
+            rp[3] = -S[3];
+            rp[4] = -0.5f * S[4];
+            rp[5] = S[5];
+            rp[6] = S[6];
+            rp[7] = S[7];
+            rp[8] = S[8];
         }
         __syncthreads();
     }
@@ -541,11 +549,9 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
     const int seg0 = 63 - __builtin_clzll(heads & le_mask);  // first lane of this lane's segment
     float v[9];
     if (valid) {
-        const float4* rp = reinterpret_cast<const float4*>(records + (size_t)j * RD_REC);
-        const float4 x = rp[0], y = rp[1];
-        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-        v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
-        v[8] = rp[2].x;
+        const float* rp = records + (size_t)j * RD_REC;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) v[c] = rp[c];
     } else {
 #pragma unroll
         for (int c = 0; c < 9; ++c) v[c] = 0.f;
@@ -569,15 +575,15 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
     const float4 o0 = make_float4(v[0], v[1], v[2], v[3]), o1 = make_float4(v[4], v[5], v[6], v[7]),
                  o2 = make_float4(v[8], 0.f, 0.f, 0.f);
     if (!began_before && !goes_on) {
-        float4* q = reinterpret_cast<float4*>(psum + (size_t)r * RD_REC);
+        float4* q = reinterpret_cast<float4*>(psum + (size_t)r * PS_REC);
         q[0] = o0; q[1] = o1; q[2] = o2;
     }
     if (began_before) {
-        float4* q = reinterpret_cast<float4*>(wpart + ((size_t)w * 2 + 0) * RD_REC);
+        float4* q = reinterpret_cast<float4*>(wpart + ((size_t)w * 2 + 0) * PS_REC);
         q[0] = o0; q[1] = o1; q[2] = o2;
     }
     if (goes_on) {
-        float4* q = reinterpret_cast<float4*>(wpart + ((size_t)w * 2 + 1) * RD_REC);
+        float4* q = reinterpret_cast<float4*>(wpart + ((size_t)w * 2 + 1) * PS_REC);
         q[0] = o0; q[1] = o1; q[2] = o2;
     }
 }
@@ -605,11 +611,11 @@ __global__ __launch_bounds__(256) void k_pair_gather(const float* __restrict__ p
         const uint32_t b = pair_off[r], e = pair_off[r + 1];
         const uint32_t wb = b >> 6, we = (e - 1u) >> 6;
         if (wb == we) {
-            acc_rec(psum + (size_t)r * RD_REC, a0, a1, a8);
+            acc_rec(psum + (size_t)r * PS_REC, a0, a1, a8);
         } else {
-            acc_rec(wpart + ((size_t)wb * 2 + 1) * RD_REC, a0, a1, a8);      // tail of the first wave
-            for (uint32_t w = wb + 1; w < we; ++w) acc_rec(wpart + (size_t)w * 2 * RD_REC, a0, a1, a8);  // whole waves
-            acc_rec(wpart + (size_t)we * 2 * RD_REC, a0, a1, a8);           // head of the last wave
+            acc_rec(wpart + ((size_t)wb * 2 + 1) * PS_REC, a0, a1, a8);      // tail of the first wave
+            for (uint32_t w = wb + 1; w < we; ++w) acc_rec(wpart + (size_t)w * 2 * PS_REC, a0, a1, a8);  // whole waves
+            acc_rec(wpart + (size_t)we * 2 * PS_REC, a0, a1, a8);           // head of the last wave
         }
     }
     dproj[0 * m + sidx] = a0.x;
@@ -623,14 +629,16 @@ __global__ __launch_bounds__(256) void k_pair_gather(const float* __restrict__ p
     dproj[8 * m + sidx] = a8;
 }
 
-// Backward workspace: records and per-pair sums (pairs <= instances <= capacity)
-// of 48 bytes each, two 48-byte partials and the first pair per 64 instances.
+// Backward workspace: 36-byte records and 48-byte per-pair sums (pairs <=
+// instances <= capacity), two 48-byte partials and the first pair per 64
+// instances.
 size_t render_bwd_ws_bytes(int64_t capacity) {
     const size_t c = (size_t)(capacity > 0 ? capacity : 1);
-    const size_t rec = c * RD_REC * sizeof(float);
+    const size_t rec = c * RD_REC * sizeof(float), ps = c * PS_REC * sizeof(float);
     const size_t nw = (c + 63) / 64;
-    const size_t wp = nw * 2 * RD_REC * sizeof(float);
-    return ((rec + 255) & ~size_t(255)) * 2 + ((wp + 255) & ~size_t(255)) + nw * sizeof(uint32_t) + 256;
+    const size_t wp = nw * 2 * PS_REC * sizeof(float);
+    return ((rec + 255) & ~size_t(255)) + ((ps + 255) & ~size_t(255)) + ((wp + 255) & ~size_t(255)) +
+           nw * sizeof(uint32_t) + 256;
 }
 
 struct BwdWs {
@@ -641,13 +649,14 @@ struct BwdWs {
 static BwdWs carve_bwd(const rgs_bins* bins, void* ws) {
     const size_t c = (size_t)(bins->capacity > 0 ? bins->capacity : 1);
     const size_t rec_bytes = (c * RD_REC * sizeof(float) + 255) & ~size_t(255);
+    const size_t ps_bytes = (c * PS_REC * sizeof(float) + 255) & ~size_t(255);
     BwdWs w;
     w.records = reinterpret_cast<float*>(ws);
     w.psum = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + rec_bytes);
-    w.wpart = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + 2 * rec_bytes);
+    w.wpart = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + rec_bytes + ps_bytes);
     const size_t nw = (c + 63) / 64;
     w.first_pair = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(w.wpart) +
-                                               ((nw * 2 * RD_REC * sizeof(float) + 255) & ~size_t(255)));
+                                               ((nw * 2 * PS_REC * sizeof(float) + 255) & ~size_t(255)));
     return w;
 }
 
