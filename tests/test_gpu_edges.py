@@ -167,6 +167,36 @@ def test_needle_gradients(rast, needles):
         assert ok, info
 
 
+def test_large_footprints_bins(rast):
+    """Every pair has a rectangle larger than the 8 x 15 tiles the record's
+    descriptor holds, so emission takes all spans from the block's row pool
+    and a chunk of 256 pairs (far more than 2048 tile rows) is taken in
+    several runs: instance lists bit-exact against the oracle."""
+    n = 1500
+    p = scenes.scene_uniform(n, seed=41, D=0, mu_s=-1.2, extent=0.5)
+    W, H, L = 1280, 720, 1
+    cam = scenes.orbit_camera(1.8, 0.3, 0.25, W, H, z_near=0.05)
+    dp = device_params(p)
+    kd = rast.kd_partition(dp, L)
+    st = rast.forward(dp, kd, [cam], EPS_T)
+    okd = oracle.kd_partition(p["means"], p["log_scales"], L)
+    order, rank_of = oracle.cell_order(L, okd["split"], cam["o"])
+    pr = oracle.project(p, cam, okd, 0)
+    vis = (pr["vis"] == 1) & (pr["count"] > 0)
+    r = pr["rect"][vis]
+    big = (((r[:, 3] >> 4) - (r[:, 2] >> 4)) >= 8) | (((r[:, 1] >> 4) - (r[:, 0] >> 4)) >= 15)
+    rows = ((r[:, 3] >> 4) - (r[:, 2] >> 4) + 1)[big]
+    log("large footprints: %d of %d visible pairs beyond the descriptor, %d tile rows" % (big.sum(), vis.sum(), rows.sum()))
+    assert big.sum() > 0.8 * vis.sum() and rows.sum() > 4 * 2048
+    assert np.array_equal(st.proj["count"][:n].cpu().numpy().view(np.uint32), pr["count"])
+    okeys, ogids = oracle.bins(pr, rank_of, L, (W + 15) // 16)
+    n_inst = st.bins_struct.n_instances
+    keys = st.bins["keys"][:n_inst].cpu().numpy().view(np.uint32)
+    src = (st.bins["vals"][:n_inst].cpu().numpy().view(np.uint64) >> np.uint64(32)).astype(np.int64)
+    assert n_inst == len(okeys)
+    assert np.array_equal(keys, okeys) and np.array_equal(src % n, ogids.astype(np.int64))
+
+
 # ---------------------------------------------------------------- full size
 @pytest.fixture(scope="module")
 def full(rast):
