@@ -317,33 +317,37 @@ __global__ void k_capacity_guard(uint32_t* __restrict__ cnt, int64_t capacity) {
     }
 }
 
+// Flags of the non-empty dense entries; block 0 also clears the 64 size-class
+// counters used by the launch order below (they run after this kernel).
 __global__ __launch_bounds__(BN_THREADS) void k_slot_flags(const uint32_t* __restrict__ dstart, int64_t m,
-                                                           uint32_t* __restrict__ flag) {
+                                                           uint32_t* __restrict__ flag, uint32_t* __restrict__ cls) {
     int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x < 64) cls[threadIdx.x] = 0u;
     if (i < m) flag[i] = dstart[i] != 0xffffffffu ? 1u : 0u;
 }
 
+// Compaction of the non-empty entries, and the first slot of every tile
+// (the scan value at its first entry; entry `dense` gets the slot count).
 __global__ __launch_bounds__(BN_THREADS) void k_slot_compact(const uint32_t* __restrict__ dstart,
                                                              const uint32_t* __restrict__ dend,
-                                                             const uint32_t* __restrict__ sidx, int64_t m,
+                                                             const uint32_t* __restrict__ sidx, int64_t m, int L,
+                                                             const uint32_t* __restrict__ n_slots,
                                                              uint32_t* __restrict__ slot_key,
-                                                             uint32_t* __restrict__ slot_range) {
+                                                             uint32_t* __restrict__ slot_range,
+                                                             uint32_t* __restrict__ tile_slot) {
     int64_t e = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (e >= m) return;
+    if (e > m) return;
+    if (e == m) {
+        tile_slot[m >> L] = *n_slots;
+        return;
+    }
+    const uint32_t s = sidx[e];
+    if ((e & ((1 << L) - 1)) == 0) tile_slot[e >> L] = s;
     const uint32_t b = dstart[e];
     if (b == 0xffffffffu) return;
-    const uint32_t s = sidx[e];
     slot_key[s] = (uint32_t)e;
     slot_range[2 * s] = b;
     slot_range[2 * s + 1] = dend[e];
-}
-
-__global__ __launch_bounds__(BN_THREADS) void k_tile_slots(const uint32_t* __restrict__ sidx, int64_t total_tiles, int K,
-                                                           const uint32_t* __restrict__ n_slots,
-                                                           uint32_t* __restrict__ tile_slot) {
-    int64_t t = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (t < total_tiles) tile_slot[t] = sidx[t * K];
-    if (t == total_tiles) tile_slot[t] = *n_slots;
 }
 
 // Launch order of the slots: largest first (size classes by floor(log2 len)),
@@ -363,26 +367,25 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_class_count(const uint32_t*
     if (threadIdx.x < 32 && s_c[threadIdx.x]) atomicAdd(&cls_cnt[threadIdx.x], s_c[threadIdx.x]);
 }
 
-// cls_cnt[32] counts -> cls_off[32] start of each class, classes in decreasing order.
-__global__ void k_slot_class_offsets(const uint32_t* __restrict__ cls_cnt, uint32_t* __restrict__ cls_off) {
-    if (threadIdx.x != 0) return;
-    uint32_t run = 0;
-    for (int c = 31; c >= 0; --c) {
-        cls_off[c] = run;
-        run += cls_cnt[c];
-    }
-}
-
-// Slots are placed class by class; within a block, positions come from LDS
-// counters and one global reservation per (block, class), so the global
-// atomics do not serialise on a handful of class counters.  The order inside
-// a class is the launch order only and does not affect any result.
+// Slots are placed class by class, classes in decreasing order: every block
+// derives the class starts from the 32 counts, positions inside a block come
+// from LDS counters and one global reservation per (block, class) in
+// cls_resv, so the global atomics do not serialise on a handful of counters.
+// The order inside a class is the launch order only and affects no result.
 __global__ __launch_bounds__(BN_THREADS) void k_slot_class_place(const uint32_t* __restrict__ slot_range,
                                                                  const uint32_t* __restrict__ n_slots,
-                                                                 uint32_t* __restrict__ cls_off,
+                                                                 const uint32_t* __restrict__ cls_cnt,
+                                                                 uint32_t* __restrict__ cls_resv,
                                                                  uint32_t* __restrict__ slot_order) {
     __shared__ uint32_t s_c[32], s_base[32];
     if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int c = 31; c >= 0; --c) {
+            s_base[c] = run;
+            run += cls_cnt[c];
+        }
+    }
     __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
     const bool ok = s < (int64_t)*n_slots;
@@ -394,7 +397,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_class_place(const uint32_t*
         local = atomicAdd(&s_c[cls], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < 32 && s_c[threadIdx.x]) s_base[threadIdx.x] = atomicAdd(&cls_off[threadIdx.x], s_c[threadIdx.x]);
+    if (threadIdx.x < 32 && s_c[threadIdx.x]) s_base[threadIdx.x] += atomicAdd(&cls_resv[threadIdx.x], s_c[threadIdx.x]);
     __syncthreads();
     if (ok) slot_order[s_base[cls] + local] = (uint32_t)s;
 }
@@ -516,18 +519,14 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     hipLaunchKernelGGL(k_fill_u32, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, 0xffffffffu);
     if (n_inst > 0)
         hipLaunchKernelGGL(k_slot_bounds, dgrid(n_inst), dim3(BN_THREADS), 0, s, bins->keys, &cnt[1], dense, dstart, dend);
-    hipLaunchKernelGGL(k_slot_flags, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, dflag);
+    hipLaunchKernelGGL(k_slot_flags, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, dflag, cls);
     if ((st = exclusive_scan_u32(dflag, sidx, dense, &cnt[2], sws, s)) != RGS_OK) return st;
-    hipLaunchKernelGGL(k_slot_compact, grid(dense), dim3(BN_THREADS), 0, s, dstart, dend, sidx, dense, bins->slot_key,
-                       bins->slot_range);
-    hipLaunchKernelGGL(k_tile_slots, grid(total_tiles + 1), dim3(BN_THREADS), 0, s, sidx, total_tiles, 1 << L, &cnt[2],
-                       bins->tile_slot);
+    hipLaunchKernelGGL(k_slot_compact, grid(dense + 1), dim3(BN_THREADS), 0, s, dstart, dend, sidx, dense, L, &cnt[2],
+                       bins->slot_key, bins->slot_range, bins->tile_slot);
     // 5. launch order of the slots (largest size class first)
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(BN_THREADS), 0, s, cls, (int64_t)32, 0u);
     hipLaunchKernelGGL(k_slot_class_count, grid(slot_bound), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], cls);
-    hipLaunchKernelGGL(k_slot_class_offsets, dim3(1), dim3(64), 0, s, cls, cls + 32);
-    hipLaunchKernelGGL(k_slot_class_place, grid(slot_bound), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], cls + 32,
-                       bins->slot_order);
+    hipLaunchKernelGGL(k_slot_class_place, grid(slot_bound), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], cls,
+                       cls + 32, bins->slot_order);
     return launch_check();
 }
 
