@@ -16,11 +16,12 @@
 // quadrant with a scalar branch.  A pixel stops after the contribution that
 // takes its T_k below eps_T; the block leaves once all 256 pixels stopped.
 //
-// Backward walks each slot back to front from the largest per-pixel `last`,
-// recovers the transmittance before every contribution from a reciprocal,
-// sums each instance's gradient over every wave's 64 pixels with a
-// reduce-scatter butterfly (no atomics), adds the four quadrant sums in a
-// fixed order and stores one record (9 floats, 36 bytes) at the
+// Backward (a 128-thread block per slot, two pixels of one row per lane)
+// walks each slot back to front from the largest per-pixel `last`, recovers
+// the transmittance before every contribution from a reciprocal, adds each
+// lane's two pixels and sums each instance's gradient over the wave's 128
+// pixels with a reduce-scatter butterfly (no atomics), adds the two half-tile
+// sums in a fixed order and stores one record (9 floats, 36 bytes) at the
 // instance's emission position; a segmented reduction then sums each pair's
 // records (contiguous by construction) in a fixed order.
 #include "common.hpp"
@@ -65,19 +66,19 @@ __device__ __forceinline__ uint32_t quad_mask(uint2 rr, int tx, int ty) {
     return m;
 }
 
-// Can a pixel centre of the 8x8 quadrant whose first pixel is (x0, y0) pass
-// the fp32 decision d^2 <= tau?  The minimum of the quadratic form over the
-// box of the quadrant's pixel centres is 0 if the mean is inside, else the
-// least of its four edge minima (a convex function of one variable each,
-// minimised at the clamped stationary point).  Against the fp32 sequence
-// used per pixel the test adds a margin of 2^-18 (ca dx^2 + cc dy^2) at the
-// box's far corner, above the rounding error of both evaluations (a few ulp
-// of |ca dx^2| + 2|cb dx dy| + |cc dy^2| <= 2 (ca dx^2 + cc dy^2)), plus
-// 2^-20 tau: a quadrant is only dropped when no pixel can contribute.
-__device__ __forceinline__ bool quad_hits(float mx, float my, float ca, float cb, float cc, float tau, float x0,
-                                          float y0) {
-    const float lx = (x0 + 0.5f) - mx, hx = (x0 + 7.5f) - mx;
-    const float ly = (y0 + 0.5f) - my, hy = (y0 + 7.5f) - my;
+// Can a pixel centre of the wx-by-wy block of pixels whose first pixel is
+// (x0, y0) pass the fp32 decision d^2 <= tau?  The minimum of the quadratic
+// form over the box of the block's pixel centres is 0 if the mean is inside,
+// else the least of its four edge minima (a convex function of one variable
+// each, minimised at the clamped stationary point).  Against the fp32
+// sequence used per pixel the test adds a margin of 2^-18 (ca dx^2 + cc dy^2)
+// at the box's far corner, above the rounding error of both evaluations (a
+// few ulp of |ca dx^2| + 2|cb dx dy| + |cc dy^2| <= 2 (ca dx^2 + cc dy^2)),
+// plus 2^-20 tau: a block is only dropped when no pixel can contribute.
+__device__ __forceinline__ bool box_hits(float mx, float my, float ca, float cb, float cc, float tau, float x0,
+                                         float y0, float wx, float wy) {
+    const float lx = (x0 + 0.5f) - mx, hx = (x0 + (wx - 0.5f)) - mx;
+    const float ly = (y0 + 0.5f) - my, hy = (y0 + (wy - 0.5f)) - my;
     if (lx <= 0.0f && hx >= 0.0f && ly <= 0.0f && hy >= 0.0f) return true;
     const float ica = __builtin_amdgcn_rcpf(ca), icc = __builtin_amdgcn_rcpf(cc);
     float qmin = INFINITY;
@@ -92,6 +93,12 @@ __device__ __forceinline__ bool quad_hits(float mx, float my, float ca, float cb
     }
     const float far = ca * fmaxf(lx * lx, hx * hx) + cc * fmaxf(ly * ly, hy * hy);
     return qmin <= tau + 0x1p-18f * far + 0x1p-20f * tau;
+}
+
+// The same test for an 8x8 quadrant of a tile.
+__device__ __forceinline__ bool quad_hits(float mx, float my, float ca, float cb, float cc, float tau, float x0,
+                                          float y0) {
+    return box_hits(mx, my, ca, cb, cc, tau, x0, y0, 8.0f, 8.0f);
 }
 
 // Quadrant mask of a Gaussian's rectangle (quad_mask) with the quadrants its
@@ -304,13 +311,47 @@ __device__ __forceinline__ void wave_sum9(const float* g, int lane, float* out_v
 }
 #undef RGS_DPP
 
-// Backward: same block layout as the forward (wave w = quadrant w, one pixel
-// per lane).  Batches of 64 instances are walked back to front from the
-// block's largest `last`; every wave sums each instance's gradient over its
-// 64 pixels (zero when culled or not contributing) into LDS, and the four
-// quadrant sums are added in a fixed order into the instance's record.
+// Backward: 128-thread block per slot.  Wave w owns the 16x8 half (rows
+// 8w .. 8w + 7) of the tile and every lane two pixels of one row, eight
+// columns apart (quadrants (0, w) and (1, w)): the lane adds its two pixels'
+// gradient terms before the cross-lane sum, so one wave sum covers 128
+// pixels.  Batches of 64 instances are walked back to front from the block's
+// largest `last`; every wave sums each instance's gradient over its 128
+// pixels (zero when culled or not contributing) into LDS, and the two half
+// sums are added in a fixed order into the instance's record.
+struct BwdPix {
+    float fx, D0, D1, D2;  // sample x, ray direction
+    float T, gB, gC0, gC1, gC2, gTf;
+    uint32_t last;
+};
+
+// One pixel's share of an instance's gradient.  A lane that does not
+// contribute takes sigma = 0, so 1 / (1 - sigma) = 1 exactly, T and <dC, B>
+// stay as they are, and every term returned is zero.
+struct PixTerms {
+    float q, dsg_g, G, wc;
+};
+
+__device__ __forceinline__ PixTerms pix_step(BwdPix& P, bool contrib, float d2, float alpha, float4 cl) {
+    PixTerms r;
+    r.G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
+    const float aG = alpha * r.G;
+    const float sgm = contrib ? fminf(0.99f, aG) : 0.0f;
+    const float rom = __builtin_amdgcn_rcpf(1.0f - sgm);
+    const float Tb = P.T * rom;  // transmittance before this contribution
+    const float dot = fmaf(P.gC2, cl.z, fmaf(P.gC1, cl.y, P.gC0 * cl.x)) - P.gB;  // <dC, c - B>
+    const float dsg = rom * fmaf(P.T, dot, -P.gTf);                               // dL/dsigma
+    r.wc = Tb * sgm;
+    P.gB = fmaf(sgm, dot, P.gB);  // B <- B + sigma (c - B)
+    P.T = Tb;
+    // clamped at 0.99: no gradient to alpha or the footprint
+    r.dsg_g = (contrib && aG < 0.99f) ? dsg : 0.0f;
+    r.q = aG * r.dsg_g;
+    return r;
+}
+
 template <bool STATS>
-__global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__ rec,
+__global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ rec,
                                                     const uint64_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
@@ -325,8 +366,8 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
     __shared__ float4 sA[NB], sB[NB], sCl[NB];
     __shared__ uint2 sR[NB];
     __shared__ uint32_t sJ[NB];
-    __shared__ float sG[4][NB][9];
-    __shared__ uint32_t s_max[4];
+    __shared__ float sG[2][NB][9];
+    __shared__ uint32_t s_max[2];
     if (blockIdx.x >= counters[2]) return;
     const uint32_t slot = slot_order[blockIdx.x];
     const int L = vt->L, K = 1 << L;
@@ -341,38 +382,48 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
     const uint32_t begin = slot_range[2 * slot], end = slot_range[2 * slot + 1];
     const float blo0 = box_lo[cell], blo1 = box_lo[K + cell], blo2 = box_lo[2 * K + cell];
     const float bhi0 = box_hi[cell], bhi1 = box_hi[K + cell], bhi2 = box_hi[2 * K + cell];
-    const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
-    const int px = tx * 16 + lx, py = ty * 16 + ly;
-    const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
-    const float dxp = (fxp - V.cx) / V.fx, dyp = (fyp - V.cy) / V.fy;
-    const float D0 = (V.R[0] * dxp + V.R[3] * dyp) + V.R[6];
-    const float D1 = (V.R[1] * dxp + V.R[4] * dyp) + V.R[7];
-    const float D2 = (V.R[2] * dxp + V.R[5] * dyp) + V.R[8];
+    const int lx = lane & 7, ly = w * 8 + (lane >> 3);
+    const int py = ty * 16 + ly;
+    const float fyp = (float)py + 0.5f;
+    const float dyp = (fyp - V.cy) / V.fy;
     const float o0 = V.o[0], o1 = V.o[1], o2 = V.o[2];
-    const int p = ly * 16 + lx;
-    const bool valid = px < V.W && py < V.H;
-    const float Tf = partT[(size_t)slot * 256 + p];
-    const uint32_t last = valid ? partLast[(size_t)slot * 256 + p] : 0u;
-    float Tcur = Tf;
-    const float gTf = valid ? dT[(size_t)slot * 256 + p] * Tf : 0.f;
-    const float gC0 = valid ? dC[(size_t)slot * 768 + p] : 0.f;
-    const float gC1 = valid ? dC[(size_t)slot * 768 + 256 + p] : 0.f;
-    const float gC2 = valid ? dC[(size_t)slot * 768 + 512 + p] : 0.f;
-    // gB = <dC_k, B>, where B is the colour blended behind the current
-    // instance (the suffix of Eq. 3): the only way B enters the gradient
-    float gB = 0.f;
+    BwdPix P[2];
+    int pxs[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int px = tx * 16 + lx + 8 * h;
+        pxs[h] = px;
+        P[h].fx = (float)px + 0.5f;
+        const float dxp = (P[h].fx - V.cx) / V.fx;
+        P[h].D0 = (V.R[0] * dxp + V.R[3] * dyp) + V.R[6];
+        P[h].D1 = (V.R[1] * dxp + V.R[4] * dyp) + V.R[7];
+        P[h].D2 = (V.R[2] * dxp + V.R[5] * dyp) + V.R[8];
+        const int p = ly * 16 + lx + 8 * h;
+        const bool valid = px < V.W && py < V.H;
+        const float Tf = partT[(size_t)slot * 256 + p];
+        P[h].T = Tf;
+        P[h].last = valid ? partLast[(size_t)slot * 256 + p] : 0u;
+        P[h].gTf = valid ? dT[(size_t)slot * 256 + p] * Tf : 0.f;
+        P[h].gC0 = valid ? dC[(size_t)slot * 768 + p] : 0.f;
+        P[h].gC1 = valid ? dC[(size_t)slot * 768 + 256 + p] : 0.f;
+        P[h].gC2 = valid ? dC[(size_t)slot * 768 + 512 + p] : 0.f;
+        // gB = <dC_k, B>, where B is the colour blended behind the current
+        // instance (the suffix of Eq. 3): the only way B enters the gradient
+        P[h].gB = 0.f;
+    }
     uint32_t n_eval = 0u, n_con = 0u;
-    const uint32_t wmax = wave_max_u32(last);
+    const uint32_t wmax = wave_max_u32(max(P[0].last, P[1].last));
     if (lane == 0) s_max[w] = wmax;
     __syncthreads();
-    const uint32_t bmax = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+    const uint32_t bmax = max(s_max[0], s_max[1]);
     const uint32_t len = end - begin;
     // instances never reached by any pixel get zero records
-    for (uint32_t k = bmax + tid; k < len; k += 256) {
+    for (uint32_t k = bmax + tid; k < len; k += 128) {
         float* rp = records + (size_t)(uint32_t)vals[begin + k] * RD_REC;
 #pragma unroll
         for (int c = 0; c < RD_REC; ++c) rp[c] = 0.f;
     }
+    const float hx0 = (float)(tx * 16), hy0 = (float)(ty * 16 + w * 8);
     for (int bstart = bmax == 0 ? -1 : (int)(((bmax - 1) / NB) * NB); bstart >= 0; bstart -= NB) {
         if (tid < NB && (uint32_t)bstart + tid < bmax) {
             const uint64_t vv = vals[begin + bstart + tid];
@@ -386,18 +437,18 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
             sR[tid] = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
             sJ[tid] = (uint32_t)vv;
         }
-        for (int k = tid; k < 4 * NB * 9; k += 256) (&sG[0][0][0])[k] = 0.f;
+        for (int k = tid; k < 2 * NB * 9; k += 128) (&sG[0][0][0])[k] = 0.f;
         __syncthreads();
         // Gaussians of this batch below the wave's largest `last` whose
-        // footprint can reach the wave's quadrant (each wave tests its own
-        // quadrant, one record per lane), walked back to front
+        // footprint can reach the wave's half tile (each wave tests its own
+        // half, one record per lane), walked back to front
         const int tl = lane;
         bool hit = (uint32_t)(bstart + tl) + 1u <= wmax && (uint32_t)(bstart + tl) < bmax;
         if (hit) {
             const float4 a = sA[tl], b = sB[tl];
             const float cb = a.w * a.z, cc = b.x + a.w * cb;  // conic from (ca, k, e)
-            hit = ((quad_mask(sR[tl], tx, ty) >> w) & 1u) &&
-                  quad_hits(a.x, a.y, a.z, cb, cc, b.z, (float)(tx * 16 + (w & 1) * 8), (float)(ty * 16 + (w >> 1) * 8));
+            hit = ((quad_mask(sR[tl], tx, ty) >> (2 * w)) & 3u) &&
+                  box_hits(a.x, a.y, a.z, cb, cc, b.z, hx0, hy0, 16.0f, 8.0f);
         }
         uint64_t rel = __ballot(hit);
         const uint64_t inside = __ballot(hit && (__float_as_uint(sCl[tl].w) & 1u));  // in one cell: no indicator test
@@ -407,53 +458,51 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
             const uint32_t pos1 = (uint32_t)(bstart + t) + 1u;  // this instance's index + 1
             const float4 a = sA[t];
             const float4 b = sB[t];
-            const float dx = fxp - a.x, dy = fyp - a.y;
-            const float u = fmaf(a.w, dy, dx);  // d^2 = ca u^2 + e dy^2
-            const float d2 = fmaf(b.x * dy, dy, (a.z * u) * u);
-            bool contrib = pos1 <= last && d2 <= b.z;
-            if (STATS && pos1 <= last) {
-                // pairs the backward must re-test: pixel inside the rectangle, at or before its last contributor
-                const uint2 rr = sR[t];
-                n_eval += (px >= (int)(int16_t)(rr.x & 0xffffu) && px <= (int)(int16_t)(rr.x >> 16) &&
-                           py >= (int)(int16_t)(rr.y & 0xffffu) && py <= (int)(int16_t)(rr.y >> 16)) ? 1u : 0u;
+            const float dy = fyp - a.y;
+            const float edy = b.x * dy;
+            float dx[2], d2[2];
+            bool con[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                dx[h] = P[h].fx - a.x;
+                const float u = fmaf(a.w, dy, dx[h]);  // d^2 = ca u^2 + e dy^2
+                d2[h] = fmaf(edy, dy, (a.z * u) * u);
+                con[h] = pos1 <= P[h].last && d2[h] <= b.z;
+                if (STATS && pos1 <= P[h].last) {
+                    // pairs the backward must re-test: pixel inside the rectangle, at or before its last contributor
+                    const uint2 rr = sR[t];
+                    n_eval += (pxs[h] >= (int)(int16_t)(rr.x & 0xffffu) && pxs[h] <= (int)(int16_t)(rr.x >> 16) &&
+                               py >= (int)(int16_t)(rr.y & 0xffffu) && py <= (int)(int16_t)(rr.y >> 16)) ? 1u : 0u;
+                }
             }
-            if (__ballot(contrib) == 0ull) continue;
+            if (__ballot(con[0] || con[1]) == 0ull) continue;
             const float4 cl = sCl[t];
             if (!((inside >> t) & 1ull)) {  // not interior to the cell: the indicator of Eq. 6
-                const float x0 = fmaf(b.w, D0, o0), x1 = fmaf(b.w, D1, o1), x2 = fmaf(b.w, D2, o2);
-                contrib = contrib && (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
-                          (x2 < bhi2);
-                if (__ballot(contrib) == 0ull) continue;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float x0 = fmaf(b.w, P[h].D0, o0), x1 = fmaf(b.w, P[h].D1, o1), x2 = fmaf(b.w, P[h].D2, o2);
+                    con[h] = con[h] && (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
+                             (x2 < bhi2);
+                }
+                if (__ballot(con[0] || con[1]) == 0ull) continue;
             }
-            // Branch-free over the wave: a lane that does not contribute takes
-            // sigma = 0, so 1 / (1 - sigma) = 1 exactly, T and <dC, B> stay as
-            // they are, and every gradient term below is zero.
-            if (STATS) n_con += contrib ? 1u : 0u;
-            const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
-            const float aG = b.y * G;
-            const float sgm = contrib ? fminf(0.99f, aG) : 0.0f;
-            const float rom = __builtin_amdgcn_rcpf(1.0f - sgm);
-            const float Tb = Tcur * rom;  // transmittance before this contribution
-            const float dot = fmaf(gC2, cl.z, fmaf(gC1, cl.y, gC0 * cl.x)) - gB;  // <dC, c - B>
-            const float dsg = Tb * dot - gTf * rom;
-            const float wc = Tb * sgm;
+            if (STATS) n_con += (con[0] ? 1u : 0u) + (con[1] ? 1u : 0u);
+            const PixTerms r0 = pix_step(P[0], con[0], d2[0], b.y, cl);
+            const PixTerms r1 = pix_step(P[1], con[1], d2[1], b.y, cl);
+            // Raw sums over the lane's two pixels; the conic and constant
+            // factors are applied per instance after the reduction
+            // (dL/d(d^2) = -q / 2)
             float g[9];
-            g[6] = wc * gC0;
-            g[7] = wc * gC1;
-            g[8] = wc * gC2;
-            gB = fmaf(sgm, dot, gB);  // B <- B + sigma (c - B)
-            Tcur = Tb;
-            // clamped at 0.99: no gradient to alpha or the footprint.  Raw sums;
-            // the conic and constant factors are applied per instance after the
-            // reduction (dL/d(d^2) = -q / 2)
-            const float dsg_g = (contrib && aG < 0.99f) ? dsg : 0.0f;
-            const float q = aG * dsg_g;
-            g[5] = dsg_g * G;
-            g[0] = q * dx;
-            g[1] = q * dy;
-            g[2] = g[0] * dx;
-            g[3] = g[0] * dy;
-            g[4] = g[1] * dy;
+            const float qx0 = r0.q * dx[0], qx1 = r1.q * dx[1];
+            g[0] = qx0 + qx1;                          // q dx
+            g[1] = (r0.q + r1.q) * dy;                 // q dy
+            g[2] = fmaf(qx1, dx[1], qx0 * dx[0]);      // q dx^2
+            g[3] = g[0] * dy;                          // q dx dy
+            g[4] = g[1] * dy;                          // q dy^2
+            g[5] = fmaf(r1.dsg_g, r1.G, r0.dsg_g * r0.G);
+            g[6] = fmaf(r1.wc, P[1].gC0, r0.wc * P[0].gC0);
+            g[7] = fmaf(r1.wc, P[1].gC1, r0.wc * P[0].gC1);
+            g[8] = fmaf(r1.wc, P[1].gC2, r0.wc * P[0].gC2);
             float sv, s8;
             wave_sum9(g, lane, &sv, &s8);
             if ((lane & 7) == 0) sG[w][t][lane >> 3] = sv;
@@ -461,11 +510,11 @@ __global__ __launch_bounds__(256, 8) void k_render_bwd(const float* __restrict__
         }
         __syncthreads();
         if (tid < NB && (uint32_t)bstart + tid < bmax) {
-            // S_c = sum over the four quadrants, in a fixed order
+            // S_c = sum over the two halves, in a fixed order
             const int t = tid;
             float S[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) S[c] = (sG[0][t][c] + sG[1][t][c]) + (sG[2][t][c] + sG[3][t][c]);
+            for (int c = 0; c < 9; ++c) S[c] = sG[0][t][c] + sG[1][t][c];
             const float4 a = sA[t];
             const float cb = a.w * a.z, cc = sB[t].x + a.w * cb;  // conic from (ca, k, e)
             float* rp = records + (size_t)sJ[t] * RD_REC;
@@ -667,12 +716,12 @@ rgs_status render_bwd_records_launch(const rgs_partials_grad* dparts, const rgs_
     const BwdWs w = carve_bwd(bins, ws);
     if (slot_bound <= 0) return RGS_OK;
     if (stats)
-        hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, bins->vals,
+        hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
                            parts->T, parts->last, dparts->dC, dparts->dT, w.records,
                            reinterpret_cast<unsigned long long*>(stats));
     else
-        hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec, bins->vals,
+        hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
                            parts->T, parts->last, dparts->dC, dparts->dT, w.records, nullptr);
     return launch_check();
