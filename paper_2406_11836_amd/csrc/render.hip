@@ -121,7 +121,8 @@ __device__ __forceinline__ uint32_t quad_mask_ellipse(uint2 rr, int tx, int ty, 
 // skips Gaussians that cannot touch its quadrant with a scalar branch.
 template <bool STATS>
 __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ rec,
-                                                    const uint64_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ inst_src,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
                                                     const uint32_t* __restrict__ slot_order,
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
         if (lane == 0) s_alive[w] = alive != 0ull ? 1u : 0u;
         const uint32_t idx = base + tid;
         if (idx < end) {
-            const uint32_t src = (uint32_t)(vals[idx] >> 32);
+            const uint32_t src = inst_src[vals[idx]];
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
             const float4 a = rp[0];
             const float4 b = rp[1], cl = rp[2], r4 = rp[3];
@@ -258,11 +259,11 @@ rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, co
     if (slot_bound <= 0) return RGS_OK;
     if (stats)
         hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec,
-                           bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
+                           bins->vals, bins->inst_src, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
                            kd->box_hi, eps_T, out->C, out->T, out->last, reinterpret_cast<unsigned long long*>(stats));
     else
         hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec,
-                           bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
+                           bins->vals, bins->inst_src, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
                            kd->box_hi, eps_T, out->C, out->T, out->last, nullptr);
     return launch_check();
 }
@@ -352,7 +353,8 @@ __device__ __forceinline__ PixTerms pix_step(BwdPix& P, bool contrib, float d2, 
 
 template <bool STATS>
 __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ rec,
-                                                    const uint64_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ inst_src,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
                                                     const uint32_t* __restrict__ slot_order,
@@ -419,15 +421,15 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
     const uint32_t len = end - begin;
     // instances never reached by any pixel get zero records
     for (uint32_t k = bmax + tid; k < len; k += 128) {
-        float* rp = records + (size_t)(uint32_t)vals[begin + k] * RD_REC;
+        float* rp = records + (size_t)vals[begin + k] * RD_REC;
 #pragma unroll
         for (int c = 0; c < RD_REC; ++c) rp[c] = 0.f;
     }
     const float hx0 = (float)(tx * 16), hy0 = (float)(ty * 16 + w * 8);
     for (int bstart = bmax == 0 ? -1 : (int)(((bmax - 1) / NB) * NB); bstart >= 0; bstart -= NB) {
         if (tid < NB && (uint32_t)bstart + tid < bmax) {
-            const uint64_t vv = vals[begin + bstart + tid];
-            const uint32_t src = (uint32_t)(vv >> 32);
+            const uint32_t jj = vals[begin + bstart + tid];
+            const uint32_t src = inst_src[jj];
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
             const float4 cl = rp[2];
             const float4 a = rp[0], b = rp[1], r4 = rp[3];
@@ -435,7 +437,7 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
             sB[tid] = b;
             sCl[tid] = cl;
             sR[tid] = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
-            sJ[tid] = (uint32_t)vv;
+            sJ[tid] = jj;
         }
         for (int k = tid; k < 2 * NB * 9; k += 128) (&sG[0][0][0])[k] = 0.f;
         __syncthreads();
@@ -605,15 +607,27 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
 #pragma unroll
         for (int c = 0; c < 9; ++c) v[c] = 0.f;
     }
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const bool take = lane - d >= seg0;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            const float u = __shfl_up(v[c], d, 64);
-            if (take) v[c] += u;
-        }
+    // Segmented inclusive scan: in-row steps by DPP row shifts (1, 2, 4, 8;
+    // lanes shifted in from outside the row read 0), then the row broadcasts
+    // of lanes 15 and 47 (into rows 1 and 3) and of lane 31 (into rows 2 and
+    // 3); a lane only adds values from its own segment.
+    const int row = lane >> 4;
+#define RGS_SEG_STEP(ctrl, rmask, take)                                                                            \
+    {                                                                                                              \
+        const bool tk = (take);                                                                                    \
+        _Pragma("unroll") for (int c = 0; c < 9; ++c) {                                                            \
+            const float u = __builtin_bit_cast(                                                                    \
+                float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v[c]), (ctrl), (rmask), 0xf, false)); \
+            if (tk) v[c] += u;                                                                                     \
+        }                                                                                                          \
     }
+    RGS_SEG_STEP(0x111, 0xf, lane - 1 >= seg0)             // row_shr:1
+    RGS_SEG_STEP(0x112, 0xf, lane - 2 >= seg0)             // row_shr:2
+    RGS_SEG_STEP(0x114, 0xf, lane - 4 >= seg0)             // row_shr:4
+    RGS_SEG_STEP(0x118, 0xf, lane - 8 >= seg0)             // row_shr:8
+    RGS_SEG_STEP(0x142, 0xa, (row & 1) && seg0 < 16 * row)  // row_bcast:15
+    RGS_SEG_STEP(0x143, 0xc, row >= 2 && seg0 < 32)         // row_bcast:31
+#undef RGS_SEG_STEP
     const int pos_next = __shfl_down(pos, 1, 64);
     const bool next_valid = lane < 63 && j + 1 < (int64_t)n_inst;
     const bool seg_end = valid && (!next_valid || pos_next != pos);
@@ -716,12 +730,12 @@ rgs_status render_bwd_records_launch(const rgs_partials_grad* dparts, const rgs_
     const BwdWs w = carve_bwd(bins, ws);
     if (slot_bound <= 0) return RGS_OK;
     if (stats)
-        hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
+        hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals, bins->inst_src,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
                            parts->T, parts->last, dparts->dC, dparts->dT, w.records,
                            reinterpret_cast<unsigned long long*>(stats));
     else
-        hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
+        hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals, bins->inst_src,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
                            parts->T, parts->last, dparts->dC, dparts->dT, w.records, nullptr);
     return launch_check();

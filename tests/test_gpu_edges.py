@@ -72,6 +72,26 @@ def test_screen_filling_gaussian(rast):
     assert np.abs(img - r["img"]).max() <= 2e-4
 
 
+def test_single_tile_one_cell(rast):
+    """A 16x16 image and L = 0: the (tile, cell) key has no bits, the sort
+    still writes the emission positions (in order) and the image matches."""
+    p = scenes.scene_uniform(400, seed=11, D=1, mu_s=-2.5, extent=0.5)
+    dp = device_params(p)
+    kd = rast.kd_partition(dp, 0)
+    cam = scenes.orbit_camera(2.0, 0.3, 0.2, 16, 16)
+    st = rast.forward(dp, kd, [cam], EPS_T)
+    n_inst = st.bins_struct.n_instances
+    assert n_inst == 400
+    pos = st.bins["vals"][:n_inst].cpu().numpy().view(np.uint32)
+    assert np.array_equal(pos, np.arange(n_inst))
+    okd = oracle.kd_partition(p["means"], p["log_scales"], 0)
+    order, _ = oracle.cell_order(0, okd["split"], cam["o"])
+    pr = oracle.project(p, cam, okd, 0)
+    r = oracle.render(pr, cam, okd, order, oracle.all_pixels(16, 16), EPS_T)
+    img = st.image.cpu().numpy().reshape(3, -1).T
+    assert np.abs(img - r["img"]).max() <= 2e-4
+
+
 def test_centres_on_split_planes(rast):
     """Many centres share coordinates, so split values coincide with centres and
     with each other; bit-exact tree and parity of the image."""
@@ -135,7 +155,8 @@ def test_needle_footprints(needles):
     okeys, ogids = oracle.bins(pr, rank_of, L, (W + 15) // 16)
     n_inst = st.bins_struct.n_instances
     keys = st.bins["keys"][:n_inst].cpu().numpy().view(np.uint32)
-    src = (st.bins["vals"][:n_inst].cpu().numpy().view(np.uint64) >> np.uint64(32)).astype(np.int64)
+    pos = st.bins["vals"][:n_inst].cpu().numpy().view(np.uint32).astype(np.int64)
+    src = st.bins["inst_src"][:n_inst].cpu().numpy().view(np.uint32).astype(np.int64)[pos]
     assert np.array_equal(keys, okeys) and np.array_equal(src % n, ogids.astype(np.int64))
     r = oracle.render(pr, cam, okd, order, oracle.all_pixels(W, H), EPS_T)
     err = np.abs(st.image.cpu().numpy().reshape(3, -1).T - r["img"]).max()
@@ -192,7 +213,8 @@ def test_large_footprints_bins(rast):
     okeys, ogids = oracle.bins(pr, rank_of, L, (W + 15) // 16)
     n_inst = st.bins_struct.n_instances
     keys = st.bins["keys"][:n_inst].cpu().numpy().view(np.uint32)
-    src = (st.bins["vals"][:n_inst].cpu().numpy().view(np.uint64) >> np.uint64(32)).astype(np.int64)
+    pos = st.bins["vals"][:n_inst].cpu().numpy().view(np.uint32).astype(np.int64)
+    src = st.bins["inst_src"][:n_inst].cpu().numpy().view(np.uint32).astype(np.int64)[pos]
     assert n_inst == len(okeys)
     assert np.array_equal(keys, okeys) and np.array_equal(src % n, ogids.astype(np.int64))
 
