@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 2
+#define RGS_ABI_VERSION 1
 #define RGS_TILE 16       /* screen tiles are 16 x 16 pixels */
 #define RGS_MAX_L 6       /* K = 2^L <= 64 cells */
 #define RGS_MAX_VIEWS 16  /* views per call */
@@ -138,11 +138,10 @@ typedef struct {
 
 /* Tile/cell instance lists and slots (one slot per non-empty (tile, cell)). */
 typedef struct {
-    int64_t capacity;       /* instance capacity of keys, vals and inst_src */
+    int64_t capacity;       /* instance capacity of keys and vals */
     int64_t slot_capacity;  /* slot capacity: >= min(instances, total_tiles * K) */
     uint32_t *keys;         /* [capacity] sorted keys (global_tile << L) | rank of cell in view order */
-    uint32_t *vals;         /* [capacity] sorted: each instance's position in emission order */
-    uint32_t *inst_src;     /* [capacity] by emission position: src (view * N + gid) of the instance's pair */
+    uint64_t *vals;         /* [capacity] sorted (src << 32) | position in emission order */
     uint32_t *pair_src;     /* [V*N] visible pairs in (view, depth, gid) order */
     uint32_t *pair_off;     /* [V*N+1] first instance of each ordered pair */
     int32_t *pair_rank;     /* [V*N] position of src in pair_src (valid where count > 0) */

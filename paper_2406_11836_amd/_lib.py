@@ -45,7 +45,7 @@ class Projected(C.Structure):
 
 
 class Bins(C.Structure):
-    _fields_ = [("capacity", i64), ("slot_capacity", i64), ("keys", vp), ("vals", vp), ("inst_src", vp), ("pair_src", vp),
+    _fields_ = [("capacity", i64), ("slot_capacity", i64), ("keys", vp), ("vals", vp), ("pair_src", vp),
                 ("pair_off", vp), ("pair_rank", vp), ("slot_key", vp), ("slot_range", vp), ("tile_slot", vp),
                 ("slot_order", vp), ("counters", vp), ("n_instances", i64)]
 

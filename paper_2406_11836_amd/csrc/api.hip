@@ -225,7 +225,7 @@ size_t rgs_bin_sort_workspace(int64_t n, int32_t n_views, int64_t total_tiles, i
 }
 
 static bool bins_ok(const rgs_bins* b) {
-    return b && b->keys && b->vals && b->inst_src && b->pair_src && b->pair_off && b->pair_rank && b->slot_key && b->slot_range &&
+    return b && b->keys && b->vals && b->pair_src && b->pair_off && b->pair_rank && b->slot_key && b->slot_range &&
            b->tile_slot && b->slot_order && b->counters && b->capacity >= 0 && b->slot_capacity >= 0;
 }
 

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ pair_off, const float* __restrict__ rec,
                                                      const uint64_t* __restrict__ cellmask, int64_t n_gauss,
                                                      const ViewTable* __restrict__ vt, uint32_t* __restrict__ keys,
-                                                     uint32_t* __restrict__ inst_src) {
+                                                     uint64_t* __restrict__ vals) {
     constexpr int ROWPOOL = 2048;  // rows of one run; a rectangle has at most 256 tile rows
     __shared__ uint32_t s_off[BN_THREADS + 1];
     __shared__ uint32_t s_src[BN_THREADS];
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict_
                 const int cell = nth_set_bit(s_mask[pl], (int)c);
                 keys[j] = ((s_vto[pl] + (uint32_t)ty * s_vtx[pl] + (uint32_t)tx) << L) |
                           (uint32_t)vt->v[s_view[pl]].rank_of_cell[cell];
-                inst_src[j] = s_src[pl];
+                vals[j] = ((uint64_t)s_src[pl] << 32) | j;
             }
             __syncthreads();  // the pool is reused by the next run
             p0 = p1;
@@ -412,7 +412,7 @@ size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t 
     c.take<uint32_t>(m + 1);          // z keys alt
     c.take<uint32_t>(m + 1);          // src alt
     c.take<uint32_t>(capacity + 1);   // instance keys alt
-    c.take<uint32_t>(capacity + 1);   // instance vals alt
+    c.take<uint64_t>(capacity + 1);   // instance vals alt
     c.take<uint32_t>(dense + 1);      // dense start
     c.take<uint32_t>(dense + 1);      // dense end
     c.take<uint32_t>(dense + 1);      // dense flags
@@ -443,7 +443,7 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     uint32_t* zkey_alt = c.take<uint32_t>(m + 1);
     uint32_t* src_alt = c.take<uint32_t>(m + 1);
     uint32_t* keys_alt = c.take<uint32_t>(bins->capacity + 1);
-    uint32_t* vals_alt = c.take<uint32_t>(bins->capacity + 1);
+    uint64_t* vals_alt = c.take<uint64_t>(bins->capacity + 1);
     uint32_t* dstart = c.take<uint32_t>(dense + 1);
     uint32_t* dend = c.take<uint32_t>(dense + 1);
     uint32_t* dflag = c.take<uint32_t>(dense + 1);
@@ -507,13 +507,12 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     // 3. emit and sort instances by (tile, rank)
     if (m > 0)
         hipLaunchKernelGGL(k_emit, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], bins->pair_off, proj->rec,
-                           proj->cellmask, n, vt_dev, bins->keys, bins->inst_src);
+                           proj->cellmask, n, vt_dev, bins->keys, bins->vals);
     RGS_LAUNCH_CHECK();
     const int key_bits = L + bits_for((uint64_t)total_tiles);
     if (key_bits > 32) return RGS_E_UNSUPPORTED;
-    // the values are the emission positions, generated by the first pass
-    if (sync) st = radix_sort_u32_index(bins->keys, bins->vals, keys_alt, vals_alt, n_inst, key_bits, rws, s);
-    else st = radix_sort_u32_index_dev(bins->keys, bins->vals, keys_alt, vals_alt, &cnt[1], n_inst, key_bits, rws, s);
+    if (sync) st = radix_sort_u32_u64(bins->keys, bins->vals, keys_alt, vals_alt, n_inst, key_bits, rws, s);
+    else st = radix_sort_u32_u64_dev(bins->keys, bins->vals, keys_alt, vals_alt, &cnt[1], n_inst, key_bits, rws, s);
     if (st != RGS_OK) return st;
 
     // 4. slots

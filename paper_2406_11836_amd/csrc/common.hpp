@@ -210,15 +210,13 @@ rgs_status scan_tile_sums(uint32_t* partial, DevN dn, int64_t tile, uint32_t* to
 size_t radix_ws_bytes(int64_t n);
 // Stable LSD sort of (key, value) by key bits [0, bits); the result ends in
 // keys/vals (the alt buffers are scratch of the same size).
+rgs_status radix_sort_u32_u64(uint32_t* keys, uint64_t* vals, uint32_t* keys_alt, uint64_t* vals_alt,
+                              int64_t n, int bits, void* ws, hipStream_t s);
 rgs_status radix_sort_u32_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                               int64_t n, int bits, void* ws, hipStream_t s);
 // The same, with n read on the device (upper bound n_max for the grid).
+rgs_status radix_sort_u32_u64_dev(uint32_t* keys, uint64_t* vals, uint32_t* keys_alt, uint64_t* vals_alt,
+                                  const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s);
 rgs_status radix_sort_u32_u32_dev(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                                   const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s);
-// Stable sort of keys whose values are their input positions 0 .. n-1: vals
-// is output only (written by the first pass; one pass runs even for bits = 0).
-rgs_status radix_sort_u32_index(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                                int bits, void* ws, hipStream_t s);
-rgs_status radix_sort_u32_index_dev(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
-                                    const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s);
 }  // namespace rgs

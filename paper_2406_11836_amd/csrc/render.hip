@@ -121,8 +121,7 @@ __device__ __forceinline__ uint32_t quad_mask_ellipse(uint2 rr, int tx, int ty, 
 // skips Gaussians that cannot touch its quadrant with a scalar branch.
 template <bool STATS>
 __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ rec,
-                                                    const uint32_t* __restrict__ vals,
-                                                    const uint32_t* __restrict__ inst_src,
+                                                    const uint64_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
                                                     const uint32_t* __restrict__ slot_order,
@@ -171,7 +170,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
         if (lane == 0) s_alive[w] = alive != 0ull ? 1u : 0u;
         const uint32_t idx = base + tid;
         if (idx < end) {
-            const uint32_t src = inst_src[vals[idx]];
+            const uint32_t src = (uint32_t)(vals[idx] >> 32);
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
             const float4 a = rp[0];
             const float4 b = rp[1], cl = rp[2], r4 = rp[3];
@@ -259,11 +258,11 @@ rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, co
     if (slot_bound <= 0) return RGS_OK;
     if (stats)
         hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec,
-                           bins->vals, bins->inst_src, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
+                           bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
                            kd->box_hi, eps_T, out->C, out->T, out->last, reinterpret_cast<unsigned long long*>(stats));
     else
         hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec,
-                           bins->vals, bins->inst_src, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
+                           bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
                            kd->box_hi, eps_T, out->C, out->T, out->last, nullptr);
     return launch_check();
 }
@@ -353,8 +352,7 @@ __device__ __forceinline__ PixTerms pix_step(BwdPix& P, bool contrib, float d2, 
 
 template <bool STATS>
 __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ rec,
-                                                    const uint32_t* __restrict__ vals,
-                                                    const uint32_t* __restrict__ inst_src,
+                                                    const uint64_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
                                                     const uint32_t* __restrict__ slot_order,
@@ -421,15 +419,15 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
     const uint32_t len = end - begin;
     // instances never reached by any pixel get zero records
     for (uint32_t k = bmax + tid; k < len; k += 128) {
-        float* rp = records + (size_t)vals[begin + k] * RD_REC;
+        float* rp = records + (size_t)(uint32_t)vals[begin + k] * RD_REC;
 #pragma unroll
         for (int c = 0; c < RD_REC; ++c) rp[c] = 0.f;
     }
     const float hx0 = (float)(tx * 16), hy0 = (float)(ty * 16 + w * 8);
     for (int bstart = bmax == 0 ? -1 : (int)(((bmax - 1) / NB) * NB); bstart >= 0; bstart -= NB) {
         if (tid < NB && (uint32_t)bstart + tid < bmax) {
-            const uint32_t jj = vals[begin + bstart + tid];
-            const uint32_t src = inst_src[jj];
+            const uint64_t vv = vals[begin + bstart + tid];
+            const uint32_t src = (uint32_t)(vv >> 32);
             const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
             const float4 cl = rp[2];
             const float4 a = rp[0], b = rp[1], r4 = rp[3];
@@ -437,7 +435,7 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
             sB[tid] = b;
             sCl[tid] = cl;
             sR[tid] = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
-            sJ[tid] = jj;
+            sJ[tid] = (uint32_t)vv;
         }
         for (int k = tid; k < 2 * NB * 9; k += 128) (&sG[0][0][0])[k] = 0.f;
         __syncthreads();
@@ -730,12 +728,12 @@ rgs_status render_bwd_records_launch(const rgs_partials_grad* dparts, const rgs_
     const BwdWs w = carve_bwd(bins, ws);
     if (slot_bound <= 0) return RGS_OK;
     if (stats)
-        hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals, bins->inst_src,
+        hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
                            parts->T, parts->last, dparts->dC, dparts->dT, w.records,
                            reinterpret_cast<unsigned long long*>(stats));
     else
-        hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals, bins->inst_src,
+        hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
                            parts->T, parts->last, dparts->dC, dparts->dT, w.records, nullptr);
     return launch_check();

@@ -11,8 +11,7 @@
 // key stably inside its tile: every wave walks its strip in order, finds the
 // lanes sharing its digit with eight ballots, and keeps a running count per
 // digit in LDS; keys are then reordered in LDS by digit so that the global
-// writes come out as contiguous runs.  A sort whose values are the input
-// positions reads no values: the first pass generates them.
+// writes come out as contiguous runs.
 #include "common.hpp"
 
 namespace rgs {
@@ -250,7 +249,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
             const int64_t i = base + (int64_t)w * RS_WAVE_ITEMS + k * 64 + lane;
             const bool valid = i < n;
             key[k] = valid ? keys_in[i] : 0u;
-            val[k] = valid ? (vals_in ? vals_in[i] : (V)i) : V(0);  // no input values: the input position
+            val[k] = valid ? vals_in[i] : V(0);
             const uint32_t d = (key[k] >> shift) & 0xffu;
             uint64_t m = __ballot(valid);
     #pragma unroll
@@ -323,34 +322,30 @@ size_t radix_ws_bytes(int64_t n) {
 
 template <typename V>
 static rgs_status radix_sort_impl(uint32_t* keys, V* vals, uint32_t* keys_alt, V* vals_alt, int64_t n,
-                                  const uint32_t* n_dev, int bits, bool index_vals, void* ws, hipStream_t s) {
-    if (n <= 0 || (bits <= 0 && !index_vals)) return RGS_OK;
+                                  const uint32_t* n_dev, int bits, void* ws, hipStream_t s) {
+    if (n <= 0 || bits <= 0) return RGS_OK;
     int64_t tiles = (n + RS_TILE - 1) / RS_TILE;
     size_t h = (size_t)256 * tiles * sizeof(uint32_t);
     size_t hpad = (h + 255) & ~size_t(255);
     uint32_t* hist = reinterpret_cast<uint32_t*>(ws);
     uint32_t* offs = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + hpad);
     uint32_t* dtot = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + 2 * hpad);  // [256]
-    int passes = bits > 0 ? (bits + 7) / 8 : 1;
+    int passes = (bits + 7) / 8;
     const unsigned grid = (unsigned)(n_dev && tiles > DEV_GRID ? DEV_GRID : tiles);
-    // pass p reads buffer p & 1 and writes the other; index values are
-    // generated by the first pass instead of read
-    uint32_t* kb[2] = {keys, keys_alt};
-    V* vb[2] = {vals, vals_alt};
+    uint32_t *ki = keys, *ko = keys_alt;
+    V *vi = vals, *vo = vals_alt;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
-        uint32_t* ki = kb[p & 1];
-        const V* vi = (p == 0 && index_vals) ? nullptr : vb[p & 1];
         hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(RS_THREADS), 0, s, ki, n, n_dev, shift, hist,
                            (int)tiles);
         hipLaunchKernelGGL(k_rs_colscan, dim3(256), dim3(RS_THREADS), 0, s, hist, n, n_dev, (int)tiles, offs, dtot);
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rs_scatter<V>), dim3(grid), dim3(RS_THREADS), 0, s, ki, vi,
-                           n, n_dev, shift, offs, dtot, (int)tiles, kb[(p + 1) & 1], vb[(p + 1) & 1]);
+                           n, n_dev, shift, offs, dtot, (int)tiles, ko, vo);
         RGS_LAUNCH_CHECK();
+        uint32_t* tk = ki; ki = ko; ko = tk;
+        V* tv = vi; vi = vo; vo = tv;
     }
-    if (passes & 1) {
-        const uint32_t* ki = keys_alt;
-        const V* vi = vals_alt;
+    if (ki != keys) {
         // odd number of passes: copy back (the elements in use only)
         const int64_t g0 = (n + 255) / 256;
         const unsigned g = (unsigned)(g0 > DEV_GRID * 8 ? DEV_GRID * 8 : g0);
@@ -360,21 +355,21 @@ static rgs_status radix_sort_impl(uint32_t* keys, V* vals, uint32_t* keys_alt, V
     return RGS_OK;
 }
 
+rgs_status radix_sort_u32_u64(uint32_t* keys, uint64_t* vals, uint32_t* keys_alt, uint64_t* vals_alt, int64_t n,
+                              int bits, void* ws, hipStream_t s) {
+    return radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, nullptr, bits, ws, s);
+}
 rgs_status radix_sort_u32_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
                               int bits, void* ws, hipStream_t s) {
-    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, nullptr, bits, false, ws, s);
+    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, nullptr, bits, ws, s);
+}
+rgs_status radix_sort_u32_u64_dev(uint32_t* keys, uint64_t* vals, uint32_t* keys_alt, uint64_t* vals_alt,
+                                  const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s) {
+    return radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n_max, n_dev, bits, ws, s);
 }
 rgs_status radix_sort_u32_u32_dev(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                                   const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s) {
-    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n_max, n_dev, bits, false, ws, s);
-}
-rgs_status radix_sort_u32_index(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                                int bits, void* ws, hipStream_t s) {
-    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, nullptr, bits, true, ws, s);
-}
-rgs_status radix_sort_u32_index_dev(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
-                                    const uint32_t* n_dev, int64_t n_max, int bits, void* ws, hipStream_t s) {
-    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n_max, n_dev, bits, true, ws, s);
+    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n_max, n_dev, bits, ws, s);
 }
 
 }  // namespace rgs

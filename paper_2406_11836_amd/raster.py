@@ -252,14 +252,13 @@ class Rasterizer:
         while True:
             slot_cap = min(cap, T * K)
             bins["keys"] = self._buf("keys", cap, torch.int32)
-            bins["vals"] = self._buf("vals", cap, torch.int32)
-            bins["inst_src"] = self._buf("inst_src", cap, torch.int32)
+            bins["vals"] = self._buf("vals", cap, torch.int64)
             bins["slot_key"] = self._buf("slot_key", slot_cap, torch.int32)
             bins["slot_range"] = self._buf("slot_range", 2 * slot_cap, torch.int32)
             bins["slot_order"] = self._buf("slot_order", slot_cap, torch.int32)
             bs = L.Bins()
             bs.capacity, bs.slot_capacity = cap, slot_cap
-            for k in ("keys", "vals", "inst_src", "pair_src", "pair_off", "pair_rank", "slot_key", "slot_range", "tile_slot",
+            for k in ("keys", "vals", "pair_src", "pair_off", "pair_rank", "slot_key", "slot_range", "tile_slot",
                       "slot_order", "counters"):
                 setattr(bs, k, bins[k].data_ptr())
             ws_bytes = lib.rgs_bin_sort_workspace(n, V, T, kd.L, cap)

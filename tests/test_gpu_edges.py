@@ -73,8 +73,8 @@ def test_screen_filling_gaussian(rast):
 
 
 def test_single_tile_one_cell(rast):
-    """A 16x16 image and L = 0: the (tile, cell) key has no bits, the sort
-    still writes the emission positions (in order) and the image matches."""
+    """A 16x16 image and L = 0: the (tile, cell) key has no bits, so no sort
+    pass runs; the instances stay in emission order and the image matches."""
     p = scenes.scene_uniform(400, seed=11, D=1, mu_s=-2.5, extent=0.5)
     dp = device_params(p)
     kd = rast.kd_partition(dp, 0)
@@ -82,8 +82,8 @@ def test_single_tile_one_cell(rast):
     st = rast.forward(dp, kd, [cam], EPS_T)
     n_inst = st.bins_struct.n_instances
     assert n_inst == 400
-    pos = st.bins["vals"][:n_inst].cpu().numpy().view(np.uint32)
-    assert np.array_equal(pos, np.arange(n_inst))
+    vals = st.bins["vals"][:n_inst].cpu().numpy().view(np.uint64)
+    assert np.array_equal(vals & np.uint64(0xffffffff), np.arange(n_inst, dtype=np.uint64))
     okd = oracle.kd_partition(p["means"], p["log_scales"], 0)
     order, _ = oracle.cell_order(0, okd["split"], cam["o"])
     pr = oracle.project(p, cam, okd, 0)
@@ -155,8 +155,7 @@ def test_needle_footprints(needles):
     okeys, ogids = oracle.bins(pr, rank_of, L, (W + 15) // 16)
     n_inst = st.bins_struct.n_instances
     keys = st.bins["keys"][:n_inst].cpu().numpy().view(np.uint32)
-    pos = st.bins["vals"][:n_inst].cpu().numpy().view(np.uint32).astype(np.int64)
-    src = st.bins["inst_src"][:n_inst].cpu().numpy().view(np.uint32).astype(np.int64)[pos]
+    src = (st.bins["vals"][:n_inst].cpu().numpy().view(np.uint64) >> np.uint64(32)).astype(np.int64)
     assert np.array_equal(keys, okeys) and np.array_equal(src % n, ogids.astype(np.int64))
     r = oracle.render(pr, cam, okd, order, oracle.all_pixels(W, H), EPS_T)
     err = np.abs(st.image.cpu().numpy().reshape(3, -1).T - r["img"]).max()
@@ -213,8 +212,7 @@ def test_large_footprints_bins(rast):
     okeys, ogids = oracle.bins(pr, rank_of, L, (W + 15) // 16)
     n_inst = st.bins_struct.n_instances
     keys = st.bins["keys"][:n_inst].cpu().numpy().view(np.uint32)
-    pos = st.bins["vals"][:n_inst].cpu().numpy().view(np.uint32).astype(np.int64)
-    src = st.bins["inst_src"][:n_inst].cpu().numpy().view(np.uint32).astype(np.int64)[pos]
+    src = (st.bins["vals"][:n_inst].cpu().numpy().view(np.uint64) >> np.uint64(32)).astype(np.int64)
     assert n_inst == len(okeys)
     assert np.array_equal(keys, okeys) and np.array_equal(src % n, ogids.astype(np.int64))
 

@@ -124,12 +124,13 @@ def test_bins_bit_exact(name, rast):
     n_inst = st.bins_struct.n_instances
     assert n_inst == len(okeys)
     keys = st.bins["keys"][:n_inst].cpu().numpy().view(np.uint32)
-    pos = st.bins["vals"][:n_inst].cpu().numpy().view(np.uint32).astype(np.int64)
-    # emission positions: a permutation, contiguous per pair in (depth, gid) order
-    assert np.array_equal(np.sort(pos), np.arange(n_inst))
-    src = st.bins["inst_src"][:n_inst].cpu().numpy().view(np.uint32).astype(np.int64)[pos]
+    vals = st.bins["vals"][:n_inst].cpu().numpy().view(np.uint64)
+    src = (vals >> np.uint64(32)).astype(np.int64)
     assert np.array_equal(keys, okeys)
     assert np.array_equal(src % n, ogids.astype(np.int64))
+    # emission positions: a permutation, contiguous per pair in (depth, gid) order
+    pos = (vals & np.uint64(0xffffffff)).astype(np.int64)
+    assert np.array_equal(np.sort(pos), np.arange(n_inst))
 
 
 @pytest.mark.parametrize("name", ["c1", "mini2", "near"])
