@@ -325,18 +325,18 @@ struct BwdPix {
     uint32_t last;
 };
 
-// One pixel's share of an instance's gradient.  A lane that does not
-// contribute takes sigma = 0, so 1 / (1 - sigma) = 1 exactly, T and <dC, B>
-// stay as they are, and every term returned is zero.
+// One pixel's share of an instance's gradient.  A pixel that does not
+// contribute comes with d^2 = +inf: G = 0 and sigma = 0, so 1 / (1 - sigma) = 1
+// exactly, T and <dC, B> stay as they are, and every term returned is zero.
 struct PixTerms {
     float q, dsg_g, G, wc;
 };
 
-__device__ __forceinline__ PixTerms pix_step(BwdPix& P, bool contrib, float d2, float alpha, float4 cl) {
+__device__ __forceinline__ PixTerms pix_step(BwdPix& P, float d2, float alpha, float4 cl) {
     PixTerms r;
     r.G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
     const float aG = alpha * r.G;
-    const float sgm = contrib ? fminf(0.99f, aG) : 0.0f;
+    const float sgm = fminf(0.99f, aG);
     const float rom = __builtin_amdgcn_rcpf(1.0f - sgm);
     const float Tb = P.T * rom;  // transmittance before this contribution
     const float dot = fmaf(P.gC2, cl.z, fmaf(P.gC1, cl.y, P.gC0 * cl.x)) - P.gB;  // <dC, c - B>
@@ -345,7 +345,7 @@ __device__ __forceinline__ PixTerms pix_step(BwdPix& P, bool contrib, float d2, 
     P.gB = fmaf(sgm, dot, P.gB);  // B <- B + sigma (c - B)
     P.T = Tb;
     // clamped at 0.99: no gradient to alpha or the footprint
-    r.dsg_g = (contrib && aG < 0.99f) ? dsg : 0.0f;
+    r.dsg_g = aG < 0.99f ? dsg : 0.0f;
     r.q = aG * r.dsg_g;
     return r;
 }
@@ -460,45 +460,47 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
             const float4 b = sB[t];
             const float dy = fyp - a.y;
             const float edy = b.x * dy;
-            float dx[2], d2[2];
-            bool con[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                dx[h] = P[h].fx - a.x;
-                const float u = fmaf(a.w, dy, dx[h]);  // d^2 = ca u^2 + e dy^2
-                d2[h] = fmaf(edy, dy, (a.z * u) * u);
-                con[h] = pos1 <= P[h].last && d2[h] <= b.z;
-                if (STATS && pos1 <= P[h].last) {
-                    // pairs the backward must re-test: pixel inside the rectangle, at or before its last contributor
-                    const uint2 rr = sR[t];
-                    n_eval += (pxs[h] >= (int)(int16_t)(rr.x & 0xffffu) && pxs[h] <= (int)(int16_t)(rr.x >> 16) &&
-                               py >= (int)(int16_t)(rr.y & 0xffffu) && py <= (int)(int16_t)(rr.y >> 16)) ? 1u : 0u;
-                }
+            const float dx0 = P[0].fx - a.x, dx1 = P[1].fx - a.x;
+            const float u0 = fmaf(a.w, dy, dx0), u1 = fmaf(a.w, dy, dx1);  // d^2 = ca u^2 + e dy^2
+            const float d20 = fmaf(edy, dy, (a.z * u0) * u0), d21 = fmaf(edy, dy, (a.z * u1) * u1);
+            bool c0 = pos1 <= P[0].last && d20 <= b.z;
+            bool c1 = pos1 <= P[1].last && d21 <= b.z;
+            if (STATS) {
+                // pairs the backward must re-test: pixel inside the rectangle, at or before its last contributor
+                const uint2 rr = sR[t];
+                const bool rowin = py >= (int)(int16_t)(rr.y & 0xffffu) && py <= (int)(int16_t)(rr.y >> 16);
+                const int xl = (int)(int16_t)(rr.x & 0xffffu), xh = (int)(int16_t)(rr.x >> 16);
+                n_eval += (pos1 <= P[0].last && rowin && pxs[0] >= xl && pxs[0] <= xh) ? 1u : 0u;
+                n_eval += (pos1 <= P[1].last && rowin && pxs[1] >= xl && pxs[1] <= xh) ? 1u : 0u;
             }
-            if (__ballot(con[0] || con[1]) == 0ull) continue;
+            if (__ballot(c0 || c1) == 0ull) continue;
             const float4 cl = sCl[t];
             if (!((inside >> t) & 1ull)) {  // not interior to the cell: the indicator of Eq. 6
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const float x0 = fmaf(b.w, P[h].D0, o0), x1 = fmaf(b.w, P[h].D1, o1), x2 = fmaf(b.w, P[h].D2, o2);
-                    con[h] = con[h] && (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
-                             (x2 < bhi2);
-                }
-                if (__ballot(con[0] || con[1]) == 0ull) continue;
+                const float x0 = fmaf(b.w, P[0].D0, o0), y0 = fmaf(b.w, P[0].D1, o1), z0 = fmaf(b.w, P[0].D2, o2);
+                const float x1 = fmaf(b.w, P[1].D0, o0), y1 = fmaf(b.w, P[1].D1, o1), z1 = fmaf(b.w, P[1].D2, o2);
+                c0 = c0 && (blo0 <= x0) && (x0 < bhi0) && (blo1 <= y0) && (y0 < bhi1) && (blo2 <= z0) && (z0 < bhi2);
+                c1 = c1 && (blo0 <= x1) && (x1 < bhi0) && (blo1 <= y1) && (y1 < bhi1) && (blo2 <= z1) && (z1 < bhi2);
+                if (__ballot(c0 || c1) == 0ull) continue;
             }
-            if (STATS) n_con += (con[0] ? 1u : 0u) + (con[1] ? 1u : 0u);
-            const PixTerms r0 = pix_step(P[0], con[0], d2[0], b.y, cl);
-            const PixTerms r1 = pix_step(P[1], con[1], d2[1], b.y, cl);
+            if (STATS) n_con += (c0 ? 1u : 0u) + (c1 ? 1u : 0u);
+            // a pixel column of the wave where no lane contributes (the
+            // instance reaches one quadrant of the half only) is skipped: its
+            // step would leave T and <dC, B> as they are and add zeros
+            const float d2c0 = c0 ? d20 : INFINITY, d2c1 = c1 ? d21 : INFINITY;
+            const bool any0 = __ballot(c0) != 0ull, any1 = __ballot(c1) != 0ull;
+            PixTerms r0 = {0.f, 0.f, 0.f, 0.f}, r1 = {0.f, 0.f, 0.f, 0.f};
+            if (any0) r0 = pix_step(P[0], d2c0, b.y, cl);
+            if (any1) r1 = pix_step(P[1], d2c1, b.y, cl);
             // Raw sums over the lane's two pixels; the conic and constant
             // factors are applied per instance after the reduction
             // (dL/d(d^2) = -q / 2)
             float g[9];
-            const float qx0 = r0.q * dx[0], qx1 = r1.q * dx[1];
-            g[0] = qx0 + qx1;                          // q dx
-            g[1] = (r0.q + r1.q) * dy;                 // q dy
-            g[2] = fmaf(qx1, dx[1], qx0 * dx[0]);      // q dx^2
-            g[3] = g[0] * dy;                          // q dx dy
-            g[4] = g[1] * dy;                          // q dy^2
+            const float qx0 = r0.q * dx0, qx1 = r1.q * dx1;
+            g[0] = qx0 + qx1;                      // q dx
+            g[1] = (r0.q + r1.q) * dy;             // q dy
+            g[2] = fmaf(qx1, dx1, qx0 * dx0);      // q dx^2
+            g[3] = g[0] * dy;                      // q dx dy
+            g[4] = g[1] * dy;                      // q dy^2
             g[5] = fmaf(r1.dsg_g, r1.G, r0.dsg_g * r0.G);
             g[6] = fmaf(r1.wc, P[1].gC0, r0.wc * P[0].gC0);
             g[7] = fmaf(r1.wc, P[1].gC1, r0.wc * P[0].gC1);
