@@ -100,9 +100,23 @@ __global__ __launch_bounds__(BN_THREADS) void k_pair_counts(const uint32_t* __re
     }
 }
 
-// pair_off[pairs] = total instances.
-__global__ void k_pair_off_tail(uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ cnt) {
-    if (threadIdx.x == 0) pair_off[cnt[0]] = cnt[1];
+// pair_off[pairs] = total instances.  With guard set (no host copy of the
+// instance count): if the count exceeds the capacity, record it in
+// counters[3] and zero the pair, instance and slot counts so that every later
+// kernel of the pass finds no work; else counters[3] = 0.
+__global__ void k_pair_off_tail(uint32_t* __restrict__ pair_off, uint32_t* __restrict__ cnt, int guard,
+                                int64_t capacity) {
+    if (threadIdx.x != 0) return;
+    pair_off[cnt[0]] = cnt[1];
+    if (!guard) return;
+    if ((int64_t)cnt[1] > capacity) {
+        cnt[3] = cnt[1];
+        cnt[0] = 0u;
+        cnt[1] = 0u;
+        cnt[2] = 0u;
+    } else {
+        cnt[3] = 0u;
+    }
 }
 
 // Position of the c-th set bit (0-based) of a 64-bit mask.
@@ -302,23 +316,6 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __re
     }
 }
 
-// Without a host copy of the instance count: if it exceeds the capacity,
-// record it in counters[3] and zero the pair, instance and slot counts so that
-// every later kernel of the pass finds no work; else counters[3] = 0.
-__global__ void k_capacity_guard(uint32_t* __restrict__ cnt, int64_t capacity) {
-    if (threadIdx.x != 0) return;
-    if ((int64_t)cnt[1] > capacity) {
-        cnt[3] = cnt[1];
-        cnt[0] = 0u;
-        cnt[1] = 0u;
-        cnt[2] = 0u;
-    } else {
-        cnt[3] = 0u;
-    }
-}
-
-// Flags of the non-empty dense entries; block 0 also clears the 64 size-class
-// counters used by the launch order below (they run after this kernel).
 __global__ __launch_bounds__(BN_THREADS) void k_slot_flags(const uint32_t* __restrict__ dstart, int64_t m,
                                                            uint32_t* __restrict__ flag, uint32_t* __restrict__ cls) {
     int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
@@ -485,7 +482,8 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
                                   bins->pair_rank, flag);
     if ((st = exclusive_scan_u32_dev(flag, bins->pair_off, DevN{&cnt[0], m, 1, 1}, m, &cnt[1], sws, s)) != RGS_OK)
         return st;
-    hipLaunchKernelGGL(k_pair_off_tail, dim3(1), dim3(64), 0, s, bins->pair_off, cnt);
+    // the tail of pair_off, and without a host copy the capacity guard
+    hipLaunchKernelGGL(k_pair_off_tail, dim3(1), dim3(64), 0, s, bins->pair_off, cnt, sync ? 0 : 1, bins->capacity);
     int64_t n_inst, slot_bound;
     if (sync) {
         uint32_t h_cnt[2] = {0u, 0u};
@@ -498,7 +496,6 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
         if (n_inst > bins->capacity || slot_bound > bins->slot_capacity) return RGS_E_CAPACITY;
     } else {
         // the count stays on the device; grids are sized by the capacity
-        hipLaunchKernelGGL(k_capacity_guard, dim3(1), dim3(64), 0, s, cnt, bins->capacity);
         bins->n_instances = -1;
         n_inst = bins->capacity;
         slot_bound = n_inst < dense ? n_inst : dense;
