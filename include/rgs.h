@@ -149,7 +149,8 @@ typedef struct {
     uint32_t *slot_range;   /* [slot_capacity][2] begin, end into keys/vals */
     uint32_t *tile_slot;    /* [total_tiles+1] first slot of each global tile (slots of a tile are in view order) */
     uint32_t *slot_order;   /* [slot_capacity] slots by decreasing size class (the render launch order) */
-    uint32_t *counters;     /* [4]: pairs, instances, slots, required instances if over capacity (async) */
+    uint32_t *counters;     /* [4]: pairs, instances, slots, required instances if over capacity (async; else 0);
+                               all four written by every bin_sort call */
     int64_t n_instances;    /* [out, host] */
 } rgs_bins;
 

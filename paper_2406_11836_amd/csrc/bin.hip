@@ -103,13 +103,14 @@ __global__ __launch_bounds__(BN_THREADS) void k_pair_counts(const uint32_t* __re
 // pair_off[pairs] = total instances.  With guard set (no host copy of the
 // instance count): if the count exceeds the capacity, record it in
 // counters[3] and zero the pair, instance and slot counts so that every later
-// kernel of the pass finds no work; else counters[3] = 0.
+// kernel of the pass finds no work; else (and always without guard)
+// counters[3] = 0.  Every counter is written by the pass: the caller need not
+// clear them.
 __global__ void k_pair_off_tail(uint32_t* __restrict__ pair_off, uint32_t* __restrict__ cnt, int guard,
                                 int64_t capacity) {
     if (threadIdx.x != 0) return;
     pair_off[cnt[0]] = cnt[1];
-    if (!guard) return;
-    if ((int64_t)cnt[1] > capacity) {
+    if (guard && (int64_t)cnt[1] > capacity) {
         cnt[3] = cnt[1];
         cnt[0] = 0u;
         cnt[1] = 0u;

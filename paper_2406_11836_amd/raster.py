@@ -244,7 +244,7 @@ class Rasterizer:
         K = 1 << kd.L
         bins = dict(pair_src=self._buf("pair_src", m, torch.int32), pair_off=self._buf("pair_off", m + 1, torch.int32),
                     pair_rank=self._buf("pair_rank", m, torch.int32), tile_slot=self._buf("tile_slot", T + 1, torch.int32),
-                    counters=self._buf("counters", 4, torch.int32).zero_())
+                    counters=self._buf("counters", 4, torch.int32))
         cap = max(self.capacity_hint, 1)
         # no host wait in binning when an earlier pass sized the buffers and the
         # slot bound stays small (the caller checks FwdState.overflow())
