@@ -91,13 +91,17 @@ __global__ __launch_bounds__(BN_THREADS) void k_view_keys(const uint32_t* __rest
 __global__ __launch_bounds__(BN_THREADS) void k_pair_counts(const uint32_t* __restrict__ pair_src,
                                                             const uint32_t* __restrict__ n_dev, int64_t m_max,
                                                             const uint32_t* __restrict__ count,
-                                                            int32_t* __restrict__ pair_rank, uint32_t* __restrict__ cnt) {
+                                                            int32_t* __restrict__ pair_rank, uint32_t* __restrict__ cnt,
+                                                            uint32_t* __restrict__ fill, int64_t n_fill) {
     const int64_t np = (int64_t)*n_dev;
     for (int64_t r = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x; r < np; r += (int64_t)gridDim.x * BN_THREADS) {
         const uint32_t s = pair_src[r];
         pair_rank[s] = (int32_t)r;
         cnt[r] = count[s];
     }
+    // the slot table's empty marks, needed after the instance sort
+    for (int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x; i < n_fill; i += (int64_t)gridDim.x * BN_THREADS)
+        fill[i] = 0xffffffffu;
 }
 
 // pair_off[pairs] = total instances.  With guard set (no host copy of the
@@ -479,8 +483,12 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
             return st;
     }
     // 2. instance offsets per ordered pair; the instance count goes to the host
-    if (m > 0) hipLaunchKernelGGL(k_pair_counts, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], m, proj->count,
-                                  bins->pair_rank, flag);
+    // (with the empty marks of the dense slot table: dstart = ~0)
+    if (m > 0)
+        hipLaunchKernelGGL(k_pair_counts, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], m, proj->count,
+                           bins->pair_rank, flag, dstart, dense);
+    else
+        hipLaunchKernelGGL(k_fill_u32, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, 0xffffffffu);
     if ((st = exclusive_scan_u32_dev(flag, bins->pair_off, DevN{&cnt[0], m, 1, 1}, m, &cnt[1], sws, s)) != RGS_OK)
         return st;
     // the tail of pair_off, and without a host copy the capacity guard
@@ -514,7 +522,6 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     if (st != RGS_OK) return st;
 
     // 4. slots
-    hipLaunchKernelGGL(k_fill_u32, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, 0xffffffffu);
     if (n_inst > 0)
         hipLaunchKernelGGL(k_slot_bounds, dgrid(n_inst), dim3(BN_THREADS), 0, s, bins->keys, &cnt[1], dense, dstart, dend);
     hipLaunchKernelGGL(k_slot_flags, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, dflag, cls);
