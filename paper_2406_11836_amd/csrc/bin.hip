@@ -313,11 +313,20 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __re
                                                             const uint32_t* __restrict__ n_dev, int64_t dense,
                                                             uint32_t* __restrict__ dstart, uint32_t* __restrict__ dend) {
     const int64_t n_inst = (int64_t)*n_dev;
-    for (int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x; i < n_inst; i += (int64_t)gridDim.x * BN_THREADS) {
-        const uint32_t k = keys[i];
-        if ((int64_t)k >= dense) continue;
-        if (i == 0 || keys[i - 1] != k) dstart[k] = (uint32_t)i;
-        if (i == n_inst - 1 || keys[i + 1] != k) dend[k] = (uint32_t)(i + 1);
+    const int lane = threadIdx.x & 63;
+    // a wave takes 64 consecutive keys per step; the neighbours come from the
+    // adjacent lanes, only the end lanes load theirs
+    for (int64_t w0 = (int64_t)blockIdx.x * BN_THREADS + (threadIdx.x & ~63); w0 < n_inst;
+         w0 += (int64_t)gridDim.x * BN_THREADS) {
+        const int64_t i = w0 + lane;
+        const bool valid = i < n_inst;
+        const uint32_t k = valid ? keys[i] : 0xffffffffu;
+        uint32_t prev = __shfl_up(k, 1, 64), next = __shfl_down(k, 1, 64);
+        if (lane == 0) prev = i > 0 ? keys[i - 1] : 0xffffffffu;
+        if (lane == 63 && i + 1 < n_inst) next = keys[i + 1];
+        if (!valid || (int64_t)k >= dense) continue;
+        if (i == 0 || prev != k) dstart[k] = (uint32_t)i;
+        if (i == n_inst - 1 || next != k) dend[k] = (uint32_t)(i + 1);
     }
 }
 
