@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 1
+#define RGS_ABI_VERSION 2
 #define RGS_TILE 16       /* screen tiles are 16 x 16 pixels */
 #define RGS_MAX_L 6       /* K = 2^L <= 64 cells */
 #define RGS_MAX_VIEWS 16  /* views per call */
@@ -118,7 +118,7 @@ typedef struct {
 } rgs_kdtree;
 
 /* Per-(view, Gaussian) projection output.  Where count is 0 (culled) only
-   count is written: rec, rect and cellmask hold whatever the buffers held. */
+   count is written: rec, rect, cellmask and depth hold whatever the buffers held. */
 typedef struct {
     float *rec;         /* [V*N][16]: mx, my, ca, k | e, alpha, tau, z | r, g, b, flags |
                            (footprint d^2 = ca (dx + k dy)^2 + e dy^2, i.e. the conic
@@ -134,6 +134,8 @@ typedef struct {
     uint32_t *count;    /* [V*N]: instances = |cellmask| * tiles of the rectangle that the
                            footprint's ellipse can reach (per tile row, the span of columns
                            holding a pixel centre of the padded ellipse); 0 = culled */
+    float *depth;       /* [V*N]: camera depth z (the same value as in rec): the key of the
+                           depth order, read densely by binning */
 } rgs_projected;
 
 /* Tile/cell instance lists and slots (one slot per non-empty (tile, cell)). */

@@ -209,7 +209,7 @@ rgs_status rgs_cell_order(int32_t L, const float* split_host, const float campos
     return RGS_OK;
 }
 
-static bool proj_ok(const rgs_projected* p) { return p && p->rec && p->rect && p->cellmask && p->count; }
+static bool proj_ok(const rgs_projected* p) { return p && p->rec && p->rect && p->cellmask && p->count && p->depth; }
 
 rgs_status rgs_project_sh(const rgs_gaussians* g, const rgs_camera* cams, int32_t n_views, const void* views_dev,
                           const rgs_kdtree* kd, const rgs_projected* out, rgs_stream stream) {

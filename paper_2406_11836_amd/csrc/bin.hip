@@ -43,7 +43,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_vis_count(const uint32_t* __rest
 // (k, wave, lane) order: one exclusive scan over the 64 (k, wave) ballot
 // counts gives every wave's offset for every k.
 __global__ __launch_bounds__(BN_THREADS) void k_vis_compact(const uint32_t* __restrict__ count,
-                                                            const float* __restrict__ rec, int64_t m,
+                                                            const float* __restrict__ depth, int64_t m,
                                                             const uint32_t* __restrict__ tile_off,
                                                             uint32_t* __restrict__ zkey, uint32_t* __restrict__ src_out) {
     __shared__ uint32_t s_c[VC_ITEMS * 4];
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_vis_compact(const uint32_t* __re
         if (f) {
             const int64_t i = base + k * BN_THREADS + threadIdx.x;
             const uint32_t p = t0 + s_c[k * 4 + w] + (uint32_t)__popcll(b & lt_mask);
-            zkey[p] = __float_as_uint(rec[i * RGS_REC_FLOATS + 7]);
+            zkey[p] = __float_as_uint(depth[i]);
             src_out[p] = (uint32_t)i;
         }
     }
@@ -480,7 +480,7 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
         hipLaunchKernelGGL(k_vis_count, dim3((unsigned)vtiles), dim3(BN_THREADS), 0, s, proj->count, m, pos);
     if ((st = scan_tile_sums(pos, DevN{nullptr, m, 1, 1}, VC_TILE, &cnt[0], s)) != RGS_OK) return st;
     if (m > 0)
-        hipLaunchKernelGGL(k_vis_compact, dim3((unsigned)vtiles), dim3(BN_THREADS), 0, s, proj->count, proj->rec, m, pos,
+        hipLaunchKernelGGL(k_vis_compact, dim3((unsigned)vtiles), dim3(BN_THREADS), 0, s, proj->count, proj->depth, m, pos,
                            zkey, bins->pair_src);
     RGS_LAUNCH_CHECK();
     if ((st = radix_sort_u32_u32_dev(zkey, bins->pair_src, zkey_alt, src_alt, &cnt[0], m, 32, rws, s)) != RGS_OK)

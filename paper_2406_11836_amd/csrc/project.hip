@@ -347,6 +347,7 @@ __global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, cons
         }
         out.count[src] = (uint32_t)__popcll(mask) * nt;
         out.cellmask[src] = mask;
+        out.depth[src] = p.z;
         const uint32_t rx = ((uint32_t)(uint16_t)r[0]) | ((uint32_t)(uint16_t)r[1] << 16);
         const uint32_t ry = ((uint32_t)(uint16_t)r[2]) | ((uint32_t)(uint16_t)r[3] << 16);
         reinterpret_cast<uint2*>(out.rect)[src] = make_uint2(rx, ry);

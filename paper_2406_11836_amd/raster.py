@@ -107,6 +107,7 @@ class FwdState:
         s = L.Projected()
         s.rec, s.rect = self.proj["rec"].data_ptr(), self.proj["rect"].data_ptr()
         s.cellmask, s.count = self.proj["cellmask"].data_ptr(), self.proj["count"].data_ptr()
+        s.depth = self.proj["depth"].data_ptr()
         return s
 
     def overflow(self) -> int:
@@ -235,9 +236,10 @@ class Rasterizer:
         ks = kd.struct()
         m = V * n
         proj = dict(rec=self._buf("rec", m * L.REC_FLOATS, torch.float32), rect=self._buf("rect", m * 4, torch.int16),
-                    cellmask=self._buf("cellmask", m, torch.int64), count=self._buf("count", m, torch.int32))
+                    cellmask=self._buf("cellmask", m, torch.int64), count=self._buf("count", m, torch.int32),
+                    depth=self._buf("depth", m, torch.float32))
         ps = L.Projected(proj["rec"].data_ptr(), proj["rect"].data_ptr(), proj["cellmask"].data_ptr(),
-                         proj["count"].data_ptr())
+                         proj["count"].data_ptr(), proj["depth"].data_ptr())
         L.check("rgs_project_sh", lib.rgs_project_sh(C.byref(g), cam_arr, V, _p(views), C.byref(ks), C.byref(ps), stream))
         _mark(marks, "project")
         T = int(lib.rgs_total_tiles(cam_arr, V))
