@@ -241,7 +241,8 @@ rgs_status rgs_cell_order(int32_t L, const float *split_host, const float campos
  * (conic), screen mean, cut threshold tau = min(9, 2 ln(255 alpha))
  * (contribution iff d^2 <= tau), SH colour 0.5 + sum f Y clamped at 0,
  * sample-pixel rectangle, the cell set (KD leaves met by the padded box of
- * the footprint's ray crossing points) and the instance count.
+ * the footprint's ray crossing points), the instance count and the camera
+ * depth (also dense in out->depth, the key of binning's depth order).
  * rec[11] holds flag bits (bit 0: the footprint lies in one cell). */
 /* If the views carry cell visibility masks, kd->center_cell must be set. */
 rgs_status rgs_project_sh(const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
