@@ -108,6 +108,9 @@ def test_project_bit_exact(name, rast):
     gpu_dec = rec[vis][:, :8]
     ora_dec = pr["dec32"][vis][:, [0, 1, 2, 8, 9, 7, 5, 6]]
     assert np.array_equal(gpu_dec.view(np.uint32), ora_dec.view(np.uint32))
+    # the dense depth array (binning's sort key) is the record's z, bit for bit
+    depth = st.proj["depth"][:n].cpu().numpy()
+    assert np.array_equal(depth[vis].view(np.uint32), pr["dec32"][vis][:, 6].view(np.uint32))
     # colour (value path, fp32 vs fp64)
     assert np.abs(rec[vis][:, 8:11] - pr["val"][vis][:, 7:10]).max() < 2e-5
     flags = rec[:, 11].view(np.uint32)
