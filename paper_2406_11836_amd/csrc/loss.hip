@@ -224,7 +224,21 @@ __global__ __launch_bounds__(LS_THREADS) void k_loss_final(const float* __restri
                                                            float* __restrict__ loss) {
     __shared__ double s_a[LS_THREADS], s_b[LS_THREADS];
     double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < nb; k += LS_THREADS) { a += part[2 * k]; b += part[2 * k + 1]; }
+    // the same order of additions per thread as one partial at a time; the
+    // loads of eight steps are issued before their adds
+    constexpr int U = 8;
+    int k = threadIdx.x;
+    for (; k + (U - 1) * LS_THREADS < nb; k += U * LS_THREADS) {
+        float2 pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pv[u] = reinterpret_cast<const float2*>(part)[k + u * LS_THREADS];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a += pv[u].x;
+            b += pv[u].y;
+        }
+    }
+    for (; k < nb; k += LS_THREADS) { a += part[2 * k]; b += part[2 * k + 1]; }
     s_a[threadIdx.x] = a;
     s_b[threadIdx.x] = b;
     __syncthreads();
