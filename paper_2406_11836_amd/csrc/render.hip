@@ -82,7 +82,7 @@ __device__ __forceinline__ bool box_hits(float mx, float my, float ca, float cb,
     if (lx <= 0.0f && hx >= 0.0f && ly <= 0.0f && hy >= 0.0f) return true;
     const float ica = __builtin_amdgcn_rcpf(ca), icc = __builtin_amdgcn_rcpf(cc);
     float qmin = INFINITY;
-#pragma unroll 1
+#pragma unroll
     for (int e = 0; e < 2; ++e) {
         const float ex = e ? hx : lx;  // vertical edge dx = ex
         const float dy = fminf(fmaxf(-(cb * ex) * icc, ly), hy);
@@ -106,7 +106,7 @@ __device__ __forceinline__ bool quad_hits(float mx, float my, float ca, float cb
 __device__ __forceinline__ uint32_t quad_mask_ellipse(uint2 rr, int tx, int ty, float mx, float my, float ca, float cb,
                                                       float cc, float tau) {
     uint32_t m = quad_mask(rr, tx, ty);
-#pragma unroll 1
+#pragma unroll
     for (int q = 0; q < 4; ++q)
         if ((m >> q) & 1u) {
             const float x0 = (float)(tx * 16 + (q & 1) * 8), y0 = (float)(ty * 16 + (q >> 1) * 8);
