@@ -23,7 +23,8 @@
  *     counter to the host (the instance count) and therefore waits once
  *     (rgs_bin_sort_async does not).
  *   - Argument errors are reported synchronously (RGS_E_ARG) and enqueue
- *     nothing.  A failed kernel launch returns RGS_E_HIP and records the HIP
+ *     nothing.  They include an output buffer that overlaps an input or
+ *     another output (byte ranges from the sizes each call implies).  A failed kernel launch returns RGS_E_HIP and records the HIP
  *     error code (rgs_last_hip_error, per thread).  Faults inside kernels
  *     surface at the caller's next synchronisation.
  *   - Degenerate data is not an error: Gaussians behind z_near, with a zero
@@ -48,11 +49,30 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 2
+#define RGS_ABI_VERSION 3
 #define RGS_TILE 16       /* screen tiles are 16 x 16 pixels */
 #define RGS_MAX_L 6       /* K = 2^L <= 64 cells */
 #define RGS_MAX_VIEWS 16  /* views per call */
 #define RGS_REC_FLOATS 16 /* floats per projected render record (64 bytes, one aligned line) */
+#define RGS_T_FLOOR 0x1p-100f /* a pixel always stops in a cell once T_k < max(eps_T, RGS_T_FLOOR) */
+
+/* How rgs_kd_partition places each node's cut (Sec. 3.3; Sec. 4.2, Table 2). */
+enum {
+    RGS_SPLIT_MEDIAN = 0,   /* the paper's KD tree: equal-count bisection */
+    RGS_SPLIT_MIDPOINT = 1  /* the fixed-size partition it is compared with: a uniform grid */
+};
+
+/* Which Gaussians each cell renders (rgs_project_sh). */
+enum {
+    RGS_CELLS_EXACT = 0,          /* every cell its footprint's ray crossing points can reach
+                                     (Eq. 6): the merged image equals the single-worker render */
+    RGS_CELLS_PAPER_SUBSETS = 1,  /* only cells k whose subset N_k (centre within the leaf box
+                                     inflated by D_i, Sec. 3.3) holds the Gaussian: contributions
+                                     whose crossing point lies elsewhere are lost ("escapes") */
+    RGS_CELLS_EXCLUSIVE = 2       /* the cell of the centre only, without the indicator of Eq. 6:
+                                     the cell-based methods the paper contrasts with (Sec. 2,
+                                     Sec. 4.2), whose borders leak */
+};
 
 typedef int32_t rgs_status;
 enum {
@@ -113,8 +133,10 @@ typedef struct {
     int32_t *center_cell;  /* [N] leaf containing each centre (output of rgs_kd_partition) */
     int32_t *counts;       /* [K] centres per leaf */
     uint32_t *own_mask;    /* [N][ceil(K/32)] the paper's subsets N_k, or NULL to skip */
-    float *cell_bounds;    /* [6][K] per cell: min x,y,z then max x,y,z of centre -/+ D_i over its
-                              Gaussians (empty cell: +inf / -inf), or NULL to skip */
+    float *cell_bounds;    /* [8][K] per cell: min x, y, z and max x, y, z of its centres (empty
+                              cell: +inf / -inf), the largest scale exp(log_scale) of its Gaussians
+                              (0 if empty), and 0; or NULL to skip.  rgs_cell_visibility reads a
+                              host copy; rgs_group_by_cell the device one. */
 } rgs_kdtree;
 
 /* Per-(view, Gaussian) projection output.  Where count is 0 (culled) only
@@ -177,13 +199,15 @@ size_t rgs_views_bytes(void);
  * per-view cell order ([host] rank_of[v][K]: rank of cell k in view v's merge
  * order, from rgs_cell_order).  Copies from host memory on `stream`; the
  * host arrays may be reused when the call returns.  Global tiles of view v
- * follow those of views 0..v-1 (16 x 16 tiles, row-major). */
+ * follow those of views 0..v-1 (16 x 16 tiles, row-major).  Returns
+ * RGS_E_UNSUPPORTED if the views hold 2^32 pixels or more in all, or if
+ * (total tiles << L) reaches 2^31 (pixel offsets and tile keys are 32-bit). */
 /* cell_visible ([host] n_views masks, or NULL = every cell): bit k clear
  * promises that no Gaussian whose centre lies in cell k (kd->center_cell) can
  * reach view v; rgs_project_sh then culls those Gaussians without reading
- * their parameters.  A caller that clears bits must be conservative (e.g. the
- * cell's centre bounds inflated by the largest 3-sigma extent, tested against
- * a padded frustum); a wrong mask changes the image. */
+ * their parameters.  rgs_cell_visibility computes such masks; a caller that
+ * clears bits by other means must be as conservative (a wrong mask changes
+ * the image). */
 rgs_status rgs_views_upload(const rgs_camera *cams, int32_t n_views, int32_t L,
                             const int32_t *rank_of, const uint64_t *cell_visible, void *views_dev,
                             rgs_stream stream);
@@ -199,11 +223,14 @@ int64_t rgs_total_tiles(const rgs_camera *cams, int32_t n_views);
 /* ------------------------------------------------------------------ */
 /* KD partition (Sec. 3.3)                                             */
 /* ------------------------------------------------------------------ */
-/* Depth-L tree: at depth l the axis is l mod 3 (X, Y, Z in turn) and the
- * split is the floor(n/2)-th smallest coordinate (0-based, IEEE total order)
- * of the node's centres; centres below the split go left, the rest right; an
- * empty node splits at the midpoint of its finite bounds (one finite bound:
- * that bound; none: 0).  Leaves are numbered by their path bits (left 0,
+/* Depth-L tree: at depth l the axis is l mod 3 (X, Y, Z in turn) and, with
+ * rule RGS_SPLIT_MEDIAN, the split is the floor(n/2)-th smallest coordinate
+ * (0-based, IEEE total order) of the node's centres; centres below the split
+ * go left, the rest right; an empty node splits at the midpoint of its finite
+ * bounds (one finite bound: that bound; none: 0).  With RGS_SPLIT_MIDPOINT
+ * every node splits at 0.5f * (lo + hi) of its extent inside the bounding box
+ * of all centres (0 if there are none): a uniform grid of 2^ceil(L/3) x
+ * 2^ceil((L-1)/3) x 2^floor(L/3) blocks.  Leaves are numbered by their path bits (left 0,
  * right 1), first level most significant.  own_mask, if not NULL, marks
  * N_k = { i : centre in the leaf box inflated by D_i on every face },
  * D_i = d_factor * max_a exp(log_scale_a) (the paper uses three times the
@@ -211,8 +238,8 @@ int64_t rgs_total_tiles(const rgs_camera *cams, int32_t n_views);
  * cell_bounds (the box of N_k's inflated centres: what a view must see for
  * cell k to matter, used for cell culling). */
 size_t rgs_kd_partition_workspace(int64_t n, int32_t L);
-rgs_status rgs_kd_partition(const rgs_gaussians *g, int32_t L, float d_factor, const rgs_kdtree *kd,
-                            void *ws, size_t ws_bytes, rgs_stream stream);
+rgs_status rgs_kd_partition(const rgs_gaussians *g, int32_t L, float d_factor, int32_t rule,
+                            const rgs_kdtree *kd, void *ws, size_t ws_bytes, rgs_stream stream);
 
 /* A copy of the Gaussians grouped by cell (Sec. 3.3: sub-model k holds the
  * Gaussians of its cell): out[j] = in[perm[j]], cells ascending, and inside
@@ -226,6 +253,22 @@ rgs_status rgs_kd_partition(const rgs_gaussians *g, int32_t L, float d_factor, c
 size_t rgs_group_by_cell_workspace(int64_t n);
 rgs_status rgs_group_by_cell(const rgs_gaussians *in, const rgs_kdtree *kd, int32_t L, const rgs_gaussians *out,
                              int32_t *perm, void *ws, size_t ws_bytes, rgs_stream stream);
+
+/* [host] Cell culling for a batch of views (Sec. 3.4: the manager hands a
+ * render request only to the sub-models it concerns).  cell_bounds_host:
+ * [8][K] as written by rgs_kd_partition; any number of views (not limited
+ * to RGS_MAX_VIEWS); visible: [n_views] masks, bit k set
+ * unless no Gaussian of cell k can reach view v.  Conservative: a cell is
+ * dropped only if, for every centre in its box and the cell's largest scale,
+ * the centre lies behind z_near or the footprint's rectangle misses the
+ * image on one side.  The bound covers the EWA linearisation at the clamped
+ * Jacobian (the footprint of an off-axis Gaussian reaches up to (1 + guard)
+ * times the 3-sigma radius), the 0.3 px^2 low-pass, tau <= 9 and the
+ * rectangle's rounding pads, so passing the masks to rgs_views_upload /
+ * rgs_views_pack changes no output.  Empty cells are dropped; cells with
+ * non-finite bounds are kept. */
+rgs_status rgs_cell_visibility(const rgs_camera *cams, int32_t n_views, int32_t L, const float *cell_bounds_host,
+                               uint64_t *visible);
 
 /* [host] The order in which any ray from campos visits the cells (Eq. 5's
  * permutation o_l): in-order traversal, near child first, near = left iff
@@ -244,10 +287,13 @@ rgs_status rgs_cell_order(int32_t L, const float *split_host, const float campos
  * the footprint's ray crossing points), the instance count and the camera
  * depth (also dense in out->depth, the key of binning's depth order).
  * rec[11] holds flag bits (bit 0: the footprint lies in one cell). */
-/* If the views carry cell visibility masks, kd->center_cell must be set. */
+/* cells (RGS_CELLS_*) restricts which cells a Gaussian is listed in:
+ * PAPER_SUBSETS needs kd->own_mask; EXCLUSIVE needs kd->center_cell and sets
+ * flag bit 0 (no indicator test).  If the views carry cell visibility masks,
+ * kd->center_cell must be set. */
 rgs_status rgs_project_sh(const rgs_gaussians *g, const rgs_camera *cams, int32_t n_views,
-                          const void *views_dev, const rgs_kdtree *kd, const rgs_projected *out,
-                          rgs_stream stream);
+                          const void *views_dev, const rgs_kdtree *kd, int32_t cells,
+                          const rgs_projected *out, rgs_stream stream);
 
 /* ------------------------------------------------------------------ */
 /* Binning and sorting                                                  */
@@ -285,7 +331,9 @@ rgs_status rgs_bin_sort_async(const rgs_projected *proj, int64_t n, const rgs_ca
  * slot's instances: the instance contributes iff d^2 <= tau and its crossing
  * point x = campos + z D(p) lies in cell k's box; sigma = min(0.99,
  * alpha exp(-d^2/2)); C_k += T_k sigma c; T_k *= 1 - sigma; a pixel stops
- * after the contribution that takes T_k below eps_T (eps_T = 0: never). */
+ * after the contribution that takes T_k below max(eps_T, RGS_T_FLOOR)
+ * (eps_T = 0: at the floor only; what lies behind it weighs less than 2^-100).
+ * eps_T must lie in [0, 1). */
 /* stats, if not NULL, must point to two device uint64 counters that are
  * incremented by the number of (pixel, instance) pairs the method must test
  * (pixel inside the Gaussian's rectangle and not yet stopped) and of pairs
@@ -364,6 +412,34 @@ rgs_status rgs_pair_reduce(const rgs_bins *bins, const rgs_projected *proj, int6
 rgs_status rgs_project_sh_bwd(const float *d_proj, const rgs_gaussians *g, const rgs_projected *proj,
                               const rgs_camera *cams, int32_t n_views, const void *views_dev,
                               const rgs_gaussians_grad *out, rgs_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Training: parameter update and re-partition reorder (Sec. 3.4, Sec. 4) */
+/* ------------------------------------------------------------------ */
+/* Adam with fp32 states and one learning rate per parameter group (the
+ * 3DGS optimiser the paper trains with; the position rate decays
+ * exponentially, which the caller passes per step in lr_means).  Per
+ * element: m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t = step >= 1.
+ * The SH rows of degree 0 (rows 0..2) use lr_sh_dc, the others lr_sh_rest.
+ * params, m and v are read and written in place (layouts as rgs_gaussians),
+ * grads is read; the four must not overlap. */
+typedef struct {
+    float lr_means, lr_log_scales, lr_quats, lr_opacity, lr_sh_dc, lr_sh_rest;
+    float beta1, beta2, eps;
+    int32_t step;
+} rgs_adam_params;
+rgs_status rgs_adam_step(const rgs_gaussians_grad *params, const rgs_gaussians_grad *grads,
+                         const rgs_gaussians_grad *m, const rgs_gaussians_grad *v, int64_t n, int32_t sh_degree,
+                         const rgs_adam_params *hp, rgs_stream stream);
+
+/* out row j = in row perm[j] for every parameter array (the same layouts;
+ * out must not overlap in or perm).  With perm from rgs_group_by_cell it
+ * carries per-Gaussian state (Adam's m and v) along when a re-partition
+ * regroups the parameters by cell.  perm entries outside [0, n) leave the
+ * row untouched. */
+rgs_status rgs_permute_gaussians(const rgs_gaussians *in, const int32_t *perm, const rgs_gaussians_grad *out,
+                                 rgs_stream stream);
 
 #ifdef __cplusplus
 }

@@ -68,7 +68,8 @@ def sh_basis(D: int, d):
     return Y[:n], dY[: 3 * n].reshape(n, 3)
 
 
-def kd_partition(means, log_scales, L: int, d_factor: float = 3.0):
+def kd_partition(means, log_scales, L: int, d_factor: float = 3.0, rule: int = 0):
+    """rule 0: equal-count bisection (the paper's KD tree); 1: fixed-size grid."""
     means = _f64(means)
     ls = _f64(log_scales)
     n = means.shape[1]
@@ -82,8 +83,8 @@ def kd_partition(means, log_scales, L: int, d_factor: float = 3.0):
     counts = np.zeros(K, np.int32)
     own = np.zeros((max(n, 1), Wm), np.uint32)
     f = lib().orc_kd_partition
-    f.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_double] + [C.c_void_p] * 7
-    rc = f(n, _p(means), _p(ls), L, d_factor, _p(split), _p(axis), _p(lo), _p(hi), _p(cc),
+    f.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int] + [C.c_void_p] * 7
+    rc = f(n, _p(means), _p(ls), L, d_factor, rule, _p(split), _p(axis), _p(lo), _p(hi), _p(cc),
            _p(counts), _p(own))
     if rc != 0:
         raise ValueError("orc_kd_partition failed")
@@ -108,8 +109,23 @@ def _split_arr(kd):
     return sp if sp.size else np.zeros(1, np.float32)
 
 
-def project(params, cam, kd, mode: int = 0):
-    """Per-Gaussian projection; mode 0 = mirror32 decisions, 1 = exact64."""
+def _cell_arrays(kd, n, cells):
+    """center_cell and own_mask rows for the subset modes (cells 1 and 2)."""
+    K = 1 << kd["L"]
+    Wm = (K + 31) // 32
+    if cells == 0:
+        return np.zeros(1, np.int32), np.zeros(1, np.uint32)
+    cc = np.ascontiguousarray(kd["center_cell"], np.int32).reshape(-1)
+    own = np.ascontiguousarray(kd["own_mask"], np.uint32).reshape(-1)
+    if cc.size < max(n, 1) or own.size < max(n, 1) * Wm:
+        raise ValueError("kd lacks center_cell / own_mask for this scene")
+    return cc, own
+
+
+def project(params, cam, kd, mode: int = 0, cells: int = 0):
+    """Per-Gaussian projection; mode 0 = mirror32 decisions, 1 = exact64.
+    cells: 0 the exact per-view cell sets, 1 the paper's subsets N_k,
+    2 exclusive subsets (the cell of the centre; cell-based methods)."""
     means, ls, q = _f64(params["means"]), _f64(params["log_scales"]), _f64(params["quats"])
     op, sh = _f64(params["opacity"]), _f64(params["sh"])
     D = int(params["sh_degree"])
@@ -123,13 +139,15 @@ def project(params, cam, kd, mode: int = 0):
     count = np.zeros(nn, np.uint32)
     camv = pack_camera(cam)
     sp = _split_arr(kd)
+    cc, own = _cell_arrays(kd, n, cells)
     f = lib().orc_project
-    f.argtypes = [C.c_int64, C.c_int] + [C.c_void_p] * 6 + [C.c_int, C.c_void_p, C.c_int] + [C.c_void_p] * 6
+    f.argtypes = [C.c_int64, C.c_int] + [C.c_void_p] * 6 + [C.c_int, C.c_void_p, C.c_int, C.c_int] + \
+        [C.c_void_p] * 8
     rc = f(n, D, _p(means), _p(ls), _p(q), _p(op), _p(sh), _p(camv), kd["L"], _p(sp),
-           mode, _p(dec), _p(val), _p(rect), _p(vis), _p(mask), _p(count))
+           mode, cells, _p(cc), _p(own), _p(dec), _p(val), _p(rect), _p(vis), _p(mask), _p(count))
     if rc != 0:
         raise ValueError("orc_project failed")
-    return dict(n=n, mode=mode, dec32=dec[:n], val=val[:n], rect=rect[:n], vis=vis[:n],
+    return dict(n=n, mode=mode, cells=cells, dec32=dec[:n], val=val[:n], rect=rect[:n], vis=vis[:n],
                 cellmask=mask[:n], count=count[:n])
 
 
@@ -148,6 +166,13 @@ def bins(proj, rank_of, L: int, tiles_x: int):
     if m < 0:
         raise RuntimeError("orc_bins capacity")
     return keys[:m], gids[:m]
+
+
+def _cells_args(proj, kd, keep):
+    cells = int(proj.get("cells", 0))
+    cc, own = _cell_arrays(kd, proj["n"], cells)
+    keep.extend([cc, own])
+    return cells, _p(cc), _p(own)
 
 
 def _render_args(proj, cam, kd, order, keep):
@@ -178,12 +203,14 @@ def render(proj, cam, kd, order, pix, eps_T: float = 0.0, restrict: bool = False
     pc = np.zeros((P, K, 3)); pt = np.zeros((P, K)); ncon = np.zeros(P, np.int32)
     f = lib().orc_render
     f.argtypes = [C.c_int64] + [C.c_void_p] * 5 + [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
-                                                   C.c_int64] + [C.c_void_p] * 9
+                                                   C.c_int64] + [C.c_void_p] * 9 + [C.c_int, C.c_void_p, C.c_void_p]
     keep = []
     a = _render_args(proj, cam, kd, order, keep)
     mode = proj["mode"] | (2 if restrict else 0)
     cm = np.ascontiguousarray(proj["cellmask"])
-    f(*a, mode, eps_T, P, _p(pix), _p(img), _p(Tf), _p(plain), _p(Tp), _p(pc), _p(pt), _p(ncon), _p(cm))
+    if f(*a, mode, eps_T, P, _p(pix), _p(img), _p(Tf), _p(plain), _p(Tp), _p(pc), _p(pt), _p(ncon), _p(cm),
+         *_cells_args(proj, kd, keep)) != 0:
+        raise ValueError("orc_render failed")
     return dict(img=img, T=Tf, plain=plain, plainT=Tp, partC=pc, partT=pt, ncon=ncon)
 
 
@@ -194,11 +221,13 @@ def render_bwd(proj, cam, kd, order, pix, dimg, dTf=None, eps_T: float = 0.0):
     dimg = _f64(dimg).reshape(P, 3)
     f = lib().orc_render_bwd
     f.argtypes = [C.c_int64] + [C.c_void_p] * 5 + [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
-                                                   C.c_int64] + [C.c_void_p] * 4
+                                                   C.c_int64] + [C.c_void_p] * 4 + [C.c_int, C.c_void_p, C.c_void_p]
     keep = []
     a = _render_args(proj, cam, kd, order, keep)
     dT = _f64(dTf).reshape(P) if dTf is not None else None
-    f(*a, proj["mode"], eps_T, P, _p(pix), _p(dimg), _p(dT) if dT is not None else None, _p(g2d))
+    if f(*a, proj["mode"], eps_T, P, _p(pix), _p(dimg), _p(dT) if dT is not None else None, _p(g2d),
+         *_cells_args(proj, kd, keep)) != 0:
+        raise ValueError("orc_render_bwd failed")
     return g2d[: proj["n"]]
 
 
@@ -232,3 +261,41 @@ def loss(img, tgt, ssim_w: float = 0.0):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (results are the same at any count)."""
+    lib().orc_set_threads(C.c_int(int(n)))
+
+
+# ------------------------------------------------------------------ training (Sec. 4, implementation details)
+SH_GROUP_ROWS = 3   # SH rows of degree 0 (one per colour channel)
+
+
+def expon_lr(step: int, lr_init: float, lr_final: float, max_steps: int) -> float:
+    """Exponential decay from lr_init at step 0 to lr_final at max_steps (the
+    paper's position schedule, 1.6e-4 -> 1.6e-6): log-linear in the step,
+    held at lr_final afterwards."""
+    t = min(max(step / max_steps, 0.0), 1.0)
+    return float(np.exp(np.log(lr_init) * (1.0 - t) + np.log(lr_final) * t))
+
+
+def adam_step(params, grads, m, v, hp: dict):
+    """One Adam step (Kingma and Ba), fp64, in place on the numpy arrays of
+    params, m and v; per-group learning rates hp["lr"][key], with the SH
+    degree-0 rows at hp["lr"]["sh_dc"] and the others at hp["lr"]["sh_rest"].
+    hp: beta1, beta2, eps, step (1-based)."""
+    b1, b2, eps, t = hp["beta1"], hp["beta2"], hp["eps"], hp["step"]
+    for k in ("means", "log_scales", "quats", "opacity", "sh"):
+        g = np.asarray(grads[k], np.float64)
+        m[k][...] = b1 * m[k] + (1.0 - b1) * g
+        v[k][...] = b2 * v[k] + (1.0 - b2) * g * g
+        mh = m[k] / (1.0 - b1 ** t)
+        vh = v[k] / (1.0 - b2 ** t)
+        if k == "sh":
+            lr = np.full(g.shape[0], hp["lr"]["sh_rest"])
+            lr[:SH_GROUP_ROWS] = hp["lr"]["sh_dc"]
+            lr = lr[:, None]
+        else:
+            lr = hp["lr"][k]
+        params[k][...] = params[k] - lr * mh / (np.sqrt(vh) + eps)

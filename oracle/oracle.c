@@ -162,16 +162,33 @@ static int cmp_u32(const void *a, const void *b) {
  * most significant bit first; nodes are stored in heap order.
  * own_mask marks the paper's subsets N_k: centre inside the leaf box
  * inflated by D_i = d_factor * max_a exp(log_scale_a) on every face. */
+/* rule 0: the equal-count bisection above (the paper's KD tree).
+ * rule 1: the fixed-size partition the paper compares it with (Sec. 4.2,
+ * Table 2): every node is cut at the midpoint of its extent, starting from
+ * the bounding box of all centres, so that the leaves are the blocks of a
+ * uniform grid (2^ceil(L/3) x 2^ceil((L-1)/3) x 2^floor(L/3)); split =
+ * 0.5f * (lo + hi) in fp32 (0 when there are no centres).  Boxes, leaf
+ * numbering, counts and N_k are as for rule 0.                          */
 int orc_kd_partition(int64_t n, const double *means, const double *log_scales, int L,
-                     double d_factor, float *split, uint8_t *axis, float *box_lo,
+                     double d_factor, int rule, float *split, uint8_t *axis, float *box_lo,
                      float *box_hi, int32_t *center_cell, int32_t *counts, uint32_t *own_mask) {
-    if (L < 0 || L > 6) return -1;
+    if (L < 0 || L > 6 || rule < 0 || rule > 1) return -1;
     int K = 1 << L;
     int32_t *node = (int32_t *)calloc(n > 0 ? n : 1, sizeof(int32_t)); /* heap index */
     uint32_t *tmp = (uint32_t *)malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
     /* node bounds (for empty nodes and leaf boxes) */
     float lo[2 * ORC_MAXK][3], hi[2 * ORC_MAXK][3];
     for (int a = 0; a < 3; a++) { lo[0][a] = -INFINITY; hi[0][a] = INFINITY; }
+    /* grid rule: each node's extent, from the bounding box of the centres */
+    float glo[2 * ORC_MAXK][3], ghi[2 * ORC_MAXK][3];
+    for (int a = 0; a < 3; a++) {
+        glo[0][a] = INFINITY; ghi[0][a] = -INFINITY;
+        for (int64_t i = 0; i < n; i++) {
+            float c = (float)means[a * n + i];
+            if (c < glo[0][a]) glo[0][a] = c;
+            if (c > ghi[0][a]) ghi[0][a] = c;
+        }
+    }
     for (int l = 0; l < L; l++) {
         int a = l % 3;
         int first = (1 << l) - 1, cnt = 1 << l;
@@ -180,7 +197,15 @@ int orc_kd_partition(int64_t n, const double *means, const double *log_scales, i
             for (int64_t i = 0; i < n; i++)
                 if (node[i] == nd) tmp[m++] = f2key((float)means[a * n + i]);
             float s;
-            if (m == 0) {
+            if (rule == 1) {
+                s = (isfinite(glo[nd][a]) && isfinite(ghi[nd][a])) ? 0.5f * (glo[nd][a] + ghi[nd][a]) : 0.0f;
+                for (int b = 0; b < 3; b++) {
+                    glo[2 * nd + 1][b] = glo[nd][b]; ghi[2 * nd + 1][b] = ghi[nd][b];
+                    glo[2 * nd + 2][b] = glo[nd][b]; ghi[2 * nd + 2][b] = ghi[nd][b];
+                }
+                ghi[2 * nd + 1][a] = s;
+                glo[2 * nd + 2][a] = s;
+            } else if (m == 0) {
                 float blo = lo[nd][a], bhi = hi[nd][a];
                 if (isfinite(blo) && isfinite(bhi)) s = 0.5f * (blo + bhi);
                 else if (isfinite(blo)) s = blo;
@@ -573,11 +598,29 @@ static uint64_t cellset64(const P64 *p, const int rect[4], const Cam *c, int L, 
 
 static int popcount64(uint64_t x) { int c = 0; while (x) { x &= x - 1; c++; } return c; }
 
+/* Which Gaussians a cell renders (cells):
+ *   0  every Gaussian whose footprint can put its crossing point in the
+ *      cell (the exact method: merged = plain);
+ *   1  the paper's subsets N_k only (Sec. 3.3, the margin D_i): the set
+ *      above restricted to the cells whose N_k holds the Gaussian (own_mask
+ *      rows of ceil(K/32) words); contributions outside N_k are lost;
+ *   2  exclusive subsets as in cell-based methods (Sec. 2): each Gaussian
+ *      belongs to the cell of its centre only and renders its whole
+ *      footprint there, without the indicator of Eq. 6 (center_cell).     */
+static uint64_t own64(const uint32_t *own_mask, int K, int64_t i) {
+    int W = (K + 31) / 32;
+    uint64_t m = own_mask[i * W];
+    if (W > 1) m |= (uint64_t)own_mask[i * W + 1] << 32;
+    return m;
+}
+
 int orc_project(int64_t n, int D, const double *means, const double *log_scales, const double *quats,
                 const double *opac, const double *sh, const double *cam, int L, const float *split,
-                int mode, float *dec32, double *val, int32_t *rect, uint8_t *vis, uint64_t *cellmask,
+                int mode, int cells, const int32_t *center_cell, const uint32_t *own_mask,
+                float *dec32, double *val, int32_t *rect, uint8_t *vis, uint64_t *cellmask,
                 uint32_t *count) {
-    if (D < 0 || D > 3 || L < 0 || L > 6) return -1;
+    if (D < 0 || D > 3 || L < 0 || L > 6 || cells < 0 || cells > 2) return -1;
+    if ((cells == 1 && !own_mask) || (cells == 2 && !center_cell)) return -1;
     Cam c; cam_unpack(cam, &c);
     #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
@@ -601,6 +644,8 @@ int orc_project(int64_t n, int D, const double *means, const double *log_scales,
             ok = p64.vis && rect64(&p64, &c, r);
             if (ok) mask = cellset64(&p64, r, &c, L, split);
         }
+        if (ok && cells == 1) mask &= own64(own_mask, 1 << L, i);
+        if (ok && cells == 2) mask = 1ull << center_cell[i];
         vis[i] = (uint8_t)ok;
         for (int k = 0; k < 4; k++) rect[4 * i + k] = ok ? r[k] : 0;
         cellmask[i] = ok ? mask : 0;
@@ -678,6 +723,7 @@ static int cmp_contrib(const void *a, const void *b) {
 typedef struct {
     int64_t n; const float *dec32; const double *val; const int32_t *rect; const uint8_t *vis;
     Cam c; int L; const float *split; int mode; const uint64_t *restrict_mask;
+    int cells; const int32_t *center_cell; const uint32_t *own_mask;
 } Scene;
 
 /* The leaf containing point x (half-open boxes: coordinate >= split goes
@@ -740,6 +786,10 @@ static int64_t collect(const Scene *s, int px, int py, Contrib **out) {
             }
         }
         if (!hit) continue;
+        /* cell-based contrast mode: the centre's cell, no indicator */
+        if (s->cells == 2) cell = s->center_cell[i];
+        /* the paper's subsets: a contribution counts only if i is in N_k */
+        if (s->cells == 1 && !((own64(s->own_mask, 1 << s->L, i) >> cell) & 1)) continue;
         /* diagnostic: keep only cells the Gaussian's emitted cell set names */
         if (s->restrict_mask && !((s->restrict_mask[i] >> cell) & 1)) continue;
         if (m == cap) { cap *= 2; v = (Contrib *)realloc(v, sizeof(Contrib) * cap); }
@@ -758,9 +808,15 @@ static int64_t collect(const Scene *s, int px, int py, Contrib **out) {
     return m;
 }
 
+/* Early termination floor: whatever the requested eps_T, a pixel stops in a
+ * cell once its transmittance falls below 2^-100 (the contributions behind
+ * it weigh less than that; the fp32 kernels keep T a normal number so that
+ * their backward can recover the transmittance before each contribution). */
+#define ORC_T_FLOOR 0x1p-100
+
 /* Forward of one pixel.  Partial (C_k, T_k) of Eq. 3/4 over the
  * contributors whose crossing point lies in cell k, in depth order, with
- * include-then-stop early termination per cell at eps_T (eps_T = 0: none);
+ * include-then-stop early termination per cell at max(eps_T, ORC_T_FLOOR);
  * merged colour by Eq. 5 over the view's cell order, plus background;
  * plain colour by Eq. 2 over all contributors (same stop rule on its own
  * transmittance).  `used` marks which contributors each cell processed. */
@@ -769,6 +825,7 @@ static void pixel_forward(const Scene *s, const Contrib *v, int64_t m, const int
                           double *Tout, double plain[3], double *Tplain) {
     int K = 1 << s->L;
     int stop[ORC_MAXK];
+    if (eps_T < ORC_T_FLOOR) eps_T = ORC_T_FLOOR;
     for (int k = 0; k < K; k++) { Ck[3 * k] = Ck[3 * k + 1] = Ck[3 * k + 2] = 0; Tk[k] = 1; stop[k] = 0; }
     for (int64_t j = 0; j < m; j++) {
         int k = v[j].cell;
@@ -801,12 +858,17 @@ static void pixel_forward(const Scene *s, const Contrib *v, int64_t m, const int
 
 /* mode: 0 mirror32 / 1 exact64 decisions; bit 1 (value 2) restricts each
  * Gaussian to the cells of its emitted cell set (restrict_mask).        */
-static void scene_init(Scene *s, int64_t n, const float *dec32, const double *val,
-                       const int32_t *rect, const uint8_t *vis, const double *cam, int L,
-                       const float *split, int mode, const uint64_t *restrict_mask) {
+/* cells: 0 / 1 / 2 as for orc_project (which Gaussians a cell renders). */
+static int scene_init(Scene *s, int64_t n, const float *dec32, const double *val,
+                      const int32_t *rect, const uint8_t *vis, const double *cam, int L,
+                      const float *split, int mode, const uint64_t *restrict_mask, int cells,
+                      const int32_t *center_cell, const uint32_t *own_mask) {
     s->n = n; s->dec32 = dec32; s->val = val; s->rect = rect; s->vis = vis;
     cam_unpack(cam, &s->c); s->L = L; s->split = split; s->mode = mode & 1;
     s->restrict_mask = (mode & 2) ? restrict_mask : NULL;
+    s->cells = cells; s->center_cell = center_cell; s->own_mask = own_mask;
+    if (cells < 0 || cells > 2 || (cells == 1 && !own_mask) || (cells == 2 && !center_cell)) return -1;
+    return 0;
 }
 
 /* Render a list of pixels (pix = x0, y0, x1, y1, ...).
@@ -817,8 +879,11 @@ int orc_render(int64_t n, const float *dec32, const double *val, const int32_t *
                const uint8_t *vis, const double *cam, int L, const float *split,
                const int32_t *order, int mode, double eps_T, int64_t npix, const int32_t *pix,
                double *img, double *Tf, double *plain, double *Tp, double *partC,
-               double *partT, int32_t *ncon, const uint64_t *cellmask) {
-    Scene s; scene_init(&s, n, dec32, val, rect, vis, cam, L, split, mode, cellmask);
+               double *partT, int32_t *ncon, const uint64_t *cellmask, int cells,
+               const int32_t *center_cell, const uint32_t *own_mask) {
+    Scene s;
+    if (scene_init(&s, n, dec32, val, rect, vis, cam, L, split, mode, cellmask, cells, center_cell, own_mask))
+        return -1;
     int K = 1 << L;
     #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t q = 0; q < npix; q++) {
@@ -854,8 +919,11 @@ typedef struct { int64_t gid; double g[9]; } GRec;
 int orc_render_bwd(int64_t n, const float *dec32, const double *val, const int32_t *rect,
                    const uint8_t *vis, const double *cam, int L, const float *split,
                    const int32_t *order, int mode, double eps_T, int64_t npix,
-                   const int32_t *pix, const double *dimg, const double *dTf, double *g2d) {
-    Scene s; scene_init(&s, n, dec32, val, rect, vis, cam, L, split, mode, NULL);
+                   const int32_t *pix, const double *dimg, const double *dTf, double *g2d, int cells,
+                   const int32_t *center_cell, const uint32_t *own_mask) {
+    Scene s;
+    if (scene_init(&s, n, dec32, val, rect, vis, cam, L, split, mode, NULL, cells, center_cell, own_mask))
+        return -1;
     int K = 1 << L;
     GRec **recs = (GRec **)calloc(npix > 0 ? npix : 1, sizeof(GRec *));
     int64_t *nrec = (int64_t *)calloc(npix > 0 ? npix : 1, sizeof(int64_t));
@@ -1152,5 +1220,15 @@ int orc_num_threads(void) {
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads of the parallel loops from now on (results do not depend on it:
+ * every reduction above runs in a fixed order). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

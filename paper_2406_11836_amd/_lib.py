@@ -13,6 +13,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librgs.so")
 
 RGS_OK, RGS_E_ARG, RGS_E_CAPACITY, RGS_E_HIP, RGS_E_UNSUPPORTED = 0, -1, -2, -3, -4
+RGS_SPLIT_MEDIAN, RGS_SPLIT_MIDPOINT = 0, 1
+RGS_CELLS_EXACT, RGS_CELLS_PAPER_SUBSETS, RGS_CELLS_EXCLUSIVE = 0, 1, 2
+RGS_T_FLOOR = 2.0 ** -100
 RGS_MAX_VIEWS = 16
 RGS_MAX_L = 6
 REC_FLOATS = 16
@@ -50,6 +53,11 @@ class Bins(C.Structure):
                 ("slot_order", vp), ("counters", vp), ("n_instances", i64)]
 
 
+class AdamParams(C.Structure):
+    _fields_ = [("lr_means", f32), ("lr_log_scales", f32), ("lr_quats", f32), ("lr_opacity", f32),
+                ("lr_sh_dc", f32), ("lr_sh_rest", f32), ("beta1", f32), ("beta2", f32), ("eps", f32), ("step", i32)]
+
+
 class Partials(C.Structure):
     _fields_ = [("C", vp), ("T", vp), ("last", vp)]
 
@@ -68,11 +76,12 @@ _SIGS = {
     "rgs_views_pack": (i32, [P(Camera), i32, i32, vp, vp, vp]),
     "rgs_total_tiles": (i64, [P(Camera), i32]),
     "rgs_kd_partition_workspace": (sz, [i64, i32]),
-    "rgs_kd_partition": (i32, [P(Gaussians), i32, f32, P(KdTree), vp, sz, vp]),
+    "rgs_kd_partition": (i32, [P(Gaussians), i32, f32, i32, P(KdTree), vp, sz, vp]),
     "rgs_cell_order": (i32, [i32, vp, vp, vp, vp]),
+    "rgs_cell_visibility": (i32, [P(Camera), i32, i32, vp, vp]),
     "rgs_group_by_cell_workspace": (sz, [i64]),
     "rgs_group_by_cell": (i32, [P(Gaussians), P(KdTree), i32, P(Gaussians), vp, vp, sz, vp]),
-    "rgs_project_sh": (i32, [P(Gaussians), P(Camera), i32, vp, P(KdTree), P(Projected), vp]),
+    "rgs_project_sh": (i32, [P(Gaussians), P(Camera), i32, vp, P(KdTree), i32, P(Projected), vp]),
     "rgs_bin_sort_workspace": (sz, [i64, i32, i64, i32, i64]),
     "rgs_bin_sort": (i32, [P(Projected), i64, P(Camera), i32, vp, i32, P(Bins), P(i64), vp, sz, vp]),
     "rgs_bin_sort_async": (i32, [P(Projected), i64, P(Camera), i32, vp, i32, P(Bins), vp, sz, vp]),
@@ -88,6 +97,9 @@ _SIGS = {
                                            P(KdTree), vp, sz, vp, vp]),
     "rgs_pair_reduce": (i32, [P(Bins), P(Projected), i64, i32, vp, vp, sz, vp]),
     "rgs_project_sh_bwd": (i32, [vp, P(Gaussians), P(Projected), P(Camera), i32, vp, P(GaussiansGrad), vp]),
+    "rgs_adam_step": (i32, [P(GaussiansGrad), P(GaussiansGrad), P(GaussiansGrad), P(GaussiansGrad), i64, i32,
+                            P(AdamParams), vp]),
+    "rgs_permute_gaussians": (i32, [P(Gaussians), vp, P(GaussiansGrad), vp]),
 }
 
 EXPORTED = tuple(_SIGS)

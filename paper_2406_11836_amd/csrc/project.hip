@@ -278,10 +278,16 @@ __device__ __forceinline__ bool screen_may_hit(float mu0, float mu1, float mu2, 
     return !(mx + ex < 0.0f || mx - ex > (float)V.W || my + ey < 0.0f || my - ey > (float)V.H);
 }
 
+// cells (which Gaussians each cell renders): RGS_CELLS_EXACT, the KD leaves
+// the footprint's crossing points can reach; RGS_CELLS_PAPER_SUBSETS, those
+// leaves whose subset N_k holds the Gaussian (own_mask); RGS_CELLS_EXCLUSIVE,
+// the leaf of the centre only, with no indicator test in the render (flag
+// bit 0 set: the render takes every pixel of the footprint for that cell).
 template <int D>
 __global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, const ViewTable* __restrict__ vt,
                                                         const float* __restrict__ split,
-                                                        const int32_t* __restrict__ center_cell, rgs_projected out) {
+                                                        const int32_t* __restrict__ center_cell, int cells,
+                                                        const uint32_t* __restrict__ own_mask, rgs_projected out) {
     const int64_t n = g.n;
     const int64_t i = (int64_t)blockIdx.x * PJ_THREADS + threadIdx.x;
     if (i >= n) return;
@@ -330,7 +336,20 @@ __global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, cons
             out.count[src] = 0u;
             continue;
         }
-        const uint64_t mask = cellset32(p, r, V, L, split);
+        const uint64_t reach = cellset32(p, r, V, L, split);
+        uint64_t mask = reach;
+        if (cells == RGS_CELLS_PAPER_SUBSETS) {
+            const int Wm = ((1 << L) + 31) >> 5;
+            uint64_t own = own_mask[i * Wm];
+            if (Wm > 1) own |= (uint64_t)own_mask[i * Wm + 1] << 32;
+            mask &= own;
+        } else if (cells == RGS_CELLS_EXCLUSIVE) {
+            mask = 1ull << center_cell[i];
+        }
+        if (mask == 0ull) {
+            out.count[src] = 0u;
+            continue;
+        }
         // tiles per cell: the row spans of the footprint inside the rectangle
         SpanPre sp;
         span_pre(p.mx, p.my, p.ca, p.k, p.e, p.tau, sp);
@@ -373,7 +392,8 @@ __global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, cons
         }
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) col[ch] = fmaxf(col[ch], 0.0f);
-        const uint32_t flags = (__popcll(mask) == 1) ? 1u : 0u;
+        // bit 0: no indicator test needed (every crossing point lies in the one cell, or exclusive cells)
+        const uint32_t flags = (__popcll(reach) == 1 || cells == RGS_CELLS_EXCLUSIVE) ? 1u : 0u;
         rec[0] = make_float4(p.mx, p.my, p.ca, p.k);
         rec[1] = make_float4(p.e, p.alpha, p.tau, p.z);
         rec[2] = make_float4(col[0], col[1], col[2], __uint_as_float(flags));
@@ -384,14 +404,18 @@ __global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, cons
 }
 
 rgs_status project_launch(const rgs_gaussians* g, const ViewTable* vt, const float* split, const int32_t* center_cell,
-                          const rgs_projected* out, hipStream_t s) {
+                          int cells, const uint32_t* own_mask, const rgs_projected* out, hipStream_t s) {
     if (g->n <= 0) return RGS_OK;
     const unsigned grid = (unsigned)((g->n + PJ_THREADS - 1) / PJ_THREADS);
     switch (g->sh_degree) {
-        case 0: hipLaunchKernelGGL(k_project<0>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, *out); break;
-        case 1: hipLaunchKernelGGL(k_project<1>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, *out); break;
-        case 2: hipLaunchKernelGGL(k_project<2>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, *out); break;
-        default: hipLaunchKernelGGL(k_project<3>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, *out); break;
+        case 0: hipLaunchKernelGGL(k_project<0>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, cells,
+                                   own_mask, *out); break;
+        case 1: hipLaunchKernelGGL(k_project<1>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, cells,
+                                   own_mask, *out); break;
+        case 2: hipLaunchKernelGGL(k_project<2>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, cells,
+                                   own_mask, *out); break;
+        default: hipLaunchKernelGGL(k_project<3>, dim3(grid), dim3(PJ_THREADS), 0, s, *g, vt, split, center_cell, cells,
+                                    own_mask, *out); break;
     }
     return launch_check();
 }

@@ -256,6 +256,11 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
                              float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s) {
     if (slot_bound <= 0) return RGS_OK;
+    // a pixel stops once T_k < max(eps_T, 2^-100): the backward recovers the
+    // transmittance before each contribution from the stored T_k by division,
+    // which needs T_k to stay a normal fp32 number (after the last factor
+    // 1 - sigma >= 0.01 it is still >= 2^-107)
+    eps_T = fmaxf(eps_T, RGS_T_FLOOR);
     if (stats)
         hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec,
                            bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,

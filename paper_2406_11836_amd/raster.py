@@ -159,23 +159,35 @@ class Rasterizer:
         return t[:nbytes].view(dtype)
 
     # ------------------------------------------------------------ KD tree
-    def kd_partition(self, params, Ldepth: int, d_factor: float = 3.0, own_mask: bool = True) -> KD:
+    def kd_partition(self, params, Ldepth: int, d_factor: float = 3.0, own_mask: bool = True,
+                     rule: int = L.RGS_SPLIT_MEDIAN) -> KD:
+        """rule: RGS_SPLIT_MEDIAN (the paper's KD tree) or RGS_SPLIT_MIDPOINT (fixed-size grid)."""
         n = int(params["means"].shape[1])
         K = 1 << Ldepth
         kd = KD(L=Ldepth, split=self._empty(max(K - 1, 1), torch.float32),
                 box_lo=self._empty(3 * K, torch.float32), box_hi=self._empty(3 * K, torch.float32),
                 center_cell=self._empty(n, torch.int32), counts=self._empty(K, torch.int32),
                 own_mask=self._empty(n * ((K + 31) // 32), torch.int32) if own_mask else None,
-                split_host=np.zeros(max(K - 1, 1), np.float32), cell_bounds=self._empty(6 * K, torch.float32))
+                split_host=np.zeros(max(K - 1, 1), np.float32), cell_bounds=self._empty(8 * K, torch.float32))
         ws_bytes = self.lib.rgs_kd_partition_workspace(n, Ldepth)
         ws = self._empty(ws_bytes, torch.uint8)
         g = gaussians_struct(params)
         ks = kd.struct()
-        L.check("rgs_kd_partition", self.lib.rgs_kd_partition(C.byref(g), Ldepth, d_factor, C.byref(ks), _p(ws), ws_bytes,
-                                                               _stream()))
+        L.check("rgs_kd_partition", self.lib.rgs_kd_partition(C.byref(g), Ldepth, d_factor, int(rule), C.byref(ks),
+                                                               _p(ws), ws_bytes, _stream()))
         kd.split_host = kd.split.cpu().numpy().copy()
-        kd.cell_bounds_host = kd.cell_bounds.cpu().numpy().reshape(6, K).copy()
+        kd.cell_bounds_host = kd.cell_bounds.cpu().numpy().reshape(8, K).copy()
         return kd
+
+    def cell_visibility(self, kd: KD, cams) -> np.ndarray:
+        """Per view, the mask of KD cells that may reach it (rgs_cell_visibility)."""
+        cam_arr = L.camera_array(cams)
+        out = np.zeros(len(cams), np.uint64)
+        cb = np.ascontiguousarray(kd.cell_bounds_host, np.float32)
+        L.check("rgs_cell_visibility", self.lib.rgs_cell_visibility(cam_arr, len(cams), kd.L,
+                                                                     cb.ctypes.data_as(C.c_void_p),
+                                                                     out.ctypes.data_as(C.c_void_p)))
+        return out
 
     def group_by_cell(self, params, kd: KD):
         """Copy of the parameters grouped by KD cell (Morton order inside a
@@ -208,10 +220,13 @@ class Rasterizer:
 
     # ------------------------------------------------------------ forward
     def forward(self, params, kd: KD, cams, eps_T: float = 5e-5, stats: torch.Tensor | None = None,
-                marks: list | None = None, cell_visible=None, no_sync: bool = False) -> FwdState:
+                marks: list | None = None, cell_visible=None, no_sync: bool = False, cull: bool = False,
+                cells: int = L.RGS_CELLS_EXACT) -> FwdState:
         """stats: optional int64 device tensor [2] (evaluated, contributing pairs), incremented.
         marks: optional list receiving (stage, event) pairs at stage ends.
-        cell_visible: optional per-view uint64 masks of the KD cells that may reach each view."""
+        cell_visible: optional per-view uint64 masks of the KD cells that may reach each view;
+        cull=True computes them with rgs_cell_visibility (changes no output).
+        cells: RGS_CELLS_EXACT / _PAPER_SUBSETS / _EXCLUSIVE (which Gaussians each cell renders)."""
         lib = self.lib
         _mark(marks, "start")
         V = len(cams)
@@ -223,6 +238,8 @@ class Rasterizer:
         ranks = self.cell_ranks(kd, cams)
         vb = lib.rgs_views_bytes()
         views = self._buf("views", vb, torch.uint8)
+        if cell_visible is None and cull and kd.L > 0:
+            cell_visible = self.cell_visibility(kd, cams)
         vis = None if cell_visible is None else np.ascontiguousarray(cell_visible, np.uint64)
         # packed on the host into pinned memory and copied on the stream without waiting
         # (torch's pinned allocator does not reuse the block before the copy is done)
@@ -240,7 +257,8 @@ class Rasterizer:
                     depth=self._buf("depth", m, torch.float32))
         ps = L.Projected(proj["rec"].data_ptr(), proj["rect"].data_ptr(), proj["cellmask"].data_ptr(),
                          proj["count"].data_ptr(), proj["depth"].data_ptr())
-        L.check("rgs_project_sh", lib.rgs_project_sh(C.byref(g), cam_arr, V, _p(views), C.byref(ks), C.byref(ps), stream))
+        L.check("rgs_project_sh", lib.rgs_project_sh(C.byref(g), cam_arr, V, _p(views), C.byref(ks), int(cells), C.byref(ps),
+                                                     stream))
         _mark(marks, "project")
         T = int(lib.rgs_total_tiles(cam_arr, V))
         K = 1 << kd.L

@@ -10,8 +10,9 @@ merge).  Requests that arrive while a batch is on the GPU wait for the next
 free worker.  One worker is the default: a batch of views at this scale
 fills the GPU by itself, and two concurrent batches on one device were
 measured to run many times slower than one after the other (their working
-sets of tens of GB compete).  Per view, KD cells whose inflated bounds miss
-the padded view frustum are culled before projection.
+sets of tens of GB compete).  Per view, KD cells that cannot reach the image
+(rgs_cell_visibility, a conservative test in the library) are culled before
+projection.
 
 Latency of a request = host time at which its batch completed - its
 scheduled arrival time.  The plain path for comparison is the same trace,
@@ -40,33 +41,6 @@ class Request:
     t_done: float = float("nan")
     batch_size: int = 0
     image: torch.Tensor | None = None
-
-
-def frustum_cell_mask(cam, cell_bounds: np.ndarray, pad_px: float = 8.0, pad_rel: float = 0.02) -> int:
-    """Bit k set unless cell k's inflated centre box lies entirely outside one
-    plane of the view frustum (padded by pad_px pixels plus pad_rel of the
-    field of view on every side).  cell_bounds: [6, K] (min xyz, max xyz)."""
-    K = cell_bounds.shape[1]
-    R = np.asarray(cam["R"], np.float64).reshape(3, 3)
-    o = np.asarray(cam["o"], np.float64)
-    fx, fy, cx, cy = float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"])
-    W, H = float(cam["W"]), float(cam["H"])
-    ax = (cx + pad_px) / fx * (1 + pad_rel)
-    bx = (W - cx + pad_px) / fx * (1 + pad_rel)
-    ay = (cy + pad_px) / fy * (1 + pad_rel)
-    by = (H - cy + pad_px) / fy * (1 + pad_rel)
-    lo, hi = cell_bounds[:3].T.astype(np.float64), cell_bounds[3:].T.astype(np.float64)   # [K, 3]
-    finite = np.all(np.isfinite(lo), 1) & np.all(np.isfinite(hi), 1)
-    lo = np.where(np.isfinite(lo), lo, 0.0)
-    hi = np.where(np.isfinite(hi), hi, 0.0)
-    sel = np.array([[(i >> a) & 1 for a in range(3)] for i in range(8)], bool)           # [8, 3]
-    corners = np.where(sel[None], hi[:, None, :], lo[:, None, :])                        # [K, 8, 3]
-    pc = (corners - o) @ R.T
-    x, y, z = pc[..., 0], pc[..., 1], pc[..., 2]
-    outside = (np.all(z < float(cam["z_near"]), 1) | np.all(x + ax * z < 0, 1) | np.all(bx * z - x < 0, 1)
-               | np.all(y + ay * z < 0, 1) | np.all(by * z - y < 0, 1))
-    vis = finite & ~outside
-    return int(sum(1 << int(k) for k in np.nonzero(vis)[0]))
 
 
 class Server:
@@ -108,7 +82,7 @@ class Server:
             if warm_cams:
                 # size the buffers for the largest batch before the trace starts
                 with torch.cuda.stream(stream):
-                    masks = [frustum_cell_mask(c, self.kd.cell_bounds_host) for c in warm_cams] if self.cull else None
+                    masks = rast.cell_visibility(self.kd, warm_cams) if self.cull else None
                     rast.forward(self.params, self.kd, warm_cams, self.eps_T, cell_visible=masks)
                     stream.synchronize()
             done.put((wid, None, 0.0, None))  # ready
@@ -123,7 +97,7 @@ class Server:
                 t0 = time.perf_counter()
                 with torch.cuda.stream(stream):
                     cams = [r.cam for r in batch]
-                    masks = [frustum_cell_mask(c, self.kd.cell_bounds_host) for c in cams] if self.cull else None
+                    masks = rast.cell_visibility(self.kd, cams) if self.cull else None
                     st = rast.forward(self.params, self.kd, cams, self.eps_T, cell_visible=masks)
                     imgs = [img.clone() for img, _ in st.images()] if self.keep_images else None
                     stream.synchronize()

@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_status(lib):
-    assert lib.rgs_abi_version() == 2
+    assert lib.rgs_abi_version() == 3
     assert lib.rgs_status_string(0) == b"ok"
     assert lib.rgs_status_string(-2) == b"buffer capacity too small"
 
@@ -83,9 +83,9 @@ def test_argument_errors_enqueue_nothing(lib):
     pt = L.Partials()
     pg = L.PartialsGrad()
     gg = L.GaussiansGrad()
-    assert lib.rgs_kd_partition(C.byref(g), 2, 3.0, C.byref(kd), None, 0, None) == E
-    assert lib.rgs_project_sh(C.byref(g), cam, 1, None, C.byref(kd), C.byref(ps), None) == E
-    assert lib.rgs_project_sh(None, cam, 1, None, C.byref(kd), C.byref(ps), None) == E
+    assert lib.rgs_kd_partition(C.byref(g), 2, 3.0, 0, C.byref(kd), None, 0, None) == E
+    assert lib.rgs_project_sh(C.byref(g), cam, 1, None, C.byref(kd), 0, C.byref(ps), None) == E
+    assert lib.rgs_project_sh(None, cam, 1, None, C.byref(kd), 0, C.byref(ps), None) == E
     need = C.c_int64(0)
     assert lib.rgs_bin_sort(C.byref(ps), 10, cam, 1, None, 2, C.byref(bs), C.byref(need), None, 0, None) == E
     assert lib.rgs_render_partial(C.byref(ps), 10, C.byref(bs), cam, 1, None, C.byref(kd), 5e-5, C.byref(pt), None, None) == E
@@ -140,7 +140,7 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2406_11836_amd import _lib as L
     structs = {"rgs_gaussians": L.Gaussians, "rgs_gaussians_grad": L.GaussiansGrad, "rgs_camera": L.Camera,
                "rgs_kdtree": L.KdTree, "rgs_projected": L.Projected, "rgs_bins": L.Bins, "rgs_partials": L.Partials,
-               "rgs_partials_grad": L.PartialsGrad}
+               "rgs_partials_grad": L.PartialsGrad, "rgs_adam_params": L.AdamParams}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rgs.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -158,3 +158,67 @@ def test_struct_layouts_match_header(tmp_path):
         for f, _ in py._fields_:
             expect.append("%s.%s %d" % (cname, f, getattr(py, f).offset))
     assert [x for x in out if x] == expect
+
+
+def _fake_gaussians(L, n, base, D=0):
+    g = L.Gaussians()
+    g.n, g.sh_degree = n, D
+    g.means, g.log_scales, g.quats, g.opacity, g.sh = (base + 0x100000 * k for k in range(5))
+    return g
+
+
+def test_aliased_buffers_are_rejected(lib):
+    """An output overlapping an input or another output is an argument error,
+    found from the byte ranges each call implies, before anything is enqueued."""
+    from paper_2406_11836_amd import _lib as L
+    E = L.RGS_E_ARG
+    ws = C.c_void_p(0x7000000)
+    cam = L.camera_array([dict(R=np.eye(3), t=[0, 0, 0], o=[0, 0, 0], fx=100, fy=100, cx=8, cy=8, W=16, H=16,
+                               z_near=0.1)])
+    # loss: d_image inside the image, the workspace inside the target
+    img, tgt, lv, d = 0x1000000, 0x2000000, 0x3000000, 0x4000000
+    assert lib.rgs_loss_l1_ssim(C.c_void_p(img), C.c_void_p(tgt), 16, 16, 0.2, C.c_void_p(lv), C.c_void_p(img + 256),
+                                ws, 1 << 24, None) == E
+    assert lib.rgs_loss_l1_ssim(C.c_void_p(img), C.c_void_p(tgt), 16, 16, 0.2, C.c_void_p(lv), C.c_void_p(d),
+                                C.c_void_p(tgt), 1 << 24, None) == E
+    # projection: the record array overlapping the SH coefficients
+    g = _fake_gaussians(L, 1000, 0x10000000)
+    kd = L.KdTree()
+    kd.L, kd.split = 0, 0x5000000
+    ps = L.Projected(g.sh + 64, 0x21000000, 0x22000000, 0x23000000, 0x24000000)
+    assert lib.rgs_project_sh(C.byref(g), cam, 1, C.c_void_p(0x6000000), C.byref(kd), 0, C.byref(ps), None) == E
+    # two outputs overlapping each other (count inside cellmask)
+    ps = L.Projected(0x20000000, 0x21000000, 0x22000000, 0x22000000 + 4000, 0x24000000)
+    assert lib.rgs_project_sh(C.byref(g), cam, 1, C.c_void_p(0x6000000), C.byref(kd), 0, C.byref(ps), None) == E
+    # subset modes need the KD tree's masks
+    ps = L.Projected(0x20000000, 0x21000000, 0x22000000, 0x23000000, 0x24000000)
+    assert lib.rgs_project_sh(C.byref(g), cam, 1, C.c_void_p(0x6000000), C.byref(kd), 1, C.byref(ps), None) == E
+    assert lib.rgs_project_sh(C.byref(g), cam, 1, C.c_void_p(0x6000000), C.byref(kd), 2, C.byref(ps), None) == E
+    assert lib.rgs_project_sh(C.byref(g), cam, 1, C.c_void_p(0x6000000), C.byref(kd), 3, C.byref(ps), None) == E
+    # projection backward: a gradient buffer on top of d_proj
+    gg = L.GaussiansGrad(0x30000000, 0x31000000, 0x32000000, 0x33000000, 0x34000000)
+    assert lib.rgs_project_sh_bwd(C.c_void_p(0x30000000 + 128), C.byref(g), C.byref(ps), cam, 1, C.c_void_p(0x6000000),
+                                  C.byref(gg), None) == E
+    # KD partition: center_cell inside the means
+    kd2 = L.KdTree()
+    kd2.L = 2
+    kd2.split, kd2.box_lo, kd2.box_hi, kd2.counts = 0x40000000, 0x41000000, 0x42000000, 0x43000000
+    kd2.center_cell = g.means + 400
+    assert lib.rgs_kd_partition(C.byref(g), 2, 3.0, 0, C.byref(kd2), C.c_void_p(0x50000000), 1 << 30, None) == E
+    kd2.center_cell = 0x44000000
+    assert lib.rgs_kd_partition(C.byref(g), 2, 3.0, 5, C.byref(kd2), C.c_void_p(0x50000000), 1 << 30, None) == E
+    # merge: the image over the partial colours
+    bs = L.Bins()
+    bs.capacity, bs.slot_capacity = 100, 10
+    (bs.keys, bs.vals, bs.pair_src, bs.pair_off, bs.pair_rank, bs.slot_key, bs.slot_range, bs.tile_slot,
+     bs.slot_order, bs.counters) = (0x60000000 + 0x100000 * k for k in range(10))
+    pt = L.Partials(0x70000000, 0x71000000, 0x72000000)
+    assert lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam, 1, C.c_void_p(0x6000000), C.c_void_p(0x70000000 + 4),
+                                  C.c_void_p(0x73000000), None) == E
+    # merge backward: dT over T
+    pg = L.PartialsGrad(0x74000000, 0x71000000 + 8)
+    assert lib.rgs_merge_partials_bwd(C.c_void_p(0x75000000), None, C.byref(pt), C.byref(bs), cam, 1,
+                                      C.c_void_p(0x6000000), C.byref(pg), None) == E
+    # binning: the sorted keys over the projected records
+    assert lib.rgs_bin_sort(C.byref(ps), 1000, cam, 1, C.c_void_p(0x6000000), 0, C.byref(bs), None,
+                            C.c_void_p(0x20000000 + 256), 1 << 30, None) == E

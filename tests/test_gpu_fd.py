@@ -9,7 +9,23 @@ fp64 central differences of the oracle's exact64 forward.  Finite
 differences of all 512 x 59 parameters would take hours on the CPU, so a
 stratified sample of 240 parameters (every parameter kind, visible
 Gaussians) is checked; parameters whose stencil crosses a cut (the value at
-h and h/4 disagree) are skipped and counted.
+h and h/4 disagree) are skipped and counted, and must stay under a tenth of
+the sample.
+
+The GPU takes its contribute decisions in fp32 (the mirror32 sequence), the
+finite differences in fp64 (exact64).  Where the two decision sets differ (a
+pixel at the 3-sigma or 1/255 cut, or a pair whose depth order flips), the
+two functions differ and so do their gradients: such Gaussians are found by
+comparing the oracle's own backward under both decision modes, counted, and
+left out of the sample.  For every other sampled parameter (no exceptions):
+  - the oracle's hand-derived fp64 gradient (exact64 decisions) agrees with
+    the finite difference to 1e-6 |fd| + 1e-7;
+  - the GPU gradient agrees with it to 1e-3 |fd| + 1e-4 max|fd| (per kind:
+    an fp32 sum over hundreds of pixels carries rounding relative to its
+    largest terms, not to a total that cancels).
+All 512 x 59 GPU gradients are also compared with the oracle's analytic
+gradient under the same fp32 decisions (per element 1e-3 |g| + 1e-3 max|g|,
+per tensor 1e-3 in the 2-norm).
 """
 import math
 
@@ -18,7 +34,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import log
+from gpu_helpers import grad_close, log
 from paper_2406_11836_amd import raster, scenes
 
 pytestmark = pytest.mark.gpu
@@ -79,9 +95,25 @@ def test_autograd_matches_fd64_on_city_crop():
     pr0 = oracle.project(p64, cam, okd, 1)
     vis = np.nonzero(pr0["vis"])[0]
     assert len(vis) > 100
+    # Gaussians whose per-pixel contributions differ between fp32 and fp64 decisions
+    pr32 = oracle.project(p64, cam, okd, 0)
+    g64 = oracle.render_bwd(pr0, cam, okd, order, pix, wv, None, 0.0)
+    g32 = oracle.render_bwd(pr32, cam, okd, order, pix, wv, None, 0.0)
+    differs = (np.abs(g64 - g32) > 1e-9 * (np.abs(g64) + 1e-9)).any(1) | (pr0["vis"] != pr32["vis"])
+    n_differs = int(differs[vis].sum())
+    log("decision sets differ between fp32 and fp64 for %d of %d visible Gaussians" % (n_differs, len(vis)))
+    assert n_differs <= len(vis) // 10
+    vis = vis[~differs[vis]]
+    # every parameter: GPU against the oracle's analytic gradient (fp32 decisions)
+    og32 = oracle.project_bwd(p64, cam, pr32, g32)
+    og64 = oracle.project_bwd(p64, cam, pr0, g64)
+    for k in raster.PARAM_KEYS:
+        ok, info = grad_close(g[k], og32[k], 1e-3, "all %s" % k)
+        log(str(info))
+        assert ok, info
     rng = np.random.default_rng(7)
     kinds = [("means", 3), ("log_scales", 3), ("quats", 4), ("opacity", 1), ("sh", 48)]
-    skipped, checked, n_bad = 0, 0, 0
+    skipped, checked, n_bad, attempted = 0, 0, 0, 0
     worst = []
     for k, rows in kinds:
         pairs = []
@@ -100,18 +132,24 @@ def test_autograd_matches_fd64_on_city_crop():
                 fm = f()
                 vals.append((fp - fm) / (2 * hh))
             x.flat[flat] = xi
+            attempted += 1
             if abs(vals[0] - vals[1]) > 1e-3 * (abs(vals[0]) + 1e-3):
                 skipped += 1
                 continue
-            pairs.append((g[k].flat[flat], vals[0]))
-        gv = np.array([a for a, _ in pairs])
-        fd = np.array([b for _, b in pairs])
+            pairs.append((g[k].flat[flat], vals[0], og64[k].flat[flat]))
+        gv = np.array([a for a, _, _ in pairs])
+        fd = np.array([b for _, b, _ in pairs])
+        an = np.array([c for _, _, c in pairs])
         scale = np.abs(fd).max()
-        bad = np.abs(gv - fd) > 1e-3 * np.abs(fd) + 1e-3 * scale
+        err = np.abs(gv - fd)
+        bad = err > 1e-3 * np.abs(fd) + 1e-4 * scale
+        bad_an = np.abs(an - fd) > 1e-6 * np.abs(fd) + 1e-7
         checked += len(pairs)
-        n_bad += int(bad.sum())
-        worst.append((k, float(np.abs(gv - fd).max() / max(scale, 1e-30)), int(bad.sum()), len(pairs)))
-    log("FD64: checked %d, skipped %d (stencil crosses a cut); per kind (max err / max |fd|, bad, n): %s"
-        % (checked, skipped, worst))
+        n_bad += int(bad.sum()) + int(bad_an.sum())
+        worst.append((k, float((err / (np.abs(fd) + 1e-4 * scale)).max()), int(bad.sum()),
+                      float((np.abs(an - fd) / (np.abs(fd) + 1e-1)).max()), int(bad_an.sum()), len(pairs)))
+    log("FD64: checked %d of %d, skipped %d (stencil crosses a cut); per kind (GPU: max err / (|fd| + 1e-4 max|fd|), "
+        "bad; oracle analytic: max rel err, bad; n): %s" % (checked, attempted, skipped, worst))
     assert checked >= 150
-    assert n_bad <= max(2, checked // 100), worst
+    assert skipped <= attempted // 10, (skipped, attempted)
+    assert n_bad == 0, worst

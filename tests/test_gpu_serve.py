@@ -28,7 +28,7 @@ def test_cell_culling_is_exact(city):
     reqs = serve.serve_trace(100.0, 6, seed=53, xy_range=250.0, res_mix=[((320, 180), 0.5), ((480, 270), 0.5)])
     n_culled = 0
     for r in reqs:
-        mask = serve.frustum_cell_mask(r.cam, kd.cell_bounds_host)
+        mask = int(rast.cell_visibility(kd, [r.cam])[0])
         n_culled += 64 - bin(mask).count("1")
         a = rast.forward(p, kd, [r.cam], 5e-5)
         b = rast.forward(p, kd, [r.cam], 5e-5, cell_visible=[mask])
@@ -47,12 +47,35 @@ def test_served_images_equal_solo_renders(city):
     srv.run(reqs)
     assert max(srv.batch_hist) > 1, srv.batch_hist
     for r in reqs:
-        mask = serve.frustum_cell_mask(r.cam, kd.cell_bounds_host)
-        solo = rast.forward(p, kd, [r.cam], 5e-5, cell_visible=[mask])
+        solo = rast.forward(p, kd, [r.cam], 5e-5, cull=True)
         assert torch.equal(solo.image, r.image.reshape(-1)), r.rid
     st = serve.latency_stats(reqs, 0, srv)
     log(str(st))
     assert st["completed"] == len(reqs)
+
+
+def test_served_images_match_the_oracle(city):
+    """Images taken through the server (batched, K = 64, cell culling) against
+    the oracle on sampled pixels of every view."""
+    p, kd, rast = city
+    reqs = serve.serve_trace(1000.0, 6, seed=58, xy_range=250.0, res_mix=[((320, 180), 0.5), ((480, 270), 0.5)])
+    srv = serve.Server(p, kd, max_batch=4, workers=1, keep_images=True)
+    srv.run(reqs)
+    pn = {k: p[k].cpu().numpy().astype(np.float64) for k in raster.PARAM_KEYS}
+    pn["sh_degree"] = int(p["sh_degree"])
+    okd = oracle.kd_partition(pn["means"], pn["log_scales"], kd.L)
+    rng = np.random.default_rng(59)
+    worst = 0.0
+    for r in reqs:
+        W, H = int(r.cam["W"]), int(r.cam["H"])
+        order, _ = oracle.cell_order(kd.L, okd["split"], r.cam["o"])
+        pr = oracle.project(pn, r.cam, okd, 0)
+        pix = np.stack([rng.integers(0, W, 1500), rng.integers(0, H, 1500)], 1).astype(np.int32)
+        o = oracle.render(pr, r.cam, okd, order, pix, 5e-5)
+        img = r.image.reshape(3, -1).cpu().numpy().T[pix[:, 1] * W + pix[:, 0]]
+        worst = max(worst, float(np.abs(img - o["img"]).max()))
+    log("served images vs oracle: max err %.2e over %d views" % (worst, len(reqs)))
+    assert worst <= 2e-4
 
 
 def test_admission_respects_memory_budget(city):

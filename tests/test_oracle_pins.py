@@ -157,6 +157,111 @@ def test_ewa_isotropic_off_axis(orc):
     assert abs(v[0] - (f * X / Z + 64)) < 1e-9 and abs(v[1] - (f * Y / Z + 64)) < 1e-9
 
 
+def test_sh_view_direction_closed_form(orc):
+    """Colour of a Gaussian with only degree-1 SH terms, seen from two opposite
+    sides: 0.5 + f Y_1m(d) with d = (mu - o) / |mu - o| the direction from the
+    camera centre to the Gaussian (Sec. 3.1, view-dependent colour).  Each
+    channel carries one l = 1 term (y, z, x), so a flipped direction, a swapped
+    axis or a dropped sign changes at least one channel."""
+    mu = np.array([0.3, -0.2, 0.4])
+    K1 = math.sqrt(3.0 / (4.0 * math.pi))
+    c = (0.6, -0.5, 0.45)
+    p = manual_scene(mu.reshape(3, 1), [[-3.0]] * 3, rgb=[[0.5], [0.5], [0.5]], D=1)
+    p["sh"][:] = 0.0
+    p["sh"][3 * 1 + 0, 0] = c[0]   # Y_1,-1 (y) -> red
+    p["sh"][3 * 2 + 1, 0] = c[1]   # Y_1,0  (z) -> green
+    p["sh"][3 * 3 + 2, 0] = c[2]   # Y_1,1  (x) -> blue
+    u = np.array([0.48, -0.6, 0.64])
+    for side in (+1.0, -1.0):
+        eye = mu + side * 2.5 * u
+        cam = scenes.make_camera(scenes.look_at(eye, mu), eye, 64, 64)
+        pr = orc.project(p, cam, kd_trivial(), 1)
+        assert pr["vis"][0] == 1
+        o = np.asarray(cam["o"], np.float64)
+        d = (p["means"][:, 0].astype(np.float64) - o)
+        d /= np.linalg.norm(d)
+        ref = [0.5 + c[0] * (-K1 * d[1]), 0.5 + c[1] * (K1 * d[2]), 0.5 + c[2] * (-K1 * d[0])]
+        got = pr["val"][0, 7:10]
+        assert np.abs(got - np.maximum(ref, 0.0)).max() < 1e-6, (side, got, ref)
+    # from the two sides the odd band flips sign: the colours mirror around 0.5
+    assert abs(ref[1] - 0.5) > 0.1
+
+
+def _guard_camera(W=64, H=48, cx=20.0, cy=30.0):
+    """Axis camera with an off-centre principal point, so that the guard
+    1.3 max(cx, W - cx) / fx differs from 1.3 cx / fx (and likewise in y)."""
+    cam = axis_camera(W, H)
+    cam["cx"], cam["cy"] = np.float32(cx), np.float32(cy)
+    return cam
+
+
+def test_ewa_guard_clamp_closed_form(orc):
+    """A Gaussian outside the 1.3x half-field-of-view guard (Sec. 3.1, EWA by
+    the Jacobian at the clamped centre): x/z is clamped to -gx (left side,
+    gx = 1.3 max(cx, W - cx) / fx) and y/z to +gy, so J = [[f/z, 0, f gx],
+    [0, f/z, -f gy]]; the screen mean stays the unclamped projection."""
+    cam = _guard_camera()
+    f = float(cam["fx"])
+    W, H, cx, cy = 64, 48, 20.0, 30.0
+    gx = 1.3 * max(cx, W - cx) / f
+    gy = 1.3 * max(cy, H - cy) / f
+    s = scale32(0.4)
+    Z = f32(2.0)
+    X, Y = f32(-1.6 * gx * Z), f32(1.4 * gy * Z)
+    p = manual_scene([[X], [Y], [Z]], [[math.log(s)]] * 3)
+    pr = orc.project(p, cam, kd_trivial(), 1)
+    J = np.array([[f / Z, 0.0, f * gx / Z], [0.0, f / Z, -f * gy / Z]])
+    S2 = s * s * (J @ J.T) + 0.3 * np.eye(2)
+    Cn = np.linalg.inv(S2)
+    v = pr["val"][0]
+    assert np.allclose([v[2], v[3], v[4]], [Cn[0, 0], Cn[0, 1], Cn[1, 1]], rtol=1e-6, atol=1e-14)
+    assert abs(v[0] - (f * X / Z + cx)) < 1e-9 and abs(v[1] - (f * Y / Z + cy)) < 1e-9
+    # the unclamped Jacobian would give a clearly different footprint
+    Ju = np.array([[f / Z, 0.0, -f * X / Z ** 2], [0.0, f / Z, -f * Y / Z ** 2]])
+    Cu = np.linalg.inv(s * s * (Ju @ Ju.T) + 0.3 * np.eye(2))
+    assert abs(Cu[0, 0] - Cn[0, 0]) > 1e-3 * abs(Cn[0, 0])
+    # mirror32 decisions carry the same clamped conic, rounded to fp32
+    d = orc.project(p, cam, kd_trivial(), 0)["dec32"][0]
+    assert abs(d[2] - Cn[0, 0]) <= 1e-5 * Cn[0, 0] and abs(d[4] - Cn[1, 1]) <= 1e-5 * Cn[1, 1]
+
+
+def test_ewa_guard_clamp_backward_fd(orc):
+    """Through the clamp the Jacobian depends on z only (x~ = -gx z), so the conic's
+    derivative w.r.t. the camera-space x of the mean comes from nothing but z's
+    share; the oracle's projection backward agrees with central differences of
+    its exact64 forward for a clamped Gaussian (Sec. 3.1)."""
+    cam = _guard_camera()
+    f = float(cam["fx"])
+    gx = 1.3 * 44.0 / f
+    gy = 1.3 * 30.0 / f
+    Z = 2.0
+    p = manual_scene([[-1.6 * gx * Z], [1.4 * gy * Z], [Z]], [[math.log(0.3)], [math.log(0.2)], [math.log(0.5)]],
+                     quats=np.array([[0.9], [0.2], [-0.3], [0.1]], np.float32))
+    for k in ("means", "log_scales", "quats", "opacity", "sh"):
+        p[k] = p[k].astype(np.float64)
+    kd = kd_trivial()
+    pr = orc.project(p, cam, kd, 1)
+    assert pr["val"][0, 11] > 0   # a valid footprint (det > 0)
+    rng = np.random.default_rng(31)
+    g2d = np.zeros((1, 9))
+    g2d[0, :5] = rng.normal(size=5)            # mean and conic rows
+    g = orc.project_bwd(p, cam, dict(pr, vis=np.ones(1, np.uint8)), g2d)
+
+    def objective():
+        v = orc.project(p, cam, kd, 1)["val"][0]
+        return float(g2d[0, 0] * v[0] + g2d[0, 1] * v[1] + g2d[0, 2] * v[2] + g2d[0, 3] * v[3] + g2d[0, 4] * v[4])
+
+    for key, rows in (("means", 3), ("log_scales", 3), ("quats", 4)):
+        for r in range(rows):
+            x0 = p[key][r, 0]
+            h = 1e-6 * max(1.0, abs(x0))
+            p[key][r, 0] = x0 + h; fp = objective()
+            p[key][r, 0] = x0 - h; fm = objective()
+            p[key][r, 0] = x0
+            fd = (fp - fm) / (2 * h)
+            assert abs(fd - g[key][r, 0]) <= 1e-5 * (abs(fd) + 1e-3), (key, r, fd, g[key][r, 0])
+
+
 def _quat_mul(a, b):
     w1, x1, y1, z1 = a
     w2, x2, y2, z2 = b
@@ -536,6 +641,175 @@ def test_paper_subsets_brute_force(orc):
     assert np.all((own >> kd["center_cell"].astype(np.uint32)) & 1)
 
 
+@pytest.mark.parametrize("L", [1, 3, 4, 6])
+def test_fixed_grid_partition_is_a_uniform_grid(orc, L):
+    """The fixed-size partition the paper compares the KD tree with (Sec. 4.2,
+    Table 2): the leaves are the blocks of a uniform grid over the centres'
+    bounding box.  With a dyadic box [0, 8]^3 every cut is exact, so each
+    leaf's finite faces sit on multiples of 8 / blocks-per-axis and its count
+    equals a plain 3D histogram of the centres on that grid."""
+    rng = np.random.default_rng(12)
+    n = 4000
+    means = rng.uniform(0.0, 8.0, size=(3, n)).astype(np.float32)
+    means[:, 0] = 0.0
+    means[:, 1] = 8.0
+    kd = orc.kd_partition(means, np.full((3, n), -3.0, np.float32), L, 3.0, rule=1)
+    nb = [1 << len([d for d in range(L) if d % 3 == a]) for a in range(3)]   # blocks per axis
+    K = 1 << L
+    for k in range(K):
+        for a in range(3):
+            lo, hi = kd["box_lo"][a, k], kd["box_hi"][a, k]
+            w = 8.0 / nb[a]
+            for v in (lo, hi):
+                assert not np.isfinite(v) or (v / w == np.round(v / w) and 0 < v < 8)
+            if np.isfinite(lo) and np.isfinite(hi):
+                assert hi - lo == w
+    edges = [np.linspace(0.0, 8.0, nb[a] + 1) for a in range(3)]
+    H, _ = np.histogramdd(means.T.astype(np.float64), bins=edges)
+    # leaf k covers block (ix, iy, iz) whose index bits are the path bits of its axis
+    got = np.zeros(nb, np.int64)
+    for k in range(K):
+        idx = [0, 0, 0]
+        for d in range(L):
+            idx[d % 3] = 2 * idx[d % 3] + ((k >> (L - 1 - d)) & 1)
+        got[tuple(idx)] = kd["counts"][k]
+    assert np.array_equal(got, H.astype(np.int64))
+
+
+def test_fixed_grid_unbalanced_where_kd_is_balanced(orc):
+    """On the clustered scene the grid's per-cell counts spread widely while the
+    KD tree's stay within one Gaussian of n / K (the paper's Table 2 contrast)."""
+    p = scenes.scene_clusters(40000, seed=21, D=0)
+    kd = orc.kd_partition(p["means"], p["log_scales"], 3)
+    gr = orc.kd_partition(p["means"], p["log_scales"], 3, 3.0, rule=1)
+    assert kd["counts"].max() - kd["counts"].min() <= 1
+    assert gr["counts"].max() > 2 * gr["counts"].min() + 1000
+    assert kd["counts"].sum() == gr["counts"].sum() == 40000
+
+
+def _pixel_rays(cam, pix):
+    R = np.asarray(cam["R"], np.float32)
+    dx = ((pix[:, 0].astype(np.float32) + np.float32(0.5)) - np.float32(cam["cx"])) / np.float32(cam["fx"])
+    dy = ((pix[:, 1].astype(np.float32) + np.float32(0.5)) - np.float32(cam["cy"])) / np.float32(cam["fy"])
+    return np.stack([(R[0, a] * dx + R[1, a] * dy) + R[2, a] for a in range(3)], 1).astype(np.float32)
+
+
+@pytest.mark.parametrize("d_factor", [0.0, 3.0])
+def test_paper_subsets_lose_exactly_the_escapes(orc, d_factor):
+    """Rendering each cell from the paper's N_k only (Sec. 3.3) drops exactly the
+    contributions whose crossing point lies in a cell that does not hold the
+    Gaussian: counted here by brute force over every (pixel, Gaussian), the
+    number of contributors lost equals that count, pixel by pixel."""
+    p = _tiny_scene(300, seed=41, mu_s=-2.2, extent=0.5)
+    kd = orc.kd_partition(p["means"], p["log_scales"], 2, d_factor)
+    cam = scenes.orbit_camera(1.8, 0.5, 0.3, 40, 32)
+    order, _ = orc.cell_order(2, kd["split"], cam["o"])
+    pr0 = orc.project(p, cam, kd, 0)
+    pr1 = orc.project(p, cam, kd, 0, cells=1)
+    pix = orc.all_pixels(40, 32)
+    r0 = orc.render(pr0, cam, kd, order, pix, 0.0)
+    r1 = orc.render(pr1, cam, kd, order, pix, 0.0)
+    D = _pixel_rays(cam, pix)
+    o = np.asarray(cam["o"], np.float32)
+    dec = pr0["dec32"]
+    lost = np.zeros(len(pix), np.int64)
+    for i in np.nonzero(pr0["vis"])[0]:
+        mx, my, ca, tau, z, k_, e = dec[i, 0], dec[i, 1], dec[i, 2], dec[i, 5], dec[i, 6], dec[i, 8], dec[i, 9]
+        dxp = (pix[:, 0].astype(np.float32) + np.float32(0.5)) - mx
+        dyp = (pix[:, 1].astype(np.float32) + np.float32(0.5)) - my
+        u = (k_ * dyp).astype(np.float64) + dxp          # fma rounding aside, decisions are far from ties here
+        d2 = e * dyp * dyp + ca * u * u
+        hit = d2 <= tau
+        x = (z * D.astype(np.float64) + o)
+        cell = np.zeros(len(pix), np.int64)
+        for kk in range(4):
+            inside = np.all((x >= kd["box_lo"][:, kk]) & (x < kd["box_hi"][:, kk]), 1)
+            cell[inside] = kk
+        owned = (kd["own_mask"][i, 0] >> cell.astype(np.uint32)) & 1
+        lost += hit & (owned == 0)
+    assert np.array_equal(r0["ncon"] - r1["ncon"], lost)
+    # instances are emitted only for cells whose N_k holds the Gaussian, within the exact cell set
+    own = kd["own_mask"][:, 0].astype(np.uint64)
+    assert np.all(pr1["cellmask"] & ~own == 0) and np.all(pr1["cellmask"] & ~pr0["cellmask"] == 0)
+    assert np.all(r1["ncon"] == orc.render(pr1, cam, kd, order, pix, 0.0, restrict=True)["ncon"])
+    if d_factor == 0.0:
+        assert lost.sum() > 50          # without a margin, straddling Gaussians escape
+    # the restriction only removes contributions: an empty loss leaves the image exact
+    same = lost == 0
+    assert np.abs(r1["img"][same] - r0["img"][same]).max() < 1e-12
+
+
+def test_paper_subsets_with_a_large_margin_are_exact(orc):
+    """With D_i large enough that every N_k holds every Gaussian, the paper's
+    subset rendering is the exact merged render (= the plain render, Eq. 5)."""
+    p = _tiny_scene(200, seed=42, mu_s=-2.2, extent=0.5)
+    kd = orc.kd_partition(p["means"], p["log_scales"], 2, 1e6)
+    assert np.all(kd["own_mask"][:, 0] == 15)
+    cam = scenes.orbit_camera(1.8, 0.9, 0.3, 32, 32)
+    order, _ = orc.cell_order(2, kd["split"], cam["o"])
+    pr = orc.project(p, cam, kd, 1, cells=1)
+    r = orc.render(pr, cam, kd, order, orc.all_pixels(32, 32), 0.0)
+    assert np.abs(r["img"] - r["plain"]).max() < 1e-12
+
+
+def test_exclusive_cells_reorder_across_the_plane(orc):
+    """Cell-based methods give each Gaussian to the cell of its centre and merge
+    cells in ray order without the indicator of Eq. 6 (Sec. 2, Sec. 4.2): a
+    Gaussian A nearer than B but centred across the plane is blended behind B.
+    At the centre pixel the exact method gives sA cA + (1 - sA) sB cB; the
+    exclusive mode gives sB cB + (1 - sB) sA cA."""
+    # camera on the left of the plane x = 0, looking along +z
+    eye = np.array([-0.05, 0.0, 0.0])
+    cam = scenes.make_camera(np.eye(3), eye, 33, 33, z_near=0.1)
+    means = [[0.01, -0.01, -5.0, 5.0], [0.0, 0.0, 5.0, 5.0], [2.0, 3.0, 30.0, 30.0]]
+    p = manual_scene(means, [[math.log(0.05)] * 4] * 3, opacity=[1.0, 1.0, 0.0, 0.0],
+                     rgb=[[0.9, 0.1, 0.5, 0.5], [0.2, 0.8, 0.5, 0.5], [0.1, 0.3, 0.5, 0.5]])
+    kd = orc.kd_partition(p["means"], p["log_scales"], 1)
+    assert kd["split"][0] == np.float32(0.01) and list(kd["center_cell"]) == [1, 0, 0, 1]
+    order, _ = orc.cell_order(1, kd["split"], cam["o"])
+    assert list(order) == [0, 1]
+    pix = np.array([[16, 16]], np.int32)
+    pe = orc.project(p, cam, kd, 1)
+    px = orc.project(p, cam, kd, 1, cells=2)
+    re_ = orc.render(pe, cam, kd, order, pix, 0.0)
+    rx = orc.render(px, cam, kd, order, pix, 0.0)
+    v = pe["val"]
+    sig = []
+    for i in (0, 1):
+        dx, dy = 16.5 - v[i, 0], 16.5 - v[i, 1]
+        d2 = v[i, 2] * dx * dx + 2 * v[i, 3] * dx * dy + v[i, 4] * dy * dy
+        sig.append(min(0.99, v[i, 5] * math.exp(-0.5 * d2)))
+    sA, sB = sig
+    cA, cB = v[0, 7:10], v[1, 7:10]
+    exact = sA * cA + (1 - sA) * sB * cB
+    leaky = sB * cB + (1 - sB) * sA * cA
+    assert np.abs(re_["img"][0] - exact).max() < 1e-12
+    assert np.abs(rx["img"][0] - leaky).max() < 1e-12
+    assert np.abs(exact - leaky).max() > 0.05
+
+
+def test_exclusive_cells_leak_in_the_validity_experiment(orc):
+    """Sec. 4.2's validity setting (camera on the dividing plane): with the
+    indicator every near-side pixel gets exactly (0, 1) from the far cell;
+    cell-based exclusive subsets leak there (Gaussians straddling the plane
+    paint the far cell's partial across the boundary) and the merged image
+    departs from the plain render.  With one cell the two modes coincide."""
+    p = _tiny_scene(400, seed=40, mu_s=-2.3, extent=0.5)
+    kd = orc.kd_partition(p["means"], p["log_scales"], 1)
+    s = float(kd["split"][0])
+    cam = scenes.with_kd_axis_aligned_camera(s, 64, 48, dist=2.0)
+    order, _ = orc.cell_order(1, kd["split"], cam["o"])
+    pix = orc.all_pixels(64, 48)
+    left_px = pix[:, 0] < 32
+    rx = orc.render(orc.project(p, cam, kd, 1, cells=2), cam, kd, order, pix, 0.0)
+    leaks = (rx["partT"][left_px, 1] < 1.0).sum() + (rx["partT"][~left_px, 0] < 1.0).sum()
+    assert leaks > 20
+    assert np.abs(rx["img"] - rx["plain"]).max() > 1e-3
+    kd0 = orc.kd_partition(p["means"], p["log_scales"], 0)
+    r0 = orc.render(orc.project(p, cam, kd0, 1, cells=2), cam, kd0, [0], pix, 0.0)
+    assert np.abs(r0["img"] - r0["plain"]).max() < 1e-12
+
+
 # ------------------------------------------------------------------ merge order o_l (Eq. 5)
 def _ray_box_entry(o, d, lo, hi):
     t0, t1 = 0.0, np.inf
@@ -820,3 +1094,72 @@ def test_loss_gradient_fd(orc):
         x.flat[i] = xi - h; lm, _ = orc.loss(x, y, 0.2)
         x.flat[i] = xi
         assert abs((lp - lm) / (2 * h) - d.flat[i]) < 1e-7
+
+
+# ------------------------------------------------------------------ training (Sec. 4)
+def test_position_lr_schedule(orc):
+    """1.6e-4 -> 1.6e-6 exponentially: endpoints, the geometric mean halfway,
+    a constant ratio per step, and held after the last step."""
+    T = 30000
+    assert abs(orc.expon_lr(0, 1.6e-4, 1.6e-6, T) - 1.6e-4) < 1e-18
+    assert abs(orc.expon_lr(T, 1.6e-4, 1.6e-6, T) - 1.6e-6) < 1e-20
+    assert abs(orc.expon_lr(T // 2, 1.6e-4, 1.6e-6, T) - 1.6e-5) < 1e-18
+    r = [orc.expon_lr(k + 1, 1.6e-4, 1.6e-6, T) / orc.expon_lr(k, 1.6e-4, 1.6e-6, T) for k in (0, 777, 20000)]
+    assert max(r) - min(r) < 1e-12 and abs(r[0] - 100.0 ** (-1.0 / T)) < 1e-12
+    assert orc.expon_lr(2 * T, 1.6e-4, 1.6e-6, T) == orc.expon_lr(T, 1.6e-4, 1.6e-6, T)
+
+
+def _adam_hp(step):
+    return dict(beta1=0.9, beta2=0.999, eps=1e-15, step=step,
+                lr=dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity=5e-2, sh_dc=2.5e-3, sh_rest=1.25e-4))
+
+
+def _param_set(rng, n, D):
+    nc = (D + 1) ** 2
+    return dict(means=rng.normal(size=(3, n)), log_scales=rng.normal(size=(3, n)), quats=rng.normal(size=(4, n)),
+                opacity=rng.normal(size=n), sh=rng.normal(size=(3 * nc, n)))
+
+
+def test_adam_first_step_is_signed_learning_rate(orc):
+    """After one step from zero moments, m_hat = g and v_hat = g^2 exactly, so
+    every element moves by lr sign(g) (to within eps / |g|)."""
+    rng = np.random.default_rng(1)
+    p = _param_set(rng, 50, 3)
+    g = _param_set(rng, 50, 3)
+    z = {k: np.zeros_like(v) for k, v in p.items()}
+    m, v = dict(z), {k: np.zeros_like(x) for k, x in p.items()}
+    p0 = {k: x.copy() for k, x in p.items()}
+    hp = _adam_hp(1)
+    orc.adam_step(p, g, m, v, hp)
+    for k in p:
+        lr = hp["lr"][k] if k != "sh" else np.r_[[hp["lr"]["sh_dc"]] * 3, [hp["lr"]["sh_rest"]] * 45][:, None]
+        assert np.allclose(p0[k] - p[k], lr * np.sign(g[k]), rtol=1e-9, atol=0)
+
+
+def test_adam_matches_torch_optimizer(orc):
+    """Five steps against torch.optim.Adam (CPU, fp64) with the same groups."""
+    import torch
+    rng = np.random.default_rng(2)
+    D = 2
+    p = _param_set(rng, 40, D)
+    m = {k: np.zeros_like(x) for k, x in p.items()}
+    v = {k: np.zeros_like(x) for k, x in p.items()}
+    tp = {k: torch.tensor(x.copy(), requires_grad=True) for k, x in p.items()}
+    lr = _adam_hp(1)["lr"]
+    groups = [{"params": [tp[k]], "lr": lr[k]} for k in ("means", "log_scales", "quats", "opacity")]
+    sh_dc = torch.tensor(p["sh"][:3].copy(), requires_grad=True)
+    sh_rest = torch.tensor(p["sh"][3:].copy(), requires_grad=True)
+    groups += [{"params": [sh_dc], "lr": lr["sh_dc"]}, {"params": [sh_rest], "lr": lr["sh_rest"]}]
+    opt = torch.optim.Adam(groups, betas=(0.9, 0.999), eps=1e-15)
+    for step in range(1, 6):
+        g = _param_set(rng, 40, D)
+        orc.adam_step(p, g, m, v, _adam_hp(step))
+        for k in ("means", "log_scales", "quats", "opacity"):
+            tp[k].grad = torch.tensor(g[k])
+        sh_dc.grad = torch.tensor(g["sh"][:3])
+        sh_rest.grad = torch.tensor(g["sh"][3:])
+        opt.step()
+    for k in ("means", "log_scales", "quats", "opacity"):
+        assert np.allclose(p[k], tp[k].detach().numpy(), rtol=1e-13, atol=1e-15), k
+    assert np.allclose(p["sh"][:3], sh_dc.detach().numpy(), rtol=1e-13, atol=1e-15)
+    assert np.allclose(p["sh"][3:], sh_rest.detach().numpy(), rtol=1e-13, atol=1e-15)
