@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 3
+#define RGS_ABI_VERSION 4
 #define RGS_TILE 16       /* screen tiles are 16 x 16 pixels */
 #define RGS_MAX_L 6       /* K = 2^L <= 64 cells */
 #define RGS_MAX_VIEWS 16  /* views per call */
@@ -426,7 +426,7 @@ rgs_status rgs_project_sh_bwd(const float *d_proj, const rgs_gaussians *g, const
  * grads is read; the four must not overlap. */
 typedef struct {
     float lr_means, lr_log_scales, lr_quats, lr_opacity, lr_sh_dc, lr_sh_rest;
-    float beta1, beta2, eps;
+    double beta1, beta2, eps; /* 1 - b1, 1 - b2 and the bias corrections are formed in fp64 and rounded once */
     int32_t step;
 } rgs_adam_params;
 rgs_status rgs_adam_step(const rgs_gaussians_grad *params, const rgs_gaussians_grad *grads,

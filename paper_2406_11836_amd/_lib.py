@@ -55,7 +55,8 @@ class Bins(C.Structure):
 
 class AdamParams(C.Structure):
     _fields_ = [("lr_means", f32), ("lr_log_scales", f32), ("lr_quats", f32), ("lr_opacity", f32),
-                ("lr_sh_dc", f32), ("lr_sh_rest", f32), ("beta1", f32), ("beta2", f32), ("eps", f32), ("step", i32)]
+                ("lr_sh_dc", f32), ("lr_sh_rest", f32), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("step", i32)]
 
 
 class Partials(C.Structure):

@@ -602,8 +602,8 @@ rgs_status rgs_adam_step(const rgs_gaussians_grad* params, const rgs_gaussians_g
                          rgs_stream stream) {
     if (n < 0 || sh_degree < 0 || sh_degree > 3 || !hp || !params || !grads || !m || !v) return RGS_E_ARG;
     if (n > 0 && (!grad_ptrs_ok(params) || !grad_ptrs_ok(grads) || !grad_ptrs_ok(m) || !grad_ptrs_ok(v))) return RGS_E_ARG;
-    if (hp->step < 1 || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) ||
-        !(hp->eps >= 0.f) || !isfinite(hp->eps))
+    if (hp->step < 1 || !(hp->beta1 >= 0.0 && hp->beta1 < 1.0) || !(hp->beta2 >= 0.0 && hp->beta2 < 1.0) ||
+        !(hp->eps >= 0.0) || !isfinite(hp->eps))
         return RGS_E_ARG;
     const float lrs[6] = {hp->lr_means, hp->lr_log_scales, hp->lr_quats, hp->lr_opacity, hp->lr_sh_dc, hp->lr_sh_rest};
     for (float lr : lrs)

@@ -24,14 +24,17 @@ struct AdamGroup {
     float lr_a, lr_b;
 };
 
+// The hyperparameters arrive in fp64; each constant the update uses is
+// formed there and rounded to fp32 once (1 - b2 for b2 = 0.999 would lose
+// 13 bits if formed from the rounded b2).
 struct AdamArgs {
     AdamGroup grp[5];
-    float beta1, beta2, eps, c1, c2;  // c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t)
+    float beta1, beta2, omb1, omb2, eps, c1, c2;  // omb = 1 - beta; c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t)
 };
 
 __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, const AdamArgs& a) {
-    m = fmaf(a.beta1, m, (1.0f - a.beta1) * g);
-    v = fmaf(a.beta2, v, ((1.0f - a.beta2) * g) * g);
+    m = fmaf(a.beta1, m, a.omb1 * g);
+    v = fmaf(a.beta2, v, (a.omb2 * g) * g);
     const float mh = m * a.c1, vh = v * a.c2;
     p = p - lr * (mh / (sqrtf(vh) + a.eps));
 }
@@ -88,10 +91,12 @@ rgs_status adam_launch(const rgs_gaussians_grad* params, const rgs_gaussians_gra
     a.grp[4].dc_len = 3 * n;  // SH rows 0..2: degree 0 (one per channel)
     a.grp[4].lr_b = hp->lr_sh_rest;
     // bias corrections from the 1-based step count, in fp64 on the host
-    const double b1t = pow((double)hp->beta1, (double)hp->step), b2t = pow((double)hp->beta2, (double)hp->step);
-    a.beta1 = hp->beta1;
-    a.beta2 = hp->beta2;
-    a.eps = hp->eps;
+    const double b1t = pow(hp->beta1, (double)hp->step), b2t = pow(hp->beta2, (double)hp->step);
+    a.beta1 = (float)hp->beta1;
+    a.beta2 = (float)hp->beta2;
+    a.omb1 = (float)(1.0 - hp->beta1);
+    a.omb2 = (float)(1.0 - hp->beta2);
+    a.eps = (float)hp->eps;
     a.c1 = (float)(1.0 / (1.0 - b1t));
     a.c2 = (float)(1.0 / (1.0 - b2t));
     const int64_t most = 3 * nc * n;

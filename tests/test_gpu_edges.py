@@ -104,7 +104,9 @@ def test_stacked_opaque_exact_mode(rast, L):
     means = np.stack([rng.uniform(-0.03, 0.03, n), rng.uniform(-0.03, 0.03, n), 2.0 + 0.05 * np.arange(n)])
     p = scenes.scene_uniform(n, seed=18, D=1, mu_s=np.log(0.15), extent=0.1)
     p["means"] = means.astype(np.float32)
-    p["log_scales"] = np.full((3, n), np.log(0.15), np.float32)
+    # slightly anisotropic, so that the rotation gradient is not identically
+    # zero (an isotropic covariance does not depend on the quaternion)
+    p["log_scales"] = np.log(np.array([[0.15], [0.12], [0.10]]) * np.ones((3, n))).astype(np.float32)
     p["opacity"] = np.full(n, np.log(0.98 / 0.02), np.float32)
     cam = scenes.make_camera(np.eye(3), np.zeros(3), 64, 64, z_near=0.1, bg=(0.2, 0.4, 0.6))
     dp = device_params(p)

@@ -8,9 +8,10 @@ sum(w * image) (w seeded N(0,1)) from the torch.autograd.Function must match
 fp64 central differences of the oracle's exact64 forward.  Finite
 differences of all 512 x 59 parameters would take hours on the CPU, so a
 stratified sample of 240 parameters (every parameter kind, visible
-Gaussians) is checked; parameters whose stencil crosses a cut (the value at
-h and h/4 disagree) are skipped and counted, and must stay under a tenth of
-the sample.
+Gaussians) is checked with the step h = 1e-6 max(1, |theta|) (positions
+measured from the crop's centre); parameters whose stencil crosses a cut
+(the value at h and h/4 disagree) are skipped and counted, and must stay
+under a tenth of the sample.
 
 The GPU takes its contribute decisions in fp32 (the mirror32 sequence), the
 finite differences in fp64 (exact64).  Where the two decision sets differ (a
@@ -62,13 +63,13 @@ def _crop():
     cam["cx"] = np.float32(128.0)
     cam["cy"] = np.float32(128.0)
     cam["bg"] = np.array([0.2, 0.3, 0.4], np.float32)
-    return crop, cam
+    return crop, cam, hit
 
 
 def test_autograd_matches_fd64_on_city_crop():
     torch.manual_seed(0)
     log("drawing 16M-Gaussian city and cropping 512")
-    crop, cam = _crop()
+    crop, cam, centre = _crop()
     rast = raster.Rasterizer()
     dp = raster.to_device({k: (v.astype(np.float32) if k != "sh_degree" else v) for k, v in crop.items()})
     for k in raster.PARAM_KEYS:
@@ -123,7 +124,12 @@ def test_autograd_matches_fd64_on_city_crop():
             x = p64[k]
             flat = (r_ * 512 + i) if x.ndim == 2 else i
             xi = float(x.flat[flat])
-            h = 1e-6 * max(1.0, abs(xi))
+            # positions are measured from the crop's centre: the function does
+            # not change under a translation of the world frame, and a step
+            # relative to the distance from the world origin (up to 800 m
+            # here) would move the footprint by ~0.02 px, across the 3-sigma
+            # cut of most Gaussians
+            h = 1e-6 * max(1.0, abs(xi - centre[r_]) if k == "means" else abs(xi))
             vals = []
             for hh in (h, h / 4):
                 x.flat[flat] = xi + hh

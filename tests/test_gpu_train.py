@@ -43,10 +43,15 @@ def test_adam_kernel_matches_oracle(n):
     dp = _dev(p32 | {"sh_degree": D})
     dm = {k: torch.zeros_like(dp[k]) for k in KEYS}
     dv = {k: torch.zeros_like(dp[k]) for k in KEYS}
+    # the first moment's recursion on |g|: fp32 rounding of each step's two
+    # products and one sum moves m by a few 2^-24 of this, whatever the signs
+    mabs = {k: np.zeros_like(p32[k]) for k in KEYS}
     lr = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity=5e-2, sh_dc=2.5e-3, sh_rest=1.25e-4)
     for step in range(1, 5):
         g = _rand_set(rng, n, D, scale=10.0 ** rng.uniform(-3, 1))
         g32 = {k: np.asarray(g[k], np.float32).astype(np.float64) for k in KEYS}
+        for k in KEYS:
+            mabs[k] = 0.9 * mabs[k] + 0.1 * np.abs(g32[k])
         train.adam_step(lib, dp, _dev(g32 | {"sh_degree": D}), dm, dv, step, lr, eps=1e-15)
         oracle.adam_step(p32, g32, m, v, dict(beta1=0.9, beta2=0.999, eps=1e-15, step=step,
                                                lr=dict(lr, means=1.6e-4)))
@@ -55,8 +60,11 @@ def test_adam_kernel_matches_oracle(n):
         got = dp[k].cpu().numpy().astype(np.float64)
         # the update is a few lr in size; fp32 storage of p rounds at 2^-24 |p|
         assert np.abs(got - p32[k]).max() <= 1e-6 * np.abs(p32[k]).max() + 1e-7, k
-        assert np.allclose(dm[k].cpu().numpy(), m[k], rtol=1e-5, atol=1e-12), k
-        assert np.allclose(dv[k].cpu().numpy(), v[k], rtol=1e-5, atol=1e-18), k
+        # four steps of at most three roundings each (2^-24 = 6e-8), plus the
+        # fp32 rounding of b1 and 1 - b1: well inside 2e-6 of the |g| recursion
+        assert np.all(np.abs(dm[k].cpu().numpy() - m[k]) <= 2e-6 * mabs[k]), k
+        # v sums positive terms, so its relative error stays a few 2^-24
+        assert np.all(np.abs(dv[k].cpu().numpy() - v[k]) <= 2e-6 * v[k]), k
 
 
 def test_permute_matches_indexing():
