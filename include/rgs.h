@@ -364,6 +364,24 @@ rgs_status rgs_loss_l1_ssim(const float *image, const float *target, int32_t H, 
                             float ssim_weight, float *loss, float *d_image, void *ws, size_t ws_bytes,
                             rgs_stream stream);
 
+/* The same loss for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, hosts that forbid allocation): no workspace
+ * argument and no allocation of any kind.  The workspace is a fixed
+ * RGS_LOSS_SCRATCH_BYTES array in device memory, one per device, which the
+ * library holds until the process ends; its address is looked up once per
+ * device on the first call there (the current device; the stream must belong
+ * to it).  Returns RGS_E_CAPACITY, with nothing enqueued, when the view needs
+ * more than the array (rgs_loss_workspace(H, W) > RGS_LOSS_SCRATCH_BYTES:
+ * up to about 3.7 Mpx, e.g. 2560x1440; 3840x2160 does not fit).  Every call
+ * on one device uses the same array: calls that overlap in time on one
+ * device (other streams, other threads) race and give wrong results; calls
+ * in one stream are ordered and safe.  Nothing in the array has to start at
+ * zero: each call writes every word it reads.  Results equal those of
+ * rgs_loss_l1_ssim. */
+#define RGS_LOSS_SCRATCH_BYTES ((size_t)128 << 20)
+rgs_status rgs_loss_l1_ssim_noalloc(const float *image, const float *target, int32_t H, int32_t W,
+                                    float ssim_weight, float *loss, float *d_image, rgs_stream stream);
+
 /* ------------------------------------------------------------------ */
 /* Backward                                                             */
 /* ------------------------------------------------------------------ */

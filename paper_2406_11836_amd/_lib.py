@@ -90,6 +90,7 @@ _SIGS = {
     "rgs_merge_partials": (i32, [P(Partials), P(Bins), P(Camera), i32, vp, vp, vp, vp]),
     "rgs_loss_workspace": (sz, [i32, i32]),
     "rgs_loss_l1_ssim": (i32, [vp, vp, i32, i32, f32, vp, vp, vp, sz, vp]),
+    "rgs_loss_l1_ssim_noalloc": (i32, [vp, vp, i32, i32, f32, vp, vp, vp]),
     "rgs_merge_partials_bwd": (i32, [vp, vp, P(Partials), P(Bins), P(Camera), i32, vp, P(PartialsGrad), vp]),
     "rgs_render_bwd_workspace": (sz, [i64]),
     "rgs_render_partial_bwd": (i32, [P(PartialsGrad), P(Partials), P(Bins), P(Projected), i64, P(Camera), i32, vp,

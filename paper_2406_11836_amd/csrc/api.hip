@@ -50,6 +50,7 @@ rgs_status permute_launch(const rgs_gaussians* in, const int32_t* perm, const rg
 size_t loss_ws_bytes(int H, int W);
 rgs_status loss_launch(const float* image, const float* target, int H, int W, float ssim_w, float* loss, float* dimg,
                        void* ws, hipStream_t s);
+rgs_status loss_scratch(void** out);
 }  // namespace rgs
 
 using namespace rgs;
@@ -504,6 +505,18 @@ rgs_status rgs_loss_l1_ssim(const float* image, const float* target, int32_t H, 
     const size_t hw = (size_t)H * (size_t)W;
     if (!disjoint({{loss, 4}, {d_image, 12 * hw}, {ws, ws_bytes}}, {{image, 12 * hw}, {target, 12 * hw}}))
         return RGS_E_ARG;
+    return loss_launch(image, target, H, W, ssim_weight, loss, d_image, ws, S(stream));
+}
+
+rgs_status rgs_loss_l1_ssim_noalloc(const float* image, const float* target, int32_t H, int32_t W, float ssim_weight,
+                                    float* loss, float* d_image, rgs_stream stream) {
+    if (!image || !target || !loss || !d_image || H <= 0 || W <= 0 || !isfinite(ssim_weight)) return RGS_E_ARG;
+    if (loss_ws_bytes(H, W) > RGS_LOSS_SCRATCH_BYTES) return RGS_E_CAPACITY;
+    const size_t hw = (size_t)H * (size_t)W;
+    if (!disjoint({{loss, 4}, {d_image, 12 * hw}}, {{image, 12 * hw}, {target, 12 * hw}})) return RGS_E_ARG;
+    void* ws = nullptr;
+    const rgs_status st = loss_scratch(&ws);
+    if (st != RGS_OK) return st;
     return loss_launch(image, target, H, W, ssim_weight, loss, d_image, ws, S(stream));
 }
 

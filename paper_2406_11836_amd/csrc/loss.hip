@@ -6,6 +6,8 @@
 // vertical 11-tap pass, both run from LDS on 32x32 tiles with a 5-pixel halo.  The backward needs d SSIM / d (mu_x, E[x^2], E[xy])
 // per pixel, convolved again with the (symmetric) window.  Block partial sums
 // are combined by one block in a fixed order, so the scalar is reproducible.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace rgs {
@@ -286,6 +288,39 @@ rgs_status loss_launch(const float* image, const float* target, int H, int W, fl
     }
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LS_THREADS), 0, s, part, parts, invN, ssim_w, loss);
     return launch_check();
+}
+
+// Fixed workspace of the allocation-free loss entry point: one copy per
+// device, held until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is a stand-in, not a device address); it
+// uses the address hipGetSymbolAddress returns for the current device, taken
+// once per device and kept.
+static __device__ __align__(256) unsigned char scratch[RGS_LOSS_SCRATCH_BYTES];
+
+static constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[SCRATCH_MAX_DEVICES];
+
+rgs_status loss_scratch(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_hip_error(e);
+        return RGS_E_HIP;
+    }
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return RGS_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return RGS_E_HIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return RGS_OK;
 }
 
 }  // namespace rgs

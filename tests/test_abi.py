@@ -95,6 +95,11 @@ def test_argument_errors_enqueue_nothing(lib):
                                       C.byref(kd), None, None, 0, None) == E
     assert lib.rgs_project_sh_bwd(None, C.byref(g), C.byref(ps), cam, 1, None, C.byref(gg), None) == E
     assert lib.rgs_loss_l1_ssim(None, None, 4, 4, 0.2, None, None, None, 0, None) == E
+    assert lib.rgs_loss_l1_ssim_noalloc(None, None, 4, 4, 0.2, None, None, None) == E
+    # the allocation-free loss: a view beyond its fixed array is refused up front
+    fk = C.c_void_p(0x100000)
+    assert lib.rgs_loss_workspace(2160, 3840) > (128 << 20) >= lib.rgs_loss_workspace(1440, 2560)
+    assert lib.rgs_loss_l1_ssim_noalloc(fk, fk, 2160, 3840, 0.2, fk, fk, None) == L.RGS_E_CAPACITY
     rk = np.zeros(4, np.int32)
     assert lib.rgs_views_upload(cam, 0, 2, rk.ctypes.data_as(C.c_void_p), None, None, None) == E
     assert lib.rgs_views_upload(cam, 1, 7, rk.ctypes.data_as(C.c_void_p), None, None, None) == E
@@ -181,6 +186,10 @@ def test_aliased_buffers_are_rejected(lib):
                                 ws, 1 << 24, None) == E
     assert lib.rgs_loss_l1_ssim(C.c_void_p(img), C.c_void_p(tgt), 16, 16, 0.2, C.c_void_p(lv), C.c_void_p(d),
                                 C.c_void_p(tgt), 1 << 24, None) == E
+    assert lib.rgs_loss_l1_ssim_noalloc(C.c_void_p(img), C.c_void_p(tgt), 16, 16, 0.2, C.c_void_p(lv),
+                                        C.c_void_p(tgt + 512), None) == E
+    assert lib.rgs_loss_l1_ssim_noalloc(C.c_void_p(img), C.c_void_p(tgt), 16, 16, 0.2, C.c_void_p(img + 4),
+                                        C.c_void_p(d), None) == E
     # projection: the record array overlapping the SH coefficients
     g = _fake_gaussians(L, 1000, 0x10000000)
     kd = L.KdTree()
