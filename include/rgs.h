@@ -330,10 +330,14 @@ rgs_status rgs_bin_sort_async(const rgs_projected *proj, int64_t n, const rgs_ca
 /* For every slot (tile t, cell k) and pixel p of t, front to back over the
  * slot's instances: the instance contributes iff d^2 <= tau and its crossing
  * point x = campos + z D(p) lies in cell k's box; sigma = min(0.99,
- * alpha exp(-d^2/2)); C_k += T_k sigma c; T_k *= 1 - sigma; a pixel stops
- * after the contribution that takes T_k below max(eps_T, RGS_T_FLOOR)
- * (eps_T = 0: at the floor only; what lies behind it weighs less than 2^-100).
- * eps_T must lie in [0, 1). */
+ * alpha exp(-d^2/2)); C_k += T_k sigma c; T_k *= 1 - sigma.  The slots of a
+ * tile are walked in the view's merge order, so P_k T_k (P_k = product of
+ * the T_m of the tile's earlier slots at p) is the merged render's
+ * transmittance: a pixel stops after the contribution that takes P_k T_k
+ * below max(eps_T, RGS_T_FLOOR), and every later slot of its tile keeps
+ * C = 0, T = 1, last = 0 at that pixel.  With the exact cell sets this is
+ * the plain render's early termination (eps_T = 0: at the floor only; what
+ * lies behind it weighs less than 2^-100).  eps_T must lie in [0, 1). */
 /* stats, if not NULL, must point to two device uint64 counters that are
  * incremented by the number of (pixel, instance) pairs the method must test
  * (pixel inside the Gaussian's rectangle and not yet stopped) and of pairs

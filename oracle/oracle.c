@@ -815,27 +815,38 @@ static int64_t collect(const Scene *s, int px, int py, Contrib **out) {
 #define ORC_T_FLOOR 0x1p-100
 
 /* Forward of one pixel.  Partial (C_k, T_k) of Eq. 3/4 over the
- * contributors whose crossing point lies in cell k, in depth order, with
- * include-then-stop early termination per cell at max(eps_T, ORC_T_FLOOR);
- * merged colour by Eq. 5 over the view's cell order, plus background;
- * plain colour by Eq. 2 over all contributors (same stop rule on its own
- * transmittance).  `used` marks which contributors each cell processed. */
+ * contributors whose crossing point lies in cell k, in depth order; the
+ * cells are walked in the view's merge order (Eq. 5), so the product of
+ * the finished cells' T_m times the current T_k is the transmittance of the
+ * merged render.  Early termination is include-then-stop on that merged
+ * transmittance at max(eps_T, ORC_T_FLOOR): the contributor that takes it
+ * below the threshold is included, every later contributor of the pixel (in
+ * this cell and in every cell after it) is not, and a cell reached after the
+ * stop keeps C_k = 0, T_k = 1.  With the exact cell sets a ray meets the
+ * cells in merge order, so this is the plain render's stop rule and merged =
+ * plain holds with early termination too.  Merged colour by Eq. 5 plus
+ * background; plain colour by Eq. 2 over all contributors (same stop rule on
+ * its own transmittance).  `used` marks the contributors that were blended. */
 static void pixel_forward(const Scene *s, const Contrib *v, int64_t m, const int32_t *order,
                           double eps_T, double *Ck, double *Tk, char *used, double out[3],
                           double *Tout, double plain[3], double *Tplain) {
     int K = 1 << s->L;
-    int stop[ORC_MAXK];
     if (eps_T < ORC_T_FLOOR) eps_T = ORC_T_FLOOR;
-    for (int k = 0; k < K; k++) { Ck[3 * k] = Ck[3 * k + 1] = Ck[3 * k + 2] = 0; Tk[k] = 1; stop[k] = 0; }
-    for (int64_t j = 0; j < m; j++) {
-        int k = v[j].cell;
-        used[j] = 0;
-        if (stop[k]) continue;
-        used[j] = 1;
-        const double *rgb = s->val + 12 * v[j].gid + 7;
-        for (int ch = 0; ch < 3; ch++) Ck[3 * k + ch] += rgb[ch] * v[j].sigma * Tk[k];
-        Tk[k] *= (1 - v[j].sigma);
-        if (Tk[k] < eps_T) stop[k] = 1;
+    for (int k = 0; k < K; k++) { Ck[3 * k] = Ck[3 * k + 1] = Ck[3 * k + 2] = 0; Tk[k] = 1; }
+    for (int64_t j = 0; j < m; j++) used[j] = 0;
+    double Tm = 1;   /* merged transmittance so far */
+    int stopped = 0;
+    for (int r = 0; r < K && !stopped; r++) {
+        int k = order[r];
+        for (int64_t j = 0; j < m; j++) {
+            if (v[j].cell != k) continue;
+            used[j] = 1;
+            const double *rgb = s->val + 12 * v[j].gid + 7;
+            for (int ch = 0; ch < 3; ch++) Ck[3 * k + ch] += rgb[ch] * v[j].sigma * Tk[k];
+            Tk[k] *= (1 - v[j].sigma);
+            Tm *= (1 - v[j].sigma);
+            if (Tm < eps_T) { stopped = 1; break; }
+        }
     }
     double C[3] = {0, 0, 0}, T = 1;
     for (int r = 0; r < K; r++) {

@@ -33,7 +33,7 @@ rgs_status group_by_cell(const rgs_gaussians* in, const rgs_kdtree* kd, int L, c
 rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt_dev, int L, int64_t total_tiles,
                     rgs_bins* bins, int64_t* n_required, bool sync, void* ws, size_t ws_bytes, hipStream_t s);
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
-                             float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s);
+                             float eps_T, const rgs_partials* out, uint64_t* stats, int64_t total_tiles, hipStream_t s);
 size_t render_bwd_ws_bytes(int64_t capacity);
 rgs_status render_bwd_records_launch(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
                                      const rgs_projected* proj, const ViewTable* vt, const rgs_kdtree* kd, void* ws,
@@ -477,7 +477,7 @@ rgs_status rgs_render_partial(const rgs_projected* proj, int64_t n, const rgs_bi
                              {{views_dev, sizeof(ViewTable)}, {kd->box_lo, (size_t)12 * K}, {kd->box_hi, (size_t)12 * K}});
     if (!disjoint(concat(parts_spans(out, bins), {{stats, 16}}), ins)) return RGS_E_ARG;
     return render_fwd_launch(proj, bins, reinterpret_cast<const ViewTable*>(views_dev), kd, eps_T, out, stats,
-                             slot_bound_of(bins, cams, n_views, kd->L), S(stream));
+                             rgs_total_tiles(cams, n_views), S(stream));
 }
 
 rgs_status rgs_merge_partials(const rgs_partials* parts, const rgs_bins* bins, const rgs_camera* cams, int32_t n_views,

@@ -115,17 +115,24 @@ __device__ __forceinline__ uint32_t quad_mask_ellipse(uint2 rr, int tx, int ty, 
     return m;
 }
 
-// Forward: one 256-thread block per slot; wave w owns the 8x8 quadrant
-// (w & 1, w >> 1) of the tile, one pixel per lane.  Records are staged 256 at
-// a time in LDS, each with the quadrant mask of its rectangle so that a wave
+// Forward: one 256-thread block per tile, walking the tile's slots (one per
+// cell that has instances there) in the view's merge order; wave w owns the
+// 8x8 quadrant (w & 1, w >> 1) of the tile, one pixel per lane.  Each pixel
+// carries P, the product of the T_k of the slots already done: the merged
+// transmittance in front of the current cell.  Within a slot, T_k starts at
+// 1 and P T_k is the merged transmittance, so a pixel stops (in this cell
+// and all later ones) after the contribution that takes P T_k below eps_T:
+// the plain render's early termination, which a pixel reaches in the cell
+// where it happens, so cells behind an opaque front are not rendered there
+// (their partial stays C = 0, T = 1, last = 0).  Records are staged 256 at a
+// time in LDS, each with the quadrant mask of its rectangle so that a wave
 // skips Gaussians that cannot touch its quadrant with a scalar branch.
 template <bool STATS>
 __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ rec,
                                                     const uint64_t* __restrict__ vals,
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
-                                                    const uint32_t* __restrict__ slot_order,
-                                                    const uint32_t* __restrict__ counters,
+                                                    const uint32_t* __restrict__ tile_slot,
                                                     const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
                                                     const float* __restrict__ box_hi, float eps_T,
                                                     float* __restrict__ outC, float* __restrict__ outT,
@@ -136,101 +143,120 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
     __shared__ uint32_t sM[NB];
     __shared__ uint2 sR[NB];
     __shared__ uint32_t s_alive[4];
-    if (blockIdx.x >= counters[2]) return;
-    const uint32_t slot = slot_order[blockIdx.x];
+    const uint32_t gt = blockIdx.x;
+    const uint32_t s0 = tile_slot[gt], s1 = tile_slot[gt + 1];
+    if (s0 >= s1) return;
     const int L = vt->L, K = 1 << L;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t key = slot_key[slot];
-    const uint32_t gt = key >> L;
     const int v = view_of_tile(vt, gt);
     const ViewParams& V = vt->v[v];
     const uint32_t lt = gt - V.tile_offset;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
-    const int cell = V.cell_of_rank[key & ((1u << L) - 1u)];
-    const uint32_t begin = slot_range[2 * slot], end = slot_range[2 * slot + 1];
-    const float blo0 = box_lo[cell], blo1 = box_lo[K + cell], blo2 = box_lo[2 * K + cell];
-    const float bhi0 = box_hi[cell], bhi1 = box_hi[K + cell], bhi2 = box_hi[2 * K + cell];
     const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
     const int px = tx * 16 + lx, py = ty * 16 + ly;
     const float fxp = (float)px + 0.5f;
-    float fyp = (float)py + 0.5f;
-    const float dxp = (fxp - V.cx) / V.fx, dyp = (fyp - V.cy) / V.fy;
+    const float dxp = (fxp - V.cx) / V.fx, dyp = ((float)py + 0.5f - V.cy) / V.fy;
     const float D0 = (V.R[0] * dxp + V.R[3] * dyp) + V.R[6];
     const float D1 = (V.R[1] * dxp + V.R[4] * dyp) + V.R[7];
     const float D2 = (V.R[2] * dxp + V.R[5] * dyp) + V.R[8];
     const float o0 = V.o[0], o1 = V.o[1], o2 = V.o[2];
     // a stopped (or off-image) pixel samples row +inf: d^2 = inf fails every test
-    if (!(px < V.W && py < V.H)) fyp = INFINITY;
-    float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    uint32_t last = 0u, n_eval = 0u, n_con = 0u;
+    bool live = px < V.W && py < V.H;
+    float P = 1.0f;
+    uint32_t n_eval = 0u, n_con = 0u;
     const uint32_t qbit = 1u << (w + 1);
+    const int p = ly * 16 + lx;
 
-    for (uint32_t base = begin; base < end; base += NB) {
-        const uint64_t alive = __ballot(fyp != INFINITY);
-        if (lane == 0) s_alive[w] = alive != 0ull ? 1u : 0u;
-        const uint32_t idx = base + tid;
-        if (idx < end) {
-            const uint32_t src = (uint32_t)(vals[idx] >> 32);
-            const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
-            const float4 a = rp[0];
-            const float4 b = rp[1], cl = rp[2], r4 = rp[3];
-            const uint2 rr = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
-            const float cb = a.w * a.z, cc = b.x + a.w * cb;  // conic from (ca, k, e)
-            sM[tid] = (quad_mask_ellipse(rr, tx, ty, a.x, a.y, a.z, cb, cc, b.z) << 1) | (__float_as_uint(cl.w) & 1u);
-            sA[tid] = a;
-            sB[tid] = b;
-            sCl[tid] = cl;
-            if (STATS) sR[tid] = rr;
-        }
-        __syncthreads();
-        if ((s_alive[0] | s_alive[1] | s_alive[2] | s_alive[3]) == 0u) break;
-        const int nb = (int)((end - base) < (uint32_t)NB ? (end - base) : (uint32_t)NB);
-        if (alive != 0ull) {
-            // Gaussians of this batch whose footprint can reach the wave's
-            // quadrant, walked in order (other waves hide the LDS latency)
+    for (uint32_t slot = s0; slot < s1; ++slot) {
+        const uint32_t key = slot_key[slot];
+        const int cell = V.cell_of_rank[key & ((1u << L) - 1u)];
+        const uint32_t begin = slot_range[2 * slot], end = slot_range[2 * slot + 1];
+        const float blo0 = box_lo[cell], blo1 = box_lo[K + cell], blo2 = box_lo[2 * K + cell];
+        const float bhi0 = box_hi[cell], bhi1 = box_hi[K + cell], bhi2 = box_hi[2 * K + cell];
+        // stop once P T < eps_T, i.e. T < eps_T / P (>= eps_T: T stays normal)
+        const float thr = live ? eps_T / P : 0.0f;
+        float fyp = live ? (float)py + 0.5f : INFINITY;
+        float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+        uint32_t last = 0u;
+        for (uint32_t base = begin; base < end; base += NB) {
+            const uint64_t alive = __ballot(fyp != INFINITY);
+            if (lane == 0) s_alive[w] = alive != 0ull ? 1u : 0u;
+            const uint32_t idx = base + tid;
+            if (idx < end) {
+                const uint32_t src = (uint32_t)(vals[idx] >> 32);
+                const float4* rp = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS);
+                const float4 a = rp[0];
+                const float4 b = rp[1], cl = rp[2], r4 = rp[3];
+                const uint2 rr = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
+                const float cb = a.w * a.z, cc = b.x + a.w * cb;  // conic from (ca, k, e)
+                sM[tid] = (quad_mask_ellipse(rr, tx, ty, a.x, a.y, a.z, cb, cc, b.z) << 1) |
+                          (__float_as_uint(cl.w) & 1u);
+                sA[tid] = a;
+                sB[tid] = b;
+                sCl[tid] = cl;
+                if (STATS) sR[tid] = rr;
+            }
+            __syncthreads();
+            if ((s_alive[0] | s_alive[1] | s_alive[2] | s_alive[3]) == 0u) break;
+            const int nb = (int)((end - base) < (uint32_t)NB ? (end - base) : (uint32_t)NB);
+            if (alive != 0ull) {
+                // Gaussians of this batch whose footprint can reach the wave's
+                // quadrant, walked in order (other waves hide the LDS latency);
+                // the wave leaves the batch once all its pixels have stopped
 #pragma unroll
-            for (int k = 0; k < NB / 64; ++k) {
-                const int tl = k * 64 + lane;
-                const uint32_t mk = tl < nb ? sM[tl] : 0u;
-                uint64_t rel = __ballot((mk & qbit) != 0u);
-                const uint64_t inside = __ballot((mk & 1u) != 0u);  // footprint in one cell: no indicator test
-                while (rel) {
-                    const int bit = (int)__builtin_ctzll(rel);
-                    const int tc = k * 64 + bit;
-                    rel &= rel - 1ull;
-                    const float4 ac = sA[tc], bc = sB[tc];
-                    const float dx = fxp - ac.x, dy = fyp - ac.y;
-                    const float u = fmaf(ac.w, dy, dx);  // d^2 = ca u^2 + e dy^2
-                    const float d2 = fmaf(bc.x * dy, dy, (ac.z * u) * u);
-                    if (STATS && fyp != INFINITY) {
-                        // pairs the method must test: pixel inside the Gaussian's rectangle
-                        const uint2 rr = sR[tc];
-                        const bool inr = px >= (int)(int16_t)(rr.x & 0xffffu) && px <= (int)(int16_t)(rr.x >> 16) &&
-                                         py >= (int)(int16_t)(rr.y & 0xffffu) && py <= (int)(int16_t)(rr.y >> 16);
-                        n_eval += inr ? 1u : 0u;
+                for (int k = 0; k < NB / 64; ++k) {
+                    if (k > 0 && __ballot(fyp != INFINITY) == 0ull) break;
+                    const int tl = k * 64 + lane;
+                    const uint32_t mk = tl < nb ? sM[tl] : 0u;
+                    uint64_t rel = __ballot((mk & qbit) != 0u);
+                    const uint64_t inside = __ballot((mk & 1u) != 0u);  // footprint in one cell: no indicator test
+                    while (rel) {
+                        const int bit = (int)__builtin_ctzll(rel);
+                        const int tc = k * 64 + bit;
+                        rel &= rel - 1ull;
+                        const float4 ac = sA[tc], bc = sB[tc];
+                        const float dx = fxp - ac.x, dy = fyp - ac.y;
+                        const float u = fmaf(ac.w, dy, dx);  // d^2 = ca u^2 + e dy^2
+                        const float d2 = fmaf(bc.x * dy, dy, (ac.z * u) * u);
+                        if (STATS && fyp != INFINITY) {
+                            // pairs the method must test: pixel inside the Gaussian's rectangle
+                            const uint2 rr = sR[tc];
+                            const bool inr = px >= (int)(int16_t)(rr.x & 0xffffu) && px <= (int)(int16_t)(rr.x >> 16) &&
+                                             py >= (int)(int16_t)(rr.y & 0xffffu) && py <= (int)(int16_t)(rr.y >> 16);
+                            n_eval += inr ? 1u : 0u;
+                        }
+                        if (!(d2 <= bc.z)) continue;
+                        const float4 cl = sCl[tc];
+                        if (!((inside >> bit) & 1ull)) {
+                            const float x0 = fmaf(bc.w, D0, o0), x1 = fmaf(bc.w, D1, o1), x2 = fmaf(bc.w, D2, o2);
+                            const bool in = (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
+                                            (x2 < bhi2);
+                            if (!in) continue;
+                        }
+                        if (STATS) ++n_con;
+                        const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
+                        const float sg = fminf(0.99f, bc.y * G);
+                        const float wgt = sg * T;
+                        C0 = fmaf(wgt, cl.x, C0);
+                        C1 = fmaf(wgt, cl.y, C1);
+                        C2 = fmaf(wgt, cl.z, C2);
+                        T = T * (1.0f - sg);
+                        last = base - begin + (uint32_t)tc + 1u;
+                        if (T < thr) fyp = INFINITY;
                     }
-                    if (!(d2 <= bc.z)) continue;
-                    const float4 cl = sCl[tc];
-                    if (!((inside >> bit) & 1ull)) {
-                        const float x0 = fmaf(bc.w, D0, o0), x1 = fmaf(bc.w, D1, o1), x2 = fmaf(bc.w, D2, o2);
-                        const bool in = (blo0 <= x0) && (x0 < bhi0) && (blo1 <= x1) && (x1 < bhi1) && (blo2 <= x2) &&
-                                        (x2 < bhi2);
-                        if (!in) continue;
-                    }
-                    if (STATS) ++n_con;
-                    const float G = __builtin_amdgcn_exp2f(d2 * -0.72134752044448170368f);  // exp(-d^2/2)
-                    const float sg = fminf(0.99f, bc.y * G);
-                    const float wgt = sg * T;
-                    C0 = fmaf(wgt, cl.x, C0);
-                    C1 = fmaf(wgt, cl.y, C1);
-                    C2 = fmaf(wgt, cl.z, C2);
-                    T = T * (1.0f - sg);
-                    last = base - begin + (uint32_t)tc + 1u;
-                    if (T < eps_T) fyp = INFINITY;
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
+        float* oc = outC + (size_t)slot * 768;
+        oc[p] = C0;
+        oc[256 + p] = C1;
+        oc[512 + p] = C2;
+        outT[(size_t)slot * 256 + p] = T;
+        outLast[(size_t)slot * 256 + p] = last;
+        // the walk stopped in this cell: every later cell is neutral here
+        if (live && T < thr) live = false;
+        P *= T;
     }
     if (STATS) {
         unsigned long long e = n_eval, c = n_con;
@@ -244,31 +270,24 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
             atomicAdd(&stats[1], c);
         }
     }
-    const int p = ly * 16 + lx;
-    float* oc = outC + (size_t)slot * 768;
-    oc[p] = C0;
-    oc[256 + p] = C1;
-    oc[512 + p] = C2;
-    outT[(size_t)slot * 256 + p] = T;
-    outLast[(size_t)slot * 256 + p] = last;
 }
 
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
-                             float eps_T, const rgs_partials* out, uint64_t* stats, int64_t slot_bound, hipStream_t s) {
-    if (slot_bound <= 0) return RGS_OK;
-    // a pixel stops once T_k < max(eps_T, 2^-100): the backward recovers the
-    // transmittance before each contribution from the stored T_k by division,
-    // which needs T_k to stay a normal fp32 number (after the last factor
-    // 1 - sigma >= 0.01 it is still >= 2^-107)
+                             float eps_T, const rgs_partials* out, uint64_t* stats, int64_t total_tiles, hipStream_t s) {
+    if (total_tiles <= 0) return RGS_OK;
+    // a pixel stops once its merged transmittance falls below max(eps_T,
+    // 2^-100): the backward recovers the transmittance before each
+    // contribution from the stored T_k by division, which needs T_k to stay
+    // a normal fp32 number (T_k >= 0.01 eps_T / P >= 2^-107)
     eps_T = fmaxf(eps_T, RGS_T_FLOOR);
     if (stats)
-        hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec,
-                           bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
-                           kd->box_hi, eps_T, out->C, out->T, out->last, reinterpret_cast<unsigned long long*>(stats));
+        hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)total_tiles), dim3(256), 0, s, proj->rec, bins->vals,
+                           bins->slot_key, bins->slot_range, bins->tile_slot, vt, kd->box_lo, kd->box_hi, eps_T, out->C,
+                           out->T, out->last, reinterpret_cast<unsigned long long*>(stats));
     else
-        hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)slot_bound), dim3(256), 0, s, proj->rec,
-                           bins->vals, bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo,
-                           kd->box_hi, eps_T, out->C, out->T, out->last, nullptr);
+        hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)total_tiles), dim3(256), 0, s, proj->rec, bins->vals,
+                           bins->slot_key, bins->slot_range, bins->tile_slot, vt, kd->box_lo, kd->box_hi, eps_T, out->C,
+                           out->T, out->last, nullptr);
     return launch_check();
 }
 

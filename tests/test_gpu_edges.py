@@ -301,8 +301,9 @@ def test_full_size_sampled_pixels(full):
 
 
 def test_full_size_sampled_gradients(full, rast):
-    """Gradients of sum(w * image) for 24 Gaussians with small footprints; the
-    oracle covers every pixel of their rectangles."""
+    """Gradients of sum(w * image) for 24 Gaussians with small footprints (the
+    2D quantities and the parameters); the oracle covers every pixel of their
+    rectangles."""
     p, cam, L, dp, kd, st, okd, order, pr = full
     W, H = cam["W"], cam["H"]
     rng = np.random.default_rng(77)
@@ -327,6 +328,14 @@ def test_full_size_sampled_gradients(full, rast):
     ok, info = grad_close(got, ref, 1e-3, "d_proj (24 Gaussians)")
     log(str(info))
     assert ok, info
+    # their parameter gradients: the projection backward is per Gaussian, so
+    # the oracle runs it on the chosen Gaussians alone
+    sub = {k: (p[k][..., chosen] if k != "sh_degree" else p[k]) for k in p}
+    og = oracle.project_bwd(sub, cam, dict(vis=pr["vis"][chosen]), ref)
+    for k in raster.PARAM_KEYS:
+        ok, info = grad_close(g[k].cpu().numpy()[..., chosen], og[k], 1e-3, "%s (24 Gaussians)" % k)
+        log(str(info))
+        assert ok, info
 
 
 def test_full_resolution_loss(rast):

@@ -946,8 +946,9 @@ def test_validity_camera_on_split_plane(orc):
 
 
 def test_early_termination_include_then_stop(orc):
-    """With eps_T, each cell includes the contributor that drops T_k below eps_T and
-    stops there; the tail changes the image by at most eps_T per cell."""
+    """With eps_T, the walk includes the contributor that drops the merged
+    transmittance below eps_T and stops there; the tail changes the image by
+    at most eps_T."""
     p = _tiny_scene(300, seed=41, mu_s=-2.0, extent=0.3)
     p["opacity"][:] = 4.0
     kd = orc.kd_partition(p["means"], p["log_scales"], 2)
@@ -960,7 +961,89 @@ def test_early_termination_include_then_stop(orc):
     assert np.any(a["partT"] < 1e-2)
     stopped = b["partT"] < 1e-2
     assert np.all(b["partT"][stopped] >= a["partT"][stopped])
-    assert np.abs(a["img"] - b["img"]).max() <= 4 * 1e-2 * 1.0 + 1e-12
+    # the skipped tail weighs at most eps_T times the brightest colour (bg = 0)
+    cmax = float(pr["val"][pr["vis"] == 1][:, 7:10].max())
+    assert np.abs(a["img"] - b["img"]).max() <= 1e-2 * cmax + 1e-12
+
+
+@pytest.mark.parametrize("L,eps_T", [(1, 1e-2), (2, 5e-5), (3, 1e-3)])
+def test_merged_equals_plain_with_early_termination(orc, L, eps_T):
+    """The partial renders split the plain render's front-to-back walk among
+    the cells (Sec. 3.2, Eq. 5): with early termination on the merged
+    transmittance, the merged image and final transmittance equal the plain
+    render under the same stop rule (both decision modes), also on pixels
+    where the walk stopped inside a front cell.  A stop per cell (on T_k)
+    would let every later cell blend on and fail this."""
+    p = _tiny_scene(400, seed=60 + L, mu_s=-2.2, extent=0.5)
+    p["opacity"][:] = 3.0
+    kd = orc.kd_partition(p["means"], p["log_scales"], L)
+    cam = scenes.orbit_camera(1.9, 0.7, 0.3, 48, 40)
+    order, _ = orc.cell_order(L, kd["split"], cam["o"])
+    pix = orc.all_pixels(48, 40)
+    for mode in (0, 1):
+        pr = orc.project(p, cam, kd, mode)
+        r = orc.render(pr, cam, kd, order, pix, eps_T)
+        stopped = r["plainT"] < eps_T
+        assert stopped.sum() > 50
+        # pixels whose walk stopped before reaching a later cell that it crosses
+        P = np.ones(len(pix))
+        behind = np.zeros(len(pix), bool)
+        for k in order:
+            behind |= (P < eps_T) & (r["partT"][:, k] == 1.0)
+            P = P * r["partT"][:, k]
+        assert behind.sum() > 10
+        assert np.abs(r["img"] - r["plain"]).max() < 1e-12
+        assert np.abs(r["T"] - r["plainT"]).max() < 1e-12
+
+
+def test_early_termination_leaves_back_cells_neutral(orc):
+    """One ray through two cells: ten nearly opaque Gaussians (alpha 0.98) in
+    the front cell, one Gaussian in the back cell.  At eps_T = 1e-3 the walk
+    stops in the front cell after the first contributor j* whose product
+    prod_{i <= j*} (1 - sigma_i) falls below 1e-3: the front partial is the
+    closed form of Eq. 3/4 over those j* contributions and the back cell's
+    partial stays exactly (0, 1).  At eps_T = 0 the walk reaches the back
+    Gaussian (ten layers at sigma < 0.9 stay far above the 2^-100 floor)."""
+    n = 11
+    p = scenes.scene_uniform(n, seed=5, D=0, mu_s=-1.0, extent=0.1)
+    z = np.concatenate([2.0 + 0.01 * np.arange(10), [3.0]])
+    p["means"] = np.stack([z, np.zeros(n), np.zeros(n)]).astype(np.float32)
+    p["log_scales"] = np.full((3, n), np.log(0.2), np.float32)
+    p["opacity"] = np.full(n, np.log(0.98 / 0.02), np.float32)
+    rgb = np.array([[0.9, 0.1, 0.1]] * 10 + [[0.1, 0.9, 0.1]])
+    p["sh"] = ((rgb - 0.5) / (0.5 / math.sqrt(math.pi))).T.astype(np.float32)
+    # camera at the origin looking along +x: the crossing point's x is the
+    # Gaussian's depth, so the root split (on x) at 2.5 puts the groups in
+    # two cells, the front one first in the merge order
+    R = scenes.look_at(np.zeros(3), np.array([1.0, 0.0, 0.0]))
+    cam = scenes.make_camera(R, np.zeros(3), 16, 16, z_near=0.1)
+    kd = dict(L=1, K=2, split=np.array([2.5], np.float32))
+    pr = orc.project(p, cam, kd, 1)
+    order = np.array([0, 1], np.int32)
+    pix = np.array([[8, 8]], np.int32)   # sample (8.5, 8.5)
+
+    def sigma(i):
+        v = pr["val"][i]
+        dx, dy = 8.5 - v[0], 8.5 - v[1]
+        d2 = v[2] * dx * dx + 2 * v[3] * dx * dy + v[4] * dy * dy
+        assert d2 <= v[10]
+        return min(0.99, v[5] * math.exp(-0.5 * d2))
+
+    C, T, j = 0.0, 1.0, 0
+    while True:
+        sg = sigma(j)
+        C += float(pr["val"][j, 7]) * sg * T
+        T *= 1 - sg
+        j += 1
+        if T < 1e-3:
+            break
+    assert 2 <= j < 10
+    r = orc.render(pr, cam, kd, order, pix, 1e-3)
+    assert abs(r["partC"][0, 0, 0] - C) < 1e-12 and abs(r["partT"][0, 0] - T) < 1e-12
+    assert r["partC"][0, 1].tolist() == [0.0, 0.0, 0.0] and r["partT"][0, 1] == 1.0
+    r0 = orc.render(pr, cam, kd, order, pix, 0.0)
+    assert r0["partT"][0, 1] < 1.0 and r0["partC"][0, 1, 1] > 0.05
+    assert abs(r0["partT"][0, 1] - (1 - sigma(10))) < 1e-12
 
 
 # ------------------------------------------------------------------ finite differences (backward)
