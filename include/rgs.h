@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 4
+#define RGS_ABI_VERSION 5
 #define RGS_TILE 16       /* screen tiles are 16 x 16 pixels */
 #define RGS_MAX_L 6       /* K = 2^L <= 64 cells */
 #define RGS_MAX_VIEWS 16  /* views per call */
@@ -172,7 +172,9 @@ typedef struct {
     uint32_t *slot_key;     /* [slot_capacity] key of each slot */
     uint32_t *slot_range;   /* [slot_capacity][2] begin, end into keys/vals */
     uint32_t *tile_slot;    /* [total_tiles+1] first slot of each global tile (slots of a tile are in view order) */
-    uint32_t *slot_order;   /* [slot_capacity] slots by decreasing size class (the render launch order) */
+    uint32_t *slot_order;   /* [slot_capacity] slots by decreasing size class (the backward's launch order) */
+    uint32_t *tile_order;   /* [total_tiles] tiles by decreasing size class of their instance count (the forward's
+                               launch order) */
     uint32_t *counters;     /* [4]: pairs, instances, slots, required instances if over capacity (async; else 0);
                                all four written by every bin_sort call */
     int64_t n_instances;    /* [out, host] */

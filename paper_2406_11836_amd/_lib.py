@@ -50,7 +50,7 @@ class Projected(C.Structure):
 class Bins(C.Structure):
     _fields_ = [("capacity", i64), ("slot_capacity", i64), ("keys", vp), ("vals", vp), ("pair_src", vp),
                 ("pair_off", vp), ("pair_rank", vp), ("slot_key", vp), ("slot_range", vp), ("tile_slot", vp),
-                ("slot_order", vp), ("counters", vp), ("n_instances", i64)]
+                ("slot_order", vp), ("tile_order", vp), ("counters", vp), ("n_instances", i64)]
 
 
 class AdamParams(C.Structure):

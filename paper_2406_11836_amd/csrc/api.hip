@@ -127,7 +127,7 @@ static Spans bins_spans(const rgs_bins* b, size_t m, size_t total_tiles) {
     const size_t c = (size_t)(b->capacity > 0 ? b->capacity : 0), sc = (size_t)(b->slot_capacity > 0 ? b->slot_capacity : 0);
     return {{b->keys, 4 * c}, {b->vals, 8 * c}, {b->pair_src, 4 * m}, {b->pair_off, 4 * (m + 1)}, {b->pair_rank, 4 * m},
             {b->slot_key, 4 * sc}, {b->slot_range, 8 * sc}, {b->tile_slot, 4 * (total_tiles + 1)},
-            {b->slot_order, 4 * sc}, {b->counters, 16}};
+            {b->slot_order, 4 * sc}, {b->tile_order, 4 * total_tiles}, {b->counters, 16}};
 }
 
 static Spans parts_spans(const rgs_partials* p, const rgs_bins* b) {
@@ -416,7 +416,7 @@ size_t rgs_bin_sort_workspace(int64_t n, int32_t n_views, int64_t total_tiles, i
 
 static bool bins_ok(const rgs_bins* b) {
     return b && b->keys && b->vals && b->pair_src && b->pair_off && b->pair_rank && b->slot_key && b->slot_range &&
-           b->tile_slot && b->slot_order && b->counters && b->capacity >= 0 && b->slot_capacity >= 0;
+           b->tile_slot && b->slot_order && b->tile_order && b->counters && b->capacity >= 0 && b->slot_capacity >= 0;
 }
 
 rgs_status rgs_bin_sort(const rgs_projected* proj, int64_t n, const rgs_camera* cams, int32_t n_views,

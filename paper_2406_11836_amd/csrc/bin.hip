@@ -333,7 +333,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __re
 __global__ __launch_bounds__(BN_THREADS) void k_slot_flags(const uint32_t* __restrict__ dstart, int64_t m,
                                                            uint32_t* __restrict__ flag, uint32_t* __restrict__ cls) {
     int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x < 64) cls[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < 128) cls[threadIdx.x] = 0u;
     if (i < m) flag[i] = dstart[i] != 0xffffffffu ? 1u : 0u;
 }
 
@@ -413,6 +413,56 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_class_place(const uint32_t*
     if (ok) slot_order[s_base[cls] + local] = (uint32_t)s;
 }
 
+// The forward render's launch order: tiles by decreasing size class of their
+// instance count (a tile's slots hold a contiguous range of the sorted
+// instances), the same two-kernel placement as the slots.
+__device__ __forceinline__ uint32_t tile_len(const uint32_t* __restrict__ tile_slot,
+                                             const uint32_t* __restrict__ slot_range, int64_t t) {
+    const uint32_t s0 = tile_slot[t], s1 = tile_slot[t + 1];
+    return s0 < s1 ? slot_range[2 * (s1 - 1) + 1] - slot_range[2 * s0] : 0u;
+}
+
+__global__ __launch_bounds__(BN_THREADS) void k_tile_class_count(const uint32_t* __restrict__ tile_slot,
+                                                                 const uint32_t* __restrict__ slot_range, int64_t T,
+                                                                 uint32_t* __restrict__ cls_cnt) {
+    __shared__ uint32_t s_c[32];
+    if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (t < T) atomicAdd(&s_c[31 - __clz(tile_len(tile_slot, slot_range, t) | 1u)], 1u);
+    __syncthreads();
+    if (threadIdx.x < 32 && s_c[threadIdx.x]) atomicAdd(&cls_cnt[threadIdx.x], s_c[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(BN_THREADS) void k_tile_class_place(const uint32_t* __restrict__ tile_slot,
+                                                                 const uint32_t* __restrict__ slot_range, int64_t T,
+                                                                 const uint32_t* __restrict__ cls_cnt,
+                                                                 uint32_t* __restrict__ cls_resv,
+                                                                 uint32_t* __restrict__ tile_order) {
+    __shared__ uint32_t s_c[32], s_base[32];
+    if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int c = 31; c >= 0; --c) {
+            s_base[c] = run;
+            run += cls_cnt[c];
+        }
+    }
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    const bool ok = t < T;
+    int cls = 0;
+    uint32_t local = 0;
+    if (ok) {
+        cls = 31 - __clz(tile_len(tile_slot, slot_range, t) | 1u);
+        local = atomicAdd(&s_c[cls], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && s_c[threadIdx.x]) s_base[threadIdx.x] += atomicAdd(&cls_resv[threadIdx.x], s_c[threadIdx.x]);
+    __syncthreads();
+    if (ok) tile_order[s_base[cls] + local] = (uint32_t)t;
+}
+
 size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t capacity) {
     const int64_t m = (int64_t)n_views * n;
     const int64_t dense = total_tiles << L;
@@ -428,7 +478,7 @@ size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t 
     c.take<uint32_t>(dense + 1);      // dense end
     c.take<uint32_t>(dense + 1);      // dense flags
     c.take<uint32_t>(dense + 1);      // slot index
-    c.take<uint32_t>(64);             // slot size classes
+    c.take<uint32_t>(128);            // slot and tile size classes
     const int64_t big = m > capacity ? m : capacity;
     const int64_t big2 = big > dense ? big : dense;
     c.take<char>(radix_ws_bytes(big2 + 1));
@@ -459,7 +509,7 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     uint32_t* dend = c.take<uint32_t>(dense + 1);
     uint32_t* dflag = c.take<uint32_t>(dense + 1);
     uint32_t* sidx = c.take<uint32_t>(dense + 1);
-    uint32_t* cls = c.take<uint32_t>(64);
+    uint32_t* cls = c.take<uint32_t>(128);
     const int64_t big = m > bins->capacity ? m : bins->capacity;
     const int64_t big2 = big > dense ? big : dense;
     void* rws = c.take<char>(radix_ws_bytes(big2 + 1));
@@ -541,6 +591,12 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     hipLaunchKernelGGL(k_slot_class_count, grid(slot_bound), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], cls);
     hipLaunchKernelGGL(k_slot_class_place, grid(slot_bound), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], cls,
                        cls + 32, bins->slot_order);
+    if (total_tiles > 0) {
+        hipLaunchKernelGGL(k_tile_class_count, grid(total_tiles), dim3(BN_THREADS), 0, s, bins->tile_slot,
+                           bins->slot_range, total_tiles, cls + 64);
+        hipLaunchKernelGGL(k_tile_class_place, grid(total_tiles), dim3(BN_THREADS), 0, s, bins->tile_slot,
+                           bins->slot_range, total_tiles, cls + 64, cls + 96, bins->tile_order);
+    }
     return launch_check();
 }
 

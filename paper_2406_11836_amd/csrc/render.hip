@@ -133,6 +133,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
                                                     const uint32_t* __restrict__ tile_slot,
+                                                    const uint32_t* __restrict__ tile_order,
                                                     const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
                                                     const float* __restrict__ box_hi, float eps_T,
                                                     float* __restrict__ outC, float* __restrict__ outT,
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
     __shared__ uint32_t sM[NB];
     __shared__ uint2 sR[NB];
     __shared__ uint32_t s_alive[4];
-    const uint32_t gt = blockIdx.x;
+    const uint32_t gt = tile_order[blockIdx.x];
     const uint32_t s0 = tile_slot[gt], s1 = tile_slot[gt + 1];
     if (s0 >= s1) return;
     const int L = vt->L, K = 1 << L;
@@ -282,11 +283,13 @@ rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, co
     eps_T = fmaxf(eps_T, RGS_T_FLOOR);
     if (stats)
         hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)total_tiles), dim3(256), 0, s, proj->rec, bins->vals,
-                           bins->slot_key, bins->slot_range, bins->tile_slot, vt, kd->box_lo, kd->box_hi, eps_T, out->C,
+                           bins->slot_key, bins->slot_range, bins->tile_slot, bins->tile_order, vt, kd->box_lo, kd->box_hi,
+                           eps_T, out->C,
                            out->T, out->last, reinterpret_cast<unsigned long long*>(stats));
     else
         hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)total_tiles), dim3(256), 0, s, proj->rec, bins->vals,
-                           bins->slot_key, bins->slot_range, bins->tile_slot, vt, kd->box_lo, kd->box_hi, eps_T, out->C,
+                           bins->slot_key, bins->slot_range, bins->tile_slot, bins->tile_order, vt, kd->box_lo, kd->box_hi,
+                           eps_T, out->C,
                            out->T, out->last, nullptr);
     return launch_check();
 }

@@ -264,6 +264,7 @@ class Rasterizer:
         K = 1 << kd.L
         bins = dict(pair_src=self._buf("pair_src", m, torch.int32), pair_off=self._buf("pair_off", m + 1, torch.int32),
                     pair_rank=self._buf("pair_rank", m, torch.int32), tile_slot=self._buf("tile_slot", T + 1, torch.int32),
+                    tile_order=self._buf("tile_order", T, torch.int32),
                     counters=self._buf("counters", 4, torch.int32))
         cap = max(self.capacity_hint, 1)
         # no host wait in binning when an earlier pass sized the buffers and the
@@ -279,7 +280,7 @@ class Rasterizer:
             bs = L.Bins()
             bs.capacity, bs.slot_capacity = cap, slot_cap
             for k in ("keys", "vals", "pair_src", "pair_off", "pair_rank", "slot_key", "slot_range", "tile_slot",
-                      "slot_order", "counters"):
+                      "slot_order", "tile_order", "counters"):
                 setattr(bs, k, bins[k].data_ptr())
             ws_bytes = lib.rgs_bin_sort_workspace(n, V, T, kd.L, cap)
             ws = self._buf("bin_ws", ws_bytes, torch.uint8)

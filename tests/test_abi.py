@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_status(lib):
-    assert lib.rgs_abi_version() == 4
+    assert lib.rgs_abi_version() == 5
     assert lib.rgs_status_string(0) == b"ok"
     assert lib.rgs_status_string(-2) == b"buffer capacity too small"
 
@@ -220,7 +220,7 @@ def test_aliased_buffers_are_rejected(lib):
     bs = L.Bins()
     bs.capacity, bs.slot_capacity = 100, 10
     (bs.keys, bs.vals, bs.pair_src, bs.pair_off, bs.pair_rank, bs.slot_key, bs.slot_range, bs.tile_slot,
-     bs.slot_order, bs.counters) = (0x60000000 + 0x100000 * k for k in range(10))
+     bs.slot_order, bs.tile_order, bs.counters) = (0x60000000 + 0x100000 * k for k in range(11))
     pt = L.Partials(0x70000000, 0x71000000, 0x72000000)
     assert lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam, 1, C.c_void_p(0x6000000), C.c_void_p(0x70000000 + 4),
                                   C.c_void_p(0x73000000), None) == E
