@@ -186,11 +186,12 @@ def serving(n: int, rates, n_req: int, warmup_req: int, paths=("batched", "batch
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t0
     out = {"workload": "%d Gaussians SH3 resident (grouped by cell), Poisson requests, 40%% 1280x720 / 40%% "
-                       "1920x1080 / 20%% 3840x2160; batched: K=64 KD cells with cell culling, <= 8 views per batch; "
+                       "1920x1080 / 20%% 3840x2160; batched: K=64 KD cells with cell culling, two workers (streams) "
+                       "overlapping on the device, <= 2 views per batch; "
                        "plain: K=1, FIFO, one view at a time" % n,
            "requests_per_rate": n_req, "warmup_requests": warmup_req, "scene_prep_s": round(prep_s, 2), "rates": {}}
-    cfg = {"batched": (kd64, dict(max_batch=8, workers=1, cull=True)),
-           "batched_K1": (kd1, dict(max_batch=8, workers=1, cull=False)),
+    cfg = {"batched": (kd64, dict(max_batch=2, workers=2, cull=True)),
+           "batched_K1": (kd1, dict(max_batch=2, workers=2, cull=False)),
            "plain": (kd1, dict(max_batch=1, workers=1, cull=False))}
     for rate in rates:
         res = {}

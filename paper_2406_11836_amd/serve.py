@@ -6,13 +6,16 @@ a dispatcher replays a request trace in real time, admits arrived requests
 into the next batch whenever a worker (one HIP stream each) is free and the
 batch's memory estimate fits the budget, and renders the batch with one call
 sequence (projection for all views at once, then binning, partial render and
-merge).  Requests that arrive while a batch is on the GPU wait for the next
-free worker.  One worker is the default: a batch of views at this scale
-fills the GPU by itself, and two concurrent batches on one device were
-measured to run many times slower than one after the other (their working
-sets of tens of GB compete).  Per view, KD cells that cannot reach the image
-(rgs_cell_visibility, a conservative test in the library) are culled before
-projection.
+merge).  Two workers are the default, so that the work of a batch that is
+admitted while another is on the GPU overlaps it on the device (each worker
+has its own stream and buffers); a request that arrives while both are busy
+waits for the next free one.  Batches are kept small (two views): a batch of
+views at 100M Gaussians holds about 10 GB of per-(view, Gaussian) arrays per
+view, and small batches on two workers gave both the lowest tail latency and
+the highest frame rate on the city trace (one worker with batches of eight,
+and three or four workers, were slower).  Per view, KD cells that cannot
+reach the image (rgs_cell_visibility, a conservative test in the library)
+are culled before projection.
 
 Latency of a request = host time at which its batch completed - its
 scheduled arrival time.  The plain path for comparison is the same trace,
@@ -44,7 +47,7 @@ class Request:
 
 
 class Server:
-    def __init__(self, params, kd: raster.KD, *, max_batch: int = 8, workers: int = 1, eps_T: float = 5e-5,
+    def __init__(self, params, kd: raster.KD, *, max_batch: int = 2, workers: int = 2, eps_T: float = 5e-5,
                  cull: bool = True, mem_budget: float | None = None, keep_images: bool = False,
                  device: str = "cuda"):
         self.params = params
