@@ -1,9 +1,11 @@
 // loss.hip -- L1 + w (1 - SSIM) on one view, forward and backward.
 //
 // SSIM uses an 11x11 Gaussian window (std 1.5, normalised), zero padding and
-// C1 = 0.01^2, C2 = 0.03^2; the window is separable, so the five local
-// moments (mu_x, mu_y, E[x^2], E[y^2], E[xy]) take a horizontal and a
-// vertical 11-tap pass, both run from LDS on 32x32 tiles with a 5-pixel halo.  The backward needs d SSIM / d (mu_x, E[x^2], E[xy])
+// C1 = 0.01^2, C2 = 0.03^2; the window is separable, so the local moments
+// take a horizontal and a vertical 11-tap pass, both run from LDS on 32x16
+// tiles with a 5-pixel halo.  E[x^2] and E[y^2] enter SSIM only through
+// sigma_x^2 + sigma_y^2, so four moments are filtered: mu_x, mu_y,
+// E[x^2 + y^2] and E[xy].  The backward needs d SSIM / d (mu_x, E[x^2], E[xy])
 // per pixel, convolved again with the (symmetric) window.  Block partial sums
 // are combined by one block in a fixed order, so the scalar is reproducible.
 #include <mutex>
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
                                                                int H, int W, Win11 win, float* __restrict__ d3,
                                                                float* __restrict__ part) {
     __shared__ float sx[TH * TW], sy[TH * TW];
-    __shared__ float hm[5][TH * TS];
+    __shared__ float hm[4][TH * TS];
     __shared__ float s_w[2][4];
     const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TSY - 1) / TSY;
     const int b = blockIdx.x;
@@ -74,29 +76,27 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
     // 14-value window in registers (the taps of each output in the same order)
     for (int k = threadIdx.x; k < TH * (TS / 4); k += LS_THREADS) {
         const int r = k >> 3, c0 = (k & 7) * 4;
-        float xv[14], yv[14], xx[14], yy[14], xy[14];
+        float xv[14], yv[14], ss[14], xy[14];
 #pragma unroll
         for (int j = 0; j < 14; ++j) {
             xv[j] = sx[r * TW + c0 + j];
             yv[j] = sy[r * TW + c0 + j];
-            xx[j] = xv[j] * xv[j];  // products once per input, not once per tap
-            yy[j] = yv[j] * yv[j];
+            ss[j] = xv[j] * xv[j] + yv[j] * yv[j];  // products once per input, not once per tap
             xy[j] = xv[j] * yv[j];
         }
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
             for (int t = 0; t < 11; ++t) {
                 const float w = win.w[t];
                 a0 = fmaf(w, xv[o + t], a0);
                 a1 = fmaf(w, yv[o + t], a1);
-                a2 = fmaf(w, xx[o + t], a2);
-                a3 = fmaf(w, yy[o + t], a3);
-                a4 = fmaf(w, xy[o + t], a4);
+                a2 = fmaf(w, ss[o + t], a2);
+                a3 = fmaf(w, xy[o + t], a3);
             }
             const int q = r * TS + c0 + o;
-            hm[0][q] = a0; hm[1][q] = a1; hm[2][q] = a2; hm[3][q] = a3; hm[4][q] = a4;
+            hm[0][q] = a0; hm[1][q] = a1; hm[2][q] = a2; hm[3][q] = a3;
         }
     }
     __syncthreads();
@@ -104,9 +104,9 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
     // vertical pass: thread (column c, row group) takes RPT consecutive rows
     {
         const int c = threadIdx.x & 31, r0 = (threadIdx.x >> 5) * RPT;
-        float mom[5][RPT];
+        float mom[4][RPT];
 #pragma unroll
-        for (int mm = 0; mm < 5; ++mm) {
+        for (int mm = 0; mm < 4; ++mm) {
             float hv[VWIN];
 #pragma unroll
             for (int j = 0; j < VWIN; ++j) hv[j] = hm[mm][(r0 + j) * TS + c];
@@ -123,12 +123,13 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
             const int r = r0 + o;
             const int gy = y0 + r, gx = x0 + c;
             if (gy >= H || gx >= W) continue;
-            const float mu_x = mom[0][o], mu_y = mom[1][o], exx = mom[2][o], eyy = mom[3][o], exy = mom[4][o];
+            const float mu_x = mom[0][o], mu_y = mom[1][o], ess = mom[2][o], exy = mom[3][o];
             const float C1 = 1e-4f, C2 = 9e-4f;
             const float A1 = 2.f * mu_x * mu_y + C1;
             const float A2 = 2.f * (exy - mu_x * mu_y) + C2;
-            const float B1 = mu_x * mu_x + mu_y * mu_y + C1;
-            const float B2 = (exx - mu_x * mu_x) + (eyy - mu_y * mu_y) + C2;
+            const float m2 = mu_x * mu_x + mu_y * mu_y;
+            const float B1 = m2 + C1;
+            const float B2 = (ess - m2) + C2;
             const float Nn = A1 * A2, Dd = B1 * B2;
             const float iD = 1.f / Dd;
             ss += Nn * iD;

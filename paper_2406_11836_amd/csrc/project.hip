@@ -284,7 +284,7 @@ __device__ __forceinline__ bool screen_may_hit(float mu0, float mu1, float mu2, 
 // the leaf of the centre only, with no indicator test in the render (flag
 // bit 0 set: the render takes every pixel of the footprint for that cell).
 template <int D>
-__global__ __launch_bounds__(PJ_THREADS, 4) void k_project(rgs_gaussians g, const ViewTable* __restrict__ vt,
+__global__ __launch_bounds__(PJ_THREADS, 3) void k_project(rgs_gaussians g, const ViewTable* __restrict__ vt,
                                                         const float* __restrict__ split,
                                                         const int32_t* __restrict__ center_cell, int cells,
                                                         const uint32_t* __restrict__ own_mask, rgs_projected out) {
