@@ -42,11 +42,15 @@ __global__ __launch_bounds__(BN_THREADS) void k_vis_count(const uint32_t* __rest
 // Entry i = base + k * 256 + t is the k-th item of thread t, so index order is
 // (k, wave, lane) order: one exclusive scan over the 64 (k, wave) ballot
 // counts gives every wave's offset for every k.
+// fold = 1: tile_off holds the tile counts unscanned; the block sums those
+// before its tile (few tiles) and the last block writes the pair count.
 __global__ __launch_bounds__(BN_THREADS) void k_vis_compact(const uint32_t* __restrict__ count,
                                                             const float* __restrict__ depth, int64_t m,
-                                                            const uint32_t* __restrict__ tile_off,
+                                                            const uint32_t* __restrict__ tile_off, int fold,
+                                                            uint32_t* __restrict__ n_pairs,
                                                             uint32_t* __restrict__ zkey, uint32_t* __restrict__ src_out) {
     __shared__ uint32_t s_c[VC_ITEMS * 4];
+    __shared__ uint32_t s_r[4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * VC_TILE;
@@ -66,7 +70,18 @@ __global__ __launch_bounds__(BN_THREADS) void k_vis_compact(const uint32_t* __re
         s_c[lane] = inc - v;  // lane = k * 4 + wave: every lane read its value before any write
     }
     __syncthreads();
-    const uint32_t t0 = tile_off[blockIdx.x];
+    uint32_t t0;
+    if (fold) {
+        uint32_t a = 0;
+        for (uint32_t t = threadIdx.x; t < blockIdx.x; t += BN_THREADS) a += tile_off[t];
+        a = wave_sum_u32(a);
+        if (lane == 0) s_r[w] = a;
+        __syncthreads();
+        t0 = (s_r[0] + s_r[1]) + (s_r[2] + s_r[3]);
+        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *n_pairs = t0 + tile_off[blockIdx.x];
+    } else {
+        t0 = tile_off[blockIdx.x];
+    }
 #pragma unroll
     for (int k = 0; k < VC_ITEMS; ++k) {
         const bool f = (fl >> k) & 1u;
@@ -102,26 +117,6 @@ __global__ __launch_bounds__(BN_THREADS) void k_pair_counts(const uint32_t* __re
     // the slot table's empty marks, needed after the instance sort
     for (int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x; i < n_fill; i += (int64_t)gridDim.x * BN_THREADS)
         fill[i] = 0xffffffffu;
-}
-
-// pair_off[pairs] = total instances.  With guard set (no host copy of the
-// instance count): if the count exceeds the capacity, record it in
-// counters[3] and zero the pair, instance and slot counts so that every later
-// kernel of the pass finds no work; else (and always without guard)
-// counters[3] = 0.  Every counter is written by the pass: the caller need not
-// clear them.
-__global__ void k_pair_off_tail(uint32_t* __restrict__ pair_off, uint32_t* __restrict__ cnt, int guard,
-                                int64_t capacity) {
-    if (threadIdx.x != 0) return;
-    pair_off[cnt[0]] = cnt[1];
-    if (guard && (int64_t)cnt[1] > capacity) {
-        cnt[3] = cnt[1];
-        cnt[0] = 0u;
-        cnt[1] = 0u;
-        cnt[2] = 0u;
-    } else {
-        cnt[3] = 0u;
-    }
 }
 
 // Position of the c-th set bit (0-based) of a 64-bit mask.
@@ -330,22 +325,17 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __re
     }
 }
 
-__global__ __launch_bounds__(BN_THREADS) void k_slot_flags(const uint32_t* __restrict__ dstart, int64_t m,
-                                                           uint32_t* __restrict__ flag, uint32_t* __restrict__ cls) {
-    int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x < 128) cls[threadIdx.x] = 0u;
-    if (i < m) flag[i] = dstart[i] != 0xffffffffu ? 1u : 0u;
-}
-
 // Compaction of the non-empty entries, and the first slot of every tile
 // (the scan value at its first entry; entry `dense` gets the slot count).
+// Block 0 also clears the size-class counters of the launch orders.
 __global__ __launch_bounds__(BN_THREADS) void k_slot_compact(const uint32_t* __restrict__ dstart,
                                                              const uint32_t* __restrict__ dend,
                                                              const uint32_t* __restrict__ sidx, int64_t m, int L,
                                                              const uint32_t* __restrict__ n_slots,
                                                              uint32_t* __restrict__ slot_key,
                                                              uint32_t* __restrict__ slot_range,
-                                                             uint32_t* __restrict__ tile_slot) {
+                                                             uint32_t* __restrict__ tile_slot, uint32_t* __restrict__ cls) {
+    if (blockIdx.x == 0 && threadIdx.x < 128) cls[threadIdx.x] = 0u;
     int64_t e = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
     if (e > m) return;
     if (e == m) {
@@ -361,106 +351,78 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_compact(const uint32_t* __r
     slot_range[2 * s + 1] = dend[e];
 }
 
-// Launch order of the slots: largest first (size classes by floor(log2 len)),
-// so that long slots do not start last and stretch the tail of the render.
-__global__ __launch_bounds__(BN_THREADS) void k_slot_class_count(const uint32_t* __restrict__ slot_range,
-                                                                 const uint32_t* __restrict__ n_slots,
-                                                                 uint32_t* __restrict__ cls_cnt) {
-    __shared__ uint32_t s_c[32];
-    if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
-    __syncthreads();
-    const int64_t s = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (s < (int64_t)*n_slots) {
-        const uint32_t len = slot_range[2 * s + 1] - slot_range[2 * s];
-        atomicAdd(&s_c[31 - __clz(len | 1u)], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < 32 && s_c[threadIdx.x]) atomicAdd(&cls_cnt[threadIdx.x], s_c[threadIdx.x]);
-}
-
-// Slots are placed class by class, classes in decreasing order: every block
-// derives the class starts from the 32 counts, positions inside a block come
-// from LDS counters and one global reservation per (block, class) in
-// cls_resv, so the global atomics do not serialise on a handful of counters.
-// The order inside a class is the launch order only and affects no result.
-__global__ __launch_bounds__(BN_THREADS) void k_slot_class_place(const uint32_t* __restrict__ slot_range,
-                                                                 const uint32_t* __restrict__ n_slots,
-                                                                 const uint32_t* __restrict__ cls_cnt,
-                                                                 uint32_t* __restrict__ cls_resv,
-                                                                 uint32_t* __restrict__ slot_order) {
-    __shared__ uint32_t s_c[32], s_base[32];
-    if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int c = 31; c >= 0; --c) {
-            s_base[c] = run;
-            run += cls_cnt[c];
-        }
-    }
-    __syncthreads();
-    const int64_t s = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    const bool ok = s < (int64_t)*n_slots;
-    int cls = 0;
-    uint32_t local = 0;
-    if (ok) {
-        const uint32_t len = slot_range[2 * s + 1] - slot_range[2 * s];
-        cls = 31 - __clz(len | 1u);
-        local = atomicAdd(&s_c[cls], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < 32 && s_c[threadIdx.x]) s_base[threadIdx.x] += atomicAdd(&cls_resv[threadIdx.x], s_c[threadIdx.x]);
-    __syncthreads();
-    if (ok) slot_order[s_base[cls] + local] = (uint32_t)s;
-}
-
-// The forward render's launch order: tiles by decreasing size class of their
-// instance count (a tile's slots hold a contiguous range of the sorted
-// instances), the same two-kernel placement as the slots.
+// Launch orders, largest first by size class floor(log2 len): the slots
+// (len = instances; the backward's order) and the tiles (len = instances of
+// all the tile's slots, which are contiguous in the sorted list; the
+// forward's order), so that long blocks do not start last and stretch the
+// tail of the render.  One count and one placement kernel serve both, a
+// thread taking slot i and tile i.  cls[0..31] / cls[32..63] hold the slot
+// class counts and reservations, cls[64..95] / cls[96..127] the tiles'.
 __device__ __forceinline__ uint32_t tile_len(const uint32_t* __restrict__ tile_slot,
                                              const uint32_t* __restrict__ slot_range, int64_t t) {
     const uint32_t s0 = tile_slot[t], s1 = tile_slot[t + 1];
     return s0 < s1 ? slot_range[2 * (s1 - 1) + 1] - slot_range[2 * s0] : 0u;
 }
 
-__global__ __launch_bounds__(BN_THREADS) void k_tile_class_count(const uint32_t* __restrict__ tile_slot,
-                                                                 const uint32_t* __restrict__ slot_range, int64_t T,
-                                                                 uint32_t* __restrict__ cls_cnt) {
-    __shared__ uint32_t s_c[32];
-    if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
+__global__ __launch_bounds__(BN_THREADS) void k_class_count(const uint32_t* __restrict__ slot_range,
+                                                            const uint32_t* __restrict__ n_slots,
+                                                            const uint32_t* __restrict__ tile_slot, int64_t T,
+                                                            uint32_t* __restrict__ cls) {
+    __shared__ uint32_t s_c[64];
+    if (threadIdx.x < 64) s_c[threadIdx.x] = 0u;
     __syncthreads();
-    const int64_t t = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (t < T) atomicAdd(&s_c[31 - __clz(tile_len(tile_slot, slot_range, t) | 1u)], 1u);
+    const int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    if (i < (int64_t)*n_slots) {
+        const uint32_t len = slot_range[2 * i + 1] - slot_range[2 * i];
+        atomicAdd(&s_c[31 - __clz(len | 1u)], 1u);
+    }
+    if (i < T) atomicAdd(&s_c[32 + 31 - __clz(tile_len(tile_slot, slot_range, i) | 1u)], 1u);
     __syncthreads();
-    if (threadIdx.x < 32 && s_c[threadIdx.x]) atomicAdd(&cls_cnt[threadIdx.x], s_c[threadIdx.x]);
+    if (threadIdx.x < 64 && s_c[threadIdx.x]) atomicAdd(&cls[threadIdx.x < 32 ? threadIdx.x : threadIdx.x + 32],
+                                                        s_c[threadIdx.x]);
 }
 
-__global__ __launch_bounds__(BN_THREADS) void k_tile_class_place(const uint32_t* __restrict__ tile_slot,
-                                                                 const uint32_t* __restrict__ slot_range, int64_t T,
-                                                                 const uint32_t* __restrict__ cls_cnt,
-                                                                 uint32_t* __restrict__ cls_resv,
-                                                                 uint32_t* __restrict__ tile_order) {
-    __shared__ uint32_t s_c[32], s_base[32];
-    if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
-    if (threadIdx.x == 0) {
+// Items are placed class by class, classes in decreasing order: every block
+// derives the class starts from the 32 counts, positions inside a block come
+// from LDS counters and one global reservation per (block, class), so the
+// global atomics do not serialise on a handful of counters.  The order inside
+// a class is the launch order only and affects no result.
+__global__ __launch_bounds__(BN_THREADS) void k_class_place(const uint32_t* __restrict__ slot_range,
+                                                            const uint32_t* __restrict__ n_slots,
+                                                            const uint32_t* __restrict__ tile_slot, int64_t T,
+                                                            uint32_t* __restrict__ cls, uint32_t* __restrict__ slot_order,
+                                                            uint32_t* __restrict__ tile_order) {
+    __shared__ uint32_t s_c[64], s_base[64];
+    if (threadIdx.x < 64) s_c[threadIdx.x] = 0u;
+    if (threadIdx.x < 2) {
+        const uint32_t* cnt = cls + 64 * threadIdx.x;  // slots: cls[0..31]; tiles: cls[64..95]
         uint32_t run = 0;
         for (int c = 31; c >= 0; --c) {
-            s_base[c] = run;
-            run += cls_cnt[c];
+            s_base[32 * threadIdx.x + c] = run;
+            run += cnt[c];
         }
     }
     __syncthreads();
-    const int64_t t = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    const bool ok = t < T;
-    int cls = 0;
-    uint32_t local = 0;
-    if (ok) {
-        cls = 31 - __clz(tile_len(tile_slot, slot_range, t) | 1u);
-        local = atomicAdd(&s_c[cls], 1u);
+    const int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
+    const bool oks = i < (int64_t)*n_slots, okt = i < T;
+    int cs = 0, ct = 0;
+    uint32_t ls = 0, lt = 0;
+    if (oks) {
+        cs = 31 - __clz((slot_range[2 * i + 1] - slot_range[2 * i]) | 1u);
+        ls = atomicAdd(&s_c[cs], 1u);
+    }
+    if (okt) {
+        ct = 32 + 31 - __clz(tile_len(tile_slot, slot_range, i) | 1u);
+        lt = atomicAdd(&s_c[ct], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < 32 && s_c[threadIdx.x]) s_base[threadIdx.x] += atomicAdd(&cls_resv[threadIdx.x], s_c[threadIdx.x]);
+    if (threadIdx.x < 64 && s_c[threadIdx.x]) {
+        const int r = threadIdx.x < 32 ? 32 + threadIdx.x : 96 + (threadIdx.x - 32);  // reservation counters
+        s_base[threadIdx.x] += atomicAdd(&cls[r], s_c[threadIdx.x]);
+    }
     __syncthreads();
-    if (ok) tile_order[s_base[cls] + local] = (uint32_t)t;
+    if (oks) slot_order[s_base[cs] + ls] = (uint32_t)i;
+    if (okt) tile_order[s_base[ct] + lt] = (uint32_t)i;
 }
 
 size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t capacity) {
@@ -476,7 +438,6 @@ size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t 
     c.take<uint64_t>(capacity + 1);   // instance vals alt
     c.take<uint32_t>(dense + 1);      // dense start
     c.take<uint32_t>(dense + 1);      // dense end
-    c.take<uint32_t>(dense + 1);      // dense flags
     c.take<uint32_t>(dense + 1);      // slot index
     c.take<uint32_t>(128);            // slot and tile size classes
     const int64_t big = m > capacity ? m : capacity;
@@ -507,7 +468,6 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     uint64_t* vals_alt = c.take<uint64_t>(bins->capacity + 1);
     uint32_t* dstart = c.take<uint32_t>(dense + 1);
     uint32_t* dend = c.take<uint32_t>(dense + 1);
-    uint32_t* dflag = c.take<uint32_t>(dense + 1);
     uint32_t* sidx = c.take<uint32_t>(dense + 1);
     uint32_t* cls = c.take<uint32_t>(128);
     const int64_t big = m > bins->capacity ? m : bins->capacity;
@@ -526,12 +486,15 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
 
     // 1. visible pairs in (view, gid) order, then stable sorts by depth and by view
     const int64_t vtiles = (m + VC_TILE - 1) / VC_TILE;
+    // up to 1024 tiles the compaction sums the tile counts itself
+    const bool vfold = vtiles <= 1024;
     if (m > 0)
         hipLaunchKernelGGL(k_vis_count, dim3((unsigned)vtiles), dim3(BN_THREADS), 0, s, proj->count, m, pos);
-    if ((st = scan_tile_sums(pos, DevN{nullptr, m, 1, 1}, VC_TILE, &cnt[0], s)) != RGS_OK) return st;
+    if (m <= 0 || !vfold)
+        if ((st = scan_tile_sums(pos, DevN{nullptr, m, 1, 1}, VC_TILE, &cnt[0], s)) != RGS_OK) return st;
     if (m > 0)
         hipLaunchKernelGGL(k_vis_compact, dim3((unsigned)vtiles), dim3(BN_THREADS), 0, s, proj->count, proj->depth, m, pos,
-                           zkey, bins->pair_src);
+                           vfold ? 1 : 0, &cnt[0], zkey, bins->pair_src);
     RGS_LAUNCH_CHECK();
     if ((st = radix_sort_u32_u32_dev(zkey, bins->pair_src, zkey_alt, src_alt, &cnt[0], m, 32, rws, s)) != RGS_OK)
         return st;
@@ -548,10 +511,11 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
                            bins->pair_rank, flag, dstart, dense);
     else
         hipLaunchKernelGGL(k_fill_u32, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, 0xffffffffu);
-    if ((st = exclusive_scan_u32_dev(flag, bins->pair_off, DevN{&cnt[0], m, 1, 1}, m, &cnt[1], sws, s)) != RGS_OK)
+    // with the tail of pair_off and, without a host copy, the capacity guard
+    const ScanTail tail{cnt, sync ? 0 : 1, bins->capacity};
+    if ((st = exclusive_scan_u32_dev(flag, bins->pair_off, DevN{&cnt[0], m, 1, 1}, m, &cnt[1], sws, s, 0, &tail)) !=
+        RGS_OK)
         return st;
-    // the tail of pair_off, and without a host copy the capacity guard
-    hipLaunchKernelGGL(k_pair_off_tail, dim3(1), dim3(64), 0, s, bins->pair_off, cnt, sync ? 0 : 1, bins->capacity);
     int64_t n_inst, slot_bound;
     if (sync) {
         uint32_t h_cnt[2] = {0u, 0u};
@@ -583,19 +547,16 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     // 4. slots
     if (n_inst > 0)
         hipLaunchKernelGGL(k_slot_bounds, dgrid(n_inst), dim3(BN_THREADS), 0, s, bins->keys, &cnt[1], dense, dstart, dend);
-    hipLaunchKernelGGL(k_slot_flags, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, dflag, cls);
-    if ((st = exclusive_scan_u32(dflag, sidx, dense, &cnt[2], sws, s)) != RGS_OK) return st;
+    if ((st = exclusive_scan_u32(dstart, sidx, dense, &cnt[2], sws, s, 1)) != RGS_OK) return st;
     hipLaunchKernelGGL(k_slot_compact, grid(dense + 1), dim3(BN_THREADS), 0, s, dstart, dend, sidx, dense, L, &cnt[2],
-                       bins->slot_key, bins->slot_range, bins->tile_slot);
-    // 5. launch order of the slots (largest size class first)
-    hipLaunchKernelGGL(k_slot_class_count, grid(slot_bound), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], cls);
-    hipLaunchKernelGGL(k_slot_class_place, grid(slot_bound), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], cls,
-                       cls + 32, bins->slot_order);
-    if (total_tiles > 0) {
-        hipLaunchKernelGGL(k_tile_class_count, grid(total_tiles), dim3(BN_THREADS), 0, s, bins->tile_slot,
-                           bins->slot_range, total_tiles, cls + 64);
-        hipLaunchKernelGGL(k_tile_class_place, grid(total_tiles), dim3(BN_THREADS), 0, s, bins->tile_slot,
-                           bins->slot_range, total_tiles, cls + 64, cls + 96, bins->tile_order);
+                       bins->slot_key, bins->slot_range, bins->tile_slot, cls);
+    // 5. launch orders of the slots and the tiles (largest size class first)
+    const int64_t nord = slot_bound > total_tiles ? slot_bound : total_tiles;
+    if (nord > 0) {
+        hipLaunchKernelGGL(k_class_count, grid(nord), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], bins->tile_slot,
+                           total_tiles, cls);
+        hipLaunchKernelGGL(k_class_place, grid(nord), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], bins->tile_slot,
+                           total_tiles, cls, bins->slot_order, bins->tile_order);
     }
     return launch_check();
 }

@@ -198,12 +198,21 @@ struct DevN {
     }
 };
 size_t scan_ws_bytes(int64_t n);
+// Optional tail of the scan of per-pair instance counts (counters cnt =
+// [pairs, instances, slots, required]; the scan's total must be &cnt[1]):
+// out[pairs] = total and the capacity guard (see k_scan_apply).
+struct ScanTail {
+    uint32_t* cnt;
+    int guard;
+    int64_t capacity;
+};
 // out[i] = sum_{j<i} in[j]; if total != nullptr, *total (device) = sum of all.
+// marks = 1 scans (in[j] != ~0) instead of in[j].
 rgs_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* ws,
-                              hipStream_t s);
+                              hipStream_t s, int marks = 0);
 // The same over the first dn.get() elements (n_max bounds the grid).
 rgs_status exclusive_scan_u32_dev(const uint32_t* in, uint32_t* out, DevN dn, int64_t n_max, uint32_t* total, void* ws,
-                                  hipStream_t s);
+                                  hipStream_t s, int marks = 0, const ScanTail* tail = nullptr);
 // Block-level tile scan pieces, for callers that produce the tile sums themselves:
 // exclusive scan (in place) of the sums of the first ceil(dn.get() / tile) tiles.
 rgs_status scan_tile_sums(uint32_t* partial, DevN dn, int64_t tile, uint32_t* total, hipStream_t s);

@@ -42,7 +42,14 @@ __device__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* s_wave /*[4]*/, ui
     return tot;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in, DevN dn,
+// marks = 1: the scanned value of entry i is 1 if in[i] != ~0 (an occupied
+// entry of a table whose empty entries hold all ones), else 0.
+__device__ __forceinline__ uint32_t scan_val(const uint32_t* __restrict__ in, int64_t i, int marks) {
+    const uint32_t v = in[i];
+    return marks ? (v != 0xffffffffu ? 1u : 0u) : v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in, DevN dn, int marks,
                                                               uint32_t* __restrict__ partial) {
     __shared__ uint32_t s_wave[4];
     const int64_t n = dn.get();
@@ -51,7 +58,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __
         uint32_t acc = 0;
         for (int k = 0; k < SCAN_ITEMS; ++k) {
             int64_t i = base + k * SCAN_THREADS + threadIdx.x;
-            if (i < n) acc += in[i];
+            if (i < n) acc += scan_val(in, i, marks);
         }
         uint32_t ex;
         uint32_t tot = block_excl_scan_256(acc, s_wave, &ex);
@@ -77,18 +84,58 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(uint32_t* __rest
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __restrict__ in, DevN dn,
-                                                             const uint32_t* __restrict__ partial,
+// The optional tail of a scan of per-pair instance counts: out[n] = total,
+// and, with guard set (no host copy of the instance count), if the total
+// exceeds the capacity, counters[3] = total and the pair, instance and slot
+// counts are zeroed so that every later kernel of the pass finds no work;
+// else (and always without guard) counters[3] = 0.
+__device__ __forceinline__ void scan_tail(const ScanTail& t, uint32_t* __restrict__ out, int64_t n, uint32_t total) {
+    if (!t.cnt) return;
+    out[n] = total;
+    if (t.guard && (int64_t)total > t.capacity) {
+        t.cnt[3] = total;
+        t.cnt[0] = 0u;
+        t.cnt[1] = 0u;
+        t.cnt[2] = 0u;
+    } else {
+        t.cnt[3] = 0u;
+    }
+}
+
+// fold = 1: the tile sums are not scanned beforehand; every block adds up the
+// sums of the tiles before its own (for at most SCAN_FOLD_TILES tiles), and
+// the block of the last tile writes the total and the tail.  fold = 0: the
+// partials hold the scanned tile offsets (k_scan_partials wrote the total).
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __restrict__ in, DevN dn, int marks,
+                                                             const uint32_t* __restrict__ partial, int fold,
+                                                             uint32_t* __restrict__ total, ScanTail tail,
                                                              uint32_t* __restrict__ out) {
     __shared__ uint32_t s[SCAN_TILE + SCAN_TILE / 32];
     __shared__ uint32_t s_wave[4];
     const int64_t n = dn.get();
-    for (int64_t tile = blockIdx.x; tile * SCAN_TILE < n; tile += gridDim.x) {
+    if (fold && n <= 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (total) *total = 0u;
+            scan_tail(tail, out, 0, 0u);
+        }
+        return;
+    }
+    const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t base = tile * SCAN_TILE;
+        uint32_t toff;
+        if (fold) {
+            uint32_t a = 0;
+            for (int64_t t = threadIdx.x; t < tile; t += SCAN_THREADS) a += partial[t];
+            uint32_t ex;
+            toff = block_excl_scan_256(a, s_wave, &ex);  // the block total of the per-thread sums
+        } else {
+            toff = partial[tile];
+        }
         for (int k = 0; k < SCAN_ITEMS; ++k) {
             int li = k * SCAN_THREADS + threadIdx.x;
             int64_t i = base + li;
-            s[skew(li)] = i < n ? in[i] : 0u;
+            s[skew(li)] = i < n ? scan_val(in, i, marks) : 0u;
         }
         __syncthreads();
         uint32_t v[SCAN_ITEMS], acc = 0;
@@ -97,8 +144,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __r
             acc += v[k];
         }
         uint32_t ex;
-        block_excl_scan_256(acc, s_wave, &ex);
-        uint32_t run = partial[tile] + ex;
+        const uint32_t tsum = block_excl_scan_256(acc, s_wave, &ex);
+        if (fold && tile == ntiles - 1 && threadIdx.x == 0) {
+            if (total) *total = toff + tsum;
+            scan_tail(tail, out, n, toff + tsum);
+        }
+        uint32_t run = toff + ex;
         for (int k = 0; k < SCAN_ITEMS; ++k) {
             s[skew(threadIdx.x * SCAN_ITEMS + k)] = run;
             run += v[k];
@@ -113,6 +164,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __r
     }
 }
 
+// The tail for the path with a separate scan of the tile sums (total known).
+__global__ void k_scan_tail(uint32_t* __restrict__ out, ScanTail tail) {
+    if (threadIdx.x != 0) return;
+    scan_tail(tail, out, tail.cnt[0], tail.cnt[1]);
+}
+
 size_t scan_ws_bytes(int64_t n) {
     int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     return (size_t)(tiles + 1) * sizeof(uint32_t) + 256;
@@ -123,26 +180,31 @@ rgs_status scan_tile_sums(uint32_t* partial, DevN dn, int64_t tile, uint32_t* to
     return launch_check();
 }
 
+// Up to this many tiles, the apply kernel sums the tile sums itself (one
+// launch fewer); beyond it a single block scans them first.
+static constexpr int64_t SCAN_FOLD_TILES = 1024;
+
 rgs_status exclusive_scan_u32_dev(const uint32_t* in, uint32_t* out, DevN dn, int64_t n_max, uint32_t* total, void* ws,
-                                  hipStream_t s) {
+                                  hipStream_t s, int marks, const ScanTail* tail) {
     uint32_t* partial = reinterpret_cast<uint32_t*>(ws);
-    if (n_max <= 0) {
-        const DevN zero{nullptr, 0, 1, 1};
-        if (total) hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, zero, (int64_t)SCAN_TILE,
-                                      total);
-        return launch_check();
-    }
+    const ScanTail tl = tail ? *tail : ScanTail{nullptr, 0, 0};
     const int64_t tiles = (n_max + SCAN_TILE - 1) / SCAN_TILE;
-    const unsigned grid = (unsigned)(dn.p && tiles > DEV_GRID ? DEV_GRID : tiles);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(SCAN_THREADS), 0, s, in, dn, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, dn, (int64_t)SCAN_TILE, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3(grid), dim3(SCAN_THREADS), 0, s, in, dn, partial, out);
+    const bool fold = tiles <= SCAN_FOLD_TILES;
+    const unsigned grid = (unsigned)(tiles < 1 ? 1 : (dn.p && tiles > DEV_GRID ? DEV_GRID : tiles));
+    if (n_max > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(SCAN_THREADS), 0, s, in, dn, marks, partial);
+    if (!fold) hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, dn, (int64_t)SCAN_TILE, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(grid), dim3(SCAN_THREADS), 0, s, in, dn, marks, partial, fold ? 1 : 0,
+                       total, tl, out);
+    if (!fold && tl.cnt) {
+        // the tail after the single-block scan of the tile sums
+        hipLaunchKernelGGL(k_scan_tail, dim3(1), dim3(64), 0, s, out, tl);
+    }
     return launch_check();
 }
 
 rgs_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* ws,
-                              hipStream_t s) {
-    return exclusive_scan_u32_dev(in, out, DevN{nullptr, n, 1, 1}, n, total, ws, s);
+                              hipStream_t s, int marks) {
+    return exclusive_scan_u32_dev(in, out, DevN{nullptr, n, 1, 1}, n, total, ws, s, marks, nullptr);
 }
 
 // ------------------------------------------------------------------ radix sort
