@@ -87,10 +87,10 @@ def source_hash() -> str:
 
 
 def measured_traffic():
-    """Per-kernel HBM bytes per dispatch from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading on a
-    copy of known size); empty when absent or when any kernel source changed
-    since the counters were taken."""
+    """Per-kernel HBM bytes per step (all of the kernel's dispatches in one
+    step) from the committed counter summary (FETCH_SIZE and WRITE_SIZE, each
+    scaled by the same counter's reading on a copy of known size); empty when
+    absent or when any kernel source changed since the counters were taken."""
     out = {}
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -466,6 +466,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=3.0, help="seconds per CPU-baseline run (3 runs x 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the bounded serving leg of the default run")
+    ap.add_argument("--no-c1", action="store_true", help="skip config 1's absolute times (e.g. for profiling)")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--serve", action="store_true",
                     help="full serving study: 100M-Gaussian city resident in HBM, Poisson traces at 50/200/800 req/s")
@@ -586,7 +587,12 @@ def main():
                       "floor_ms": round(fl * 1e3, 4), "frac": round(fl / t, 4),
                       "bound": "hbm" if b / (HBM_PEAK_GBS * 1e9) >= f / (FP32_VECTOR_PEAK_TFLOPS * 1e12) else "alu"}
     # HBM bytes from the counters (per dispatch, summed over the row's kernels)
-    row_kernels = {"project": ["k_project"], "render_fwd": ["k_render_fwd"], "merge": ["k_merge_fwd"],
+    row_kernels = {"project": ["k_project"],
+                   "bin_sort": ["k_vis_count", "k_vis_compact", "k_rs_hist", "k_rs_colscan", "k_rs_scatter",
+                                "k_pair_counts", "k_scan_reduce", "k_scan_apply", "k_emit", "k_slot_bounds",
+                                "k_slot_compact", "k_class_count", "k_class_place"],
+                   "render_fwd": ["k_render_fwd"], "merge": ["k_merge_fwd"],
+                   "loss": ["k_ssim_fwd_tiled", "k_ssim_bwd_tiled", "k_loss_final"],
                    "merge_bwd": ["k_merge_bwd"], "render_bwd": ["k_render_bwd"],
                    "pair_reduce": ["k_wave_first", "k_pair_seg", "k_pair_gather"],
                    "project_bwd": ["k_project_bwd_geo", "k_project_bwd_sh"]}
@@ -612,7 +618,7 @@ def main():
               "pairs_contributing": n_con, "flop_per_rejected_pair": 7, "flop_per_contributing_pair": 22,
               "avg_ms": round(stages["render_fwd"], 4)}
 
-    c1 = c1_times(rast)
+    c1 = None if args.no_c1 else c1_times(rast)
     serve_res = None
     if not args.no_serve:
         serve_res = serving(args.serve_n, [200.0, 800.0], 300, 50, paths=("batched", "plain"))
