@@ -95,26 +95,6 @@ __device__ __forceinline__ bool box_hits(float mx, float my, float ca, float cb,
     return qmin <= tau + 0x1p-18f * far + 0x1p-20f * tau;
 }
 
-// The same test for an 8x8 quadrant of a tile.
-__device__ __forceinline__ bool quad_hits(float mx, float my, float ca, float cb, float cc, float tau, float x0,
-                                          float y0) {
-    return box_hits(mx, my, ca, cb, cc, tau, x0, y0, 8.0f, 8.0f);
-}
-
-// Quadrant mask of a Gaussian's rectangle (quad_mask) with the quadrants its
-// ellipse d^2 <= tau cannot reach removed.
-__device__ __forceinline__ uint32_t quad_mask_ellipse(uint2 rr, int tx, int ty, float mx, float my, float ca, float cb,
-                                                      float cc, float tau) {
-    uint32_t m = quad_mask(rr, tx, ty);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if ((m >> q) & 1u) {
-            const float x0 = (float)(tx * 16 + (q & 1) * 8), y0 = (float)(ty * 16 + (q >> 1) * 8);
-            if (!quad_hits(mx, my, ca, cb, cc, tau, x0, y0)) m &= ~(1u << q);
-        }
-    return m;
-}
-
 // Forward: one 256-thread block per tile, walking the tile's slots (one per
 // cell that has instances there) in the view's merge order; wave w owns the
 // 8x8 quadrant (w & 1, w >> 1) of the tile, one pixel per lane.  Each pixel
@@ -189,9 +169,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
                 const float4 a = rp[0];
                 const float4 b = rp[1], cl = rp[2], r4 = rp[3];
                 const uint2 rr = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
-                const float cb = a.w * a.z, cc = b.x + a.w * cb;  // conic from (ca, k, e)
-                sM[tid] = (quad_mask_ellipse(rr, tx, ty, a.x, a.y, a.z, cb, cc, b.z) << 1) |
-                          (__float_as_uint(cl.w) & 1u);
+                sM[tid] = (quad_mask(rr, tx, ty) << 1) | (__float_as_uint(cl.w) & 1u);
                 sA[tid] = a;
                 sB[tid] = b;
                 sCl[tid] = cl;
