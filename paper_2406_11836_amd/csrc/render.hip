@@ -298,6 +298,9 @@ __device__ __forceinline__ float swap16_sum(float x, float y) {
     return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
 }
 
+// Lane mask of a comparison (the compare writes it to scalar registers).
+__device__ __forceinline__ uint64_t wmask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 #define RGS_DPP(v, ctrl) __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (v)), (ctrl), 0xf, 0xf, false))
 
 __device__ __forceinline__ void wave_sum9(const float* g, int lane, float* out_v, float* out_8) {
@@ -468,8 +471,11 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
             const float dx0 = P[0].fx - a.x, dx1 = P[1].fx - a.x;
             const float u0 = fmaf(a.w, dy, dx0), u1 = fmaf(a.w, dy, dx1);  // d^2 = ca u^2 + e dy^2
             const float d20 = fmaf(edy, dy, (a.z * u0) * u0), d21 = fmaf(edy, dy, (a.z * u1) * u1);
-            bool c0 = pos1 <= P[0].last && d20 <= b.z;
-            bool c1 = pos1 <= P[1].last && d21 <= b.z;
+            // contributing lanes as wave masks: one ballot per comparison (the
+            // compare's own lane mask), combined in scalar registers; a lane's
+            // flag is read back with an inverse ballot
+            uint64_t m0 = wmask(pos1 <= P[0].last) & wmask(d20 <= b.z);
+            uint64_t m1 = wmask(pos1 <= P[1].last) & wmask(d21 <= b.z);
             if (STATS) {
                 // pairs the backward must re-test: pixel inside the rectangle, at or before its last contributor
                 const uint2 rr = sR[t];
@@ -478,21 +484,24 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
                 n_eval += (pos1 <= P[0].last && rowin && pxs[0] >= xl && pxs[0] <= xh) ? 1u : 0u;
                 n_eval += (pos1 <= P[1].last && rowin && pxs[1] >= xl && pxs[1] <= xh) ? 1u : 0u;
             }
-            if (__ballot(c0 || c1) == 0ull) continue;
+            if ((m0 | m1) == 0ull) continue;
             const float4 cl = sCl[t];
             if (!((inside >> t) & 1ull)) {  // not interior to the cell: the indicator of Eq. 6
                 const float x0 = fmaf(b.w, P[0].D0, o0), y0 = fmaf(b.w, P[0].D1, o1), z0 = fmaf(b.w, P[0].D2, o2);
                 const float x1 = fmaf(b.w, P[1].D0, o0), y1 = fmaf(b.w, P[1].D1, o1), z1 = fmaf(b.w, P[1].D2, o2);
-                c0 = c0 && (blo0 <= x0) && (x0 < bhi0) && (blo1 <= y0) && (y0 < bhi1) && (blo2 <= z0) && (z0 < bhi2);
-                c1 = c1 && (blo0 <= x1) && (x1 < bhi0) && (blo1 <= y1) && (y1 < bhi1) && (blo2 <= z1) && (z1 < bhi2);
-                if (__ballot(c0 || c1) == 0ull) continue;
+                m0 &= wmask(blo0 <= x0) & wmask(x0 < bhi0) & wmask(blo1 <= y0) & wmask(y0 < bhi1) & wmask(blo2 <= z0) &
+                      wmask(z0 < bhi2);
+                m1 &= wmask(blo0 <= x1) & wmask(x1 < bhi0) & wmask(blo1 <= y1) & wmask(y1 < bhi1) & wmask(blo2 <= z1) &
+                      wmask(z1 < bhi2);
+                if ((m0 | m1) == 0ull) continue;
             }
+            const bool c0 = __builtin_amdgcn_inverse_ballot_w64(m0), c1 = __builtin_amdgcn_inverse_ballot_w64(m1);
             if (STATS) n_con += (c0 ? 1u : 0u) + (c1 ? 1u : 0u);
             // a pixel column of the wave where no lane contributes (the
             // instance reaches one quadrant of the half only) is skipped: its
             // step would leave T and <dC, B> as they are and add zeros
             const float d2c0 = c0 ? d20 : INFINITY, d2c1 = c1 ? d21 : INFINITY;
-            const bool any0 = __ballot(c0) != 0ull, any1 = __ballot(c1) != 0ull;
+            const bool any0 = m0 != 0ull, any1 = m1 != 0ull;
             PixTerms r0 = {0.f, 0.f, 0.f, 0.f}, r1 = {0.f, 0.f, 0.f, 0.f};
             if (any0) r0 = pix_step(P[0], d2c0, b.y, cl);
             if (any1) r1 = pix_step(P[1], d2c1, b.y, cl);
@@ -512,8 +521,11 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
             g[8] = fmaf(r1.wc, P[1].gC2, r0.wc * P[0].gC2);
             float sv, s8;
             wave_sum9(g, lane, &sv, &s8);
-            if ((lane & 7) == 0) sG[w][t][lane >> 3] = sv;
-            if (lane == 63) sG[w][t][8] = s8;
+            // 32-bit LDS offsets (t * 9 in scalar registers)
+            float* const gw = &sG[w][0][0];
+            const uint32_t gt = (uint32_t)t * 9u;
+            if ((lane & 7) == 0) gw[gt + (uint32_t)(lane >> 3)] = sv;
+            if (lane == 63) gw[gt + 8u] = s8;
         }
         __syncthreads();
         if (tid < NB && (uint32_t)bstart + tid < bmax) {
