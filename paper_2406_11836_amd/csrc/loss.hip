@@ -47,6 +47,11 @@ static constexpr int TS = 32, TW = TS + 2 * HALO;       // output / staged colum
 static constexpr int TSY = 16, TH = TSY + 2 * HALO;     // output / staged rows (26)
 static constexpr int RPT = TSY / 8;                      // output rows per thread in the vertical pass
 static constexpr int VWIN = RPT + 2 * HALO;              // its window of horizontal results
+// Staging: thread (column c, row group g) of TW x SG loads rows g, g + SG, ...
+// of the tile with its halo (index arithmetic once per thread, not per value).
+static constexpr int SG = LS_THREADS / TW;               // 6 row groups
+static_assert(SG >= 1 && TW * SG <= LS_THREADS, "staging layout");
+static constexpr int SR = (TH + SG - 1) / SG;            // rows per thread (5)
 
 // Forward: SSIM map terms and d SSIM / d (mu_x, E[x^2], E[xy]) per pixel,
 // plus block sums of the SSIM map and of |x - y|.
@@ -64,12 +69,28 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
     const int64_t HW = (int64_t)H * W;
     const float* xc = x + ch * HW;
     const float* yc = y + ch * HW;
-    for (int k = threadIdx.x; k < TH * TW; k += LS_THREADS) {
-        const int r = k / TW, c = k % TW;
-        const int gy = y0 + r - HALO, gx = x0 + c - HALO;
-        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-        sx[k] = in ? xc[(int64_t)gy * W + gx] : 0.f;
-        sy[k] = in ? yc[(int64_t)gy * W + gx] : 0.f;
+    if (threadIdx.x < TW * SG) {
+        const int c = threadIdx.x % TW, g = threadIdx.x / TW;
+        const int gx = x0 + c - HALO;
+        const bool xin = gx >= 0 && gx < W;
+        // all loads of the thread are issued before the stores
+        float vx[SR], vy[SR];
+#pragma unroll
+        for (int i = 0; i < SR; ++i) {
+            const int r = g + SG * i, gy = y0 + r - HALO;
+            const bool in = r < TH && xin && gy >= 0 && gy < H;
+            const int64_t gi = (int64_t)gy * W + gx;
+            vx[i] = in ? xc[gi] : 0.f;
+            vy[i] = in ? yc[gi] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < SR; ++i) {
+            const int r = g + SG * i;
+            if (r < TH) {
+                sx[r * TW + c] = vx[i];
+                sy[r * TW + c] = vy[i];
+            }
+        }
     }
     __syncthreads();
     // horizontal pass: a thread takes 4 consecutive outputs of one row from a
@@ -167,14 +188,29 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __re
     const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TSY;
     const int64_t HW = (int64_t)H * W;
     const int64_t m = 3 * HW;
-    for (int k = threadIdx.x; k < TH * TW; k += LS_THREADS) {
-        const int r = k / TW, c = k % TW;
-        const int gy = y0 + r - HALO, gx = x0 + c - HALO;
-        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-        const int64_t i = ch * HW + (int64_t)gy * W + gx;
-        sd[0][k] = in ? d3[i] : 0.f;
-        sd[1][k] = in ? d3[m + i] : 0.f;
-        sd[2][k] = in ? d3[2 * m + i] : 0.f;
+    if (threadIdx.x < TW * SG) {
+        const int c = threadIdx.x % TW, g = threadIdx.x / TW;
+        const int gx = x0 + c - HALO;
+        const bool xin = gx >= 0 && gx < W;
+        float v0[SR], v1[SR], v2[SR];
+#pragma unroll
+        for (int k = 0; k < SR; ++k) {
+            const int r = g + SG * k, gy = y0 + r - HALO;
+            const bool in = r < TH && xin && gy >= 0 && gy < H;
+            const int64_t i = ch * HW + (int64_t)gy * W + gx;
+            v0[k] = in ? d3[i] : 0.f;
+            v1[k] = in ? d3[m + i] : 0.f;
+            v2[k] = in ? d3[2 * m + i] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < SR; ++k) {
+            const int r = g + SG * k;
+            if (r < TH) {
+                sd[0][r * TW + c] = v0[k];
+                sd[1][r * TW + c] = v1[k];
+                sd[2][r * TW + c] = v2[k];
+            }
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < TH * (TS / 4); k += LS_THREADS) {
