@@ -27,12 +27,16 @@ __global__ __launch_bounds__(BN_THREADS) void k_vis_count(const uint32_t* __rest
                                                           uint32_t* __restrict__ tile_sum) {
     __shared__ uint32_t s_w[4];
     const int64_t base = (int64_t)blockIdx.x * VC_TILE;
-    uint32_t c = 0;
+    // all loads first (a lane past the end reads the last entry and counts nothing)
+    uint32_t cv[VC_ITEMS];
 #pragma unroll
     for (int k = 0; k < VC_ITEMS; ++k) {
         const int64_t i = base + k * BN_THREADS + threadIdx.x;
-        c += (i < m && count[i] != 0u) ? 1u : 0u;
+        cv[k] = count[i < m ? i : m - 1];
     }
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < VC_ITEMS; ++k) c += (base + k * BN_THREADS + threadIdx.x < m && cv[k] != 0u) ? 1u : 0u;
     c = wave_sum_u32(c);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = c;
     __syncthreads();
@@ -55,10 +59,16 @@ __global__ __launch_bounds__(BN_THREADS) void k_vis_compact(const uint32_t* __re
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * VC_TILE;
     uint32_t fl = 0;
+    uint32_t cv[VC_ITEMS];
 #pragma unroll
     for (int k = 0; k < VC_ITEMS; ++k) {
         const int64_t i = base + k * BN_THREADS + threadIdx.x;
-        const bool f = i < m && count[i] != 0u;
+        cv[k] = count[i < m ? i : m - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < VC_ITEMS; ++k) {
+        const int64_t i = base + k * BN_THREADS + threadIdx.x;
+        const bool f = i < m && cv[k] != 0u;
         fl |= (f ? 1u : 0u) << k;
         const uint64_t b = __ballot(f);
         if (lane == 0) s_c[k * 4 + w] = (uint32_t)__popcll(b);
@@ -82,6 +92,13 @@ __global__ __launch_bounds__(BN_THREADS) void k_vis_compact(const uint32_t* __re
     } else {
         t0 = tile_off[blockIdx.x];
     }
+    // the depths of the kept entries, all loads before the stores
+    float dv[VC_ITEMS];
+#pragma unroll
+    for (int k = 0; k < VC_ITEMS; ++k) {
+        const int64_t i = base + k * BN_THREADS + threadIdx.x;
+        dv[k] = ((fl >> k) & 1u) ? depth[i] : 0.f;
+    }
 #pragma unroll
     for (int k = 0; k < VC_ITEMS; ++k) {
         const bool f = (fl >> k) & 1u;
@@ -89,7 +106,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_vis_compact(const uint32_t* __re
         if (f) {
             const int64_t i = base + k * BN_THREADS + threadIdx.x;
             const uint32_t p = t0 + s_c[k * 4 + w] + (uint32_t)__popcll(b & lt_mask);
-            zkey[p] = __float_as_uint(depth[i]);
+            zkey[p] = __float_as_uint(dv[k]);
             src_out[p] = (uint32_t)i;
         }
     }

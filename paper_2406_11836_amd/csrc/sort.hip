@@ -55,11 +55,16 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __
     const int64_t n = dn.get();
     for (int64_t tile = blockIdx.x; tile * SCAN_TILE < n; tile += gridDim.x) {
         const int64_t base = tile * SCAN_TILE;
-        uint32_t acc = 0;
+        // all loads first (a lane past the end reads the last entry and adds nothing)
+        uint32_t v[SCAN_ITEMS];
+#pragma unroll
         for (int k = 0; k < SCAN_ITEMS; ++k) {
-            int64_t i = base + k * SCAN_THREADS + threadIdx.x;
-            if (i < n) acc += scan_val(in, i, marks);
+            const int64_t i = base + k * SCAN_THREADS + threadIdx.x;
+            v[k] = scan_val(in, i < n ? i : n - 1, marks);
         }
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) acc += base + k * SCAN_THREADS + threadIdx.x < n ? v[k] : 0u;
         uint32_t ex;
         uint32_t tot = block_excl_scan_256(acc, s_wave, &ex);
         if (threadIdx.x == 0) partial[tile] = tot;
@@ -132,10 +137,18 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __r
         } else {
             toff = partial[tile];
         }
-        for (int k = 0; k < SCAN_ITEMS; ++k) {
-            int li = k * SCAN_THREADS + threadIdx.x;
-            int64_t i = base + li;
-            s[skew(li)] = i < n ? scan_val(in, i, marks) : 0u;
+        {
+            uint32_t lv[SCAN_ITEMS];
+#pragma unroll
+            for (int k = 0; k < SCAN_ITEMS; ++k) {
+                const int64_t i = base + k * SCAN_THREADS + threadIdx.x;
+                lv[k] = scan_val(in, i < n ? i : n - 1, marks);
+            }
+#pragma unroll
+            for (int k = 0; k < SCAN_ITEMS; ++k) {
+                const int li = k * SCAN_THREADS + threadIdx.x;
+                s[skew(li)] = base + li < n ? lv[k] : 0u;
+            }
         }
         __syncthreads();
         uint32_t v[SCAN_ITEMS], acc = 0;
@@ -230,10 +243,16 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restri
         s_h[threadIdx.x] = 0;
         __syncthreads();
         const int64_t base = (int64_t)tile * RS_TILE;
+        // all loads first (a lane past the end reads the last key and adds nothing)
+        uint32_t kv[RS_ITEMS];
+#pragma unroll
         for (int k = 0; k < RS_ITEMS; ++k) {
-            int64_t i = base + k * RS_THREADS + threadIdx.x;
-            if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & 0xffu], 1u);
+            const int64_t i = base + k * RS_THREADS + threadIdx.x;
+            kv[k] = keys[i < n ? i : n - 1];
         }
+#pragma unroll
+        for (int k = 0; k < RS_ITEMS; ++k)
+            if (base + k * RS_THREADS + threadIdx.x < n) atomicAdd(&s_h[(kv[k] >> shift) & 0xffu], 1u);
         __syncthreads();
         hist[(int64_t)threadIdx.x * ntiles + tile] = s_h[threadIdx.x];
         __syncthreads();
@@ -307,11 +326,17 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
         uint32_t key[RS_ITEMS];
         V val[RS_ITEMS];
         uint32_t rank[RS_ITEMS];
+        // all loads first, without branches (a lane past the end reads the last element)
+#pragma unroll
+        for (int k = 0; k < RS_ITEMS; ++k) {
+            const int64_t i = base + (int64_t)w * RS_WAVE_ITEMS + k * 64 + lane;
+            const int64_t ic = i < n ? i : n - 1;
+            key[k] = keys_in[ic];
+            val[k] = vals_in[ic];
+        }
         for (int k = 0; k < RS_ITEMS; ++k) {
             const int64_t i = base + (int64_t)w * RS_WAVE_ITEMS + k * 64 + lane;
             const bool valid = i < n;
-            key[k] = valid ? keys_in[i] : 0u;
-            val[k] = valid ? vals_in[i] : V(0);
             const uint32_t d = (key[k] >> shift) & 0xffu;
             uint64_t m = __ballot(valid);
     #pragma unroll
