@@ -325,20 +325,28 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __re
                                                             const uint32_t* __restrict__ n_dev, int64_t dense,
                                                             uint32_t* __restrict__ dstart, uint32_t* __restrict__ dend) {
     const int64_t n_inst = (int64_t)*n_dev;
-    const int lane = threadIdx.x & 63;
-    // a wave takes 64 consecutive keys per step; the neighbours come from the
-    // adjacent lanes, only the end lanes load theirs
-    for (int64_t w0 = (int64_t)blockIdx.x * BN_THREADS + (threadIdx.x & ~63); w0 < n_inst;
-         w0 += (int64_t)gridDim.x * BN_THREADS) {
-        const int64_t i = w0 + lane;
-        const bool valid = i < n_inst;
-        const uint32_t k = valid ? keys[i] : 0xffffffffu;
-        uint32_t prev = __shfl_up(k, 1, 64), next = __shfl_down(k, 1, 64);
-        if (lane == 0) prev = i > 0 ? keys[i - 1] : 0xffffffffu;
-        if (lane == 63 && i + 1 < n_inst) next = keys[i + 1];
-        if (!valid || (int64_t)k >= dense) continue;
-        if (i == 0 || prev != k) dstart[k] = (uint32_t)i;
-        if (i == n_inst - 1 || next != k) dend[k] = (uint32_t)(i + 1);
+    // a thread takes SB_ITEMS keys BN_THREADS apart per step; every key and
+    // its two neighbours are loaded (coalesced, overlapping in cache) before
+    // any is used
+    constexpr int SB_ITEMS = 4;
+    for (int64_t i0 = (int64_t)blockIdx.x * (BN_THREADS * SB_ITEMS) + threadIdx.x; i0 < n_inst;
+         i0 += (int64_t)gridDim.x * (BN_THREADS * SB_ITEMS)) {
+        uint32_t k[SB_ITEMS], pv[SB_ITEMS], nx[SB_ITEMS];
+#pragma unroll
+        for (int u = 0; u < SB_ITEMS; ++u) {
+            const int64_t i = i0 + u * BN_THREADS;
+            const int64_t ic = i < n_inst ? i : n_inst - 1;
+            k[u] = keys[ic];
+            pv[u] = keys[ic > 0 ? ic - 1 : 0];
+            nx[u] = keys[ic + 1 < n_inst ? ic + 1 : ic];
+        }
+#pragma unroll
+        for (int u = 0; u < SB_ITEMS; ++u) {
+            const int64_t i = i0 + u * BN_THREADS;
+            if (i >= n_inst || (int64_t)k[u] >= dense) continue;
+            if (i == 0 || pv[u] != k[u]) dstart[k[u]] = (uint32_t)i;
+            if (i == n_inst - 1 || nx[u] != k[u]) dend[k[u]] = (uint32_t)(i + 1);
+        }
     }
 }
 
