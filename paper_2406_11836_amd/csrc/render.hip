@@ -601,10 +601,23 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
     if (j0 >= (int64_t)n_inst) return;  // uniform per wave
     const int64_t j = j0 + lane;
     const bool valid = j < (int64_t)n_inst;
+    // the records first: they do not depend on the pair lookup
+    float v[9];
+    {
+        const float* rp = records + (size_t)(valid ? j : (int64_t)n_inst - 1) * RD_REC;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) v[c] = rp[c];
+        if (!valid) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) v[c] = 0.f;
+        }
+    }
     const uint32_t r0 = first_pair[w];  // the pair holding instance j0
-    // starts of the next 64 pairs (increasing); pos = how many start at or before j
+    // starts of the next 64 pairs (increasing, the tail entry included); pos =
+    // how many start at or before j (at most 63: they start after j0)
     const uint32_t rk = r0 + 1u + (uint32_t)lane;
-    const int64_t bk = rk < n_pairs ? (int64_t)pair_off[rk] : INT64_MAX;
+    const int64_t bk = rk <= n_pairs ? (int64_t)pair_off[rk] : INT64_MAX;
+    const int64_t b_r0 = (int64_t)pair_off[r0];
     int pos = 0;
 #pragma unroll
     for (int step = 32; step >= 1; step >>= 1) {
@@ -615,15 +628,9 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
     const uint64_t heads = __ballot(lane == 0 || pos != pos_prev);
     const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
     const int seg0 = 63 - __builtin_clzll(heads & le_mask);  // first lane of this lane's segment
-    float v[9];
-    if (valid) {
-        const float* rp = records + (size_t)j * RD_REC;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) v[c] = rp[c];
-    } else {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) v[c] = 0.f;
-    }
+    // the start and end of this lane's pair, from the starts already loaded
+    const int64_t b_at = __shfl(bk, pos > 0 ? pos - 1 : 0, 64);
+    const int64_t e_at = __shfl(bk, pos, 64);
     // Segmented inclusive scan: in-row steps by DPP row shifts (1, 2, 4, 8;
     // lanes shifted in from outside the row read 0), then the row broadcasts
     // of lanes 15 and 47 (into rows 1 and 3) and of lane 31 (into rows 2 and
@@ -650,8 +657,8 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
     const bool seg_end = valid && (!next_valid || pos_next != pos);
     if (!seg_end) return;
     const uint32_t r = r0 + (uint32_t)pos;
-    const bool began_before = (int64_t)pair_off[r] < j0;
-    const bool goes_on = (int64_t)pair_off[r + 1] > j0 + 64;
+    const bool began_before = (pos > 0 ? b_at : b_r0) < j0;
+    const bool goes_on = e_at > j0 + 64;
     const float4 o0 = make_float4(v[0], v[1], v[2], v[3]), o1 = make_float4(v[4], v[5], v[6], v[7]),
                  o2 = make_float4(v[8], 0.f, 0.f, 0.f);
     if (!began_before && !goes_on) {
