@@ -369,6 +369,7 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
                                                     const float* __restrict__ box_hi, const float* __restrict__ partT,
                                                     const uint32_t* __restrict__ partLast, const float* __restrict__ dC,
                                                     const float* __restrict__ dT, float* __restrict__ records,
+                                                    uint32_t* __restrict__ touched,
                                                     unsigned long long* __restrict__ stats) {
     constexpr int NB = 64;
     __shared__ float4 sA[NB], sB[NB], sCl[NB];
@@ -424,13 +425,9 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
     if (lane == 0) s_max[w] = wmax;
     __syncthreads();
     const uint32_t bmax = max(s_max[0], s_max[1]);
-    const uint32_t len = end - begin;
-    // instances never reached by any pixel get zero records
-    for (uint32_t k = bmax + tid; k < len; k += 128) {
-        float* rp = records + (size_t)(uint32_t)vals[begin + k] * RD_REC;
-#pragma unroll
-        for (int c = 0; c < RD_REC; ++c) rp[c] = 0.f;
-    }
+    // instances behind every pixel's last contributor (k >= bmax) get no
+    // record: their bit in `touched` stays clear and the pair reduction
+    // counts them as zero
     const float hx0 = (float)(tx * 16), hy0 = (float)(ty * 16 + w * 8);
     for (int bstart = bmax == 0 ? -1 : (int)(((bmax - 1) / NB) * NB); bstart >= 0; bstart -= NB) {
         if (tid < NB && (uint32_t)bstart + tid < bmax) {
@@ -536,7 +533,9 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
             for (int c = 0; c < 9; ++c) S[c] = sG[0][t][c] + sG[1][t][c];
             const float4 a = sA[t];
             const float cb = a.w * a.z, cc = sB[t].x + a.w * cb;  // conic from (ca, k, e)
-            float* rp = records + (size_t)sJ[t] * RD_REC;
+            const uint32_t jr = sJ[t];
+            float* rp = records + (size_t)jr * RD_REC;
+            atomicOr(&touched[jr >> 5], 1u << (jr & 31u));
             // d mx = sum q (ca dx + cb dy), d my = sum q (cb dx + cc dy); d ca, d cb, d cc
             // carry dL/d(d^2) = -q / 2 (d cb counts the cross term twice); then d alpha, colour
             rp[0] = a.z * S[0] + cb * S[1];
@@ -590,7 +589,9 @@ __global__ __launch_bounds__(256) void k_wave_first(const uint32_t* __restrict__
     }
 }
 
-__global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ records, const uint32_t* __restrict__ pair_off,
+__global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ records,
+                                                  const uint32_t* __restrict__ touched,
+                                                  const uint32_t* __restrict__ pair_off,
                                                   const uint32_t* __restrict__ counters,
                                                   const uint32_t* __restrict__ first_pair, float* __restrict__ psum,
                                                   float* __restrict__ wpart) {
@@ -601,15 +602,18 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
     if (j0 >= (int64_t)n_inst) return;  // uniform per wave
     const int64_t j = j0 + lane;
     const bool valid = j < (int64_t)n_inst;
-    // the records first: they do not depend on the pair lookup
+    // the records first (they do not depend on the pair lookup); an instance
+    // without a record (behind its tile's last contributors) counts as zero
     float v[9];
     {
-        const float* rp = records + (size_t)(valid ? j : (int64_t)n_inst - 1) * RD_REC;
+        const uint32_t jc = (uint32_t)(valid ? j : (int64_t)n_inst - 1);
+        const bool has = valid && ((touched[jc >> 5] >> (jc & 31u)) & 1u);
 #pragma unroll
-        for (int c = 0; c < 9; ++c) v[c] = rp[c];
-        if (!valid) {
+        for (int c = 0; c < 9; ++c) v[c] = 0.f;
+        if (has) {
+            const float* rp = records + (size_t)jc * RD_REC;
 #pragma unroll
-            for (int c = 0; c < 9; ++c) v[c] = 0.f;
+            for (int c = 0; c < 9; ++c) v[c] = rp[c];
         }
     }
     const uint32_t r0 = first_pair[w];  // the pair holding instance j0
@@ -725,13 +729,19 @@ size_t render_bwd_ws_bytes(int64_t capacity) {
     const size_t nw = (c + 63) / 64;
     const size_t wp = nw * 2 * PS_REC * sizeof(float);
     return ((rec + 255) & ~size_t(255)) + ((ps + 255) & ~size_t(255)) + ((wp + 255) & ~size_t(255)) +
-           nw * sizeof(uint32_t) + 256;
+           ((nw * sizeof(uint32_t) + 255) & ~size_t(255)) + (c + 31) / 32 * sizeof(uint32_t) + 256;
 }
 
 struct BwdWs {
     float *records, *psum, *wpart;
     uint32_t* first_pair;
+    uint32_t* touched;  // bit j: instance j (emission position) has a record
+    size_t touched_words;
 };
+
+__global__ __launch_bounds__(256) void k_clear_words(uint32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
 
 static BwdWs carve_bwd(const rgs_bins* bins, void* ws) {
     const size_t c = (size_t)(bins->capacity > 0 ? bins->capacity : 1);
@@ -744,6 +754,9 @@ static BwdWs carve_bwd(const rgs_bins* bins, void* ws) {
     const size_t nw = (c + 63) / 64;
     w.first_pair = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(w.wpart) +
                                                ((nw * 2 * PS_REC * sizeof(float) + 255) & ~size_t(255)));
+    w.touched = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(w.first_pair) +
+                                            ((nw * sizeof(uint32_t) + 255) & ~size_t(255)));
+    w.touched_words = (c + 31) / 32;
     return w;
 }
 
@@ -752,16 +765,22 @@ rgs_status render_bwd_records_launch(const rgs_partials_grad* dparts, const rgs_
                                      const rgs_projected* proj, const ViewTable* vt, const rgs_kdtree* kd, void* ws,
                                      uint64_t* stats, int64_t slot_bound, hipStream_t s) {
     const BwdWs w = carve_bwd(bins, ws);
-    if (slot_bound <= 0) return RGS_OK;
+    // no record yet (a fill kernel, not a memset: the call may be captured)
+    {
+        const int64_t nb = ((int64_t)w.touched_words + 255) / 256;
+        hipLaunchKernelGGL(k_clear_words, dim3((unsigned)(nb < 1024 ? (nb > 0 ? nb : 1) : 1024)), dim3(256), 0, s,
+                           w.touched, (int64_t)w.touched_words);
+    }
+    if (slot_bound <= 0) return launch_check();
     if (stats)
         hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
-                           parts->T, parts->last, dparts->dC, dparts->dT, w.records,
+                           parts->T, parts->last, dparts->dC, dparts->dT, w.records, w.touched,
                            reinterpret_cast<unsigned long long*>(stats));
     else
         hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
                            bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
-                           parts->T, parts->last, dparts->dC, dparts->dT, w.records, nullptr);
+                           parts->T, parts->last, dparts->dC, dparts->dT, w.records, w.touched, nullptr);
     return launch_check();
 }
 
@@ -777,7 +796,7 @@ rgs_status pair_reduce_launch(const rgs_bins* bins, const rgs_projected* proj, i
         hipLaunchKernelGGL(k_wave_first, dim3((unsigned)(pb < 2048 ? pb : 2048)), dim3(256), 0, s, bins->pair_off,
                            bins->counters, w.first_pair);
         hipLaunchKernelGGL(k_pair_seg, dim3((unsigned)((bins->capacity + 255) / 256)), dim3(256), 0, s, w.records,
-                           bins->pair_off, bins->counters, w.first_pair, w.psum, w.wpart);
+                           w.touched, bins->pair_off, bins->counters, w.first_pair, w.psum, w.wpart);
     }
     RGS_LAUNCH_CHECK();
     if (m > 0)
