@@ -377,6 +377,7 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
     __shared__ uint32_t sJ[NB];
     __shared__ float sG[2][NB][9];
     __shared__ uint32_t s_max[2];
+    __shared__ uint64_t s_wrote[2];  // per wave: the batch's instances it wrote half sums for
     if (blockIdx.x >= counters[2]) return;
     const uint32_t slot = slot_order[blockIdx.x];
     const int L = vt->L, K = 1 << L;
@@ -442,7 +443,6 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
             sR[tid] = make_uint2(__float_as_uint(r4.x), __float_as_uint(r4.y));
             sJ[tid] = (uint32_t)vv;
         }
-        for (int k = tid; k < 2 * NB * 9; k += 128) (&sG[0][0][0])[k] = 0.f;
         __syncthreads();
         // Gaussians of this batch below the wave's largest `last` whose
         // footprint can reach the wave's half tile (each wave tests its own
@@ -456,6 +456,7 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
                   box_hits(a.x, a.y, a.z, cb, cc, b.z, hx0, hy0, 16.0f, 8.0f);
         }
         uint64_t rel = __ballot(hit);
+        uint64_t wrote = 0ull;
         const uint64_t inside = __ballot(hit && (__float_as_uint(sCl[tl].w) & 1u));  // in one cell: no indicator test
         while (rel) {
             const int t = 63 - (int)__builtin_clzll(rel);
@@ -523,14 +524,20 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
             const uint32_t gt = (uint32_t)t * 9u;
             if ((lane & 7) == 0) gw[gt + (uint32_t)(lane >> 3)] = sv;
             if (lane == 63) gw[gt + 8u] = s8;
+            wrote |= 1ull << t;
         }
+        if (lane == 0) s_wrote[w] = wrote;
         __syncthreads();
-        if (tid < NB && (uint32_t)bstart + tid < bmax) {
-            // S_c = sum over the two halves, in a fixed order
+        const uint64_t h0 = s_wrote[0], h1 = s_wrote[1];
+        // a record for every instance that either half wrote (the others add nothing)
+        if (tid < NB && (uint32_t)bstart + tid < bmax && (((h0 | h1) >> tid) & 1ull)) {
+            // S_c = sum over the two halves, in a fixed order (a half that
+            // wrote nothing adds zero)
             const int t = tid;
+            const bool w0 = (h0 >> t) & 1ull, w1 = (h1 >> t) & 1ull;
             float S[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) S[c] = sG[0][t][c] + sG[1][t][c];
+            for (int c = 0; c < 9; ++c) S[c] = (w0 ? sG[0][t][c] : 0.f) + (w1 ? sG[1][t][c] : 0.f);
             const float4 a = sA[t];
             const float cb = a.w * a.z, cc = sB[t].x + a.w * cb;  // conic from (ca, k, e)
             const uint32_t jr = sJ[t];
