@@ -612,9 +612,10 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
     // the records first (they do not depend on the pair lookup); an instance
     // without a record (behind its tile's last contributors) counts as zero
     float v[9];
+    bool has;
     {
         const uint32_t jc = (uint32_t)(valid ? j : (int64_t)n_inst - 1);
-        const bool has = valid && ((touched[jc >> 5] >> (jc & 31u)) & 1u);
+        has = valid && ((touched[jc >> 5] >> (jc & 31u)) & 1u);
 #pragma unroll
         for (int c = 0; c < 9; ++c) v[c] = 0.f;
         if (has) {
@@ -656,12 +657,14 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
             if (tk) v[c] += u;                                                                                     \
         }                                                                                                          \
     }
-    RGS_SEG_STEP(0x111, 0xf, lane - 1 >= seg0)             // row_shr:1
-    RGS_SEG_STEP(0x112, 0xf, lane - 2 >= seg0)             // row_shr:2
-    RGS_SEG_STEP(0x114, 0xf, lane - 4 >= seg0)             // row_shr:4
-    RGS_SEG_STEP(0x118, 0xf, lane - 8 >= seg0)             // row_shr:8
-    RGS_SEG_STEP(0x142, 0xa, (row & 1) && seg0 < 16 * row)  // row_bcast:15
-    RGS_SEG_STEP(0x143, 0xc, row >= 2 && seg0 < 32)         // row_bcast:31
+    if (__ballot(has) != 0ull) {  // a wave without records sums zeros: no scan
+        RGS_SEG_STEP(0x111, 0xf, lane - 1 >= seg0)             // row_shr:1
+        RGS_SEG_STEP(0x112, 0xf, lane - 2 >= seg0)             // row_shr:2
+        RGS_SEG_STEP(0x114, 0xf, lane - 4 >= seg0)             // row_shr:4
+        RGS_SEG_STEP(0x118, 0xf, lane - 8 >= seg0)             // row_shr:8
+        RGS_SEG_STEP(0x142, 0xa, (row & 1) && seg0 < 16 * row)  // row_bcast:15
+        RGS_SEG_STEP(0x143, 0xc, row >= 2 && seg0 < 32)         // row_bcast:31
+    }
 #undef RGS_SEG_STEP
     const int pos_next = __shfl_down(pos, 1, 64);
     const bool next_valid = lane < 63 && j + 1 < (int64_t)n_inst;
