@@ -47,8 +47,9 @@ TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic_1M_1600x1060_K8.txt")
 
 # Algorithmic work of each step of the path per unit (bytes the method must
 # move, FLOP it must compute), from the counts of the seeded workload:
-#   N Gaussians, V visible (view, Gaussian) pairs, I instances, S slots,
-#   P tested (pixel, instance) pairs, Pc contributing, HW pixels.
+#   N Gaussians, V visible (view, Gaussian) pairs, I instances, Ib of them
+#   ahead of their slot's last contributor (the backward's), S slots, P tested
+#   (pixel, instance) pairs, Pc contributing, HW pixels.
 def row_work(c):
     N, I, S, HW = c["N"], c["I"], c["S"], c["HW"]
     return {
@@ -64,10 +65,13 @@ def row_work(c):
         # L1 36 B per pixel; SSIM ~220 FLOP per pixel-channel
         "loss": (36.0 * HW, 220.0 * 3 * HW),
         "merge_bwd": (48.0 * 256 * S, 0.0),
-        # 7 FLOP per rejected pair, 55 per contributing pair; 36 B record written per instance
-        "render_bwd": (36.0 * I + 72.0 * I, 7.0 * (c["P_b"] - c["Pc_b"]) + 55.0 * c["Pc_b"]),
-        # 36 B per instance read + 36 B per Gaussian written
-        "pair_reduce": (36.0 * I + 36.0 * N, 0.0),
+        # 7 FLOP per rejected pair, 55 per contributing pair; per instance it visits
+        # 72 B read (value + record) and a 36 B gradient record written; 24 B per
+        # pixel per slot (T, last, dT, dC)
+        "render_bwd": (108.0 * c["Ib"] + 24.0 * 256 * S, 7.0 * (c["P_b"] - c["Pc_b"]) + 55.0 * c["Pc_b"]),
+        # the records (36 B per visited instance) and a bit per instance read, 36 B
+        # per Gaussian written
+        "pair_reduce": (36.0 * c["Ib"] + I / 8.0 + 36.0 * N, 0.0),
         # ~570 B and ~600 FLOP per Gaussian
         "project_bwd": (570.0 * N, 600.0 * N),
     }
@@ -540,7 +544,11 @@ def main():
     n_inst = int(st0.bins_struct.n_instances)
     n_slots = int(st0.bins["counters"][2].item())
     n_vis = int(st0.bins["counters"][0].item())
-    del st0
+    # instances the backward visits: those ahead of their slot's last contributor
+    last = st0.parts["last"][: n_slots * 256].view(n_slots, 256).to(torch.int64).amax(dim=1)
+    srange = st0.bins["slot_range"][: 2 * n_slots].view(n_slots, 2).to(torch.int64)
+    n_inst_bwd = int(torch.minimum(last, srange[:, 1] - srange[:, 0]).sum().item())
+    del st0, last, srange
 
     for _ in range(args.warmup):
         step()
@@ -574,7 +582,8 @@ def main():
     stages = {k: float(np.mean(v)) for k, v in stage_ms.items()}
 
     mpix = (W * H) / (ms_step * 1e-3) / 1e6
-    counts = dict(N=args.n, I=n_inst, S=n_slots, HW=W * H, P_f=n_eval, Pc_f=n_con, P_b=nb_eval, Pc_b=nb_con)
+    counts = dict(N=args.n, I=n_inst, Ib=n_inst_bwd, S=n_slots, HW=W * H, P_f=n_eval, Pc_f=n_con, P_b=nb_eval,
+                  Pc_b=nb_con)
     work = row_work(counts)
     traffic = measured_traffic()
     rows = {}
@@ -635,7 +644,7 @@ def main():
         "config": {"workload": "1M Gaussians SH3, 1600x1060, K=8 KD cells, L1+0.2(1-SSIM) fwd+bwd",
                    "gaussians": args.n, "width": W, "height": H, "cells": 1 << L, "eps_T": eps_T},
         "breakdown_ms": {k: round(v, 4) for k, v in stages.items()},
-        "counts": {"visible_pairs": n_vis, "instances": n_inst, "slots": n_slots},
+        "counts": {"visible_pairs": n_vis, "instances": n_inst, "instances_backward": n_inst_bwd, "slots": n_slots},
         "loss": round(float(lv0.item()), 6),
         "wall_s": round(wall, 3),
         "roofline": roof,
