@@ -124,6 +124,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
     __shared__ uint32_t sM[NB];
     __shared__ uint2 sR[NB];
     __shared__ uint32_t s_alive[4];
+    __shared__ uint32_t s_live[4];
     const uint32_t gt = tile_order[blockIdx.x];
     const uint32_t s0 = tile_slot[gt], s1 = tile_slot[gt + 1];
     if (s0 >= s1) return;
@@ -149,6 +150,25 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
     const int p = ly * 16 + lx;
 
     for (uint32_t slot = s0; slot < s1; ++slot) {
+        if (slot > s0) {
+            // once every pixel of the tile has stopped, the remaining slots are
+            // neutral: written without staging a record (P only decreases, so
+            // the tile stays stopped)
+            const uint64_t lv = __ballot(live);
+            if (lane == 0) s_live[w] = lv != 0ull ? 1u : 0u;
+            __syncthreads();
+            if ((s_live[0] | s_live[1] | s_live[2] | s_live[3]) == 0u) {
+                for (uint32_t sn = slot; sn < s1; ++sn) {
+                    float* on = outC + (size_t)sn * 768;
+                    on[p] = 0.f;
+                    on[256 + p] = 0.f;
+                    on[512 + p] = 0.f;
+                    outT[(size_t)sn * 256 + p] = 1.f;
+                    outLast[(size_t)sn * 256 + p] = 0u;
+                }
+                break;
+            }
+        }
         const uint32_t key = slot_key[slot];
         const int cell = V.cell_of_rank[key & ((1u << L) - 1u)];
         const uint32_t begin = slot_range[2 * slot], end = slot_range[2 * slot + 1];
