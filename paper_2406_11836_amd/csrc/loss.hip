@@ -259,29 +259,33 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __re
     }
 }
 
-__global__ __launch_bounds__(LS_THREADS) void k_loss_final(const float* __restrict__ part, int nb, float invN, float w,
+// The final sums of the block partials: one block of LF_THREADS threads, a
+// fixed order of additions for a given thread count (reproducible).
+static constexpr int LF_THREADS = 1024;
+
+__global__ __launch_bounds__(LF_THREADS) void k_loss_final(const float* __restrict__ part, int nb, float invN, float w,
                                                            float* __restrict__ loss) {
-    __shared__ double s_a[LS_THREADS], s_b[LS_THREADS];
+    __shared__ double s_a[LF_THREADS], s_b[LF_THREADS];
     double a = 0.0, b = 0.0;
     // the same order of additions per thread as one partial at a time; the
     // loads of eight steps are issued before their adds
     constexpr int U = 8;
     int k = threadIdx.x;
-    for (; k + (U - 1) * LS_THREADS < nb; k += U * LS_THREADS) {
+    for (; k + (U - 1) * LF_THREADS < nb; k += U * LF_THREADS) {
         float2 pv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) pv[u] = reinterpret_cast<const float2*>(part)[k + u * LS_THREADS];
+        for (int u = 0; u < U; ++u) pv[u] = reinterpret_cast<const float2*>(part)[k + u * LF_THREADS];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             a += pv[u].x;
             b += pv[u].y;
         }
     }
-    for (; k < nb; k += LS_THREADS) { a += part[2 * k]; b += part[2 * k + 1]; }
+    for (; k < nb; k += LF_THREADS) { a += part[2 * k]; b += part[2 * k + 1]; }
     s_a[threadIdx.x] = a;
     s_b[threadIdx.x] = b;
     __syncthreads();
-    for (int st = LS_THREADS / 2; st > 0; st >>= 1) {
+    for (int st = LF_THREADS / 2; st > 0; st >>= 1) {
         if (threadIdx.x < st) { s_a[threadIdx.x] += s_a[threadIdx.x + st]; s_b[threadIdx.x] += s_b[threadIdx.x + st]; }
         __syncthreads();
     }
@@ -323,7 +327,7 @@ rgs_status loss_launch(const float* image, const float* target, int H, int W, fl
                            invN, -ssim_w * invN, dimg);
         parts = (int)nt;
     }
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LS_THREADS), 0, s, part, parts, invN, ssim_w, loss);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LF_THREADS), 0, s, part, parts, invN, ssim_w, loss);
     return launch_check();
 }
 
