@@ -416,8 +416,11 @@ rgs_status rgs_render_partial_bwd(const rgs_partials_grad *dparts, const rgs_par
 /* The same in two calls (the backward's blend and its reduction, Sec. 3.4),
  * so that each can be timed on its own.  rgs_render_partial_bwd_records
  * writes the per-instance records into ws (same workspace and arguments as
- * above, minus d_proj); stats, if not NULL, points to two device uint64
- * counters incremented by the (pixel, instance) pairs tested (pixel inside
+ * above, minus d_proj): a record for each instance that some pixel of its
+ * slot reaches at or before its last contributor, marked in a bitmask by
+ * emission position in the same ws (the others count as zero); stats, if
+ * not NULL, points to two device uint64 counters incremented by the
+ * (pixel, instance) pairs tested (pixel inside
  * the rectangle, at or before its last contributor) and the contributing
  * pairs.  rgs_pair_reduce then sums each pair's records from the same ws into
  * d_proj ([9][V*N], as above). */
