@@ -107,6 +107,17 @@ static constexpr uint64_t RGS_NO_SPANS = ~0ull;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Work item of block b out of n: workgroups are handed to the eight XCDs in
+// turn (block b to XCD b mod 8), and each XCD has its own L2, so block b
+// takes item (b mod 8) q + min(b mod 8, n mod 8) + b / 8 (q = n / 8): every
+// XCD walks one contiguous band of items, and lines that neighbouring items
+// share (a halo, the ends of a run of writes) stay in one L2.  A bijection of
+// [0, n) for every n.
+__device__ __forceinline__ int xcd_band(int b, int n) {
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Wave64 sum reduction with DPP row operations; the total lands in lane 63.
 __device__ __forceinline__ float wave_sum_to_lane63(float v) {
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xb1, 0xf, 0xf, false)); // quad_perm [1,0,3,2]

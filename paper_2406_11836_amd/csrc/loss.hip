@@ -41,7 +41,8 @@ __global__ __launch_bounds__(LS_THREADS) void k_l1_only(const float* __restrict_
 // with the 5-pixel halo staged in LDS; both separable passes run from LDS.
 // (32x16 rather than 32x32: 25 KB of LDS per block instead of 41 KB, so that
 // five blocks share a CU instead of three and the passes of one block
-// overlap the loads of another.)
+// overlap the loads of another.)  Tiles are handed out in XCD bands: a tile's
+// halo rows were loaded by the tile row above it into the same L2.
 static constexpr int HALO = 5;
 static constexpr int TS = 32, TW = TS + 2 * HALO;       // output / staged columns (42)
 static constexpr int TSY = 16, TH = TSY + 2 * HALO;     // output / staged rows (26)
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
     __shared__ float hm[4][TH * TS];
     __shared__ float s_w[2][4];
     const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TSY - 1) / TSY;
-    const int b = blockIdx.x;
+    const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);  // neighbouring tiles on one XCD
     const int ch = b / (tiles_x * tiles_y);
     const int tt = b % (tiles_x * tiles_y);
     const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TSY;
@@ -169,8 +170,8 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
     if ((threadIdx.x & 63) == 0) { s_w[0][threadIdx.x >> 6] = l1; s_w[1][threadIdx.x >> 6] = ss; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = (s_w[0][0] + s_w[0][1]) + (s_w[0][2] + s_w[0][3]);
-        part[2 * blockIdx.x + 1] = (s_w[1][0] + s_w[1][1]) + (s_w[1][2] + s_w[1][3]);
+        part[2 * b] = (s_w[0][0] + s_w[0][1]) + (s_w[0][2] + s_w[0][3]);
+        part[2 * b + 1] = (s_w[1][0] + s_w[1][1]) + (s_w[1][2] + s_w[1][3]);
     }
 }
 
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __re
     __shared__ float sd[3][TH * TW];
     __shared__ float hm[3][TH * TS];
     const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TSY - 1) / TSY;
-    const int b = blockIdx.x;
+    const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);  // neighbouring tiles on one XCD
     const int ch = b / (tiles_x * tiles_y);
     const int tt = b % (tiles_x * tiles_y);
     const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TSY;
