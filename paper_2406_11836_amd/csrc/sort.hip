@@ -232,9 +232,11 @@ __device__ __forceinline__ int64_t rs_n(int64_t n, const uint32_t* n_dev) {
 
 // Blocks loop over tiles (with a device-side count the grid is capped and
 // sized for the largest possible count, so no block is launched only to exit);
-// a block's first tile comes from its XCD's band, so that the tiles that
-// write neighbouring parts of a digit's output run on one XCD and the cache
-// lines their runs share are completed in one L2.
+// the n-th tile a block takes (n = block + round * grid) is tile
+// xcd_band(n, tiles): with a grid that is a multiple of 8 (or a single
+// round) every XCD takes one contiguous band of tiles, the same number each,
+// so that the tiles that write neighbouring parts of a digit's output run on
+// one XCD and the cache lines their runs share are completed in one L2.
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n_host,
                                                         const uint32_t* __restrict__ n_dev, int shift,
                                                         uint32_t* __restrict__ hist, int ntiles) {
@@ -242,7 +244,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restri
     const int64_t n = rs_n(n_host, n_dev);
     // with a device count the table is [256][tiles in use]
     if (n_dev) ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
-    for (int tile = xcd_band((int)blockIdx.x, (int)gridDim.x); tile < ntiles; tile += gridDim.x) {
+    for (int nth = blockIdx.x; nth < ntiles; nth += gridDim.x) {
+        const int tile = xcd_band(nth, ntiles);
         s_h[threadIdx.x] = 0;
         __syncthreads();
         const int64_t base = (int64_t)tile * RS_TILE;
@@ -315,12 +318,13 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
     if (n_dev) ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (xcd_band((int)blockIdx.x, (int)gridDim.x) < ntiles) {  // the block has a tile (uniform per block)
+    if ((int)blockIdx.x < ntiles) {  // the block has a tile (uniform per block)
         uint32_t ex;
         block_excl_scan_256(dtot[threadIdx.x], s_wave, &ex);
         s_dbase[threadIdx.x] = ex;
     }
-    for (int tile = xcd_band((int)blockIdx.x, (int)gridDim.x); tile < ntiles; tile += gridDim.x) {
+    for (int nth = blockIdx.x; nth < ntiles; nth += gridDim.x) {
+        const int tile = xcd_band(nth, ntiles);
         for (int k = threadIdx.x; k < 4 * 256; k += RS_THREADS) (&s_cnt[0][0])[k] = 0;
         __syncthreads();
 
