@@ -621,9 +621,9 @@ def main():
     row_kernels = {"project": ["k_project"],
                    "bin_sort": ["k_vis_count", "k_vis_compact", "k_rs_hist", "k_rs_colscan", "k_rs_scatter",
                                 "k_pair_counts", "k_scan_reduce", "k_scan_apply", "k_emit", "k_slot_bounds",
-                                "k_slot_compact", "k_class_count", "k_class_place"],
+                                "k_slot_build", "k_class_place"],
                    "render_fwd": ["k_render_fwd"], "merge": ["k_merge_fwd"],
-                   "loss": ["k_ssim_fwd_tiled", "k_ssim_bwd_tiled", "k_loss_final"],
+                   "loss": ["k_ssim_fwd_tiled", "k_ssim_bwd_tiled"],
                    "merge_bwd": ["k_merge_bwd"], "render_bwd": ["k_render_bwd"],
                    "pair_reduce": ["k_wave_first", "k_pair_seg", "k_pair_gather"],
                    "project_bwd": ["k_project_bwd_geo", "k_project_bwd_sh"]}

@@ -120,16 +120,47 @@ __global__ __launch_bounds__(BN_THREADS) void k_view_keys(const uint32_t* __rest
 }
 
 // Per ordered pair: its rank, and its instance count (for the offsets scan).
+// A block takes RGS_SCAN_TILE consecutive pairs, a tile of that scan, and
+// writes the tile's count sum to tsum[tile], so the scan skips its reduce
+// pass.  All blocks also fill the slot table's empty marks.
+static constexpr int PC_ITEMS = (int)(RGS_SCAN_TILE / BN_THREADS);
+static_assert(PC_ITEMS * BN_THREADS == RGS_SCAN_TILE, "a block covers one scan tile");
+
 __global__ __launch_bounds__(BN_THREADS) void k_pair_counts(const uint32_t* __restrict__ pair_src,
-                                                            const uint32_t* __restrict__ n_dev, int64_t m_max,
+                                                            const uint32_t* __restrict__ n_dev,
                                                             const uint32_t* __restrict__ count,
                                                             int32_t* __restrict__ pair_rank, uint32_t* __restrict__ cnt,
-                                                            uint32_t* __restrict__ fill, int64_t n_fill) {
+                                                            uint32_t* __restrict__ tsum, uint32_t* __restrict__ fill,
+                                                            int64_t n_fill) {
+    __shared__ uint32_t s_w[BN_THREADS / 64];
     const int64_t np = (int64_t)*n_dev;
-    for (int64_t r = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x; r < np; r += (int64_t)gridDim.x * BN_THREADS) {
-        const uint32_t s = pair_src[r];
-        pair_rank[s] = (int32_t)r;
-        cnt[r] = count[s];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t tile = blockIdx.x; tile * RGS_SCAN_TILE < np; tile += gridDim.x) {
+        const int64_t base = tile * RGS_SCAN_TILE;
+        // all loads first (a lane past the end reads the last pair and adds nothing)
+        uint32_t sv[PC_ITEMS], cv[PC_ITEMS];
+#pragma unroll
+        for (int k = 0; k < PC_ITEMS; ++k) {
+            const int64_t i = base + k * BN_THREADS + threadIdx.x;
+            sv[k] = pair_src[i < np ? i : np - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < PC_ITEMS; ++k) cv[k] = count[sv[k]];
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < PC_ITEMS; ++k) {
+            const int64_t i = base + k * BN_THREADS + threadIdx.x;
+            if (i < np) {
+                pair_rank[sv[k]] = (int32_t)i;
+                cnt[i] = cv[k];
+                acc += cv[k];
+            }
+        }
+        acc = wave_sum_u32(acc);
+        if (lane == 0) s_w[w] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) tsum[tile] = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+        __syncthreads();  // s_w is reused by the next tile
     }
     // the slot table's empty marks, needed after the instance sort
     for (int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x; i < n_fill; i += (int64_t)gridDim.x * BN_THREADS)
@@ -318,12 +349,15 @@ __global__ __launch_bounds__(BN_THREADS) void k_fill_u32(uint32_t* __restrict__ 
     if (i < m) p[i] = v;
 }
 
-// Slot boundaries on the dense (tile, rank) table.
+// Slot boundaries on the dense (tile, rank) table; block 0 also clears the
+// size-class counters of the launch orders (launched even without instances).
 // (A key at or past the table's end would mean an emission bug; it is skipped
 // rather than written out of bounds.)
 __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __restrict__ keys,
                                                             const uint32_t* __restrict__ n_dev, int64_t dense,
-                                                            uint32_t* __restrict__ dstart, uint32_t* __restrict__ dend) {
+                                                            uint32_t* __restrict__ dstart, uint32_t* __restrict__ dend,
+                                                            uint32_t* __restrict__ cls) {
+    if (blockIdx.x == 0 && threadIdx.x < 128) cls[threadIdx.x] = 0u;
     const int64_t n_inst = (int64_t)*n_dev;
     // a thread takes SB_ITEMS keys BN_THREADS apart per step; every key and
     // its two neighbours are loaded (coalesced, overlapping in cache) before
@@ -350,32 +384,6 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __re
     }
 }
 
-// Compaction of the non-empty entries, and the first slot of every tile
-// (the scan value at its first entry; entry `dense` gets the slot count).
-// Block 0 also clears the size-class counters of the launch orders.
-__global__ __launch_bounds__(BN_THREADS) void k_slot_compact(const uint32_t* __restrict__ dstart,
-                                                             const uint32_t* __restrict__ dend,
-                                                             const uint32_t* __restrict__ sidx, int64_t m, int L,
-                                                             const uint32_t* __restrict__ n_slots,
-                                                             uint32_t* __restrict__ slot_key,
-                                                             uint32_t* __restrict__ slot_range,
-                                                             uint32_t* __restrict__ tile_slot, uint32_t* __restrict__ cls) {
-    if (blockIdx.x == 0 && threadIdx.x < 128) cls[threadIdx.x] = 0u;
-    int64_t e = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (e > m) return;
-    if (e == m) {
-        tile_slot[m >> L] = *n_slots;
-        return;
-    }
-    const uint32_t s = sidx[e];
-    if ((e & ((1 << L) - 1)) == 0) tile_slot[e >> L] = s;
-    const uint32_t b = dstart[e];
-    if (b == 0xffffffffu) return;
-    slot_key[s] = (uint32_t)e;
-    slot_range[2 * s] = b;
-    slot_range[2 * s + 1] = dend[e];
-}
-
 // Launch orders, largest first by size class floor(log2 len): the slots
 // (len = instances; the backward's order) and the tiles (len = instances of
 // all the tile's slots, which are contiguous in the sorted list; the
@@ -389,22 +397,116 @@ __device__ __forceinline__ uint32_t tile_len(const uint32_t* __restrict__ tile_s
     return s0 < s1 ? slot_range[2 * (s1 - 1) + 1] - slot_range[2 * s0] : 0u;
 }
 
-__global__ __launch_bounds__(BN_THREADS) void k_class_count(const uint32_t* __restrict__ slot_range,
-                                                            const uint32_t* __restrict__ n_slots,
-                                                            const uint32_t* __restrict__ tile_slot, int64_t T,
-                                                            uint32_t* __restrict__ cls) {
+// The slot table from the dense (tile, rank) table, RGS_SCAN_TILE entries
+// per block, in one pass: an entry is a slot iff its start is not ~0, and its
+// slot index is the number of slots before it (the tile sums of the marks,
+// summed over the earlier tiles of the dense table when fold = 1, else
+// already scanned, plus the block's own exclusive scan).  Writes slot_key,
+// slot_range, tile_slot (a tile's first slot; entry T = the slot count) and,
+// with fold = 1, the slot count; counts the size classes of the slots and of
+// all T tiles (a tile's length: its instances, from its first slot's start to
+// its last slot's end) into cls[0..31] and cls[64..95].
+static constexpr int SL_ITEMS = (int)(RGS_SCAN_TILE / BN_THREADS);
+// Up to this many tiles a block sums the earlier tiles' marks itself.
+static constexpr int64_t SLOT_FOLD_TILES = 1024;
+
+__global__ __launch_bounds__(BN_THREADS) void k_slot_build(const uint32_t* __restrict__ dstart,
+                                                           const uint32_t* __restrict__ dend,
+                                                           const uint32_t* __restrict__ partial, int fold, int64_t dense,
+                                                           int L, uint32_t* __restrict__ n_slots,
+                                                           uint32_t* __restrict__ slot_key,
+                                                           uint32_t* __restrict__ slot_range,
+                                                           uint32_t* __restrict__ tile_slot, uint32_t* __restrict__ cls) {
+    __shared__ uint32_t s_st[RGS_SCAN_TILE], s_en[RGS_SCAN_TILE];
     __shared__ uint32_t s_c[64];
-    if (threadIdx.x < 64) s_c[threadIdx.x] = 0u;
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * BN_THREADS + threadIdx.x;
-    if (i < (int64_t)*n_slots) {
-        const uint32_t len = slot_range[2 * i + 1] - slot_range[2 * i];
-        atomicAdd(&s_c[31 - __clz(len | 1u)], 1u);
+    __shared__ uint32_t s_w[BN_THREADS / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t base = (int64_t)blockIdx.x * RGS_SCAN_TILE;
+    const int nloc = (int)((dense - base) < RGS_SCAN_TILE ? (dense - base) : RGS_SCAN_TILE);
+    const int K = 1 << L;
+    if (t < 64) s_c[t] = 0u;
+    // the first earlier tile sum of the thread is loaded with the entries
+    const uint32_t p0 = (fold && (uint32_t)t < blockIdx.x) ? partial[t] : 0u;
+    {  // coalesced loads (all first), into LDS
+        uint32_t a[SL_ITEMS], b[SL_ITEMS];
+#pragma unroll
+        for (int k = 0; k < SL_ITEMS; ++k) {
+            const int e = k * BN_THREADS + t;
+            const int64_t i = base + (e < nloc ? e : nloc - 1);
+            a[k] = dstart[i];
+            b[k] = dend[i];
+        }
+#pragma unroll
+        for (int k = 0; k < SL_ITEMS; ++k) {
+            const int e = k * BN_THREADS + t;
+            s_st[e] = e < nloc ? a[k] : 0xffffffffu;
+            s_en[e] = b[k];
+        }
     }
-    if (i < T) atomicAdd(&s_c[32 + 31 - __clz(tile_len(tile_slot, slot_range, i) | 1u)], 1u);
+    uint32_t toff;
+    if (fold) {
+        uint32_t a = p0;
+        for (uint32_t u = t + BN_THREADS; u < blockIdx.x; u += BN_THREADS) a += partial[u];
+        a = wave_sum_u32(a);
+        if (lane == 0) s_w[w] = a;
+        __syncthreads();
+        toff = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+        __syncthreads();  // s_w is reused by the scan
+    } else {
+        toff = partial[blockIdx.x];
+        __syncthreads();
+    }
+    // thread t takes entries t * SL_ITEMS .. + SL_ITEMS - 1
+    const int e0 = t * SL_ITEMS;
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < SL_ITEMS; ++j) c += s_st[e0 + j] != 0xffffffffu ? 1u : 0u;
+    const uint32_t inc = wave_incl_scan(c);
+    if (lane == 63) s_w[w] = inc;
     __syncthreads();
-    if (threadIdx.x < 64 && s_c[threadIdx.x]) atomicAdd(&cls[threadIdx.x < 32 ? threadIdx.x : threadIdx.x + 32],
-                                                        s_c[threadIdx.x]);
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < BN_THREADS / 64; ++k) {
+        before += k < w ? s_w[k] : 0u;
+        tot += s_w[k];
+    }
+    uint32_t run = toff + before + inc - c;
+#pragma unroll
+    for (int j = 0; j < SL_ITEMS; ++j) {
+        const int e = e0 + j;
+        if (e >= nloc) break;
+        const int64_t ge = base + e;
+        if ((ge & (K - 1)) == 0) {
+            // the tile's first slot, and its length over its K entries (in LDS: a
+            // tile never crosses a block, K dividing RGS_SCAN_TILE)
+            tile_slot[ge >> L] = run;
+            uint32_t lo = 0xffffffffu, hi = 0u;
+            for (int q = 0; q < K && e + q < nloc; ++q) {
+                const uint32_t a = s_st[e + q];
+                if (a != 0xffffffffu) {
+                    lo = lo < a ? lo : a;
+                    hi = s_en[e + q];
+                }
+            }
+            const uint32_t tl = lo != 0xffffffffu ? hi - lo : 0u;
+            atomicAdd(&s_c[32 + 31 - __clz(tl | 1u)], 1u);
+        }
+        const uint32_t a = s_st[e];
+        if (a != 0xffffffffu) {
+            const uint32_t b = s_en[e];
+            slot_key[run] = (uint32_t)ge;
+            slot_range[2 * run] = a;
+            slot_range[2 * run + 1] = b;
+            atomicAdd(&s_c[31 - __clz((b - a) | 1u)], 1u);
+            ++run;
+        }
+    }
+    if (base + nloc == dense && t == 0) {
+        tile_slot[dense >> L] = toff + tot;
+        if (fold) *n_slots = toff + tot;
+    }
+    __syncthreads();
+    if (t < 64 && s_c[t]) atomicAdd(&cls[t < 32 ? t : t + 32], s_c[t]);
 }
 
 // Items are placed class by class, classes in decreasing order: every block
@@ -463,7 +565,6 @@ size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t 
     c.take<uint64_t>(capacity + 1);   // instance vals alt
     c.take<uint32_t>(dense + 1);      // dense start
     c.take<uint32_t>(dense + 1);      // dense end
-    c.take<uint32_t>(dense + 1);      // slot index
     c.take<uint32_t>(128);            // slot and tile size classes
     const int64_t big = m > capacity ? m : capacity;
     const int64_t big2 = big > dense ? big : dense;
@@ -493,7 +594,6 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     uint64_t* vals_alt = c.take<uint64_t>(bins->capacity + 1);
     uint32_t* dstart = c.take<uint32_t>(dense + 1);
     uint32_t* dend = c.take<uint32_t>(dense + 1);
-    uint32_t* sidx = c.take<uint32_t>(dense + 1);
     uint32_t* cls = c.take<uint32_t>(128);
     const int64_t big = m > bins->capacity ? m : bins->capacity;
     const int64_t big2 = big > dense ? big : dense;
@@ -532,13 +632,14 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     // 2. instance offsets per ordered pair; the instance count goes to the host
     // (with the empty marks of the dense slot table: dstart = ~0)
     if (m > 0)
-        hipLaunchKernelGGL(k_pair_counts, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], m, proj->count,
-                           bins->pair_rank, flag, dstart, dense);
+        hipLaunchKernelGGL(k_pair_counts, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], proj->count,
+                           bins->pair_rank, flag, reinterpret_cast<uint32_t*>(sws), dstart, dense);
     else
         hipLaunchKernelGGL(k_fill_u32, grid(dense), dim3(BN_THREADS), 0, s, dstart, dense, 0xffffffffu);
     // with the tail of pair_off and, without a host copy, the capacity guard
     const ScanTail tail{cnt, sync ? 0 : 1, bins->capacity};
-    if ((st = exclusive_scan_u32_dev(flag, bins->pair_off, DevN{&cnt[0], m, 1, 1}, m, &cnt[1], sws, s, 0, &tail)) !=
+    // (k_pair_counts wrote the tile sums; without pairs the scan reads none)
+    if ((st = exclusive_scan_u32_dev(flag, bins->pair_off, DevN{&cnt[0], m, 1, 1}, m, &cnt[1], sws, s, 0, &tail, 1)) !=
         RGS_OK)
         return st;
     int64_t n_inst, slot_bound;
@@ -569,20 +670,28 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     else st = radix_sort_u32_u64_dev(bins->keys, bins->vals, keys_alt, vals_alt, &cnt[1], n_inst, key_bits, rws, s);
     if (st != RGS_OK) return st;
 
-    // 4. slots
-    if (n_inst > 0)
-        hipLaunchKernelGGL(k_slot_bounds, dgrid(n_inst), dim3(BN_THREADS), 0, s, bins->keys, &cnt[1], dense, dstart, dend);
-    if ((st = exclusive_scan_u32(dstart, sidx, dense, &cnt[2], sws, s, 1)) != RGS_OK) return st;
-    hipLaunchKernelGGL(k_slot_compact, grid(dense + 1), dim3(BN_THREADS), 0, s, dstart, dend, sidx, dense, L, &cnt[2],
-                       bins->slot_key, bins->slot_range, bins->tile_slot, cls);
+    // 4. slots (k_slot_bounds also clears the size-class counters): the tile
+    // sums of the slot marks, then the slot table and the class counts
+    hipLaunchKernelGGL(k_slot_bounds, dgrid(n_inst), dim3(BN_THREADS), 0, s, bins->keys, &cnt[1], dense, dstart, dend,
+                       cls);
+    if (dense > 0) {
+        uint32_t* dpart = reinterpret_cast<uint32_t*>(sws);
+        const int64_t dtiles = (dense + RGS_SCAN_TILE - 1) / RGS_SCAN_TILE;
+        const bool fold = dtiles <= SLOT_FOLD_TILES;
+        if ((st = scan_tile_reduce(dstart, dense, 1, dpart, s)) != RGS_OK) return st;
+        if (!fold && (st = scan_tile_sums(dpart, DevN{nullptr, dense, 1, 1}, RGS_SCAN_TILE, &cnt[2], s)) != RGS_OK)
+            return st;
+        hipLaunchKernelGGL(k_slot_build, dim3((unsigned)dtiles), dim3(BN_THREADS), 0, s, dstart, dend, dpart,
+                           fold ? 1 : 0, dense, L, &cnt[2], bins->slot_key, bins->slot_range, bins->tile_slot, cls);
+    } else {
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(BN_THREADS), 0, s, bins->tile_slot, (int64_t)1, 0u);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(BN_THREADS), 0, s, &cnt[2], (int64_t)1, 0u);
+    }
     // 5. launch orders of the slots and the tiles (largest size class first)
     const int64_t nord = slot_bound > total_tiles ? slot_bound : total_tiles;
-    if (nord > 0) {
-        hipLaunchKernelGGL(k_class_count, grid(nord), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], bins->tile_slot,
-                           total_tiles, cls);
+    if (nord > 0)
         hipLaunchKernelGGL(k_class_place, grid(nord), dim3(BN_THREADS), 0, s, bins->slot_range, &cnt[2], bins->tile_slot,
                            total_tiles, cls, bins->slot_order, bins->tile_order);
-    }
     return launch_check();
 }
 

@@ -217,16 +217,22 @@ struct ScanTail {
     int guard;
     int64_t capacity;
 };
+// Elements per tile of the scans below.
+static constexpr int64_t RGS_SCAN_TILE = 4096;
 // out[i] = sum_{j<i} in[j]; if total != nullptr, *total (device) = sum of all.
 // marks = 1 scans (in[j] != ~0) instead of in[j].
 rgs_status exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, void* ws,
                               hipStream_t s, int marks = 0);
 // The same over the first dn.get() elements (n_max bounds the grid).
+// sums_ready = 1: the caller has written the sums of the RGS_SCAN_TILE-element
+// tiles to the first words of ws (the reduce pass is skipped).
 rgs_status exclusive_scan_u32_dev(const uint32_t* in, uint32_t* out, DevN dn, int64_t n_max, uint32_t* total, void* ws,
-                                  hipStream_t s, int marks = 0, const ScanTail* tail = nullptr);
+                                  hipStream_t s, int marks = 0, const ScanTail* tail = nullptr, int sums_ready = 0);
 // Block-level tile scan pieces, for callers that produce the tile sums themselves:
 // exclusive scan (in place) of the sums of the first ceil(dn.get() / tile) tiles.
 rgs_status scan_tile_sums(uint32_t* partial, DevN dn, int64_t tile, uint32_t* total, hipStream_t s);
+// ... and the sums of the RGS_SCAN_TILE-element tiles of in[0, n) (marks as above).
+rgs_status scan_tile_reduce(const uint32_t* in, int64_t n, int marks, uint32_t* partial, hipStream_t s);
 size_t radix_ws_bytes(int64_t n);
 // Stable LSD sort of (key, value) by key bits [0, bits); the result ends in
 // keys/vals (the alt buffers are scratch of the same size).

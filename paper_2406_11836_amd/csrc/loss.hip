@@ -175,15 +175,72 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_fwd_tiled(const float* __re
     }
 }
 
+// The final sums of the block partials in one block of NT threads: a fixed
+// order of additions for a given NT (reproducible).  s_a, s_b: NT doubles of
+// LDS each.
+template <int NT>
+__device__ __forceinline__ void loss_final_sums(const float* __restrict__ part, int nb, float invN, float w,
+                                                float* __restrict__ loss, double* s_a, double* s_b) {
+    double a = 0.0, b = 0.0;
+    // the same order of additions per thread as one partial at a time; the
+    // loads of eight steps are issued before their adds
+    constexpr int U = 8;
+    int k = threadIdx.x;
+    for (; k + (U - 1) * NT < nb; k += U * NT) {
+        float2 pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pv[u] = reinterpret_cast<const float2*>(part)[k + u * NT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a += pv[u].x;
+            b += pv[u].y;
+        }
+    }
+    for (; k < nb; k += NT) { a += part[2 * k]; b += part[2 * k + 1]; }
+    s_a[threadIdx.x] = a;
+    s_b[threadIdx.x] = b;
+    __syncthreads();
+    for (int st = NT / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) { s_a[threadIdx.x] += s_a[threadIdx.x + st]; s_b[threadIdx.x] += s_b[threadIdx.x + st]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double l = s_a[0] * (double)invN;
+        if (w != 0.f) l += (double)w * (1.0 - s_b[0] * (double)invN);
+        *loss = (float)l;
+    }
+}
+
+// The final sums after the L1-only loss.
+static constexpr int LF_THREADS = 1024;
+
+__global__ __launch_bounds__(LF_THREADS) void k_loss_final(const float* __restrict__ part, int nb, float invN, float w,
+                                                           float* __restrict__ loss) {
+    __shared__ double s_a[LF_THREADS], s_b[LF_THREADS];
+    loss_final_sums<LF_THREADS>(part, nb, invN, w, loss, s_a, s_b);
+}
+
 // Backward: convolve the three derivative maps with the (symmetric) window
 // and combine: dL/dx = sign(x - y)/N + sc (w*g_mu + 2 x w*g_xx + y w*g_xy).
+// Block 0 adds up the forward's block partials into the loss (dispatched
+// first, it runs beside the tiles instead of as a launch of its own);
+// blocks 1.. take the tiles.
 __global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __restrict__ x, const float* __restrict__ y,
                                                                const float* __restrict__ d3, int H, int W, Win11 win,
-                                                               float invN, float sc, float* __restrict__ dx) {
-    __shared__ float sd[3][TH * TW];
+                                                               float invN, float sc, float* __restrict__ dx,
+                                                               const float* __restrict__ part, float ssim_w,
+                                                               float* __restrict__ loss) {
+    __shared__ __align__(16) float sd[3][TH * TW];
     __shared__ float hm[3][TH * TS];
+    static_assert(sizeof(sd) >= 2 * LS_THREADS * sizeof(double), "final sums reuse the staging array");
     const int tiles_x = (W + TS - 1) / TS, tiles_y = (H + TSY - 1) / TSY;
-    const int b = xcd_band((int)blockIdx.x, (int)gridDim.x);  // neighbouring tiles on one XCD
+    const int ntiles = (int)gridDim.x - 1;
+    if (blockIdx.x == 0) {
+        double* s2 = reinterpret_cast<double*>(&sd[0][0]);
+        loss_final_sums<LS_THREADS>(part, ntiles, invN, ssim_w, loss, s2, s2 + LS_THREADS);
+        return;
+    }
+    const int b = xcd_band((int)blockIdx.x - 1, ntiles);  // neighbouring tiles on one XCD
     const int ch = b / (tiles_x * tiles_y);
     const int tt = b % (tiles_x * tiles_y);
     const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TSY;
@@ -260,43 +317,6 @@ __global__ __launch_bounds__(LS_THREADS) void k_ssim_bwd_tiled(const float* __re
     }
 }
 
-// The final sums of the block partials: one block of LF_THREADS threads, a
-// fixed order of additions for a given thread count (reproducible).
-static constexpr int LF_THREADS = 1024;
-
-__global__ __launch_bounds__(LF_THREADS) void k_loss_final(const float* __restrict__ part, int nb, float invN, float w,
-                                                           float* __restrict__ loss) {
-    __shared__ double s_a[LF_THREADS], s_b[LF_THREADS];
-    double a = 0.0, b = 0.0;
-    // the same order of additions per thread as one partial at a time; the
-    // loads of eight steps are issued before their adds
-    constexpr int U = 8;
-    int k = threadIdx.x;
-    for (; k + (U - 1) * LF_THREADS < nb; k += U * LF_THREADS) {
-        float2 pv[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) pv[u] = reinterpret_cast<const float2*>(part)[k + u * LF_THREADS];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            a += pv[u].x;
-            b += pv[u].y;
-        }
-    }
-    for (; k < nb; k += LF_THREADS) { a += part[2 * k]; b += part[2 * k + 1]; }
-    s_a[threadIdx.x] = a;
-    s_b[threadIdx.x] = b;
-    __syncthreads();
-    for (int st = LF_THREADS / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) { s_a[threadIdx.x] += s_a[threadIdx.x + st]; s_b[threadIdx.x] += s_b[threadIdx.x + st]; }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        double l = s_a[0] * (double)invN;
-        if (w != 0.f) l += (double)w * (1.0 - s_b[0] * (double)invN);
-        *loss = (float)l;
-    }
-}
-
 size_t loss_ws_bytes(int H, int W) {
     const int64_t m = 3 * (int64_t)H * W;
     const int64_t nb = (m + LS_THREADS - 1) / LS_THREADS;
@@ -318,17 +338,15 @@ rgs_status loss_launch(const float* image, const float* target, int H, int W, fl
     double g[11], gs = 0.0;
     for (int k = 0; k < 11; ++k) { g[k] = exp(-((k - 5) * (k - 5)) / (2.0 * 1.5 * 1.5)); gs += g[k]; }
     for (int k = 0; k < 11; ++k) win.w[k] = (float)(g[k] / gs);
-    int parts;
     if (ssim_w == 0.f) {
         hipLaunchKernelGGL(k_l1_only, dim3((unsigned)nb), dim3(LS_THREADS), 0, s, image, target, m, invN, dimg, part);
-        parts = (int)nb;
+        hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LF_THREADS), 0, s, part, (int)nb, invN, ssim_w, loss);
     } else {
         hipLaunchKernelGGL(k_ssim_fwd_tiled, dim3((unsigned)nt), dim3(LS_THREADS), 0, s, image, target, H, W, win, d3, part);
-        hipLaunchKernelGGL(k_ssim_bwd_tiled, dim3((unsigned)nt), dim3(LS_THREADS), 0, s, image, target, d3, H, W, win,
-                           invN, -ssim_w * invN, dimg);
-        parts = (int)nt;
+        // the final sums in its block 0
+        hipLaunchKernelGGL(k_ssim_bwd_tiled, dim3((unsigned)nt + 1u), dim3(LS_THREADS), 0, s, image, target, d3, H, W,
+                           win, invN, -ssim_w * invN, dimg, part, ssim_w, loss);
     }
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(LF_THREADS), 0, s, part, parts, invN, ssim_w, loss);
     return launch_check();
 }
 

@@ -22,6 +22,7 @@ static constexpr int SCAN_THREADS = 256;
 static constexpr unsigned DEV_GRID = 2048;
 static constexpr int SCAN_ITEMS = 16;
 static constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+static_assert(SCAN_TILE == RGS_SCAN_TILE, "callers producing tile sums use RGS_SCAN_TILE");
 
 __device__ __forceinline__ int skew(int i) { return i + (i >> 5); }
 
@@ -188,6 +189,14 @@ size_t scan_ws_bytes(int64_t n) {
     return (size_t)(tiles + 1) * sizeof(uint32_t) + 256;
 }
 
+rgs_status scan_tile_reduce(const uint32_t* in, int64_t n, int marks, uint32_t* partial, hipStream_t s) {
+    if (n <= 0) return RGS_OK;
+    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(SCAN_THREADS), 0, s, in, DevN{nullptr, n, 1, 1}, marks,
+                       partial);
+    return launch_check();
+}
+
 rgs_status scan_tile_sums(uint32_t* partial, DevN dn, int64_t tile, uint32_t* total, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, dn, tile, total);
     return launch_check();
@@ -198,13 +207,14 @@ rgs_status scan_tile_sums(uint32_t* partial, DevN dn, int64_t tile, uint32_t* to
 static constexpr int64_t SCAN_FOLD_TILES = 1024;
 
 rgs_status exclusive_scan_u32_dev(const uint32_t* in, uint32_t* out, DevN dn, int64_t n_max, uint32_t* total, void* ws,
-                                  hipStream_t s, int marks, const ScanTail* tail) {
+                                  hipStream_t s, int marks, const ScanTail* tail, int sums_ready) {
     uint32_t* partial = reinterpret_cast<uint32_t*>(ws);
     const ScanTail tl = tail ? *tail : ScanTail{nullptr, 0, 0};
     const int64_t tiles = (n_max + SCAN_TILE - 1) / SCAN_TILE;
     const bool fold = tiles <= SCAN_FOLD_TILES;
     const unsigned grid = (unsigned)(tiles < 1 ? 1 : (dn.p && tiles > DEV_GRID ? DEV_GRID : tiles));
-    if (n_max > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(SCAN_THREADS), 0, s, in, dn, marks, partial);
+    if (n_max > 0 && !sums_ready)
+        hipLaunchKernelGGL(k_scan_reduce, dim3(grid), dim3(SCAN_THREADS), 0, s, in, dn, marks, partial);
     if (!fold) hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, dn, (int64_t)SCAN_TILE, total);
     hipLaunchKernelGGL(k_scan_apply, dim3(grid), dim3(SCAN_THREADS), 0, s, in, dn, marks, partial, fold ? 1 : 0,
                        total, tl, out);

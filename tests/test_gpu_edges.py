@@ -372,3 +372,23 @@ def test_sixteen_views_sixty_four_cells(rast):
     assert worst <= 2e-4
     alone = rast.forward(dp, kd, [cams[7]], EPS_T)
     assert torch.equal(alone.image, st.images()[7][0].reshape(-1))
+
+
+def test_slot_table_beyond_fold(rast):
+    """A dense (tile, rank) table of more than 1024 scan tiles (16 views of
+    1088x1056 at L = 6: 71,808 tiles, 4.6M entries) takes the slot build's
+    path with a separate scan of the tile sums; each view rendered alone (a
+    small table, the folded path) must be bit-identical to it in the batch."""
+    p = scenes.scene_clusters(20000, seed=67, D=2)
+    cams = [scenes.orbit_camera(4.0, 0.4 * k, np.radians(10 + 3 * k), 1088, 1056, z_near=0.2, bg=(0.1, 0.02 * k, 0.3))
+            for k in range(16)]
+    dp = device_params(p)
+    kd = rast.kd_partition(dp, 6)
+    st = rast.forward(dp, kd, cams, EPS_T)
+    tiles = 16 * 68 * 66
+    assert (tiles << 6) > 1024 * 4096
+    n_slots = int(st.bins["counters"][2].item())
+    assert 0 < n_slots <= tiles << 6
+    for v in (0, 5, 15):
+        alone = rast.forward(dp, kd, [cams[v]], EPS_T)
+        assert torch.equal(alone.image, st.images()[v][0].reshape(-1))
