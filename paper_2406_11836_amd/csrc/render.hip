@@ -597,12 +597,13 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
 //  1. k_pair_seg: a wave takes 64 consecutive records; the pairs covering
 //     them come from the wave's first pair (k_wave_first) and one coalesced
 //     load of the next 64 pair offsets; a segmented inclusive scan (fixed tree of
-//     shuffles) sums each pair's records within the wave.  Pairs complete in
-//     the wave are written to psum[rank]; the wave's first segment (pair
-//     begun before it) and last segment (pair going on after it) are kept as
-//     wave partials.
+//     shuffles) sums each pair's records within the wave.  The wave's first
+//     segment (pair begun before it) and last segment (pair going on after
+//     it) are kept as wave partials; every pair gets its psum[rank] entry in
+//     the wave where it ends: its sum if it lies in that wave, else the
+//     first and last wave it spans (a flag in the entry's last word).
 //  2. k_pair_gather: thread per (view, Gaussian): zero if culled, else the
-//     pair's sum from psum, or, for a pair spanning several waves, its tail
+//     pair's psum entry, or, for a pair spanning several waves, its tail
 //     partial + whole-wave partials + head partial, in instance order.
 // first_pair[w] = the pair holding instance 64 w: each pair writes the waves
 // that start inside it (one thread per pair, grid-stride over the device count).
@@ -691,13 +692,19 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
     const bool seg_end = valid && (!next_valid || pos_next != pos);
     if (!seg_end) return;
     const uint32_t r = r0 + (uint32_t)pos;
-    const bool began_before = (pos > 0 ? b_at : b_r0) < j0;
+    const int64_t pb = pos > 0 ? b_at : b_r0;  // the pair's instances: [pb, e_at)
+    const bool began_before = pb < j0;
     const bool goes_on = e_at > j0 + 64;
     const float4 o0 = make_float4(v[0], v[1], v[2], v[3]), o1 = make_float4(v[4], v[5], v[6], v[7]),
                  o2 = make_float4(v[8], 0.f, 0.f, 0.f);
-    if (!began_before && !goes_on) {
+    if (!goes_on) {
         float4* q = reinterpret_cast<float4*>(psum + (size_t)r * PS_REC);
-        q[0] = o0; q[1] = o1; q[2] = o2;
+        if (!began_before) {
+            q[0] = o0; q[1] = o1; q[2] = o2;
+        } else {  // spans waves pb / 64 .. (e_at - 1) / 64: its sum is in the wave partials
+            q[2] = make_float4(0.f, __uint_as_float((uint32_t)(pb >> 6)), __uint_as_float((uint32_t)((e_at - 1) >> 6)),
+                               __uint_as_float(1u));
+        }
     }
     if (began_before) {
         float4* q = reinterpret_cast<float4*>(wpart + ((size_t)w * 2 + 0) * PS_REC);
@@ -720,23 +727,29 @@ __device__ __forceinline__ void acc_rec(const float* __restrict__ p, float4& a0,
 __global__ __launch_bounds__(256) void k_pair_gather(const float* __restrict__ psum, const float* __restrict__ wpart,
                                                      const uint32_t* __restrict__ count,
                                                      const int32_t* __restrict__ pair_rank,
-                                                     const uint32_t* __restrict__ pair_off,
-                                                     const uint32_t* __restrict__ n_pairs, int64_t m,
+                                                     const uint32_t* __restrict__ counters, int64_t m,
                                                      float* __restrict__ dproj) {
     const int64_t sidx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (sidx >= m) return;
     float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0;
     float a8 = 0.f;
     const int32_t r = count[sidx] > 0u ? pair_rank[sidx] : -1;
-    if (r >= 0 && (uint32_t)r < n_pairs[0]) {  // a pass that ran out of capacity has no pairs
-        const uint32_t b = pair_off[r], e = pair_off[r + 1];
-        const uint32_t wb = b >> 6, we = (e - 1u) >> 6;
-        if (wb == we) {
-            acc_rec(psum + (size_t)r * PS_REC, a0, a1, a8);
+    if (r >= 0 && (uint32_t)r < counters[0]) {  // a pass that ran out of capacity has no pairs
+        const float4* q = reinterpret_cast<const float4*>(psum + (size_t)r * PS_REC);
+        const float4 x = q[0], y = q[1], z = q[2];
+        if (__float_as_uint(z.w) == 0u) {  // the pair lies in one wave: its sum
+            a0 = x;
+            a1 = y;
+            a8 = z.x;
         } else {
-            acc_rec(wpart + ((size_t)wb * 2 + 1) * PS_REC, a0, a1, a8);      // tail of the first wave
-            for (uint32_t w = wb + 1; w < we; ++w) acc_rec(wpart + (size_t)w * 2 * PS_REC, a0, a1, a8);  // whole waves
-            acc_rec(wpart + (size_t)we * 2 * PS_REC, a0, a1, a8);           // head of the last wave
+            const uint32_t wb = __float_as_uint(z.y), we = __float_as_uint(z.z);
+            // the range the pair reduction wrote lies in the instance array (checked all the same)
+            const uint32_t nw = (uint32_t)(((uint64_t)counters[1] + 63u) >> 6);
+            if (wb < we && we < nw) {
+                acc_rec(wpart + ((size_t)wb * 2 + 1) * PS_REC, a0, a1, a8);  // tail of the first wave
+                for (uint32_t w = wb + 1; w < we; ++w) acc_rec(wpart + (size_t)w * 2 * PS_REC, a0, a1, a8);  // whole waves
+                acc_rec(wpart + (size_t)we * 2 * PS_REC, a0, a1, a8);       // head of the last wave
+            }
         }
     }
     dproj[0 * m + sidx] = a0.x;
@@ -831,7 +844,7 @@ rgs_status pair_reduce_launch(const rgs_bins* bins, const rgs_projected* proj, i
     RGS_LAUNCH_CHECK();
     if (m > 0)
         hipLaunchKernelGGL(k_pair_gather, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, w.psum, w.wpart,
-                           proj->count, bins->pair_rank, bins->pair_off, bins->counters, m, dproj);
+                           proj->count, bins->pair_rank, bins->counters, m, dproj);
     return launch_check();
 }
 
