@@ -34,6 +34,7 @@ steps/s), --partition (KD tree against the fixed grid, the paper's subsets).
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -564,6 +565,10 @@ def main():
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    # no cyclic garbage collection inside the three passes: a collection
+    # pause on the host can leave the stream idle between two launches
+    gc.collect()
+    gc.disable()
     wall0 = time.perf_counter()
     t_start.record()
     last = None
@@ -594,6 +599,7 @@ def main():
         step(marks=marks)
         all_marks.append(marks)
     torch.cuda.synchronize()
+    gc.enable()
     marked_ms = []
     for marks in all_marks:
         for (a, ea), (b, eb) in zip(marks[:-1], marks[1:]):
