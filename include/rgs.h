@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 5
+#define RGS_ABI_VERSION 6
 #define RGS_TILE 16       /* screen tiles are 16 x 16 pixels */
 #define RGS_MAX_L 6       /* K = 2^L <= 64 cells */
 #define RGS_MAX_VIEWS 16  /* views per call */
@@ -348,6 +348,21 @@ rgs_status rgs_render_partial(const rgs_projected *proj, int64_t n, const rgs_bi
                               const rgs_camera *cams, int32_t n_views, const void *views_dev,
                               const rgs_kdtree *kd, float eps_T, const rgs_partials *out,
                               uint64_t *stats, rgs_stream stream);
+
+/* The partial render and the merge of Eq. 5 in one launch, for a caller
+ * that renders every cell of a tile itself (one GPU): writes the same
+ * partials as rgs_render_partial, and image / T_final exactly as
+ * rgs_merge_partials would write them from those partials (the render block
+ * folds each slot into the merged pixel in the same order and arithmetic as
+ * the merge, so the results are bit-identical; the merge's second read of
+ * the partials is saved).  image: concatenated [3][H][W] per view; T_final:
+ * concatenated [H][W]; both device memory owned by the caller, disjoint from
+ * every other buffer of the call (RGS_E_ARG otherwise).  Other arguments,
+ * stats and errors as rgs_render_partial. */
+rgs_status rgs_render_partial_merged(const rgs_projected *proj, int64_t n, const rgs_bins *bins,
+                                     const rgs_camera *cams, int32_t n_views, const void *views_dev,
+                                     const rgs_kdtree *kd, float eps_T, const rgs_partials *out,
+                                     float *image, float *T_final, uint64_t *stats, rgs_stream stream);
 
 /* ------------------------------------------------------------------ */
 /* Merge (Eq. 5)                                                        */

@@ -87,6 +87,8 @@ _SIGS = {
     "rgs_bin_sort": (i32, [P(Projected), i64, P(Camera), i32, vp, i32, P(Bins), P(i64), vp, sz, vp]),
     "rgs_bin_sort_async": (i32, [P(Projected), i64, P(Camera), i32, vp, i32, P(Bins), vp, sz, vp]),
     "rgs_render_partial": (i32, [P(Projected), i64, P(Bins), P(Camera), i32, vp, P(KdTree), f32, P(Partials), vp, vp]),
+    "rgs_render_partial_merged": (i32, [P(Projected), i64, P(Bins), P(Camera), i32, vp, P(KdTree), f32, P(Partials),
+                                        vp, vp, vp, vp]),
     "rgs_merge_partials": (i32, [P(Partials), P(Bins), P(Camera), i32, vp, vp, vp, vp]),
     "rgs_loss_workspace": (sz, [i32, i32]),
     "rgs_loss_l1_ssim": (i32, [vp, vp, i32, i32, f32, vp, vp, vp, sz, vp]),

@@ -32,8 +32,11 @@ rgs_status group_by_cell(const rgs_gaussians* in, const rgs_kdtree* kd, int L, c
                          void* ws, size_t ws_bytes, hipStream_t s);
 rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const ViewTable* vt_dev, int L, int64_t total_tiles,
                     rgs_bins* bins, int64_t* n_required, bool sync, void* ws, size_t ws_bytes, hipStream_t s);
+// image / T_final non-null: the merged image of the partials as well (the
+// merge's fold, run in the render block)
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
-                             float eps_T, const rgs_partials* out, uint64_t* stats, int64_t total_tiles, hipStream_t s);
+                             float eps_T, const rgs_partials* out, uint64_t* stats, int64_t total_tiles, hipStream_t s,
+                             float* image = nullptr, float* T_final = nullptr);
 size_t render_bwd_ws_bytes(int64_t capacity);
 rgs_status render_bwd_records_launch(const rgs_partials_grad* dparts, const rgs_partials* parts, const rgs_bins* bins,
                                      const rgs_projected* proj, const ViewTable* vt, const rgs_kdtree* kd, void* ws,
@@ -478,6 +481,26 @@ rgs_status rgs_render_partial(const rgs_projected* proj, int64_t n, const rgs_bi
     if (!disjoint(concat(parts_spans(out, bins), {{stats, 16}}), ins)) return RGS_E_ARG;
     return render_fwd_launch(proj, bins, reinterpret_cast<const ViewTable*>(views_dev), kd, eps_T, out, stats,
                              rgs_total_tiles(cams, n_views), S(stream));
+}
+
+rgs_status rgs_render_partial_merged(const rgs_projected* proj, int64_t n, const rgs_bins* bins,
+                                     const rgs_camera* cams, int32_t n_views, const void* views_dev,
+                                     const rgs_kdtree* kd, float eps_T, const rgs_partials* out, float* image,
+                                     float* T_final, uint64_t* stats, rgs_stream stream) {
+    if (!proj_ok(proj) || n < 0 || !bins_ok(bins) || !cams_ok(cams, n_views) || !views_dev || !kd || !kd->box_lo ||
+        !kd->box_hi || !out || !out->C || !out->T || !out->last || !(eps_T >= 0.f) || eps_T >= 1.f || !image ||
+        !T_final)
+        return RGS_E_ARG;
+    const size_t m = (size_t)n_views * (size_t)(n > 0 ? n : 0);
+    const int K = 1 << kd->L;
+    const size_t px = pixels_of(cams, n_views);
+    const Spans ins = concat(concat(proj_spans(proj, m), bins_spans(bins, m, total_tiles_of(cams, n_views))),
+                             {{views_dev, sizeof(ViewTable)}, {kd->box_lo, (size_t)12 * K}, {kd->box_hi, (size_t)12 * K}});
+    // outputs pairwise disjoint and disjoint from the inputs
+    if (!disjoint(concat(parts_spans(out, bins), {{stats, 16}, {image, 12 * px}, {T_final, 4 * px}}), ins))
+        return RGS_E_ARG;
+    return render_fwd_launch(proj, bins, reinterpret_cast<const ViewTable*>(views_dev), kd, eps_T, out, stats,
+                             rgs_total_tiles(cams, n_views), S(stream), image, T_final);
 }
 
 rgs_status rgs_merge_partials(const rgs_partials* parts, const rgs_bins* bins, const rgs_camera* cams, int32_t n_views,

@@ -118,7 +118,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
                                                     const float* __restrict__ box_hi, float eps_T,
                                                     float* __restrict__ outC, float* __restrict__ outT,
                                                     uint32_t* __restrict__ outLast,
-                                                    unsigned long long* __restrict__ stats) {
+                                                    unsigned long long* __restrict__ stats,
+                                                    float* __restrict__ image, float* __restrict__ T_final) {
     constexpr int NB = 256;
     __shared__ float4 sA[NB], sB[NB], sCl[NB];
     __shared__ uint32_t sM[NB];
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
     __shared__ uint32_t s_live[4];
     const uint32_t gt = tile_order[blockIdx.x];
     const uint32_t s0 = tile_slot[gt], s1 = tile_slot[gt + 1];
-    if (s0 >= s1) return;
+    if (s0 >= s1 && !image) return;
     const int L = vt->L, K = 1 << L;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int v = view_of_tile(vt, gt);
@@ -136,6 +137,9 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
     const int lx = (w & 1) * 8 + (lane & 7), ly = (w >> 1) * 8 + (lane >> 3);
     const int px = tx * 16 + lx, py = ty * 16 + ly;
+    // merged image (image != null): the fold of Eq. 5 over the tile's slots in
+    // their order, as the merge does it from the stored partials
+    float M0 = 0.f, M1 = 0.f, M2 = 0.f;
     const float fxp = (float)px + 0.5f;
     const float dxp = (fxp - V.cx) / V.fx, dyp = ((float)py + 0.5f - V.cy) / V.fy;
     const float D0 = (V.R[0] * dxp + V.R[3] * dyp) + V.R[6];
@@ -255,7 +259,18 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
         outLast[(size_t)slot * 256 + p] = last;
         // the walk stopped in this cell: every later cell is neutral here
         if (live && T < thr) live = false;
+        M0 = fmaf(P, C0, M0);
+        M1 = fmaf(P, C1, M1);
+        M2 = fmaf(P, C2, M2);
         P *= T;
+    }
+    if (image && px < V.W && py < V.H) {
+        const size_t HW = (size_t)V.W * V.H, pix = (size_t)py * V.W + px;
+        float* img = image + 3 * (size_t)V.pix_offset;
+        img[pix] = fmaf(P, V.bg[0], M0);
+        img[HW + pix] = fmaf(P, V.bg[1], M1);
+        img[2 * HW + pix] = fmaf(P, V.bg[2], M2);
+        T_final[V.pix_offset + pix] = P;
     }
     if (STATS) {
         unsigned long long e = n_eval, c = n_con;
@@ -272,7 +287,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float* __restrict__ re
 }
 
 rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, const ViewTable* vt, const rgs_kdtree* kd,
-                             float eps_T, const rgs_partials* out, uint64_t* stats, int64_t total_tiles, hipStream_t s) {
+                             float eps_T, const rgs_partials* out, uint64_t* stats, int64_t total_tiles, hipStream_t s,
+                             float* image, float* T_final) {
     if (total_tiles <= 0) return RGS_OK;
     // a pixel stops once its merged transmittance falls below max(eps_T,
     // 2^-100): the backward recovers the transmittance before each
@@ -282,13 +298,12 @@ rgs_status render_fwd_launch(const rgs_projected* proj, const rgs_bins* bins, co
     if (stats)
         hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)total_tiles), dim3(256), 0, s, proj->rec, bins->vals,
                            bins->slot_key, bins->slot_range, bins->tile_slot, bins->tile_order, vt, kd->box_lo, kd->box_hi,
-                           eps_T, out->C,
-                           out->T, out->last, reinterpret_cast<unsigned long long*>(stats));
+                           eps_T, out->C, out->T, out->last, reinterpret_cast<unsigned long long*>(stats), image,
+                           T_final);
     else
         hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)total_tiles), dim3(256), 0, s, proj->rec, bins->vals,
                            bins->slot_key, bins->slot_range, bins->tile_slot, bins->tile_order, vt, kd->box_lo, kd->box_hi,
-                           eps_T, out->C,
-                           out->T, out->last, nullptr);
+                           eps_T, out->C, out->T, out->last, nullptr, image, T_final);
     return launch_check();
 }
 

@@ -4,7 +4,7 @@
 and calls the C ABI in order:
 
   forward:  rgs_views_upload -> rgs_project_sh -> rgs_bin_sort
-            -> rgs_render_partial -> rgs_merge_partials
+            -> rgs_render_partial_merged (or rgs_render_partial -> rgs_merge_partials)
   backward: rgs_merge_partials_bwd -> rgs_render_partial_bwd
             -> rgs_project_sh_bwd
 
@@ -221,8 +221,10 @@ class Rasterizer:
     # ------------------------------------------------------------ forward
     def forward(self, params, kd: KD, cams, eps_T: float = 5e-5, stats: torch.Tensor | None = None,
                 marks: list | None = None, cell_visible=None, no_sync: bool = False, cull: bool = False,
-                cells: int = L.RGS_CELLS_EXACT) -> FwdState:
+                cells: int = L.RGS_CELLS_EXACT, merged: bool = True) -> FwdState:
         """stats: optional int64 device tensor [2] (evaluated, contributing pairs), incremented.
+        merged: the partial render writes the merged image too (rgs_render_partial_merged);
+        False runs rgs_render_partial, then rgs_merge_partials (bit-identical results).
         marks: optional list receiving (stage, event) pairs at stage ends.
         cell_visible: optional per-view uint64 masks of the KD cells that may reach each view;
         cull=True computes them with rgs_cell_visibility (changes no output).
@@ -308,15 +310,22 @@ class Rasterizer:
         parts = dict(C=self._buf("C", slot_cap * 768, torch.float32), T=self._buf("T", slot_cap * 256, torch.float32),
                      last=self._buf("last", slot_cap * 256, torch.int32))
         pt = L.Partials(parts["C"].data_ptr(), parts["T"].data_ptr(), parts["last"].data_ptr())
-        L.check("rgs_render_partial", lib.rgs_render_partial(C.byref(ps), n, C.byref(bs), cam_arr, V, _p(views),
-                                                             C.byref(ks), float(eps_T), C.byref(pt), _p(stats), stream))
-        _mark(marks, "render_fwd")
         npix = sum(int(c["W"]) * int(c["H"]) for c in cams)
         image = self._buf("image", 3 * npix, torch.float32)
         T_final = self._buf("T_final", npix, torch.float32)
-        L.check("rgs_merge_partials", lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam_arr, V, _p(views), _p(image),
-                                                             _p(T_final), stream))
-        _mark(marks, "merge")
+        if merged:
+            L.check("rgs_render_partial_merged",
+                    lib.rgs_render_partial_merged(C.byref(ps), n, C.byref(bs), cam_arr, V, _p(views), C.byref(ks),
+                                                  float(eps_T), C.byref(pt), _p(image), _p(T_final), _p(stats), stream))
+            _mark(marks, "render_fwd")
+        else:
+            L.check("rgs_render_partial", lib.rgs_render_partial(C.byref(ps), n, C.byref(bs), cam_arr, V, _p(views),
+                                                                 C.byref(ks), float(eps_T), C.byref(pt), _p(stats),
+                                                                 stream))
+            _mark(marks, "render_fwd")
+            L.check("rgs_merge_partials", lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam_arr, V, _p(views),
+                                                                 _p(image), _p(T_final), stream))
+            _mark(marks, "merge")
         return FwdState(n=n, cams=list(cams), cam_arr=cam_arr, kd=kd, views=views, proj=proj, bins=bins,
                         bins_struct=bs, parts=parts, image=image, T_final=T_final, eps_T=eps_T, total_tiles=T,
                         slot_capacity=slot_cap, keep=[ws, n_inst])

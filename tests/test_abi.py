@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_status(lib):
-    assert lib.rgs_abi_version() == 5
+    assert lib.rgs_abi_version() == 6
     assert lib.rgs_status_string(0) == b"ok"
     assert lib.rgs_status_string(-2) == b"buffer capacity too small"
 

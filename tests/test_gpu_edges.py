@@ -374,6 +374,30 @@ def test_sixteen_views_sixty_four_cells(rast):
     assert torch.equal(alone.image, st.images()[7][0].reshape(-1))
 
 
+def test_merged_render_matches_separate_merge(rast):
+    """rgs_render_partial_merged writes the partials rgs_render_partial writes
+    and the image / T_final that rgs_merge_partials folds from them, bit for
+    bit: three ragged views (tiles without any instance among them), K = 8
+    and K = 64."""
+    p = scenes.scene_clusters(20000, seed=71, D=2)
+    sizes = [(200, 136), (96, 80), (33, 17)]
+    cams = [scenes.orbit_camera(4.0, 0.7 * k, np.radians(12 + 5 * k), W, H, z_near=0.2, bg=(0.2, 0.1 * k, 0.3))
+            for k, (W, H) in enumerate(sizes)]
+    dp = device_params(p)
+    for L in (3, 6):
+        kd = rast.kd_partition(dp, L)
+        a = rast.forward(dp, kd, cams, EPS_T, merged=True)
+        ia, ta = a.image.clone(), a.T_final.clone()
+        n = int(a.bins["counters"][2].item())
+        pa = {k: v[: n * (768 if k == "C" else 256)].clone() for k, v in a.parts.items()}
+        b = rast.forward(dp, kd, cams, EPS_T, merged=False)
+        assert int(b.bins["counters"][2].item()) == n
+        assert torch.equal(ia, b.image) and torch.equal(ta, b.T_final)
+        for k, v in pa.items():
+            assert torch.equal(v, b.parts[k][: v.numel()])
+        # some tile of these views has no slot (background only)
+        assert bool((ta == 1.0).any())
+
 def test_slot_table_beyond_fold(rast):
     """A dense (tile, rank) table of more than 1024 scan tiles (16 views of
     1088x1056 at L = 6: 71,808 tiles, 4.6M entries) takes the slot build's
