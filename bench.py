@@ -556,6 +556,12 @@ def main():
     n_inst_bwd = int(torch.minimum(last, srange[:, 1] - srange[:, 0]).sum().item())
     del st0, last, srange
 
+    # no cyclic garbage collection from the warm-up to the end of the three
+    # passes: a collection pause on the host can leave the stream idle between
+    # two launches (and a pause right before the timed region lets the clocks
+    # drop for its first steps)
+    gc.collect()
+    gc.disable()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -565,10 +571,6 @@ def main():
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    # no cyclic garbage collection inside the three passes: a collection
-    # pause on the host can leave the stream idle between two launches
-    gc.collect()
-    gc.disable()
     wall0 = time.perf_counter()
     t_start.record()
     last = None

@@ -172,7 +172,9 @@ typedef struct {
     uint32_t *slot_key;     /* [slot_capacity] key of each slot */
     uint32_t *slot_range;   /* [slot_capacity][2] begin, end into keys/vals */
     uint32_t *tile_slot;    /* [total_tiles+1] first slot of each global tile (slots of a tile are in view order) */
-    uint32_t *slot_order;   /* [slot_capacity] slots by decreasing size class (the backward's launch order) */
+    uint32_t *slot_order;   /* [slot_capacity] slots by decreasing size class of their instance count (the
+                               backward launches its slots by the instances it visits instead, ordered in its
+                               workspace from the forward's `last`) */
     uint32_t *tile_order;   /* [total_tiles] tiles by decreasing size class of their instance count (the forward's
                                launch order) */
     uint32_t *counters;     /* [4]: pairs, instances, slots, required instances if over capacity (async; else 0);
@@ -437,8 +439,11 @@ rgs_status rgs_render_partial_bwd(const rgs_partials_grad *dparts, const rgs_par
  * not NULL, points to two device uint64 counters incremented by the
  * (pixel, instance) pairs tested (pixel inside
  * the rectangle, at or before its last contributor) and the contributing
- * pairs.  rgs_pair_reduce then sums each pair's records from the same ws into
- * d_proj ([9][V*N], as above). */
+ * pairs.  Its blocks are launched by decreasing size class of the instances
+ * each slot is walked over (the largest `last` of its pixels; slots without
+ * a contribution are not launched), an order it builds in ws from
+ * parts->last.  rgs_pair_reduce then sums each pair's records from the same
+ * ws into d_proj ([9][V*N], as above). */
 rgs_status rgs_render_partial_bwd_records(const rgs_partials_grad *dparts, const rgs_partials *parts,
                                           const rgs_bins *bins, const rgs_projected *proj, int64_t n,
                                           const rgs_camera *cams, int32_t n_views, const void *views_dev,

@@ -399,7 +399,7 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
                                                     const uint32_t* __restrict__ slot_key,
                                                     const uint32_t* __restrict__ slot_range,
                                                     const uint32_t* __restrict__ slot_order,
-                                                    const uint32_t* __restrict__ counters,
+                                                    const uint32_t* __restrict__ n_launch,
                                                     const ViewTable* __restrict__ vt, const float* __restrict__ box_lo,
                                                     const float* __restrict__ box_hi, const float* __restrict__ partT,
                                                     const uint32_t* __restrict__ partLast, const float* __restrict__ dC,
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
     __shared__ float sG[2][NB][9];
     __shared__ uint32_t s_max[2];
     __shared__ uint64_t s_wrote[2];  // per wave: the batch's instances it wrote half sums for
-    if (blockIdx.x >= counters[2]) return;
+    if (blockIdx.x >= *n_launch) return;
     const uint32_t slot = slot_order[blockIdx.x];
     const int L = vt->L, K = 1 << L;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -786,8 +786,11 @@ size_t render_bwd_ws_bytes(int64_t capacity) {
     const size_t rec = c * RD_REC * sizeof(float), ps = c * PS_REC * sizeof(float);
     const size_t nw = (c + 63) / 64;
     const size_t wp = nw * 2 * PS_REC * sizeof(float);
+    const size_t tw = ((c + 31) / 32 + 64) * sizeof(uint32_t);  // bitmask + launch count
+    const size_t tab = (c + 63) / 64 * 32 * sizeof(uint32_t);       // launch-order class counts per 64 slots
     return ((rec + 255) & ~size_t(255)) + ((ps + 255) & ~size_t(255)) + ((wp + 255) & ~size_t(255)) +
-           ((nw * sizeof(uint32_t) + 255) & ~size_t(255)) + (c + 31) / 32 * sizeof(uint32_t) + 256;
+           ((nw * sizeof(uint32_t) + 255) & ~size_t(255)) + ((tw + 255) & ~size_t(255)) +
+           2 * ((c * sizeof(uint32_t) + 255) & ~size_t(255)) + ((tab + 255) & ~size_t(255)) + 256;
 }
 
 struct BwdWs {
@@ -795,6 +798,10 @@ struct BwdWs {
     uint32_t* first_pair;
     uint32_t* touched;  // bit j: instance j (emission position) has a record
     size_t touched_words;
+    uint32_t* wcls;     // the number of slots launched (after the bitmask)
+    uint32_t* work;     // per slot: instances the backward visits (its largest `last`)
+    uint32_t* order;    // the backward's launch order
+    uint32_t* wtab;     // [blocks of SW_SLOTS slots][32] class counts
 };
 
 __global__ __launch_bounds__(256) void k_clear_words(uint32_t* __restrict__ p, int64_t n) {
@@ -815,7 +822,132 @@ static BwdWs carve_bwd(const rgs_bins* bins, void* ws) {
     w.touched = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(w.first_pair) +
                                             ((nw * sizeof(uint32_t) + 255) & ~size_t(255)));
     w.touched_words = (c + 31) / 32;
+    w.wcls = w.touched + w.touched_words;
+    const size_t tw = ((c + 31) / 32 + 64) * sizeof(uint32_t);
+    w.work = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(w.touched) + ((tw + 255) & ~size_t(255)));
+    w.order = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(w.work) + ((c * sizeof(uint32_t) + 255) & ~size_t(255)));
+    w.wtab = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(w.order) + ((c * sizeof(uint32_t) + 255) & ~size_t(255)));
     return w;
+}
+
+// The backward's launch order: the slots by decreasing size class
+// floor(log2 w) of the instances the backward visits (w = the largest `last`
+// over the slot's pixels: it walks instances 0 .. w - 1), so that the
+// heaviest blocks start first; a slot with w = 0 (no contribution) is not
+// launched.  Two passes without global atomics (which serialise on a handful
+// of class counters): k_slot_work, SW_SLOTS slots per block, a wave per slot
+// at a time (256 `last` values, four per lane), stores w and the block's
+// class counts as one row of a table; k_slot_place, the same SW_SLOTS slots
+// per block, derives every class's start and the block's offset in it from
+// the table and places its slots (the order inside a class is the launch
+// order only and affects no result).
+static constexpr int SW_SLOTS = 64;
+static constexpr int SW_CHUNK = 16;  // slots per wave whose loads are issued together
+static_assert(SW_SLOTS % (4 * SW_CHUNK) == 0, "a block's four waves take whole chunks");
+static_assert(SW_SLOTS == 64, "render_bwd_ws_bytes sizes the class table for 64 slots per row");
+
+// Largest u32 of the wave, into lane 63 (DPP row operations, as the sums
+// above; a lane a broadcast does not reach keeps its value: max with 0).
+__device__ __forceinline__ uint32_t wave_max_to_lane63(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false));  // row_ror:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false));  // row_ror:8
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return v;
+}
+
+// (The same launch clears the record bitmask, grid-stride.)
+__global__ __launch_bounds__(256) void k_slot_work(const uint32_t* __restrict__ partLast,
+                                                   const uint32_t* __restrict__ counters, uint32_t* __restrict__ work,
+                                                   uint32_t* __restrict__ wtab, uint32_t* __restrict__ touched,
+                                                   int64_t touched_words) {
+    __shared__ uint32_t s_c[32];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < touched_words; i += (int64_t)gridDim.x * 256)
+        touched[i] = 0u;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t ns = (int64_t)counters[2];
+    const int64_t base = (int64_t)blockIdx.x * SW_SLOTS + wv * (SW_SLOTS / 4);
+    for (int k0 = 0; k0 < SW_SLOTS / 4; k0 += SW_CHUNK) {
+        // all loads first (a slot past the count reads slot 0 and is not stored;
+        // this launch has at least one slot of capacity)
+        uint4 v[SW_CHUNK];
+#pragma unroll
+        for (int k = 0; k < SW_CHUNK; ++k) {
+            const int64_t slot = base + k0 + k;
+            v[k] = reinterpret_cast<const uint4*>(partLast + (slot < ns ? slot : 0) * 256)[lane];
+        }
+#pragma unroll
+        for (int k = 0; k < SW_CHUNK; ++k) {
+            const int64_t slot = base + k0 + k;
+            const uint32_t m = wave_max_to_lane63(max(max(v[k].x, v[k].y), max(v[k].z, v[k].w)));
+            if (lane == 63 && slot < ns) {
+                work[slot] = m;
+                if (m) atomicAdd(&s_c[31 - __clz(m)], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) wtab[(size_t)blockIdx.x * 32 + threadIdx.x] = s_c[threadIdx.x];
+}
+
+// n_launch: the number of launched slots (written by block 0).
+__global__ __launch_bounds__(256) void k_slot_place(const uint32_t* __restrict__ work,
+                                                    const uint32_t* __restrict__ counters,
+                                                    const uint32_t* __restrict__ wtab, uint32_t* __restrict__ n_launch,
+                                                    uint32_t* __restrict__ order) {
+    __shared__ uint32_t s_tot[8][32], s_bef[8][32], s_base[32], s_c[32];
+    const int t = threadIdx.x, c = t & 31, g = t >> 5;
+    const int64_t ns = (int64_t)counters[2];
+    const int nblk = (int)((ns + SW_SLOTS - 1) / SW_SLOTS);
+    {  // the table's column c, rows g, g + 8, ...: all blocks, and the blocks before this one
+        uint32_t tot = 0, bef = 0;
+        for (int r0 = g; r0 < nblk; r0 += 64) {
+            uint32_t x[8];  // eight loads issued before their adds
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int r = r0 + 8 * k;
+                x[k] = r < nblk ? wtab[(size_t)r * 32 + c] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                tot += x[k];
+                bef += r0 + 8 * k < (int)blockIdx.x ? x[k] : 0u;
+            }
+        }
+        s_tot[g][c] = tot;
+        s_bef[g][c] = bef;
+    }
+    if (t < 32) s_c[t] = 0u;
+    __syncthreads();
+    if (t < 32) {
+        uint32_t tot = 0, bef = 0;
+        for (int k = 0; k < 8; ++k) {
+            tot += s_tot[k][t];
+            bef += s_bef[k][t];
+        }
+        s_tot[0][t] = tot;
+        s_bef[0][t] = bef;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int k = 31; k >= 0; --k) {
+            s_base[k] = run + s_bef[0][k];
+            run += s_tot[0][k];
+        }
+        if (blockIdx.x == 0) *n_launch = run;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * SW_SLOTS + t;
+    const uint32_t wk = (t < SW_SLOTS && i < ns) ? work[i] : 0u;
+    if (wk) {
+        const int k = 31 - __clz(wk);
+        order[s_base[k] + atomicAdd(&s_c[k], 1u)] = (uint32_t)i;
+    }
 }
 
 // The partial-render backward alone: per-instance records into the workspace.
@@ -823,21 +955,26 @@ rgs_status render_bwd_records_launch(const rgs_partials_grad* dparts, const rgs_
                                      const rgs_projected* proj, const ViewTable* vt, const rgs_kdtree* kd, void* ws,
                                      uint64_t* stats, int64_t slot_bound, hipStream_t s) {
     const BwdWs w = carve_bwd(bins, ws);
-    // no record yet (a fill kernel, not a memset: the call may be captured)
-    {
+    // no record yet: the bitmask is cleared by a fill kernel (not a memset:
+    // the call may be captured), with the launch order's first pass
+    if (slot_bound <= 0) {
         const int64_t nb = ((int64_t)w.touched_words + 255) / 256;
         hipLaunchKernelGGL(k_clear_words, dim3((unsigned)(nb < 1024 ? (nb > 0 ? nb : 1) : 1024)), dim3(256), 0, s,
                            w.touched, (int64_t)w.touched_words);
+        return launch_check();
     }
-    if (slot_bound <= 0) return launch_check();
+    const unsigned nblk = (unsigned)((slot_bound + SW_SLOTS - 1) / SW_SLOTS);
+    hipLaunchKernelGGL(k_slot_work, dim3(nblk), dim3(256), 0, s, parts->last, bins->counters, w.work, w.wtab, w.touched,
+                       (int64_t)w.touched_words);
+    hipLaunchKernelGGL(k_slot_place, dim3(nblk), dim3(256), 0, s, w.work, bins->counters, w.wtab, w.wcls, w.order);
     if (stats)
         hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
-                           bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
+                           bins->slot_key, bins->slot_range, w.order, w.wcls, vt, kd->box_lo, kd->box_hi,
                            parts->T, parts->last, dparts->dC, dparts->dT, w.records, w.touched,
                            reinterpret_cast<unsigned long long*>(stats));
     else
         hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
-                           bins->slot_key, bins->slot_range, bins->slot_order, bins->counters, vt, kd->box_lo, kd->box_hi,
+                           bins->slot_key, bins->slot_range, w.order, w.wcls, vt, kd->box_lo, kd->box_hi,
                            parts->T, parts->last, dparts->dC, dparts->dT, w.records, w.touched, nullptr);
     return launch_check();
 }
