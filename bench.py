@@ -632,8 +632,8 @@ def main():
                                 "k_slot_build", "k_class_place"],
                    "render_fwd": ["k_render_fwd"],
                    "loss": ["k_ssim_fwd_tiled", "k_ssim_bwd_tiled"],
-                   "merge_bwd": ["k_merge_bwd"], "render_bwd": ["k_render_bwd"],
-                   "pair_reduce": ["k_wave_first", "k_pair_seg", "k_pair_gather"],
+                   "merge_bwd": ["k_merge_bwd"], "render_bwd": ["k_slot_work", "k_slot_place", "k_render_bwd"],
+                   "pair_reduce": ["k_pair_seg", "k_pair_gather"],
                    "project_bwd": ["k_project_bwd_geo", "k_project_bwd_sh"]}
     for name, ks in row_kernels.items():
         if traffic and all(k in traffic for k in ks):

@@ -443,7 +443,9 @@ rgs_status rgs_render_partial_bwd(const rgs_partials_grad *dparts, const rgs_par
  * each slot is walked over (the largest `last` of its pixels; slots without
  * a contribution are not launched), an order it builds in ws from
  * parts->last.  rgs_pair_reduce then sums each pair's records from the same
- * ws into d_proj ([9][V*N], as above). */
+ * ws into d_proj ([9][V*N], as above), with the per-64-instance pair lookup
+ * the records call also left there (so it must follow a records call on the
+ * same bins and ws). */
 rgs_status rgs_render_partial_bwd_records(const rgs_partials_grad *dparts, const rgs_partials *parts,
                                           const rgs_bins *bins, const rgs_projected *proj, int64_t n,
                                           const rgs_camera *cams, int32_t n_views, const void *views_dev,

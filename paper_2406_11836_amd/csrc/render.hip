@@ -610,7 +610,8 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
 // pair are contiguous (emission order), so the sum is a segmented reduction
 // over the instance array, balanced over instances:
 //  1. k_pair_seg: a wave takes 64 consecutive records; the pairs covering
-//     them come from the wave's first pair (k_wave_first) and one coalesced
+//     them come from the wave's first pair (first_pair, written by the
+//     backward's records call along with its launch order) and one coalesced
 //     load of the next 64 pair offsets; a segmented inclusive scan (fixed tree of
 //     shuffles) sums each pair's records within the wave.  The wave's first
 //     segment (pair begun before it) and last segment (pair going on after
@@ -622,14 +623,20 @@ __global__ __launch_bounds__(128) void k_render_bwd(const float* __restrict__ re
 //     partial + whole-wave partials + head partial, in instance order.
 // first_pair[w] = the pair holding instance 64 w: each pair writes the waves
 // that start inside it (one thread per pair, grid-stride over the device count).
-__global__ __launch_bounds__(256) void k_wave_first(const uint32_t* __restrict__ pair_off,
-                                                    const uint32_t* __restrict__ counters,
-                                                    uint32_t* __restrict__ first_pair) {
+__device__ __forceinline__ void wave_first_pairs(const uint32_t* __restrict__ pair_off,
+                                                 const uint32_t* __restrict__ counters,
+                                                 uint32_t* __restrict__ first_pair) {
     const int64_t np = counters[0];
-    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < np; r += (int64_t)gridDim.x * 256) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < np; r += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t b = pair_off[r], e = pair_off[r + 1];
         for (uint32_t w = (b + 63u) >> 6; (w << 6) < e; ++w) first_pair[w] = (uint32_t)r;
     }
+}
+
+__global__ __launch_bounds__(256) void k_wave_first(const uint32_t* __restrict__ pair_off,
+                                                    const uint32_t* __restrict__ counters,
+                                                    uint32_t* __restrict__ first_pair) {
+    wave_first_pairs(pair_off, counters, first_pair);
 }
 
 __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ records,
@@ -858,14 +865,17 @@ __device__ __forceinline__ uint32_t wave_max_to_lane63(uint32_t v) {
     return v;
 }
 
-// (The same launch clears the record bitmask, grid-stride.)
+// (The same launch clears the record bitmask and writes the pair reduction's
+// first pair of every 64 instances, both grid-stride.)
 __global__ __launch_bounds__(256) void k_slot_work(const uint32_t* __restrict__ partLast,
                                                    const uint32_t* __restrict__ counters, uint32_t* __restrict__ work,
                                                    uint32_t* __restrict__ wtab, uint32_t* __restrict__ touched,
-                                                   int64_t touched_words) {
+                                                   int64_t touched_words, const uint32_t* __restrict__ pair_off,
+                                                   uint32_t* __restrict__ first_pair) {
     __shared__ uint32_t s_c[32];
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < touched_words; i += (int64_t)gridDim.x * 256)
         touched[i] = 0u;
+    wave_first_pairs(pair_off, counters, first_pair);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
     __syncthreads();
@@ -957,15 +967,20 @@ rgs_status render_bwd_records_launch(const rgs_partials_grad* dparts, const rgs_
     const BwdWs w = carve_bwd(bins, ws);
     // no record yet: the bitmask is cleared by a fill kernel (not a memset:
     // the call may be captured), with the launch order's first pass
+    // (and the pair reduction's first pair of every 64 instances, which it
+    // reads from this workspace)
     if (slot_bound <= 0) {
         const int64_t nb = ((int64_t)w.touched_words + 255) / 256;
         hipLaunchKernelGGL(k_clear_words, dim3((unsigned)(nb < 1024 ? (nb > 0 ? nb : 1) : 1024)), dim3(256), 0, s,
                            w.touched, (int64_t)w.touched_words);
+        const int64_t pb = (bins->capacity + 255) / 256;
+        hipLaunchKernelGGL(k_wave_first, dim3((unsigned)(pb < 2048 ? (pb > 0 ? pb : 1) : 2048)), dim3(256), 0, s,
+                           bins->pair_off, bins->counters, w.first_pair);
         return launch_check();
     }
     const unsigned nblk = (unsigned)((slot_bound + SW_SLOTS - 1) / SW_SLOTS);
     hipLaunchKernelGGL(k_slot_work, dim3(nblk), dim3(256), 0, s, parts->last, bins->counters, w.work, w.wtab, w.touched,
-                       (int64_t)w.touched_words);
+                       (int64_t)w.touched_words, bins->pair_off, w.first_pair);
     hipLaunchKernelGGL(k_slot_place, dim3(nblk), dim3(256), 0, s, w.work, bins->counters, w.wtab, w.wcls, w.order);
     if (stats)
         hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)slot_bound), dim3(128), 0, s, proj->rec, bins->vals,
@@ -986,10 +1001,8 @@ rgs_status pair_reduce_launch(const rgs_bins* bins, const rgs_projected* proj, i
     const int64_t m = (int64_t)n_views * n;
     // one wave per 64 instances up to the capacity; waves past the device-side
     // instance count return at once
+    // (the records call wrote first_pair)
     if (bins->capacity > 0) {
-        const int64_t pb = (bins->capacity + 255) / 256;
-        hipLaunchKernelGGL(k_wave_first, dim3((unsigned)(pb < 2048 ? pb : 2048)), dim3(256), 0, s, bins->pair_off,
-                           bins->counters, w.first_pair);
         hipLaunchKernelGGL(k_pair_seg, dim3((unsigned)((bins->capacity + 255) / 256)), dim3(256), 0, s, w.records,
                            w.touched, bins->pair_off, bins->counters, w.first_pair, w.psum, w.wpart);
     }
