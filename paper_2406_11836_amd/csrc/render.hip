@@ -31,6 +31,10 @@ namespace rgs {
 static constexpr int RD_BATCH = 64;
 static constexpr int RD_REC = 9;   // floats per backward record (36 bytes, read back contiguously)
 static constexpr int PS_REC = 12;  // floats per per-pair / per-wave sum (48 bytes, float4-aligned)
+// The backward's launch order: slots per block of its two passes, and the
+// size classes (half octaves of the instances a slot is walked over)
+static constexpr int SW_SLOTS = 64;
+static constexpr int SW_CLS = 64;
 
 struct SlotGeom {
     int v, px, py0, cell;
@@ -794,7 +798,7 @@ size_t render_bwd_ws_bytes(int64_t capacity) {
     const size_t nw = (c + 63) / 64;
     const size_t wp = nw * 2 * PS_REC * sizeof(float);
     const size_t tw = ((c + 31) / 32 + 64) * sizeof(uint32_t);  // bitmask + launch count
-    const size_t tab = (c + 63) / 64 * 32 * sizeof(uint32_t);       // launch-order class counts per 64 slots
+    const size_t tab = (c + SW_SLOTS - 1) / SW_SLOTS * SW_CLS * sizeof(uint32_t);  // launch-order class counts
     return ((rec + 255) & ~size_t(255)) + ((ps + 255) & ~size_t(255)) + ((wp + 255) & ~size_t(255)) +
            ((nw * sizeof(uint32_t) + 255) & ~size_t(255)) + ((tw + 255) & ~size_t(255)) +
            2 * ((c * sizeof(uint32_t) + 255) & ~size_t(255)) + ((tab + 255) & ~size_t(255)) + 256;
@@ -837,8 +841,8 @@ static BwdWs carve_bwd(const rgs_bins* bins, void* ws) {
     return w;
 }
 
-// The backward's launch order: the slots by decreasing size class
-// floor(log2 w) of the instances the backward visits (w = the largest `last`
+// The backward's launch order: the slots by decreasing size class (half
+// octaves, slot_class) of the instances the backward visits (w = the largest `last`
 // over the slot's pixels: it walks instances 0 .. w - 1), so that the
 // heaviest blocks start first; a slot with w = 0 (no contribution) is not
 // launched.  Two passes without global atomics (which serialise on a handful
@@ -848,10 +852,16 @@ static BwdWs carve_bwd(const rgs_bins* bins, void* ws) {
 // per block, derives every class's start and the block's offset in it from
 // the table and places its slots (the order inside a class is the launch
 // order only and affects no result).
-static constexpr int SW_SLOTS = 64;
 static constexpr int SW_CHUNK = 16;  // slots per wave whose loads are issued together
 static_assert(SW_SLOTS % (4 * SW_CHUNK) == 0, "a block's four waves take whole chunks");
-static_assert(SW_SLOTS == 64, "render_bwd_ws_bytes sizes the class table for 64 slots per row");
+static_assert(SW_CLS == 32 || SW_CLS == 64, "the placement's column sums split 256 threads by class");
+
+// Class of w > 0: 2 floor(log2 w) plus the bit below the leading one.
+__device__ __forceinline__ int slot_class(uint32_t w) {
+    const int hb = 31 - __clz(w);
+    if (SW_CLS == 32) return hb;
+    return 2 * hb + (hb > 0 ? (int)((w >> (hb - 1)) & 1u) : 0);
+}
 
 // Largest u32 of the wave, into lane 63 (DPP row operations, as the sums
 // above; a lane a broadcast does not reach keeps its value: max with 0).
@@ -872,12 +882,12 @@ __global__ __launch_bounds__(256) void k_slot_work(const uint32_t* __restrict__ 
                                                    uint32_t* __restrict__ wtab, uint32_t* __restrict__ touched,
                                                    int64_t touched_words, const uint32_t* __restrict__ pair_off,
                                                    uint32_t* __restrict__ first_pair) {
-    __shared__ uint32_t s_c[32];
+    __shared__ uint32_t s_c[SW_CLS];
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < touched_words; i += (int64_t)gridDim.x * 256)
         touched[i] = 0u;
     wave_first_pairs(pair_off, counters, first_pair);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (threadIdx.x < 32) s_c[threadIdx.x] = 0u;
+    if (threadIdx.x < SW_CLS) s_c[threadIdx.x] = 0u;
     __syncthreads();
     const int64_t ns = (int64_t)counters[2];
     const int64_t base = (int64_t)blockIdx.x * SW_SLOTS + wv * (SW_SLOTS / 4);
@@ -896,12 +906,12 @@ __global__ __launch_bounds__(256) void k_slot_work(const uint32_t* __restrict__ 
             const uint32_t m = wave_max_to_lane63(max(max(v[k].x, v[k].y), max(v[k].z, v[k].w)));
             if (lane == 63 && slot < ns) {
                 work[slot] = m;
-                if (m) atomicAdd(&s_c[31 - __clz(m)], 1u);
+                if (m) atomicAdd(&s_c[slot_class(m)], 1u);
             }
         }
     }
     __syncthreads();
-    if (threadIdx.x < 32) wtab[(size_t)blockIdx.x * 32 + threadIdx.x] = s_c[threadIdx.x];
+    if (threadIdx.x < SW_CLS) wtab[(size_t)blockIdx.x * SW_CLS + threadIdx.x] = s_c[threadIdx.x];
 }
 
 // n_launch: the number of launched slots (written by block 0).
@@ -909,33 +919,34 @@ __global__ __launch_bounds__(256) void k_slot_place(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ counters,
                                                     const uint32_t* __restrict__ wtab, uint32_t* __restrict__ n_launch,
                                                     uint32_t* __restrict__ order) {
-    __shared__ uint32_t s_tot[8][32], s_bef[8][32], s_base[32], s_c[32];
-    const int t = threadIdx.x, c = t & 31, g = t >> 5;
+    constexpr int NG = 256 / SW_CLS;  // row groups per class column
+    __shared__ uint32_t s_tot[NG][SW_CLS], s_bef[NG][SW_CLS], s_base[SW_CLS], s_c[SW_CLS];
+    const int t = threadIdx.x, c = t % SW_CLS, g = t / SW_CLS;
     const int64_t ns = (int64_t)counters[2];
     const int nblk = (int)((ns + SW_SLOTS - 1) / SW_SLOTS);
-    {  // the table's column c, rows g, g + 8, ...: all blocks, and the blocks before this one
+    {  // the table's column c, rows g, g + NG, ...: all blocks, and the blocks before this one
         uint32_t tot = 0, bef = 0;
-        for (int r0 = g; r0 < nblk; r0 += 64) {
+        for (int r0 = g; r0 < nblk; r0 += 8 * NG) {
             uint32_t x[8];  // eight loads issued before their adds
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const int r = r0 + 8 * k;
-                x[k] = r < nblk ? wtab[(size_t)r * 32 + c] : 0u;
+                const int r = r0 + NG * k;
+                x[k] = r < nblk ? wtab[(size_t)r * SW_CLS + c] : 0u;
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 tot += x[k];
-                bef += r0 + 8 * k < (int)blockIdx.x ? x[k] : 0u;
+                bef += r0 + NG * k < (int)blockIdx.x ? x[k] : 0u;
             }
         }
         s_tot[g][c] = tot;
         s_bef[g][c] = bef;
     }
-    if (t < 32) s_c[t] = 0u;
+    if (t < SW_CLS) s_c[t] = 0u;
     __syncthreads();
-    if (t < 32) {
+    if (t < SW_CLS) {
         uint32_t tot = 0, bef = 0;
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < NG; ++k) {
             tot += s_tot[k][t];
             bef += s_bef[k][t];
         }
@@ -945,7 +956,7 @@ __global__ __launch_bounds__(256) void k_slot_place(const uint32_t* __restrict__
     __syncthreads();
     if (t == 0) {
         uint32_t run = 0;
-        for (int k = 31; k >= 0; --k) {
+        for (int k = SW_CLS - 1; k >= 0; --k) {
             s_base[k] = run + s_bef[0][k];
             run += s_tot[0][k];
         }
@@ -955,7 +966,7 @@ __global__ __launch_bounds__(256) void k_slot_place(const uint32_t* __restrict__
     const int64_t i = (int64_t)blockIdx.x * SW_SLOTS + t;
     const uint32_t wk = (t < SW_SLOTS && i < ns) ? work[i] : 0u;
     if (wk) {
-        const int k = 31 - __clz(wk);
+        const int k = slot_class(wk);
         order[s_base[k] + atomicAdd(&s_c[k], 1u)] = (uint32_t)i;
     }
 }
