@@ -408,20 +408,27 @@ def partition_bench(args):
             cell = cell_of_rank[view, keys & (K - 1)]
             inst = np.bincount(cell, weights=rng_[:, 1] - rng_[:, 0], minlength=K).astype(np.int64)
             slots = np.bincount(cell, minlength=K)
-            # time each cell's slots alone: a launch order holding only that cell's slots
-            order_all = st.bins["slot_order"][:S].cpu().numpy()
+            # time each cell's slots alone, as a worker holding one cell renders
+            # them (every pixel starting from P = 1): a slot table with only
+            # that cell's slots (the forward walks a tile's slots from
+            # tile_slot), copied into buffers of the full capacities
+            T = int(st.total_tiles)
+            cap = int(st.slot_capacity)
             ms = []
             bs = st.bins_struct
-            saved = (bs.slot_order, bs.counters)
+            saved = (bs.slot_key, bs.slot_range, bs.tile_slot)
             for k in range(K):
-                sel = order_all[cell[order_all] == k].astype(np.int32)
+                sel = np.nonzero(cell == k)[0]
                 if sel.size == 0:
                     ms.append(0.0)
                     continue
-                so = torch.from_numpy(sel).cuda()
-                cnt = st.bins["counters"].clone()
-                cnt[2] = int(sel.size)
-                bs.slot_order, bs.counters = so.data_ptr(), cnt.data_ptr()
+                idx = torch.from_numpy(sel).cuda()
+                sk = torch.zeros(cap, dtype=torch.int32, device="cuda")
+                sr = torch.zeros(2 * cap, dtype=torch.int32, device="cuda")
+                sk[: sel.size] = st.bins["slot_key"][idx]
+                sr[: 2 * sel.size] = st.bins["slot_range"][: 2 * S].view(S, 2)[idx].reshape(-1)
+                tsl = torch.from_numpy(np.searchsorted(gt[sel], np.arange(T + 1), side="left").astype(np.int32)).cuda()
+                bs.slot_key, bs.slot_range, bs.tile_slot = sk.data_ptr(), sr.data_ptr(), tsl.data_ptr()
                 ts = []
                 for rep in range(4):
                     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -437,7 +444,8 @@ def partition_bench(args):
                     if rep:
                         ts.append(a.elapsed_time(b))
                 ms.append(float(np.median(ts)))
-            bs.slot_order, bs.counters = saved
+                del sk, sr, tsl
+            bs.slot_key, bs.slot_range, bs.tile_slot = saved
             counts = kd.counts.cpu().numpy()
             res[rule_name] = {"gaussians_per_cell": counts.tolist(), "instances_per_cell": inst.tolist(),
                               "slots_per_cell": slots.tolist(), "render_ms_per_cell": [round(x, 4) for x in ms],
