@@ -349,6 +349,22 @@ __global__ __launch_bounds__(BN_THREADS) void k_fill_u32(uint32_t* __restrict__ 
     if (i < m) p[i] = v;
 }
 
+// Size classes of the launch orders: the slots by whole octaves of their
+// length (32 classes), the tiles (the forward's order) by half octaves of
+// their instance count (TCLS classes).  cls holds the slot counts [0, 32),
+// the slot reservations [32, 64), the tile counts [64, 64 + TCLS) and the tile
+// reservations [64 + TCLS, 64 + 2 TCLS).
+static constexpr int TCLS = 64;
+static constexpr int NCLS_WORDS = 64 + 2 * TCLS;
+static_assert(NCLS_WORDS <= BN_THREADS, "one block clears and scans the class words");
+
+__device__ __forceinline__ int tile_class(uint32_t len) {
+    const uint32_t v = len | 1u;
+    const int hb = 31 - __clz(v);
+    if (TCLS == 32) return hb;
+    return 2 * hb + (hb > 0 ? (int)((v >> (hb - 1)) & 1u) : 0);
+}
+
 // Slot boundaries on the dense (tile, rank) table; block 0 also clears the
 // size-class counters of the launch orders (launched even without instances).
 // (A key at or past the table's end would mean an emission bug; it is skipped
@@ -357,7 +373,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __re
                                                             const uint32_t* __restrict__ n_dev, int64_t dense,
                                                             uint32_t* __restrict__ dstart, uint32_t* __restrict__ dend,
                                                             uint32_t* __restrict__ cls) {
-    if (blockIdx.x == 0 && threadIdx.x < 128) cls[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < NCLS_WORDS) cls[threadIdx.x] = 0u;
     const int64_t n_inst = (int64_t)*n_dev;
     // a thread takes SB_ITEMS keys BN_THREADS apart per step; every key and
     // its two neighbours are loaded (coalesced, overlapping in cache) before
@@ -384,13 +400,12 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __re
     }
 }
 
-// Launch orders, largest first by size class floor(log2 len): the slots
+// Launch orders, largest first by size class (tile_class; octaves for the slots): the slots
 // (len = instances; the backward's order) and the tiles (len = instances of
 // all the tile's slots, which are contiguous in the sorted list; the
 // forward's order), so that long blocks do not start last and stretch the
 // tail of the render.  One count and one placement kernel serve both, a
-// thread taking slot i and tile i.  cls[0..31] / cls[32..63] hold the slot
-// class counts and reservations, cls[64..95] / cls[96..127] the tiles'.
+// thread taking slot i and tile i (class layout of cls above).
 __device__ __forceinline__ uint32_t tile_len(const uint32_t* __restrict__ tile_slot,
                                              const uint32_t* __restrict__ slot_range, int64_t t) {
     const uint32_t s0 = tile_slot[t], s1 = tile_slot[t + 1];
@@ -405,7 +420,7 @@ __device__ __forceinline__ uint32_t tile_len(const uint32_t* __restrict__ tile_s
 // slot_range, tile_slot (a tile's first slot; entry T = the slot count) and,
 // with fold = 1, the slot count; counts the size classes of the slots and of
 // all T tiles (a tile's length: its instances, from its first slot's start to
-// its last slot's end) into cls[0..31] and cls[64..95].
+// its last slot's end) into cls (layout above).
 static constexpr int SL_ITEMS = (int)(RGS_SCAN_TILE / BN_THREADS);
 // Up to this many tiles a block sums the earlier tiles' marks itself.
 static constexpr int64_t SLOT_FOLD_TILES = 1024;
@@ -418,13 +433,13 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_build(const uint32_t* __res
                                                            uint32_t* __restrict__ slot_range,
                                                            uint32_t* __restrict__ tile_slot, uint32_t* __restrict__ cls) {
     __shared__ uint32_t s_st[RGS_SCAN_TILE], s_en[RGS_SCAN_TILE];
-    __shared__ uint32_t s_c[64];
+    __shared__ uint32_t s_c[32 + TCLS];
     __shared__ uint32_t s_w[BN_THREADS / 64];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t base = (int64_t)blockIdx.x * RGS_SCAN_TILE;
     const int nloc = (int)((dense - base) < RGS_SCAN_TILE ? (dense - base) : RGS_SCAN_TILE);
     const int K = 1 << L;
-    if (t < 64) s_c[t] = 0u;
+    if (t < 32 + TCLS) s_c[t] = 0u;
     // the first earlier tile sum of the thread is loaded with the entries
     const uint32_t p0 = (fold && (uint32_t)t < blockIdx.x) ? partial[t] : 0u;
     {  // coalesced loads (all first), into LDS
@@ -489,7 +504,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_build(const uint32_t* __res
                 }
             }
             const uint32_t tl = lo != 0xffffffffu ? hi - lo : 0u;
-            atomicAdd(&s_c[32 + 31 - __clz(tl | 1u)], 1u);
+            atomicAdd(&s_c[32 + tile_class(tl)], 1u);
         }
         const uint32_t a = s_st[e];
         if (a != 0xffffffffu) {
@@ -506,7 +521,7 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_build(const uint32_t* __res
         if (fold) *n_slots = toff + tot;
     }
     __syncthreads();
-    if (t < 64 && s_c[t]) atomicAdd(&cls[t < 32 ? t : t + 32], s_c[t]);
+    if (t < 32 + TCLS && s_c[t]) atomicAdd(&cls[t < 32 ? t : t + 32], s_c[t]);
 }
 
 // Items are placed class by class, classes in decreasing order: every block
@@ -519,12 +534,14 @@ __global__ __launch_bounds__(BN_THREADS) void k_class_place(const uint32_t* __re
                                                             const uint32_t* __restrict__ tile_slot, int64_t T,
                                                             uint32_t* __restrict__ cls, uint32_t* __restrict__ slot_order,
                                                             uint32_t* __restrict__ tile_order) {
-    __shared__ uint32_t s_c[64], s_base[64];
-    if (threadIdx.x < 64) s_c[threadIdx.x] = 0u;
+    __shared__ uint32_t s_c[32 + TCLS], s_base[32 + TCLS];
+    if (threadIdx.x < 32 + TCLS) s_c[threadIdx.x] = 0u;
     if (threadIdx.x < 2) {
-        const uint32_t* cnt = cls + 64 * threadIdx.x;  // slots: cls[0..31]; tiles: cls[64..95]
+        // slots: counts cls[0..31] into s_base[0..31]; tiles: cls[64..] into s_base[32..]
+        const int nc = threadIdx.x == 0 ? 32 : TCLS;
+        const uint32_t* cnt = cls + 64 * threadIdx.x;
         uint32_t run = 0;
-        for (int c = 31; c >= 0; --c) {
+        for (int c = nc - 1; c >= 0; --c) {
             s_base[32 * threadIdx.x + c] = run;
             run += cnt[c];
         }
@@ -539,12 +556,12 @@ __global__ __launch_bounds__(BN_THREADS) void k_class_place(const uint32_t* __re
         ls = atomicAdd(&s_c[cs], 1u);
     }
     if (okt) {
-        ct = 32 + 31 - __clz(tile_len(tile_slot, slot_range, i) | 1u);
+        ct = 32 + tile_class(tile_len(tile_slot, slot_range, i));
         lt = atomicAdd(&s_c[ct], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < 64 && s_c[threadIdx.x]) {
-        const int r = threadIdx.x < 32 ? 32 + threadIdx.x : 96 + (threadIdx.x - 32);  // reservation counters
+    if (threadIdx.x < 32 + TCLS && s_c[threadIdx.x]) {
+        const int r = threadIdx.x < 32 ? 32 + threadIdx.x : 64 + TCLS + (threadIdx.x - 32);  // reservation counters
         s_base[threadIdx.x] += atomicAdd(&cls[r], s_c[threadIdx.x]);
     }
     __syncthreads();
@@ -565,7 +582,7 @@ size_t bin_ws_bytes(int64_t n, int n_views, int64_t total_tiles, int L, int64_t 
     c.take<uint64_t>(capacity + 1);   // instance vals alt
     c.take<uint32_t>(dense + 1);      // dense start
     c.take<uint32_t>(dense + 1);      // dense end
-    c.take<uint32_t>(128);            // slot and tile size classes
+    c.take<uint32_t>(NCLS_WORDS);     // slot and tile size classes
     const int64_t big = m > capacity ? m : capacity;
     const int64_t big2 = big > dense ? big : dense;
     c.take<char>(radix_ws_bytes(big2 + 1));
@@ -594,7 +611,7 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     uint64_t* vals_alt = c.take<uint64_t>(bins->capacity + 1);
     uint32_t* dstart = c.take<uint32_t>(dense + 1);
     uint32_t* dend = c.take<uint32_t>(dense + 1);
-    uint32_t* cls = c.take<uint32_t>(128);
+    uint32_t* cls = c.take<uint32_t>(NCLS_WORDS);
     const int64_t big = m > bins->capacity ? m : bins->capacity;
     const int64_t big2 = big > dense ? big : dense;
     void* rws = c.take<char>(radix_ws_bytes(big2 + 1));
