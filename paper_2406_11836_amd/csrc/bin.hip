@@ -356,13 +356,15 @@ __global__ __launch_bounds__(BN_THREADS) void k_fill_u32(uint32_t* __restrict__ 
 // reservations [64 + TCLS, 64 + 2 TCLS).
 static constexpr int TCLS = 64;
 static constexpr int NCLS_WORDS = 64 + 2 * TCLS;
-static_assert(NCLS_WORDS <= BN_THREADS, "one block clears and scans the class words");
+static_assert(TCLS == 32 || TCLS == 64 || TCLS == 128, "octaves, half or quarter octaves");
+static_assert(32 + TCLS <= BN_THREADS, "a thread per class in the count and placement passes");
 
 __device__ __forceinline__ int tile_class(uint32_t len) {
     const uint32_t v = len | 1u;
     const int hb = 31 - __clz(v);
     if (TCLS == 32) return hb;
-    return 2 * hb + (hb > 0 ? (int)((v >> (hb - 1)) & 1u) : 0);
+    if (TCLS == 64) return 2 * hb + (hb > 0 ? (int)((v >> (hb - 1)) & 1u) : 0);
+    return 4 * hb + (hb >= 2 ? (int)((v >> (hb - 2)) & 3u) : (hb == 1 ? (int)((v & 1u) << 1) : 0));
 }
 
 // Slot boundaries on the dense (tile, rank) table; block 0 also clears the
@@ -373,7 +375,8 @@ __global__ __launch_bounds__(BN_THREADS) void k_slot_bounds(const uint32_t* __re
                                                             const uint32_t* __restrict__ n_dev, int64_t dense,
                                                             uint32_t* __restrict__ dstart, uint32_t* __restrict__ dend,
                                                             uint32_t* __restrict__ cls) {
-    if (blockIdx.x == 0 && threadIdx.x < NCLS_WORDS) cls[threadIdx.x] = 0u;
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < NCLS_WORDS; k += BN_THREADS) cls[k] = 0u;
     const int64_t n_inst = (int64_t)*n_dev;
     // a thread takes SB_ITEMS keys BN_THREADS apart per step; every key and
     // its two neighbours are loaded (coalesced, overlapping in cache) before

@@ -854,13 +854,15 @@ static BwdWs carve_bwd(const rgs_bins* bins, void* ws) {
 // order only and affects no result).
 static constexpr int SW_CHUNK = 16;  // slots per wave whose loads are issued together
 static_assert(SW_SLOTS % (4 * SW_CHUNK) == 0, "a block's four waves take whole chunks");
-static_assert(SW_CLS == 32 || SW_CLS == 64, "the placement's column sums split 256 threads by class");
+static_assert(SW_CLS == 32 || SW_CLS == 64 || SW_CLS == 128, "the placement's column sums split 256 threads by class");
 
-// Class of w > 0: 2 floor(log2 w) plus the bit below the leading one.
+// Class of w > 0: 2 floor(log2 w) plus the bit below the leading one (half
+// octaves; whole or quarter octaves for 32 or 128 classes).
 __device__ __forceinline__ int slot_class(uint32_t w) {
     const int hb = 31 - __clz(w);
     if (SW_CLS == 32) return hb;
-    return 2 * hb + (hb > 0 ? (int)((w >> (hb - 1)) & 1u) : 0);
+    if (SW_CLS == 64) return 2 * hb + (hb > 0 ? (int)((w >> (hb - 1)) & 1u) : 0);
+    return 4 * hb + (hb >= 2 ? (int)((w >> (hb - 2)) & 3u) : (hb == 1 ? (int)((w & 1u) << 1) : 0));
 }
 
 // Largest u32 of the wave, into lane 63 (DPP row operations, as the sums
