@@ -89,6 +89,8 @@ def test_argument_errors_enqueue_nothing(lib):
     need = C.c_int64(0)
     assert lib.rgs_bin_sort(C.byref(ps), 10, cam, 1, None, 2, C.byref(bs), C.byref(need), None, 0, None) == E
     assert lib.rgs_render_partial(C.byref(ps), 10, C.byref(bs), cam, 1, None, C.byref(kd), 5e-5, C.byref(pt), None, None) == E
+    assert lib.rgs_render_partial_merged(C.byref(ps), 10, C.byref(bs), cam, 1, None, C.byref(kd), 5e-5, C.byref(pt),
+                                         None, None, None, None) == E
     assert lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam, 1, None, None, None, None) == E
     assert lib.rgs_merge_partials_bwd(None, None, C.byref(pt), C.byref(bs), cam, 1, None, C.byref(pg), None) == E
     assert lib.rgs_render_partial_bwd(C.byref(pg), C.byref(pt), C.byref(bs), C.byref(ps), 10, cam, 1, None,
@@ -224,6 +226,16 @@ def test_aliased_buffers_are_rejected(lib):
     pt = L.Partials(0x70000000, 0x71000000, 0x72000000)
     assert lib.rgs_merge_partials(C.byref(pt), C.byref(bs), cam, 1, C.c_void_p(0x6000000), C.c_void_p(0x70000000 + 4),
                                   C.c_void_p(0x73000000), None) == E
+    # merged render: the image over the partial colours, T_final inside the image
+    kdm = L.KdTree()
+    kdm.L, kdm.box_lo, kdm.box_hi = 0, 0x5100000, 0x5200000
+    psm = L.Projected(0x20000000, 0x21000000, 0x22000000, 0x23000000, 0x24000000)
+    assert lib.rgs_render_partial_merged(C.byref(psm), 1000, C.byref(bs), cam, 1, C.c_void_p(0x6000000),
+                                         C.byref(kdm), 5e-5, C.byref(pt), C.c_void_p(0x70000000 + 4),
+                                         C.c_void_p(0x73000000), None, None) == E
+    assert lib.rgs_render_partial_merged(C.byref(psm), 1000, C.byref(bs), cam, 1, C.c_void_p(0x6000000),
+                                         C.byref(kdm), 5e-5, C.byref(pt), C.c_void_p(0x73000000),
+                                         C.c_void_p(0x73000000 + 64), None, None) == E
     # merge backward: dT over T
     pg = L.PartialsGrad(0x74000000, 0x71000000 + 8)
     assert lib.rgs_merge_partials_bwd(C.c_void_p(0x75000000), None, C.byref(pt), C.byref(bs), cam, 1,
