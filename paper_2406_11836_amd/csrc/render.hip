@@ -677,15 +677,20 @@ __global__ __launch_bounds__(256) void k_pair_seg(const float* __restrict__ reco
     const uint32_t rk = r0 + 1u + (uint32_t)lane;
     const int64_t bk = rk <= n_pairs ? (int64_t)pair_off[rk] : INT64_MAX;
     const int64_t b_r0 = (int64_t)pair_off[r0];
-    int pos = 0;
-#pragma unroll
-    for (int step = 32; step >= 1; step >>= 1) {
-        const int64_t bv = __shfl(bk, pos + step - 1, 64);
-        if (bv <= j) pos += step;
-    }
-    const int pos_prev = __shfl_up(pos, 1, 64);
-    const uint64_t heads = __ballot(lane == 0 || pos != pos_prev);
+    // the lanes where those pairs start, as a lane mask: a start inside the
+    // wave (never at its lane 0) sets its lane's byte in the wave's 64 bytes of
+    // LDS (starts are distinct; one wave's LDS operations run in order)
+    __shared__ uint8_t s_flag[4][64];
+    uint8_t* fl = s_flag[threadIdx.x >> 6];
+    fl[lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    const int64_t dl = bk - j0;
+    if (dl > 0 && dl < 64) fl[dl] = 1;
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t starts = __ballot(fl[lane] != 0);
     const uint64_t le_mask = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int pos = __popcll(starts & le_mask);  // pairs after r0 starting at or before j
+    const uint64_t heads = starts | 1ull;
     const int seg0 = 63 - __builtin_clzll(heads & le_mask);  // first lane of this lane's segment
     // the start and end of this lane's pair, from the starts already loaded
     const int64_t b_at = __shfl(bk, pos > 0 ? pos - 1 : 0, 64);
