@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define RGS_ABI_VERSION 6
+#define RGS_ABI_VERSION 7
 #define RGS_TILE 16       /* screen tiles are 16 x 16 pixels */
 #define RGS_MAX_L 6       /* K = 2^L <= 64 cells */
 #define RGS_MAX_VIEWS 16  /* views per call */
@@ -140,7 +140,7 @@ typedef struct {
 } rgs_kdtree;
 
 /* Per-(view, Gaussian) projection output.  Where count is 0 (culled) only
-   count is written: rec, rect, cellmask and depth hold whatever the buffers held. */
+   count is written: rec, bin and depth hold whatever the buffers held. */
 typedef struct {
     float *rec;         /* [V*N][16]: mx, my, ca, k | e, alpha, tau, z | r, g, b, flags |
                            (footprint d^2 = ca (dx + k dy)^2 + e dy^2, i.e. the conic
@@ -151,9 +151,12 @@ typedef struct {
                            (tiles of row k) << 4 | (its first column - the rectangle's
                            first tile column), else all ones;
                            64-byte aligned: the render kernels fetch one line per instance */
-    int16_t *rect;      /* [V*N][4]: sample-pixel rectangle x_lo, x_hi, y_lo, y_hi */
-    uint64_t *cellmask; /* [V*N]: cells the footprint can reach (bit k = cell k) */
-    uint32_t *count;    /* [V*N]: instances = |cellmask| * tiles of the rectangle that the
+    uint32_t *bin;      /* [V*N][8] words, 32-byte aligned: the binning record of a pair, which
+                           the instance emission reads as one line: words 0-1 the rect (as in
+                           rec), words 2-3 the row-span descriptor (as in rec), words 4-5 the
+                           cell mask (low word first; bit k = cell k: the cells the footprint
+                           can reach), word 6 the instance count, word 7 the tiles per cell */
+    uint32_t *count;    /* [V*N]: instances = |cell mask| * tiles of the rectangle that the
                            footprint's ellipse can reach (per tile row, the span of columns
                            holding a pixel centre of the padded ellipse); 0 = culled */
     float *depth;       /* [V*N]: camera depth z (the same value as in rec): the key of the

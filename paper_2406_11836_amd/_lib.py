@@ -44,7 +44,7 @@ class KdTree(C.Structure):
 
 
 class Projected(C.Structure):
-    _fields_ = [("rec", vp), ("rect", vp), ("cellmask", vp), ("count", vp), ("depth", vp)]
+    _fields_ = [("rec", vp), ("bin", vp), ("count", vp), ("depth", vp)]
 
 
 class Bins(C.Structure):

@@ -122,7 +122,7 @@ static Spans grad_spans(const rgs_gaussians_grad* o, const rgs_gaussians* g) {
 
 // m = views * Gaussians
 static Spans proj_spans(const rgs_projected* p, size_t m) {
-    return {{p->rec, (size_t)RGS_REC_FLOATS * 4 * m}, {p->rect, 8 * m}, {p->cellmask, 8 * m}, {p->count, 4 * m},
+    return {{p->rec, (size_t)RGS_REC_FLOATS * 4 * m}, {p->bin, 32 * m}, {p->count, 4 * m},
             {p->depth, 4 * m}};
 }
 
@@ -395,7 +395,7 @@ rgs_status rgs_cell_visibility(const rgs_camera* cams, int32_t n_views, int32_t 
     return RGS_OK;
 }
 
-static bool proj_ok(const rgs_projected* p) { return p && p->rec && p->rect && p->cellmask && p->count && p->depth; }
+static bool proj_ok(const rgs_projected* p) { return p && p->rec && p->bin && p->count && p->depth; }
 
 rgs_status rgs_project_sh(const rgs_gaussians* g, const rgs_camera* cams, int32_t n_views, const void* views_dev,
                           const rgs_kdtree* kd, int32_t cells, const rgs_projected* out, rgs_stream stream) {

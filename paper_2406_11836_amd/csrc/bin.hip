@@ -198,7 +198,7 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t a, uint32_t b) {
 // consecutive pairs whose rows fit.
 __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict__ pair_src, const uint32_t* __restrict__ n_dev,
                                                      const uint32_t* __restrict__ pair_off, const float* __restrict__ rec,
-                                                     const uint64_t* __restrict__ cellmask, int64_t n_gauss,
+                                                     const uint32_t* __restrict__ bin, int64_t n_gauss,
                                                      const ViewTable* __restrict__ vt, uint32_t* __restrict__ keys,
                                                      uint64_t* __restrict__ vals) {
     constexpr int ROWPOOL = 2048;  // rows of one run; a rectangle has at most 256 tile rows
@@ -222,15 +222,17 @@ __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict_
         uint32_t rows = 0;
         if (t < nb) {
             const uint32_t src = pair_src[r0 + t];
-            const float4 r4 = reinterpret_cast<const float4*>(rec + (size_t)src * RGS_REC_FLOATS)[3];
-            const uint64_t m = cellmask[src];
+            // the pair's binning record: one 32-byte line
+            const uint4* bp = reinterpret_cast<const uint4*>(bin) + 2 * (size_t)src;
+            const uint4 b0 = bp[0], b1 = bp[1];
             const int v = (int)(src / (uint64_t)n_gauss);  // once per pair
             const ViewParams& V = vt->v[v];
-            const uint64_t desc = (uint64_t)__float_as_uint(r4.z) | ((uint64_t)__float_as_uint(r4.w) << 32);
-            const uint32_t ry = __float_as_uint(r4.y);
+            const uint64_t desc = (uint64_t)b0.z | ((uint64_t)b0.w << 32);
+            const uint32_t ry = b0.y;
             s_src[t] = src;
-            s_mask[t] = m;
-            s_rect[t] = make_uint2(__float_as_uint(r4.x), ry);
+            s_mask[t] = (uint64_t)b1.x | ((uint64_t)b1.y << 32);
+            s_nt[t] = b1.w;
+            s_rect[t] = make_uint2(b0.x, ry);
             s_desc[t] = desc;
             s_off[t] = pair_off[r0 + t];
             s_vto[t] = V.tile_offset;
@@ -251,8 +253,6 @@ __global__ __launch_bounds__(BN_THREADS) void k_emit(const uint32_t* __restrict_
             s_rend[t] = before + inc;
         }
         __syncthreads();
-        // tiles per cell = the pair's instances / its cells (no second gather of the counts)
-        if (t < nb) s_nt[t] = (s_off[t + 1] - s_off[t]) / (uint32_t)__popcll(s_mask[t]);
         for (int p0 = 0; p0 < nb;) {
             // the longest run of pairs from p0 whose pooled rows fit (at least p0 itself)
             const uint32_t rbase = p0 > 0 ? s_rend[p0 - 1] : 0u;
@@ -682,7 +682,7 @@ rgs_status bin_sort(const rgs_projected* proj, int64_t n, int n_views, const Vie
     // 3. emit and sort instances by (tile, rank)
     if (m > 0)
         hipLaunchKernelGGL(k_emit, dgrid(m), dim3(BN_THREADS), 0, s, bins->pair_src, &cnt[0], bins->pair_off, proj->rec,
-                           proj->cellmask, n, vt_dev, bins->keys, bins->vals);
+                           proj->bin, n, vt_dev, bins->keys, bins->vals);
     RGS_LAUNCH_CHECK();
     const int key_bits = L + bits_for((uint64_t)total_tiles);
     if (key_bits > 32) return RGS_E_UNSUPPORTED;

@@ -364,12 +364,16 @@ __global__ __launch_bounds__(PJ_THREADS, 3) void k_project(rgs_gaussians g, cons
             nt += len;
             if (small && len) desc |= (uint64_t)((len << 4) | (uint32_t)(cs.x - tx0)) << (8 * (ty - ty0));
         }
-        out.count[src] = (uint32_t)__popcll(mask) * nt;
-        out.cellmask[src] = mask;
+        const uint32_t cnt = (uint32_t)__popcll(mask) * nt;
+        out.count[src] = cnt;
         out.depth[src] = p.z;
         const uint32_t rx = ((uint32_t)(uint16_t)r[0]) | ((uint32_t)(uint16_t)r[1] << 16);
         const uint32_t ry = ((uint32_t)(uint16_t)r[2]) | ((uint32_t)(uint16_t)r[3] << 16);
-        reinterpret_cast<uint2*>(out.rect)[src] = make_uint2(rx, ry);
+        {  // the binning record, one 32-byte line for the emission
+            uint4* bp = reinterpret_cast<uint4*>(out.bin) + 2 * src;
+            bp[0] = make_uint4(rx, ry, (uint32_t)desc, (uint32_t)(desc >> 32));
+            bp[1] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), cnt, nt);
+        }
         // colour from the view direction (value path)
         float dx = mu0 - V.o[0], dy = mu1 - V.o[1], dz = mu2 - V.o[2];
         const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);

@@ -105,8 +105,8 @@ class FwdState:
 
     def proj_struct(self) -> L.Projected:
         s = L.Projected()
-        s.rec, s.rect = self.proj["rec"].data_ptr(), self.proj["rect"].data_ptr()
-        s.cellmask, s.count = self.proj["cellmask"].data_ptr(), self.proj["count"].data_ptr()
+        s.rec, s.bin = self.proj["rec"].data_ptr(), self.proj["bin"].data_ptr()
+        s.count = self.proj["count"].data_ptr()
         s.depth = self.proj["depth"].data_ptr()
         return s
 
@@ -254,11 +254,11 @@ class Rasterizer:
         g = gaussians_struct(params)
         ks = kd.struct()
         m = V * n
-        proj = dict(rec=self._buf("rec", m * L.REC_FLOATS, torch.float32), rect=self._buf("rect", m * 4, torch.int16),
-                    cellmask=self._buf("cellmask", m, torch.int64), count=self._buf("count", m, torch.int32),
+        proj = dict(rec=self._buf("rec", m * L.REC_FLOATS, torch.float32), bin=self._buf("bin", m * 8, torch.int32),
+                    count=self._buf("count", m, torch.int32),
                     depth=self._buf("depth", m, torch.float32))
-        ps = L.Projected(proj["rec"].data_ptr(), proj["rect"].data_ptr(), proj["cellmask"].data_ptr(),
-                         proj["count"].data_ptr(), proj["depth"].data_ptr())
+        ps = L.Projected(proj["rec"].data_ptr(), proj["bin"].data_ptr(), proj["count"].data_ptr(),
+                         proj["depth"].data_ptr())
         L.check("rgs_project_sh", lib.rgs_project_sh(C.byref(g), cam_arr, V, _p(views), C.byref(ks), int(cells), C.byref(ps),
                                                      stream))
         _mark(marks, "project")

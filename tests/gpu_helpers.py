@@ -26,6 +26,16 @@ def oracle_scene(params, cam, L):
     return kd, order, rank_of, pr
 
 
+def proj_bin(st, n):
+    """The first n binning records of a projection: rectangle (int32 [n, 4]:
+    x_lo, x_hi, y_lo, y_hi), cell mask (uint64 [n]), instance count and tiles
+    per cell (uint32 [n] each).  Only rows with a non-zero count are defined."""
+    b = st.proj["bin"][: 8 * n].view(n, 8).cpu().numpy().view(np.uint32)
+    rect = np.ascontiguousarray(b[:, :2]).view(np.int16).astype(np.int32)
+    mask = np.ascontiguousarray(b[:, 4:6]).view(np.uint64)[:, 0]
+    return rect, mask, b[:, 6].copy(), b[:, 7].copy()
+
+
 def gpu_partials_dense(st, view=0):
     """GPU per-slot partials scattered to [H*W, K] per-cell maps of one view
     (cells without a slot in a tile: C = 0, T = 1)."""

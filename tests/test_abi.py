@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_status(lib):
-    assert lib.rgs_abi_version() == 6
+    assert lib.rgs_abi_version() == 7
     assert lib.rgs_status_string(0) == b"ok"
     assert lib.rgs_status_string(-2) == b"buffer capacity too small"
 
@@ -196,13 +196,13 @@ def test_aliased_buffers_are_rejected(lib):
     g = _fake_gaussians(L, 1000, 0x10000000)
     kd = L.KdTree()
     kd.L, kd.split = 0, 0x5000000
-    ps = L.Projected(g.sh + 64, 0x21000000, 0x22000000, 0x23000000, 0x24000000)
+    ps = L.Projected(g.sh + 64, 0x21000000, 0x23000000, 0x24000000)
     assert lib.rgs_project_sh(C.byref(g), cam, 1, C.c_void_p(0x6000000), C.byref(kd), 0, C.byref(ps), None) == E
-    # two outputs overlapping each other (count inside cellmask)
-    ps = L.Projected(0x20000000, 0x21000000, 0x22000000, 0x22000000 + 4000, 0x24000000)
+    # two outputs overlapping each other (count inside the binning records)
+    ps = L.Projected(0x20000000, 0x21000000, 0x21000000 + 4000, 0x24000000)
     assert lib.rgs_project_sh(C.byref(g), cam, 1, C.c_void_p(0x6000000), C.byref(kd), 0, C.byref(ps), None) == E
     # subset modes need the KD tree's masks
-    ps = L.Projected(0x20000000, 0x21000000, 0x22000000, 0x23000000, 0x24000000)
+    ps = L.Projected(0x20000000, 0x21000000, 0x23000000, 0x24000000)
     assert lib.rgs_project_sh(C.byref(g), cam, 1, C.c_void_p(0x6000000), C.byref(kd), 1, C.byref(ps), None) == E
     assert lib.rgs_project_sh(C.byref(g), cam, 1, C.c_void_p(0x6000000), C.byref(kd), 2, C.byref(ps), None) == E
     assert lib.rgs_project_sh(C.byref(g), cam, 1, C.c_void_p(0x6000000), C.byref(kd), 3, C.byref(ps), None) == E
@@ -229,7 +229,7 @@ def test_aliased_buffers_are_rejected(lib):
     # merged render: the image over the partial colours, T_final inside the image
     kdm = L.KdTree()
     kdm.L, kdm.box_lo, kdm.box_hi = 0, 0x5100000, 0x5200000
-    psm = L.Projected(0x20000000, 0x21000000, 0x22000000, 0x23000000, 0x24000000)
+    psm = L.Projected(0x20000000, 0x21000000, 0x23000000, 0x24000000)
     assert lib.rgs_render_partial_merged(C.byref(psm), 1000, C.byref(bs), cam, 1, C.c_void_p(0x6000000),
                                          C.byref(kdm), 5e-5, C.byref(pt), C.c_void_p(0x70000000 + 4),
                                          C.c_void_p(0x73000000), None, None) == E

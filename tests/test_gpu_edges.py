@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import device_params, gpu_partials_dense, grad_close, log
+from gpu_helpers import device_params, gpu_partials_dense, grad_close, log, proj_bin
 from paper_2406_11836_amd import raster, scenes
 
 pytestmark = pytest.mark.gpu
@@ -196,7 +196,7 @@ def test_needle_footprints(needles):
     d = pr["dec32"][vis].astype(np.float64)
     assert (1 + d[:, 8] ** 2 * d[:, 2] / d[:, 9]).max() > 1e4  # s00 s11 / det
     assert np.array_equal(st.proj["count"][:n].cpu().numpy().view(np.uint32), pr["count"])
-    rect = st.proj["rect"][: 4 * n].view(n, 4).cpu().numpy().astype(np.int32)
+    rect = proj_bin(st, n)[0]
     assert np.array_equal(rect[vis], pr["rect"][vis])
     okeys, ogids = oracle.bins(pr, rank_of, L, (W + 15) // 16)
     n_inst = st.bins_struct.n_instances

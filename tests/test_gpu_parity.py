@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import device_params, gpu_partials_dense, grad_close, log, oracle_scene
+from gpu_helpers import device_params, gpu_partials_dense, grad_close, log, oracle_scene, proj_bin
 from paper_2406_11836_amd import scenes
 
 pytestmark = pytest.mark.gpu
@@ -96,9 +96,13 @@ def test_project_bit_exact(name, rast):
     assert np.array_equal(cnt, pr["count"]), "instance counts"
     vis = pr["vis"] == 1
     assert vis.sum() > 0.3 * n
-    assert np.array_equal(st.proj["cellmask"][:n].cpu().numpy().view(np.uint64)[vis], pr["cellmask"][vis])
-    rect = st.proj["rect"][: 4 * n].view(n, 4).cpu().numpy().astype(np.int32)
+    rect, mask, bcnt, bnt = proj_bin(st, n)
+    assert np.array_equal(mask[vis], pr["cellmask"][vis])
     assert np.array_equal(rect[vis], pr["rect"][vis])
+    # the binning record repeats the count, and its tiles per cell divide it by the cells
+    assert np.array_equal(bcnt[vis], pr["count"][vis])
+    ncell = np.array([bin(int(x)).count("1") for x in pr["cellmask"][vis]], np.uint32)
+    assert np.array_equal(bnt[vis] * ncell, pr["count"][vis])
     # the render record carries the same rectangle (x_lo | x_hi << 16, y_lo | y_hi << 16)
     packed = rec[vis][:, 12:14].view(np.uint32)
     unpack = np.stack([packed[:, 0] & 0xffff, packed[:, 0] >> 16, packed[:, 1] & 0xffff, packed[:, 1] >> 16], 1)
@@ -183,7 +187,7 @@ def test_validity_camera_on_split_plane(rast):
     assert np.all(partC[left, 1] == 0.0) and np.all(partT[left, 1] == 1.0)
     assert np.all(partC[~left, 0] == 0.0) and np.all(partT[~left, 0] == 1.0)
     assert partC[left, 0].max() > 0.05 and partC[~left, 1].max() > 0.05
-    mask = st.proj["cellmask"][: 20000].cpu().numpy()[st.proj["count"][: 20000].cpu().numpy() != 0]
+    mask = proj_bin(st, 20000)[1][st.proj["count"][: 20000].cpu().numpy() != 0]
     assert (mask == 3).sum() > 10   # Gaussians straddling the plane are in both cells
 
 

@@ -17,7 +17,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import device_params, gpu_partials_dense, grad_close, log
+from gpu_helpers import device_params, gpu_partials_dense, grad_close, log, proj_bin
 from paper_2406_11836_amd import _lib as L
 from paper_2406_11836_amd import raster, scenes
 
@@ -101,7 +101,7 @@ def test_subset_modes_parity(cells, rast):
     cnt = st.proj["count"][:n].cpu().numpy().view(np.uint32)
     assert np.array_equal(cnt, pr["count"])
     vis = pr["count"] > 0
-    assert np.array_equal(st.proj["cellmask"][:n].cpu().numpy().view(np.uint64)[vis], pr["cellmask"][vis])
+    assert np.array_equal(proj_bin(st, n)[1][vis], pr["cellmask"][vis])
     okeys, ogids = oracle.bins(pr, rank_of, Ld, (cam["W"] + 15) // 16)
     n_inst = st.bins_struct.n_instances
     assert n_inst == len(okeys)
