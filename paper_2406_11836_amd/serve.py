@@ -74,7 +74,7 @@ class Server:
     # arrays plus per-pixel instance, partial-map and workspace storage
     def est_bytes(self, cam) -> float:
         px = float(cam["W"]) * float(cam["H"])
-        return self.n * 104.0 + px * 320.0
+        return self.n * 120.0 + px * 320.0
 
     def _worker(self, wid, jobs: queue.Queue, done: queue.Queue, warm_cams):
         try:
